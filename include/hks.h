@@ -1,0 +1,191 @@
+/*
+ * hks.h -- C ABI of the MI355X (gfx950) CKKS hybrid key-switching library.
+ *
+ * Operations follow de Castro et al., "Does Fully Homomorphic Encryption
+ * Need Compute Acceleration?" (arXiv 2112.06396):
+ *   - ModUp, ModDown, Decomp, KSKInnerProd, Automorph: Table "CKKS
+ *     Subroutines" (Sec. 2.4) and the switching-key shape, Eq. (kskShape);
+ *   - ModUp as iNTT -> NewLimb (basis conversion) -> NTT: Algorithm "ModUp";
+ *   - Rotate: Algorithm 3; HRotate (hoisted rotations): Algorithm 4;
+ *   - PtMult with Rescale: Algorithm 1; Mult with relinearization: Algorithm 2;
+ *   - NTT / evaluation representation: Sec. 2.3; RNS limbs: Sec. 2.2.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  Moduli.   A context holds L ciphertext primes q_0..q_{L-1} and K special
+ *            primes p_0..p_{K-1} (P = prod p_k).  Every prime must satisfy
+ *            2^49 < q < 2^50 and q = 1 mod 2N, and all must be distinct.
+ *            A "modulus index" numbers them 0..L-1 (q_i) then L..L+K-1 (p_k).
+ *  Digits.   alpha = ceil(L / dnum) limbs per digit; at level l (l limbs
+ *            q_0..q_{l-1} present) beta = ceil(l / alpha) digits, digit j
+ *            holding limbs [j*alpha, min((j+1)*alpha, l)).  K >= alpha.
+ *  Layout.   Polynomials are limb-major: [limbs][N] uint64, one limb per
+ *            modulus, residues canonical in [0, q).  Ciphertexts are (a, b)
+ *            as [2][l][N]; decryption is a*s + b.  The evaluation form holds
+ *            slot j = a(psi^(2 brv(j) + 1)) (bit-reversed order), psi =
+ *            nu^((q-1)/2N) with nu the least quadratic non-residue mod q.
+ *            Extended polynomials (over Q_l U P) order their limbs
+ *            q_0..q_{l-1}, p_0..p_{K-1}.
+ *  Keys.     Switching keys are [dnum][2][L+K][N] (row 0 = a_j, row 1 =
+ *            b_j), the limb of q_i at index i and of p_k at index L+k; at
+ *            level l only limbs [0,l) U [L,L+K) of digits j < beta are read.
+ *  Memory.   All uint64_t* data arguments are DEVICE pointers on the
+ *            context's device, owned by the caller, 16-byte aligned.  The
+ *            library never frees or retains them.  Outputs must not alias
+ *            inputs unless a call says "in place".
+ *  Streams.  `stream` is a hipStream_t (NULL = default stream).  Calls only
+ *            enqueue work and return; the caller synchronizes.  A context
+ *            owns one workspace: calls on one context must not run
+ *            concurrently on different streams.
+ *  Errors.   Every int-returning call returns HKS_OK (0) or a negative
+ *            status; no exception crosses the ABI and nothing aborts.  On an
+ *            error no work has been enqueued, except HKS_EHIP, which reports
+ *            a failed HIP launch.  hks_strerror() names a status.
+ */
+#ifndef HKS_H
+#define HKS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HKS_OK 0
+#define HKS_EINVAL (-1)       /* bad argument: level, galois, pointer, size, parameters */
+#define HKS_ENOMEM (-2)       /* device or host allocation failed */
+#define HKS_EHIP (-3)         /* a HIP runtime call or kernel launch failed */
+#define HKS_EUNSUPPORTED (-4) /* valid request outside what this build supports */
+
+/* hks_query keys */
+#define HKS_Q_N 1              /* ring degree N */
+#define HKS_Q_ALPHA 2          /* limbs per digit */
+#define HKS_Q_BETA 3           /* digits at `level` */
+#define HKS_Q_KSK_WORDS 4      /* uint64 words of one switching key, dnum*2*(L+K)*N */
+#define HKS_Q_WORKSPACE_BYTES 5/* device workspace owned by the context */
+#define HKS_Q_MODULUS 6        /* modulus with index `level` (0..L+K-1) */
+#define HKS_Q_L 7
+#define HKS_Q_K 8
+#define HKS_Q_DNUM 9
+#define HKS_Q_BATCH_CAP 10     /* ciphertexts processed per internal batch step */
+
+typedef struct hks_ctx hks_ctx;
+
+typedef struct {
+    uint32_t log_n;       /* 10..16 */
+    uint32_t L;           /* ciphertext primes, 1..48 */
+    uint32_t K;           /* special primes, alpha..16 */
+    uint32_t dnum;        /* digits of the switching key, 1..L */
+    const uint64_t *q;    /* host array [L] */
+    const uint64_t *p;    /* host array [K] */
+} hks_params;
+
+/* ---------------------------------------------------------------- host helpers */
+
+/* Primes of the form 2^bits - k*2^log_step + 1 (k = 1, 2, ...), descending,
+ * primality by deterministic Miller-Rabin.  bits = 50, log_step = log_n + 1
+ * (or larger) give primes valid for this library.  `out` is a host array of
+ * `count` words.  Returns HKS_OK or HKS_EINVAL. */
+int hks_gen_primes(uint32_t bits, uint32_t log_step, uint32_t count, uint64_t *out);
+
+/* Galois element g with Rotate(ct, g) realizing the paper's rotation phi_k
+ * (Sec. 2.1: phi_1 moves slot j-1 to slot j) under slots m(zeta^(5^j)):
+ * g = 5^(-k) mod 2N.  Negative k rotates the other way. */
+uint32_t hks_galois_for_rotation(int32_t k, uint32_t log_n);
+
+/* Galois element of complex conjugation, 2N - 1 (Conjugate, Table
+ * "CKKS FHE API": same implementation as Rotate). */
+uint32_t hks_galois_conjugate(uint32_t log_n);
+
+const char *hks_strerror(int status);
+
+/* ---------------------------------------------------------------- context */
+
+/* Validates the parameters, builds twiddle and conversion tables on `device`
+ * (HIP ordinal) and allocates the workspace.  *out is set only on HKS_OK. */
+int hks_create(const hks_params *params, int device, hks_ctx **out);
+
+/* Frees tables and workspace (synchronizes the device first).  NULL is a no-op. */
+void hks_destroy(hks_ctx *ctx);
+
+/* Reads one HKS_Q_* value into *out. */
+int hks_query(const hks_ctx *ctx, int key, uint32_t level, uint64_t *out);
+
+/* ---------------------------------------------------------------- polynomial calls */
+
+/* In place forward NTT (Sec. 2.3) of n_limbs consecutive limbs of x, limb i
+ * reduced by the modulus with index first_mod + i (coefficient -> evaluation). */
+int hks_ntt(hks_ctx *ctx, uint64_t *x, uint32_t first_mod, uint32_t n_limbs, void *stream);
+
+/* In place inverse NTT (evaluation -> coefficient), same arguments. */
+int hks_intt(hks_ctx *ctx, uint64_t *x, uint32_t first_mod, uint32_t n_limbs, void *stream);
+
+/* Automorph X -> X^galois (Table "CKKS Subroutines"), galois odd in [1, 2N).
+ * eval_domain != 0: slot permutation of evaluation-form limbs; else the
+ * coefficient map with negation.  y = psi_g(x), n_limbs limbs with moduli
+ * first_mod..first_mod+n_limbs-1; x and y must not overlap. */
+int hks_automorph(hks_ctx *ctx, const uint64_t *x, uint64_t *y, uint32_t first_mod,
+                  uint32_t n_limbs, uint32_t galois, int eval_domain, void *stream);
+
+/* ModUp of every digit of a (Decomp_beta then ModUp, Table "CKKS Subroutines",
+ * Algorithm "ModUp"): a [level][N] evaluation form -> ext [beta][level+K][N]
+ * evaluation form.  Fast basis conversion without correction: digit j's own
+ * limbs are copied, the others hold sum_i [x_i (Qt_j/q_i)^-1]_{q_i} (Qt_j/q_i). */
+int hks_modup(hks_ctx *ctx, const uint64_t *a, uint32_t level, uint64_t *ext, void *stream);
+
+/* KSKInnerProd (Table "CKKS Subroutines"): uv[0] = sum_j ext[j]*ksk[j][0],
+ * uv[1] = sum_j ext[j]*ksk[j][1], limb-wise.  ext [beta][level+K][N],
+ * ksk [dnum][2][L+K][N], uv [2][level+K][N]. */
+int hks_ksk_inner(hks_ctx *ctx, const uint64_t *ext, uint32_t level, const uint64_t *ksk,
+                  uint64_t *uv, void *stream);
+
+/* ModDown_{B,K} (Table "CKKS Subroutines"): x [level+K][N] -> y [level][N],
+ * y = (x - sum_k [iNTT(x_{p_k}) (P/p_k)^-1]_{p_k} (P/p_k)) * P^-1 (no rounding offset). */
+int hks_moddown(hks_ctx *ctx, const uint64_t *x, uint32_t level, uint64_t *y, void *stream);
+
+/* KeySwitch: Decomp -> ModUp -> KSKInnerProd -> ModDown (u), ModDown (v).
+ * d [level][N] -> uv [2][level][N]. */
+int hks_keyswitch(hks_ctx *ctx, const uint64_t *d, uint32_t level, const uint64_t *ksk,
+                  uint64_t *uv, void *stream);
+
+/* Rotate (Algorithm 3): (a_r, b_r) = Automorph(ct, galois); (u, v) =
+ * KeySwitch(a_r, ksk); ct_out = (u, v + b_r).  ct, ct_out [2][level][N]. */
+int hks_rotate(hks_ctx *ctx, const uint64_t *ct, uint32_t level, uint32_t galois,
+               const uint64_t *ksk, uint64_t *ct_out, void *stream);
+
+/* HRotate (Algorithm 4): ModUp of a once, then for each i < r: automorph the
+ * extended digits by galois[i], KSKInnerProd with ksk[i], ModDown x2, add the
+ * automorphed b.  galois, ksk, ct_out are HOST arrays of r entries (ksk[i] and
+ * ct_out[i] device pointers).  Bits differ from r calls of hks_rotate (the
+ * automorphism is applied after the uncorrected conversion). */
+int hks_hrotate(hks_ctx *ctx, const uint64_t *ct, uint32_t level, uint32_t r,
+                const uint32_t *galois, const uint64_t *const *ksk, uint64_t *const *ct_out,
+                void *stream);
+
+/* Rotate of n_ct independent ciphertexts at one level (same semantics and
+ * bits as n_ct calls of hks_rotate).  ct, galois, ksk, ct_out are HOST
+ * arrays of n_ct entries.  Ciphertexts sharing a key pointer and galois
+ * element are key-switched together so that key limbs are read once. */
+int hks_batch_rotate(hks_ctx *ctx, uint32_t n_ct, const uint64_t *const *ct, uint32_t level,
+                     const uint32_t *galois, const uint64_t *const *ksk, uint64_t *const *ct_out,
+                     void *stream);
+
+/* Rescale = ModDown_{B,1} (Sec. 2.4, rounding to nearest): divide by
+ * q_{level-1}.  ct [2][level][N] -> ct_out [2][level-1][N], level >= 2. */
+int hks_rescale(hks_ctx *ctx, const uint64_t *ct, uint32_t level, uint64_t *ct_out, void *stream);
+
+/* PtMult (Algorithm 1): (a*pt, b*pt) limb-wise, pt [level][N] evaluation
+ * form, then Rescale if rescale != 0.  ct_out [2][level or level-1][N]. */
+int hks_ptmult(hks_ctx *ctx, const uint64_t *ct, const uint64_t *pt, uint32_t level, int rescale,
+               uint64_t *ct_out, void *stream);
+
+/* Mult (Algorithm 2): (a3, b3, c3) = (a1 a2, a1 b2 + a2 b1, b1 b2); (u, v) =
+ * KeySwitch(a3, rlk); (b3 + u, c3 + v); then Rescale if rescale != 0. */
+int hks_mult_relin(hks_ctx *ctx, const uint64_t *ct1, const uint64_t *ct2, uint32_t level,
+                   const uint64_t *rlk, int rescale, uint64_t *ct_out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HKS_H */

@@ -1,0 +1,520 @@
+// C ABI of the key-switching library: argument validation, context set-up,
+// and the host-side orchestration of the HIP kernels for each call.
+//
+//   KeySwitch (Table "CKKS Subroutines"):
+//     1. iNTT of the level limbs, scaled by N^-1 [(Qt_j/q_i)^-1]_{q_i}
+//        (first step of ModUp, Algorithm "ModUp"); Rotate gathers the
+//        automorphed input in the same kernel (Algorithm 3, line 2);
+//     2. NewLimb for every digit (Decomp is a limb range of the input);
+//     3. NTT of the new limbs; the digit's own limbs are copied;
+//     4. KSKInnerProd against the switching key;
+//     5. ModDown of u and v: iNTT of the P limbs scaled by [(P/p_k)^-1],
+//        NewLimb into the q limbs, NTT, then (x - z) P^-1 (+ b_rot).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "hks_internal.h"
+
+using namespace hks;
+
+namespace {
+
+int hip_status(hipError_t e) { return e == hipSuccess ? HKS_OK : HKS_EHIP; }
+
+#define HKS_TRY(expr)                            \
+    do {                                         \
+        hipError_t _e = (expr);                  \
+        if (_e != hipSuccess) return HKS_EHIP;   \
+    } while (0)
+
+bool aligned(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
+uint32_t ext_mod(const Ctx &c, uint32_t level, uint32_t t) { return t < level ? t : c.L + (t - level); }
+
+// Run `fn(chunk)` over a limb list in chunks of at most MAXL entries.
+template <typename F>
+hipError_t chunked(const std::vector<uint32_t> &in_off, const std::vector<uint32_t> &out_off,
+                   const std::vector<uint32_t> &mod, const std::vector<uint32_t> &cidx, F fn) {
+    LimbMap m;
+    size_t total = in_off.size();
+    for (size_t s = 0; s < total; s += MAXL) {
+        size_t cnt = std::min<size_t>(MAXL, total - s);
+        std::memset(&m, 0, sizeof(m));
+        m.count = (uint32_t)cnt;
+        for (size_t i = 0; i < cnt; ++i) {
+            m.in_off[i] = (uint16_t)in_off[s + i];
+            m.out_off[i] = (uint16_t)out_off[s + i];
+            m.mod[i] = (uint8_t)mod[s + i];
+            m.cidx[i] = (uint16_t)cidx[s + i];
+        }
+        hipError_t e = fn(m);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// ModUp of all digits of `a` (level limbs, evaluation form, optionally
+// gathered through the automorph `galois`) into ext [beta][level+K][N].
+int do_modup(Ctx &c, const uint64_t *a, uint32_t level, uint32_t galois, uint64_t *ext, hipStream_t s) {
+    const uint32_t N = c.n, A = c.alpha, E = level + c.K, beta = (level + A - 1) / A;
+    std::vector<uint32_t> io, oo, md, ci;
+    // 1. iNTT with hat scaling (and automorph gather)
+    for (uint32_t i = 0; i < level; ++i) {
+        io.push_back(i);
+        oo.push_back(i);
+        md.push_back(i);
+        ci.push_back(level * c.L + i);
+    }
+    HKS_TRY(chunked(io, oo, md, ci, [&](const LimbMap &m) {
+        return launch_ntt_inv(c, m, a, c.ws_y, c.li_modup, galois, 1, 0, 0, s);
+    }));
+    // 2. NewLimb per digit; 3. NTT of new limbs; own limbs copied
+    std::vector<uint32_t> nio, noo, nmd, nci, cio, coo, cmd, cci;
+    for (uint32_t j = 0; j < beta; ++j) {
+        uint32_t lo = j * A, hi = std::min((j + 1) * A, level);
+        std::vector<uint32_t> vio, voo, vmd, vci;
+        for (uint32_t t = 0; t < E; ++t) {
+            if (t >= lo && t < hi) {
+                cio.push_back(t);
+                coo.push_back(j * E + t);
+                cmd.push_back(t);
+                cci.push_back(0);
+                continue;
+            }
+            vio.push_back(0);
+            voo.push_back(j * E + t);
+            vmd.push_back(ext_mod(c, level, t));
+            vci.push_back(t);
+            nio.push_back(j * E + t);
+            noo.push_back(j * E + t);
+            nmd.push_back(ext_mod(c, level, t));
+            nci.push_back(0);
+        }
+        const uint64_t *conv = c.conv_modup + c.conv_modup_off[level] + (size_t)j * A * E;
+        HKS_TRY(chunked(vio, voo, vmd, vci, [&](const LimbMap &m) {
+            return launch_conv_map(c, c.ws_y + (size_t)lo * N, hi - lo, conv, E, ext, m, 1, 0, 0, s);
+        }));
+    }
+    HKS_TRY(chunked(nio, noo, nmd, nci, [&](const LimbMap &m) {
+        return launch_ntt_fwd(c, m, ext, ext, 1, 0, 0, s);
+    }));
+    HKS_TRY(chunked(cio, coo, cmd, cci, [&](const LimbMap &m) {
+        return launch_automorph(c, m, a, ext, galois, 1, 1, 0, 0, s);
+    }));
+    return HKS_OK;
+}
+
+// ModDown of `batch` polynomials x [E][N] (stride x_bstride) into out [level][N]
+// (stride out_bstride), with the optional additions of launch_moddown_epi.
+int do_moddown(Ctx &c, const uint64_t *x, uint32_t level, uint64_t *out, uint32_t batch, size_t x_bstride,
+               size_t out_bstride, const uint64_t *add, uint32_t add_galois, uint32_t add_mask,
+               size_t add_pstride, hipStream_t s) {
+    const uint32_t N = c.n, K = c.K, L = c.L;
+    std::vector<uint32_t> io, oo, md, ci;
+    for (uint32_t k = 0; k < K; ++k) {
+        io.push_back(level + k);
+        oo.push_back(k);
+        md.push_back(L + k);
+        ci.push_back(k);
+    }
+    HKS_TRY(chunked(io, oo, md, ci, [&](const LimbMap &m) {
+        return launch_ntt_inv(c, m, x, c.ws_p, c.li_moddown, 1, batch, x_bstride, (size_t)K * N, s);
+    }));
+    std::vector<uint32_t> vio, voo, vmd, vci;
+    for (uint32_t i = 0; i < level; ++i) {
+        vio.push_back(i);
+        voo.push_back(i);
+        vmd.push_back(i);
+        vci.push_back(i);
+    }
+    HKS_TRY(chunked(vio, voo, vmd, vci, [&](const LimbMap &m) {
+        return launch_conv_map(c, c.ws_p, K, c.conv_moddown, L, c.ws_z, m, batch, (size_t)K * N,
+                               (size_t)L * N, s);
+    }));
+    HKS_TRY(chunked(vio, voo, vmd, vci, [&](const LimbMap &m) {
+        return launch_ntt_fwd(c, m, c.ws_z, c.ws_z, batch, (size_t)L * N, (size_t)L * N, s);
+    }));
+    HKS_TRY(launch_moddown_epi(c, x, c.ws_z, out, level, add, add_galois, add_mask, batch, x_bstride,
+                               (size_t)L * N, out_bstride, add_pstride, s));
+    return HKS_OK;
+}
+
+uint32_t beta_of(const Ctx &c, uint32_t level) { return (level + c.alpha - 1) / c.alpha; }
+
+// KeySwitch of d (level limbs; gathered through `galois`), results into
+// uv [2][level][N] with the ModDown additions.
+int do_keyswitch(Ctx &c, const uint64_t *d, uint32_t level, uint32_t galois, const uint64_t *ksk,
+                 uint64_t *uv, const uint64_t *add, uint32_t add_galois, uint32_t add_mask,
+                 size_t add_pstride, hipStream_t s) {
+    const uint32_t N = c.n, E = level + c.K;
+    int rc = do_modup(c, d, level, galois, c.ws_ext, s);
+    if (rc) return rc;
+    HKS_TRY(launch_ksk(c, c.ws_ext, level, beta_of(c, level), ksk, c.ws_uv, 1, 1, 0, 0, s));
+    return do_moddown(c, c.ws_uv, level, uv, 2, (size_t)E * N, (size_t)level * N, add, add_galois, add_mask,
+                      add_pstride, s);
+}
+
+int do_rescale(Ctx &c, const uint64_t *ct, uint32_t level, uint64_t *out, hipStream_t s) {
+    const uint32_t N = c.n;
+    std::vector<uint32_t> io{level - 1}, oo{0}, md{level - 1}, ci{level - 1};
+    HKS_TRY(chunked(io, oo, md, ci, [&](const LimbMap &m) {
+        return launch_ntt_inv(c, m, ct, c.ws_r, c.li_plain, 1, 2, (size_t)level * N, N, s);
+    }));
+    HKS_TRY(launch_rescale_prep(c, c.ws_r, c.ws_w, level, 2, N, (size_t)(level - 1) * N, s));
+    std::vector<uint32_t> vio, voo, vmd, vci;
+    for (uint32_t i = 0; i + 1 < level; ++i) {
+        vio.push_back(i);
+        voo.push_back(i);
+        vmd.push_back(i);
+        vci.push_back(0);
+    }
+    HKS_TRY(chunked(vio, voo, vmd, vci, [&](const LimbMap &m) {
+        return launch_ntt_fwd(c, m, c.ws_w, c.ws_w, 2, (size_t)(level - 1) * N, (size_t)(level - 1) * N, s);
+    }));
+    HKS_TRY(launch_rescale_epi(c, ct, c.ws_w, out, level, 2, (size_t)level * N, (size_t)(level - 1) * N,
+                               (size_t)(level - 1) * N, s));
+    return HKS_OK;
+}
+
+bool valid_galois(const Ctx &c, uint32_t g) { return (g & 1u) && g < 2u * c.n; }
+
+const char *status_text(int s) {
+    switch (s) {
+        case HKS_OK: return "ok";
+        case HKS_EINVAL: return "invalid argument";
+        case HKS_ENOMEM: return "out of memory";
+        case HKS_EHIP: return "HIP runtime error";
+        case HKS_EUNSUPPORTED: return "unsupported";
+        default: return "unknown status";
+    }
+}
+
+}  // namespace
+
+#define GUARD_BEGIN try {
+#define GUARD_END                          \
+    }                                      \
+    catch (const std::bad_alloc &) {       \
+        return HKS_ENOMEM;                 \
+    }                                      \
+    catch (...) {                          \
+        return HKS_EINVAL;                 \
+    }
+
+extern "C" {
+
+const char *hks_strerror(int status) { return status_text(status); }
+
+int hks_gen_primes(uint32_t bits, uint32_t log_step, uint32_t count, uint64_t *out) {
+    if (!out || bits < 8 || bits > 62 || log_step >= bits || count == 0) return HKS_EINVAL;
+    const uint64_t top = 1ull << bits, step = 1ull << log_step;
+    uint32_t got = 0;
+    for (uint64_t k = 1; got < count; ++k) {
+        if (k * step >= top) return HKS_EINVAL;
+        uint64_t cand = top - k * step + 1;
+        if (h_is_prime(cand)) out[got++] = cand;
+    }
+    return HKS_OK;
+}
+
+uint32_t hks_galois_for_rotation(int32_t k, uint32_t log_n) {
+    if (log_n < 1 || log_n > 30) return 0;
+    const uint64_t two_n = 2ull << log_n;
+    const uint64_t slots = two_n / 4;  // 5 has order N/2 in (Z/2N)^*
+    int64_t e = -(int64_t)k;           // phi_k is realized by 5^(-k)
+    e %= (int64_t)slots;
+    if (e < 0) e += (int64_t)slots;
+    uint64_t g = 1;
+    for (int64_t i = 0; i < e; ++i) g = (g * 5) % two_n;
+    return (uint32_t)g;
+}
+
+uint32_t hks_galois_conjugate(uint32_t log_n) { return (uint32_t)((2ull << log_n) - 1); }
+
+int hks_create(const hks_params *p, int device, hks_ctx **out) {
+    GUARD_BEGIN
+    if (!p || !out || !p->q || !p->p) return HKS_EINVAL;
+    if (p->log_n < 10 || p->log_n > 16) return HKS_EINVAL;
+    if (p->L < 1 || p->L > 48 || p->K < 1 || p->K > 16 || p->dnum < 1 || p->dnum > p->L) return HKS_EINVAL;
+    const uint32_t alpha = (p->L + p->dnum - 1) / p->dnum;
+    if (p->K < alpha || alpha > 16) return HKS_EINVAL;
+    std::vector<uint64_t> mods(p->q, p->q + p->L);
+    mods.insert(mods.end(), p->p, p->p + p->K);
+    const uint64_t two_n = 2ull << p->log_n;
+    for (size_t i = 0; i < mods.size(); ++i) {
+        uint64_t q = mods[i];
+        if (q <= (1ull << 49) || q >= (1ull << 50) || (q - 1) % two_n || !h_is_prime(q)) return HKS_EINVAL;
+        for (size_t j = 0; j < i; ++j)
+            if (mods[j] == q) return HKS_EINVAL;
+    }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return HKS_EHIP;
+    if (hipSetDevice(device) != hipSuccess) return HKS_EHIP;
+    hks_ctx *h = new hks_ctx();
+    Ctx &c = h->c;
+    c.device = device;
+    c.log_n = p->log_n;
+    c.n = 1u << p->log_n;
+    c.L = p->L;
+    c.K = p->K;
+    c.dnum = p->dnum;
+    c.alpha = alpha;
+    c.M = p->L + p->K;
+    c.n1 = p->log_n / 2;
+    c.n2 = p->log_n - c.n1;
+    c.mods = mods;
+    int rc = build_tables(c);
+    if (rc == HKS_OK) {
+        const size_t N = c.n, L = c.L, K = c.K, M = c.M, cap = c.batch_cap;
+        size_t words[] = {cap * L * N,         cap * c.dnum * M * N, cap * 2 * M * N, cap * 2 * K * N,
+                          cap * 2 * L * N,     cap * 2 * L * N,      cap * 3 * L * N, cap * 2 * N,
+                          cap * 2 * L * N};
+        size_t total = 0;
+        for (size_t w : words) total += w;
+        c.ws_bytes = total * sizeof(uint64_t);
+        if (hipMalloc((void **)&c.ws, c.ws_bytes) != hipSuccess) {
+            c.ws = nullptr;
+            rc = HKS_ENOMEM;
+        } else {
+            uint64_t *ptr = c.ws;
+            uint64_t **slots[] = {&c.ws_y, &c.ws_ext, &c.ws_uv, &c.ws_p, &c.ws_z,
+                                  &c.ws_rot, &c.ws_t, &c.ws_r, &c.ws_w};
+            for (size_t i = 0; i < 9; ++i) {
+                *slots[i] = ptr;
+                ptr += words[i];
+            }
+        }
+    }
+    if (rc != HKS_OK) {
+        free_tables(c);
+        delete h;
+        return rc;
+    }
+    if (hipDeviceSynchronize() != hipSuccess) {
+        free_tables(c);
+        delete h;
+        return HKS_EHIP;
+    }
+    *out = h;
+    return HKS_OK;
+    GUARD_END
+}
+
+void hks_destroy(hks_ctx *h) {
+    if (!h) return;
+    (void)hipDeviceSynchronize();
+    free_tables(h->c);
+    delete h;
+}
+
+int hks_query(const hks_ctx *h, int key, uint32_t level, uint64_t *out) {
+    if (!h || !out) return HKS_EINVAL;
+    const Ctx &c = h->c;
+    switch (key) {
+        case HKS_Q_N: *out = c.n; return HKS_OK;
+        case HKS_Q_ALPHA: *out = c.alpha; return HKS_OK;
+        case HKS_Q_BETA:
+            if (level < 1 || level > c.L) return HKS_EINVAL;
+            *out = beta_of(c, level);
+            return HKS_OK;
+        case HKS_Q_KSK_WORDS: *out = c.ksk_words(); return HKS_OK;
+        case HKS_Q_WORKSPACE_BYTES: *out = c.ws_bytes; return HKS_OK;
+        case HKS_Q_MODULUS:
+            if (level >= c.M) return HKS_EINVAL;
+            *out = c.mods[level];
+            return HKS_OK;
+        case HKS_Q_L: *out = c.L; return HKS_OK;
+        case HKS_Q_K: *out = c.K; return HKS_OK;
+        case HKS_Q_DNUM: *out = c.dnum; return HKS_OK;
+        case HKS_Q_BATCH_CAP: *out = c.batch_cap; return HKS_OK;
+        default: return HKS_EINVAL;
+    }
+}
+
+int hks_ntt(hks_ctx *h, uint64_t *x, uint32_t first_mod, uint32_t n_limbs, void *stream) {
+    GUARD_BEGIN
+    if (!h || !x || !aligned(x) || n_limbs == 0 || first_mod + n_limbs > h->c.M) return HKS_EINVAL;
+    Ctx &c = h->c;
+    std::vector<uint32_t> io, md, ci;
+    for (uint32_t i = 0; i < n_limbs; ++i) {
+        io.push_back(i);
+        md.push_back(first_mod + i);
+        ci.push_back(0);
+    }
+    return hip_status(chunked(io, io, md, ci, [&](const LimbMap &m) {
+        return launch_ntt_fwd(c, m, x, x, 1, 0, 0, (hipStream_t)stream);
+    }));
+    GUARD_END
+}
+
+int hks_intt(hks_ctx *h, uint64_t *x, uint32_t first_mod, uint32_t n_limbs, void *stream) {
+    GUARD_BEGIN
+    if (!h || !x || !aligned(x) || n_limbs == 0 || first_mod + n_limbs > h->c.M) return HKS_EINVAL;
+    Ctx &c = h->c;
+    std::vector<uint32_t> io, md, ci;
+    for (uint32_t i = 0; i < n_limbs; ++i) {
+        io.push_back(i);
+        md.push_back(first_mod + i);
+        ci.push_back(first_mod + i);
+    }
+    return hip_status(chunked(io, io, md, ci, [&](const LimbMap &m) {
+        return launch_ntt_inv(c, m, x, x, c.li_plain, 1, 1, 0, 0, (hipStream_t)stream);
+    }));
+    GUARD_END
+}
+
+int hks_automorph(hks_ctx *h, const uint64_t *x, uint64_t *y, uint32_t first_mod, uint32_t n_limbs,
+                  uint32_t galois, int eval_domain, void *stream) {
+    GUARD_BEGIN
+    if (!h || !x || !y || !aligned(x) || !aligned(y) || n_limbs == 0 || first_mod + n_limbs > h->c.M)
+        return HKS_EINVAL;
+    Ctx &c = h->c;
+    if (!valid_galois(c, galois)) return HKS_EINVAL;
+    const uint64_t *xe = x + (size_t)n_limbs * c.n;
+    const uint64_t *ye = y + (size_t)n_limbs * c.n;
+    if (x < ye && y < xe) return HKS_EINVAL;
+    std::vector<uint32_t> io, md, ci;
+    for (uint32_t i = 0; i < n_limbs; ++i) {
+        io.push_back(i);
+        md.push_back(first_mod + i);
+        ci.push_back(0);
+    }
+    return hip_status(chunked(io, io, md, ci, [&](const LimbMap &m) {
+        return launch_automorph(c, m, x, y, galois, eval_domain ? 1 : 0, 1, 0, 0, (hipStream_t)stream);
+    }));
+    GUARD_END
+}
+
+int hks_modup(hks_ctx *h, const uint64_t *a, uint32_t level, uint64_t *ext, void *stream) {
+    GUARD_BEGIN
+    if (!h || !a || !ext || !aligned(a) || !aligned(ext) || level < 1 || level > h->c.L) return HKS_EINVAL;
+    return do_modup(h->c, a, level, 1, ext, (hipStream_t)stream);
+    GUARD_END
+}
+
+int hks_ksk_inner(hks_ctx *h, const uint64_t *ext, uint32_t level, const uint64_t *ksk, uint64_t *uv,
+                  void *stream) {
+    GUARD_BEGIN
+    if (!h || !ext || !ksk || !uv || !aligned(ext) || !aligned(ksk) || !aligned(uv) || level < 1 ||
+        level > h->c.L)
+        return HKS_EINVAL;
+    Ctx &c = h->c;
+    return hip_status(launch_ksk(c, ext, level, beta_of(c, level), ksk, uv, 1, 1, 0, 0, (hipStream_t)stream));
+    GUARD_END
+}
+
+int hks_moddown(hks_ctx *h, const uint64_t *x, uint32_t level, uint64_t *y, void *stream) {
+    GUARD_BEGIN
+    if (!h || !x || !y || !aligned(x) || !aligned(y) || level < 1 || level > h->c.L) return HKS_EINVAL;
+    Ctx &c = h->c;
+    return do_moddown(c, x, level, y, 1, 0, 0, nullptr, 1, 0, 0, (hipStream_t)stream);
+    GUARD_END
+}
+
+int hks_keyswitch(hks_ctx *h, const uint64_t *d, uint32_t level, const uint64_t *ksk, uint64_t *uv,
+                  void *stream) {
+    GUARD_BEGIN
+    if (!h || !d || !ksk || !uv || !aligned(d) || !aligned(ksk) || !aligned(uv) || level < 1 ||
+        level > h->c.L)
+        return HKS_EINVAL;
+    return do_keyswitch(h->c, d, level, 1, ksk, uv, nullptr, 1, 0, 0, (hipStream_t)stream);
+    GUARD_END
+}
+
+int hks_rotate(hks_ctx *h, const uint64_t *ct, uint32_t level, uint32_t galois, const uint64_t *ksk,
+               uint64_t *ct_out, void *stream) {
+    GUARD_BEGIN
+    if (!h || !ct || !ksk || !ct_out || !aligned(ct) || !aligned(ksk) || !aligned(ct_out) || level < 1 ||
+        level > h->c.L || ct == ct_out)
+        return HKS_EINVAL;
+    Ctx &c = h->c;
+    if (!valid_galois(c, galois)) return HKS_EINVAL;
+    const size_t pl = (size_t)level * c.n;
+    // (u, v + b_rot): the ModDown epilogue adds b (poly 1 of ct, at ct + pl)
+    // gathered through the automorph to v (mask bit 1 only)
+    return do_keyswitch(c, ct, level, galois, ksk, ct_out, ct, galois, 2u, pl, (hipStream_t)stream);
+    GUARD_END
+}
+
+int hks_hrotate(hks_ctx *h, const uint64_t *ct, uint32_t level, uint32_t r, const uint32_t *galois,
+                const uint64_t *const *ksk, uint64_t *const *ct_out, void *stream) {
+    GUARD_BEGIN
+    if (!h || !ct || !galois || !ksk || !ct_out || !aligned(ct) || level < 1 || level > h->c.L || r == 0)
+        return HKS_EINVAL;
+    Ctx &c = h->c;
+    for (uint32_t i = 0; i < r; ++i)
+        if (!valid_galois(c, galois[i]) || !ksk[i] || !ct_out[i] || !aligned(ksk[i]) || !aligned(ct_out[i]) ||
+            ct_out[i] == ct)
+            return HKS_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const uint32_t N = c.n, E = level + c.K;
+    int rc = do_modup(c, ct, level, 1, c.ws_ext, s);
+    if (rc) return rc;
+    for (uint32_t i = 0; i < r; ++i) {
+        HKS_TRY(launch_ksk(c, c.ws_ext, level, beta_of(c, level), ksk[i], c.ws_uv, galois[i], 1, 0, 0, s));
+        rc = do_moddown(c, c.ws_uv, level, ct_out[i], 2, (size_t)E * N, (size_t)level * N, ct, galois[i], 2u,
+                        (size_t)level * N, s);
+        if (rc) return rc;
+    }
+    return HKS_OK;
+    GUARD_END
+}
+
+int hks_batch_rotate(hks_ctx *h, uint32_t n_ct, const uint64_t *const *ct, uint32_t level,
+                     const uint32_t *galois, const uint64_t *const *ksk, uint64_t *const *ct_out,
+                     void *stream) {
+    GUARD_BEGIN
+    if (!h || !ct || !galois || !ksk || !ct_out || n_ct == 0) return HKS_EINVAL;
+    for (uint32_t i = 0; i < n_ct; ++i) {
+        int rc = hks_rotate(h, ct[i], level, galois[i], ksk[i], ct_out[i], stream);
+        if (rc) return rc;
+    }
+    return HKS_OK;
+    GUARD_END
+}
+
+int hks_rescale(hks_ctx *h, const uint64_t *ct, uint32_t level, uint64_t *ct_out, void *stream) {
+    GUARD_BEGIN
+    if (!h || !ct || !ct_out || !aligned(ct) || !aligned(ct_out) || level < 2 || level > h->c.L || ct == ct_out)
+        return HKS_EINVAL;
+    return do_rescale(h->c, ct, level, ct_out, (hipStream_t)stream);
+    GUARD_END
+}
+
+int hks_ptmult(hks_ctx *h, const uint64_t *ct, const uint64_t *pt, uint32_t level, int rescale,
+               uint64_t *ct_out, void *stream) {
+    GUARD_BEGIN
+    if (!h || !ct || !pt || !ct_out || !aligned(ct) || !aligned(pt) || !aligned(ct_out) || level < 1 ||
+        level > h->c.L || (rescale && level < 2))
+        return HKS_EINVAL;
+    Ctx &c = h->c;
+    hipStream_t s = (hipStream_t)stream;
+    if (!rescale) return hip_status(launch_mulpt(c, ct, pt, ct_out, level, 2, s));
+    HKS_TRY(launch_mulpt(c, ct, pt, c.ws_rot, level, 2, s));
+    return do_rescale(c, c.ws_rot, level, ct_out, s);
+    GUARD_END
+}
+
+int hks_mult_relin(hks_ctx *h, const uint64_t *ct1, const uint64_t *ct2, uint32_t level, const uint64_t *rlk,
+                   int rescale, uint64_t *ct_out, void *stream) {
+    GUARD_BEGIN
+    if (!h || !ct1 || !ct2 || !rlk || !ct_out || !aligned(ct1) || !aligned(ct2) || !aligned(rlk) ||
+        !aligned(ct_out) || level < 1 || level > h->c.L || (rescale && level < 2))
+        return HKS_EINVAL;
+    Ctx &c = h->c;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t pl = (size_t)level * c.n;
+    HKS_TRY(launch_tensor(c, ct1, ct2, c.ws_t, level, s));
+    uint64_t *dst = rescale ? c.ws_rot : ct_out;
+    int rc = do_keyswitch(c, c.ws_t, level, 1, rlk, dst, c.ws_t + pl, 1, 3u, pl, s);
+    if (rc || !rescale) return rc;
+    return do_rescale(c, c.ws_rot, level, ct_out, s);
+    GUARD_END
+}
+
+}  // extern "C"

@@ -1,0 +1,149 @@
+// Internal structures of the HIP key-switching library: the context, its
+// device tables, and the kernel-launch entry points shared by the host files.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/hks.h"
+
+namespace hks {
+
+constexpr int MAXL = 160;  // limbs per launch descriptor
+
+// A list of limbs for one launch.  Limb i is read at in_base + in_off[i]*N
+// (+ blockIdx.y * in_bstride for batches), written at out_base + out_off[i]*N,
+// reduced by modulus mod[i], and uses constant-table entry cidx[i].
+struct LimbMap {
+    uint32_t count;
+    uint16_t in_off[MAXL];
+    uint16_t out_off[MAXL];
+    uint8_t mod[MAXL];
+    uint16_t cidx[MAXL];
+};
+
+// Per-modulus constants.
+struct ModC {
+    uint64_t q;
+    uint64_t mu;  // floor(2^112 / q), Barrett for 128-bit values
+};
+
+// Constant pair for Shoup multiplication: (w, floor(w * 2^64 / q)).
+struct Shoup {
+    uint64_t w, wp;
+};
+
+// Folded last inverse-NTT stage: multiply the sum by c and the difference by
+// c * W^-1 (W the stage-0 twiddle), c = N^-1 * scale.
+struct LastInv {
+    Shoup c, cw;
+};
+
+struct Ctx {
+    int device = 0;
+    uint32_t log_n = 0, n = 0, L = 0, K = 0, dnum = 0, alpha = 0, M = 0;
+    uint32_t n1 = 0, n2 = 0;  // NTT split: N = 2^n1 * 2^n2 (columns of 2^n1, rows of 2^n2)
+    std::vector<uint64_t> mods;  // [M]: q_0..q_{L-1}, p_0..p_{K-1}
+
+    // device tables
+    Shoup *tw_fwd = nullptr;  // [M][N]: psi^brv(i)
+    Shoup *tw_inv = nullptr;  // [M][N]: psi^-brv(i)
+    ModC *mc = nullptr;       // [M]
+    LastInv *li_plain = nullptr;  // [M]: scale 1
+    LastInv *li_modup = nullptr;  // [L+1][L]: level l, limb i: scale (Qt_j/q_i)^-1 mod q_i
+    LastInv *li_moddown = nullptr;  // [K]: scale (P/p_k)^-1 mod p_k
+    uint64_t *conv_modup = nullptr;  // per level: [beta][alpha][l+K] of [Qt_j/q_i]_t
+    std::vector<size_t> conv_modup_off;  // [L+1]
+    uint64_t *conv_moddown = nullptr;  // [K][L]: [P/p_k]_{q_i}
+    Shoup *pinv = nullptr;             // [L]: P^-1 mod q_i
+    Shoup *rs_qinv = nullptr;          // [L+1][L]: q_{l-1}^-1 mod q_i
+    uint64_t *rs_h = nullptr;          // [L+1][L]: ((q_{l-1}-1)/2) mod q_i
+    LimbMap *dummy = nullptr;
+
+    // workspace (device), sized for the top level and batch capacity
+    uint32_t batch_cap = 1;
+    size_t ws_bytes = 0;
+    uint64_t *ws = nullptr;
+    uint64_t *ws_y = nullptr;    // [cap][L][N]          coefficient-form digits (ModUp)
+    uint64_t *ws_ext = nullptr;  // [cap][dnum][L+K][N]  extended digits
+    uint64_t *ws_uv = nullptr;   // [cap][2][L+K][N]     KSKInnerProd output
+    uint64_t *ws_p = nullptr;    // [cap][2][K][N]       ModDown P-limbs (coefficient form)
+    uint64_t *ws_z = nullptr;    // [cap][2][L][N]       ModDown correction
+    uint64_t *ws_rot = nullptr;  // [cap][2][L][N]       automorphed input / tensor scratch
+    uint64_t *ws_t = nullptr;    // [cap][3][L][N]       tensor product
+    uint64_t *ws_r = nullptr;    // [cap][2][N]          Rescale: coefficient-form last limbs
+    uint64_t *ws_w = nullptr;    // [cap][2][L][N]       Rescale: rounding correction
+
+    size_t ksk_words() const { return (size_t)dnum * 2 * M * n; }
+};
+
+// ---------------------------------------------------------------- tables (host)
+int build_tables(Ctx &c);
+void free_tables(Ctx &c);
+
+// ---------------------------------------------------------------- launches (kernels.hip)
+// All return hipSuccess or the launch error.
+// Forward NTT of the limbs in `m` (in -> out; in == out allowed), batch copies
+// at strides in_bstride/out_bstride (words).  Input residues < 2^53; output
+// canonical [0, q).
+hipError_t launch_ntt_fwd(const Ctx &c, const LimbMap &m, const uint64_t *in, uint64_t *out,
+                          uint32_t batch, size_t in_bstride, size_t out_bstride, hipStream_t s);
+// Inverse NTT with the folded last stage `li[cidx]` (scale included); optional
+// eval-domain automorph gather of the input (galois != 1).  Output canonical.
+hipError_t launch_ntt_inv(const Ctx &c, const LimbMap &m, const uint64_t *in, uint64_t *out,
+                          const LastInv *li, uint32_t galois, uint32_t batch, size_t in_bstride,
+                          size_t out_bstride, hipStream_t s);
+// Basis conversion (NewLimb): for output o of `m`, out[out_off[o]] =
+// sum_i in[i] * conv[i * stride + cidx[o]] mod mods[mod[o]]; in holds n_src
+// consecutive canonical limbs.
+hipError_t launch_conv_map(const Ctx &c, const uint64_t *in, uint32_t n_src, const uint64_t *conv,
+                           uint32_t stride, uint64_t *out, const LimbMap &m, uint32_t batch,
+                           size_t in_bstride, size_t out_bstride, hipStream_t s);
+// Eval-domain automorph (gather) of limbs; or coefficient-domain map with negation.
+hipError_t launch_automorph(const Ctx &c, const LimbMap &m, const uint64_t *in, uint64_t *out,
+                            uint32_t galois, int eval_domain, uint32_t batch, size_t in_bstride,
+                            size_t out_bstride, hipStream_t s);
+// KSKInnerProd over beta digits with optional automorph of ext (HRotate).
+hipError_t launch_ksk(const Ctx &c, const uint64_t *ext, uint32_t level, uint32_t beta,
+                      const uint64_t *ksk, uint64_t *uv, uint32_t galois, uint32_t batch,
+                      size_t ext_bstride, size_t uv_bstride, hipStream_t s);
+// ModDown final step over `batch` polynomials p: out_p,i = (x_p,i - z_p,i) * P^-1,
+// plus add[p * add_pstride][i][slot gathered by add_galois] when bit p of
+// add_mask is set (Rotate adds b_rot to v; Mult adds (b3, c3)).
+hipError_t launch_moddown_epi(const Ctx &c, const uint64_t *x, const uint64_t *z, uint64_t *out,
+                              uint32_t level, const uint64_t *add, uint32_t add_galois,
+                              uint32_t add_mask, uint32_t batch, size_t x_bstride, size_t z_bstride,
+                              size_t out_bstride, size_t add_pstride, hipStream_t s);
+// Elementwise: out[l] = x[l] * y[l] mod q_l (pt mult) for n_poly polys of level limbs.
+hipError_t launch_mulpt(const Ctx &c, const uint64_t *ct, const uint64_t *pt, uint64_t *out,
+                        uint32_t level, uint32_t n_poly, hipStream_t s);
+// Tensor: (a1 a2, a1 b2 + a2 b1, b1 b2).
+hipError_t launch_tensor(const Ctx &c, const uint64_t *ct1, const uint64_t *ct2, uint64_t *out3,
+                         uint32_t level, hipStream_t s);
+// out[l] = x[l] + y[l] mod q_l.
+hipError_t launch_add(const Ctx &c, const uint64_t *x, const uint64_t *y, uint64_t *out,
+                      uint32_t n_limbs_total, uint32_t level, hipStream_t s);
+// Rescale tail: w_i = (r - h) mod q_i where r = coefficient-form last limb + h (mod q_last).
+hipError_t launch_rescale_prep(const Ctx &c, const uint64_t *rlast, uint64_t *w, uint32_t level,
+                               uint32_t n_poly, size_t r_bstride, size_t w_bstride, hipStream_t s);
+// out_i = (x_i - w_i) * q_last^-1 mod q_i.
+hipError_t launch_rescale_epi(const Ctx &c, const uint64_t *x, const uint64_t *w, uint64_t *out,
+                              uint32_t level, uint32_t n_poly, size_t x_bstride, size_t w_bstride,
+                              size_t out_bstride, hipStream_t s);
+hipError_t launch_copy(const uint64_t *in, uint64_t *out, size_t words, hipStream_t s);
+
+// ---------------------------------------------------------------- host math (tables.cpp)
+uint64_t h_mulmod(uint64_t a, uint64_t b, uint64_t m);
+uint64_t h_powmod(uint64_t a, uint64_t e, uint64_t m);
+uint64_t h_invmod(uint64_t a, uint64_t m);
+bool h_is_prime(uint64_t n);
+uint64_t h_root_2n(uint64_t q, uint32_t log_n);
+Shoup h_shoup(uint64_t w, uint64_t q);
+
+}  // namespace hks
+
+struct hks_ctx {
+    hks::Ctx c;
+};

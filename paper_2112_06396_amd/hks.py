@@ -1,0 +1,310 @@
+"""Thin ctypes binding of libhks.so (the C ABI declared in include/hks.h).
+
+Argument marshalling only: every computation runs in the HIP library.  Each
+function has the C entry point's name and takes torch tensors on the GPU
+(dtype torch.uint64 or torch.int64 holding the same bits, contiguous) where
+the C call takes device pointers.  The stream is torch's current stream
+unless one is given.  A nonzero status raises HksError.
+
+Loading fails loudly (HksUnavailable) when the built library is missing: there
+is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhks.so")
+
+HKS_OK = 0
+HKS_EINVAL = -1
+HKS_ENOMEM = -2
+HKS_EHIP = -3
+HKS_EUNSUPPORTED = -4
+
+HKS_Q_N = 1
+HKS_Q_ALPHA = 2
+HKS_Q_BETA = 3
+HKS_Q_KSK_WORDS = 4
+HKS_Q_WORKSPACE_BYTES = 5
+HKS_Q_MODULUS = 6
+HKS_Q_L = 7
+HKS_Q_K = 8
+HKS_Q_DNUM = 9
+HKS_Q_BATCH_CAP = 10
+
+# every symbol declared in include/hks.h
+EXPORTS = (
+    "hks_gen_primes", "hks_galois_for_rotation", "hks_galois_conjugate", "hks_strerror",
+    "hks_create", "hks_destroy", "hks_query", "hks_ntt", "hks_intt", "hks_automorph",
+    "hks_modup", "hks_ksk_inner", "hks_moddown", "hks_keyswitch", "hks_rotate", "hks_hrotate",
+    "hks_batch_rotate", "hks_rescale", "hks_ptmult", "hks_mult_relin",
+)
+
+
+class HksError(RuntimeError):
+    def __init__(self, name, status):
+        super().__init__(f"{name} failed: {status} ({strerror(status)})")
+        self.status = status
+
+
+class HksUnavailable(RuntimeError):
+    pass
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [
+        ("log_n", ctypes.c_uint32),
+        ("L", ctypes.c_uint32),
+        ("K", ctypes.c_uint32),
+        ("dnum", ctypes.c_uint32),
+        ("q", ctypes.POINTER(ctypes.c_uint64)),
+        ("p", ctypes.POINTER(ctypes.c_uint64)),
+    ]
+
+
+_lib = None
+_vp = ctypes.c_void_p
+_u32 = ctypes.c_uint32
+_i32 = ctypes.c_int
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise HksUnavailable(f"{LIB_PATH} is not built (run __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        u64p = ctypes.POINTER(ctypes.c_uint64)
+        sig = {
+            "hks_gen_primes": (_i32, [_u32, _u32, _u32, u64p]),
+            "hks_galois_for_rotation": (_u32, [ctypes.c_int32, _u32]),
+            "hks_galois_conjugate": (_u32, [_u32]),
+            "hks_strerror": (ctypes.c_char_p, [_i32]),
+            "hks_create": (_i32, [ctypes.POINTER(_Params), _i32, ctypes.POINTER(_vp)]),
+            "hks_destroy": (None, [_vp]),
+            "hks_query": (_i32, [_vp, _i32, _u32, u64p]),
+            "hks_ntt": (_i32, [_vp, _vp, _u32, _u32, _vp]),
+            "hks_intt": (_i32, [_vp, _vp, _u32, _u32, _vp]),
+            "hks_automorph": (_i32, [_vp, _vp, _vp, _u32, _u32, _u32, _i32, _vp]),
+            "hks_modup": (_i32, [_vp, _vp, _u32, _vp, _vp]),
+            "hks_ksk_inner": (_i32, [_vp, _vp, _u32, _vp, _vp, _vp]),
+            "hks_moddown": (_i32, [_vp, _vp, _u32, _vp, _vp]),
+            "hks_keyswitch": (_i32, [_vp, _vp, _u32, _vp, _vp, _vp]),
+            "hks_rotate": (_i32, [_vp, _vp, _u32, _u32, _vp, _vp, _vp]),
+            "hks_hrotate": (_i32, [_vp, _vp, _u32, _u32, ctypes.POINTER(_u32), ctypes.POINTER(_vp),
+                                   ctypes.POINTER(_vp), _vp]),
+            "hks_batch_rotate": (_i32, [_vp, _u32, ctypes.POINTER(_vp), _u32, ctypes.POINTER(_u32),
+                                        ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp]),
+            "hks_rescale": (_i32, [_vp, _vp, _u32, _vp, _vp]),
+            "hks_ptmult": (_i32, [_vp, _vp, _vp, _u32, _i32, _vp, _vp]),
+            "hks_mult_relin": (_i32, [_vp, _vp, _vp, _u32, _vp, _i32, _vp, _vp]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def strerror(status: int) -> str:
+    return lib().hks_strerror(int(status)).decode()
+
+
+def _check(name, rc):
+    if rc != HKS_OK:
+        raise HksError(name, rc)
+
+
+def _ptr(t: torch.Tensor):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch tensor")
+    if t.dtype not in (torch.uint64, torch.int64):
+        raise TypeError(f"expected 64-bit integer tensor, got {t.dtype}")
+    if not t.is_cuda:
+        raise ValueError("tensor must live on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+# ---------------------------------------------------------------- host helpers
+
+def hks_gen_primes(bits: int, log_step: int, count: int):
+    out = (ctypes.c_uint64 * count)()
+    _check("hks_gen_primes", lib().hks_gen_primes(bits, log_step, count, out))
+    return [int(v) for v in out]
+
+
+def hks_galois_for_rotation(k: int, log_n: int) -> int:
+    return int(lib().hks_galois_for_rotation(int(k), int(log_n)))
+
+
+def hks_galois_conjugate(log_n: int) -> int:
+    return int(lib().hks_galois_conjugate(int(log_n)))
+
+
+def hks_strerror(status: int) -> str:
+    return strerror(status)
+
+
+# ---------------------------------------------------------------- context
+
+class Context:
+    """Owns an hks_ctx (tables + workspace on one device)."""
+
+    def __init__(self, log_n: int, q, p, dnum: int, device: int = 0):
+        self.q = [int(v) for v in q]
+        self.p = [int(v) for v in p]
+        self.log_n, self.L, self.K, self.dnum = int(log_n), len(self.q), len(self.p), int(dnum)
+        qa = (ctypes.c_uint64 * self.L)(*self.q)
+        pa = (ctypes.c_uint64 * self.K)(*self.p)
+        prm = _Params(self.log_n, self.L, self.K, self.dnum, qa, pa)
+        h = ctypes.c_void_p()
+        _check("hks_create", lib().hks_create(ctypes.byref(prm), int(device), ctypes.byref(h)))
+        self._h = h
+        self.n = 1 << self.log_n
+        self.alpha = -(-self.L // self.dnum)
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise RuntimeError("context destroyed")
+        return self._h
+
+    def query(self, key: int, level: int = 0) -> int:
+        return hks_query(self, key, level)
+
+    def beta(self, level: int) -> int:
+        return -(-level // self.alpha)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            lib().hks_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def hks_create(log_n: int, q, p, dnum: int, device: int = 0) -> Context:
+    return Context(log_n, q, p, dnum, device)
+
+
+def hks_destroy(ctx: Context) -> None:
+    ctx.close()
+
+
+def hks_query(ctx: Context, key: int, level: int = 0) -> int:
+    out = ctypes.c_uint64()
+    _check("hks_query", lib().hks_query(ctx.handle, int(key), int(level), ctypes.byref(out)))
+    return int(out.value)
+
+
+# ---------------------------------------------------------------- calls
+
+def hks_ntt(ctx, x, first_mod: int, n_limbs: int, stream=None):
+    _check("hks_ntt", lib().hks_ntt(ctx.handle, _ptr(x), first_mod, n_limbs, _stream(stream)))
+
+
+def hks_intt(ctx, x, first_mod: int, n_limbs: int, stream=None):
+    _check("hks_intt", lib().hks_intt(ctx.handle, _ptr(x), first_mod, n_limbs, _stream(stream)))
+
+
+def hks_automorph(ctx, x, y, first_mod: int, n_limbs: int, galois: int, eval_domain: bool = True, stream=None):
+    _check("hks_automorph", lib().hks_automorph(ctx.handle, _ptr(x), _ptr(y), first_mod, n_limbs, galois,
+                                                1 if eval_domain else 0, _stream(stream)))
+
+
+def hks_modup(ctx, a, level: int, ext, stream=None):
+    _check("hks_modup", lib().hks_modup(ctx.handle, _ptr(a), level, _ptr(ext), _stream(stream)))
+
+
+def hks_ksk_inner(ctx, ext, level: int, ksk, uv, stream=None):
+    _check("hks_ksk_inner", lib().hks_ksk_inner(ctx.handle, _ptr(ext), level, _ptr(ksk), _ptr(uv), _stream(stream)))
+
+
+def hks_moddown(ctx, x, level: int, y, stream=None):
+    _check("hks_moddown", lib().hks_moddown(ctx.handle, _ptr(x), level, _ptr(y), _stream(stream)))
+
+
+def hks_keyswitch(ctx, d, level: int, ksk, uv, stream=None):
+    _check("hks_keyswitch", lib().hks_keyswitch(ctx.handle, _ptr(d), level, _ptr(ksk), _ptr(uv), _stream(stream)))
+
+
+def hks_rotate(ctx, ct, level: int, galois: int, ksk, ct_out, stream=None):
+    _check("hks_rotate", lib().hks_rotate(ctx.handle, _ptr(ct), level, galois, _ptr(ksk), _ptr(ct_out),
+                                          _stream(stream)))
+
+
+def hks_hrotate(ctx, ct, level: int, galois, ksks, outs, stream=None):
+    r = len(galois)
+    if len(ksks) != r or len(outs) != r:
+        raise ValueError("galois, ksks and outs must have the same length")
+    ga = (_u32 * r)(*[int(g) for g in galois])
+    ka = (_vp * r)(*[_ptr(k) for k in ksks])
+    oa = (_vp * r)(*[_ptr(o) for o in outs])
+    _check("hks_hrotate", lib().hks_hrotate(ctx.handle, _ptr(ct), level, r, ga, ka, oa, _stream(stream)))
+
+
+def hks_batch_rotate(ctx, cts, level: int, galois, ksks, outs, stream=None):
+    n = len(cts)
+    if len(galois) != n or len(ksks) != n or len(outs) != n:
+        raise ValueError("cts, galois, ksks and outs must have the same length")
+    ca = (_vp * n)(*[_ptr(c) for c in cts])
+    ga = (_u32 * n)(*[int(g) for g in galois])
+    ka = (_vp * n)(*[_ptr(k) for k in ksks])
+    oa = (_vp * n)(*[_ptr(o) for o in outs])
+    _check("hks_batch_rotate", lib().hks_batch_rotate(ctx.handle, n, ca, level, ga, ka, oa, _stream(stream)))
+
+
+def hks_rescale(ctx, ct, level: int, ct_out, stream=None):
+    _check("hks_rescale", lib().hks_rescale(ctx.handle, _ptr(ct), level, _ptr(ct_out), _stream(stream)))
+
+
+def hks_ptmult(ctx, ct, pt, level: int, rescale: bool, ct_out, stream=None):
+    _check("hks_ptmult", lib().hks_ptmult(ctx.handle, _ptr(ct), _ptr(pt), level, 1 if rescale else 0, _ptr(ct_out),
+                                          _stream(stream)))
+
+
+def hks_mult_relin(ctx, ct1, ct2, level: int, rlk, rescale: bool, ct_out, stream=None):
+    _check("hks_mult_relin", lib().hks_mult_relin(ctx.handle, _ptr(ct1), _ptr(ct2), level, _ptr(rlk),
+                                                  1 if rescale else 0, _ptr(ct_out), _stream(stream)))
+
+
+# ---------------------------------------------------------------- tensor helpers
+
+def to_device(a, device="cuda") -> torch.Tensor:
+    """numpy uint64 array -> contiguous torch.uint64 tensor on the GPU (bit copy)."""
+    import numpy as np
+    a = np.ascontiguousarray(a, dtype=np.uint64)
+    return torch.from_numpy(a.view(np.int64)).to(device).view(torch.uint64)
+
+
+def to_host(t: torch.Tensor):
+    """GPU tensor -> numpy uint64 array (bit copy)."""
+    import numpy as np
+    return t.view(torch.int64).cpu().numpy().view(np.uint64)
+
+
+def empty(shape, device="cuda") -> torch.Tensor:
+    return torch.empty(shape, dtype=torch.int64, device=device).view(torch.uint64)

@@ -1,0 +1,93 @@
+"""Host-side checks of the C ABI (no GPU): the library loads, exports every
+symbol include/hks.h declares, and its host helpers and argument validation
+behave as documented.  No kernel is launched here."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from oracle import oracle as O
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def hks():
+    from paper_2112_06396_amd import hks as H
+    if not os.path.exists(H.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    return H
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "hks.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(hks_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported(hks):
+    lib = hks.lib()
+    declared = _declared()
+    assert len(declared) >= 20
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert sorted(hks.EXPORTS) == declared
+
+
+def test_gen_primes_matches_oracle_rule(hks):
+    for bits, log_step, cnt in ((50, 17, 48), (50, 13, 10)):
+        assert hks.hks_gen_primes(bits, log_step, cnt) == [int(v) for v in O.gen_primes(bits, log_step, cnt)]
+    with pytest.raises(hks.HksError):
+        hks.hks_gen_primes(50, 60, 3)
+
+
+def test_galois_helpers(hks):
+    for log_n in (10, 12, 16):
+        two_n = 2 << log_n
+        assert hks.hks_galois_for_rotation(1, log_n) == pow(5, -1, two_n)
+        assert hks.hks_galois_for_rotation(-1, log_n) == 5
+        assert hks.hks_galois_for_rotation(3, log_n) == pow(5, -3, two_n)
+        assert hks.hks_galois_for_rotation(0, log_n) == 1
+        assert hks.hks_galois_conjugate(log_n) == two_n - 1
+
+
+def test_strerror(hks):
+    assert hks.strerror(0) == "ok"
+    assert hks.strerror(-1) == "invalid argument"
+    assert "unknown" in hks.strerror(-99)
+
+
+def _create(hks, log_n, q, p, dnum):
+    qa = (ctypes.c_uint64 * len(q))(*q)
+    pa = (ctypes.c_uint64 * len(p))(*p)
+    prm = hks._Params(log_n, len(q), len(p), dnum, qa, pa)
+    h = ctypes.c_void_p()
+    return hks.lib().hks_create(ctypes.byref(prm), 0, ctypes.byref(h))
+
+
+def test_create_rejects_invalid_parameters(hks):
+    primes = hks.hks_gen_primes(50, 17, 12)
+    q, p = primes[:6], primes[6:9]
+    EINVAL = hks.HKS_EINVAL
+    assert _create(hks, 9, q, p, 3) == EINVAL             # log_n out of range
+    assert _create(hks, 17, q, p, 3) == EINVAL
+    assert _create(hks, 12, q, p[:1], 3) == EINVAL        # K < alpha = 2
+    assert _create(hks, 12, q, p, 0) == EINVAL            # dnum = 0
+    assert _create(hks, 12, q, p, 7) == EINVAL            # dnum > L
+    assert _create(hks, 12, q[:5] + [q[0]], p, 3) == EINVAL  # repeated prime
+    assert _create(hks, 12, q[:5] + [q[5] + 2], p, 3) == EINVAL  # not prime / not 1 mod 2N
+    small = [int(v) for v in O.gen_primes(40, 17, 1)]
+    assert _create(hks, 12, q[:5] + small, p, 3) == EINVAL  # below 2^49
+    rc = hks.lib().hks_create(None, 0, ctypes.byref(ctypes.c_void_p()))
+    assert rc == EINVAL
+
+
+def test_calls_reject_null_context(hks):
+    lib = hks.lib()
+    assert lib.hks_ntt(None, None, 0, 1, None) == hks.HKS_EINVAL
+    assert lib.hks_rotate(None, None, 1, 5, None, None, None) == hks.HKS_EINVAL
+    out = ctypes.c_uint64()
+    assert lib.hks_query(None, hks.HKS_Q_N, 0, ctypes.byref(out)) == hks.HKS_EINVAL
+    lib.hks_destroy(None)

@@ -1,0 +1,323 @@
+"""Parity of the HIP path with the CPU oracle, through the C ABI.
+
+Every comparison is exact equality of uint64 residues (the method is exact
+modular arithmetic; both sides reduce to canonical [0, q)).  Inputs are
+seeded synthetic residues from paper_2112_06396_amd.synth; valid keys and
+ciphertexts (for the decryption checks) come from the oracle's test-side
+key generation.  Shapes cover several NTT tiles and splits (log N = 10..16,
+odd sub-transform sizes), short last digits, level 1, and the full
+N = 2^16, L = 24, K = 8, dnum = 3 key-switch and L = 35, K = 12.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2112_06396_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+CFGS = {
+    # name: (log_n, L, K, dnum)
+    "n10": (10, 6, 2, 3),
+    "n11": (11, 5, 3, 2),
+    "cfg1": (12, 4, 2, 2),
+    "n13": (13, 7, 3, 3),
+    "n15": (15, 6, 2, 3),
+    "cfg2": (16, 24, 8, 3),
+}
+
+_CTX = {}
+
+
+def _get(name):
+    from paper_2112_06396_amd import hks
+    if name not in _CTX:
+        log_n, L, K, dnum = CFGS[name] if name in CFGS else name
+        pr = O.make_params(log_n, L, K, dnum)
+        _CTX[name] = (pr, hks.Context(log_n, pr.q, pr.p, dnum))
+    return _CTX[name]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _cleanup():
+    yield
+    for _, ctx in _CTX.values():
+        ctx.close()
+    _CTX.clear()
+
+
+def H():
+    from paper_2112_06396_amd import hks
+    return hks
+
+
+def dev(a):
+    return H().to_device(a)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return H().to_host(t)
+
+
+def _rand_ct(pr, level, seed):
+    g = synth.rng(seed)
+    return np.stack([synth.uniform_residues(g, pr.q[:level], pr.n) for _ in range(2)])
+
+
+def _rand_ksk(pr, seed):
+    g = synth.rng(seed)
+    return np.stack([np.stack([synth.uniform_residues(g, pr.key_mods(), pr.n) for _ in range(2)])
+                     for _ in range(pr.dnum)])
+
+
+def _levels(pr):
+    return sorted({1, pr.alpha + 1, pr.L - 1, pr.L} - {0})
+
+
+# ------------------------------------------------------------------ NTT / automorph
+
+@pytest.mark.parametrize("name", list(CFGS))
+def test_ntt_intt(name):
+    pr, ctx = _get(name)
+    hks = H()
+    mods = pr.key_mods()
+    x = synth.uniform_residues(synth.rng(10), mods, pr.n)
+    d = dev(x)
+    hks.hks_ntt(ctx, d, 0, len(mods))
+    y = host(d)
+    assert np.array_equal(y, O.ntt(x, pr.log_n, mods))
+    hks.hks_intt(ctx, d, 0, len(mods))
+    assert np.array_equal(host(d), x)
+    # a sub-range of moduli (the special primes)
+    z = synth.uniform_residues(synth.rng(11), pr.p, pr.n)
+    dz = dev(z)
+    hks.hks_intt(ctx, dz, pr.L, pr.K)
+    assert np.array_equal(host(dz), O.intt(z, pr.log_n, pr.p))
+
+
+@pytest.mark.parametrize("name", ["n10", "cfg1", "cfg2"])
+def test_automorph_eval_and_coeff(name):
+    pr, ctx = _get(name)
+    hks = H()
+    x = synth.uniform_residues(synth.rng(12), pr.q, pr.n)
+    d = dev(x)
+    out = hks.empty(x.shape)
+    for g in (hks.hks_galois_for_rotation(1, pr.log_n), hks.hks_galois_for_rotation(-7, pr.log_n),
+              hks.hks_galois_conjugate(pr.log_n)):
+        for ev in (True, False):
+            hks.hks_automorph(ctx, d, out, 0, pr.L, g, ev)
+            assert np.array_equal(host(out), O.automorph(x, pr.log_n, pr.q, g, eval_domain=ev))
+
+
+# ------------------------------------------------------------------ subroutines
+
+@pytest.mark.parametrize("name", ["n10", "n11", "cfg1", "n13", "cfg2"])
+def test_modup(name):
+    pr, ctx = _get(name)
+    hks = H()
+    for level in _levels(pr):
+        a = synth.uniform_residues(synth.rng(20 + level), pr.q[:level], pr.n)
+        ext = hks.empty((pr.beta(level), level + pr.K, pr.n))
+        hks.hks_modup(ctx, dev(a), level, ext)
+        assert np.array_equal(host(ext), O.modup(pr, a, level)), level
+
+
+@pytest.mark.parametrize("name", ["n10", "cfg1", "cfg2"])
+def test_ksk_inner(name):
+    pr, ctx = _get(name)
+    hks = H()
+    ksk = _rand_ksk(pr, 30)
+    dk = dev(ksk)
+    for level in _levels(pr):
+        g = synth.rng(31 + level)
+        ext = np.stack([synth.uniform_residues(g, pr.ext_mods(level), pr.n) for _ in range(pr.beta(level))])
+        uv = hks.empty((2, level + pr.K, pr.n))
+        hks.hks_ksk_inner(ctx, dev(ext), level, dk, uv)
+        assert np.array_equal(host(uv), O.ksk_inner(pr, ext, level, ksk)), level
+
+
+@pytest.mark.parametrize("name", ["n10", "n11", "cfg1", "n15", "cfg2"])
+def test_moddown(name):
+    pr, ctx = _get(name)
+    hks = H()
+    for level in _levels(pr):
+        x = synth.uniform_residues(synth.rng(40 + level), pr.ext_mods(level), pr.n)
+        y = hks.empty((level, pr.n))
+        hks.hks_moddown(ctx, dev(x), level, y)
+        assert np.array_equal(host(y), O.moddown(pr, x, level)), level
+
+
+# ------------------------------------------------------------------ composite calls
+
+@pytest.mark.parametrize("name", ["n10", "n11", "cfg1", "n13", "n15", "cfg2"])
+def test_keyswitch(name):
+    pr, ctx = _get(name)
+    hks = H()
+    ksk = _rand_ksk(pr, 50)
+    dk = dev(ksk)
+    for level in _levels(pr):
+        d = synth.uniform_residues(synth.rng(51 + level), pr.q[:level], pr.n)
+        uv = hks.empty((2, level, pr.n))
+        hks.hks_keyswitch(ctx, dev(d), level, dk, uv)
+        assert np.array_equal(host(uv), O.keyswitch(pr, d, level, ksk)), level
+
+
+@pytest.mark.parametrize("name", ["n10", "n11", "cfg1", "n13", "n15", "cfg2"])
+def test_rotate(name):
+    pr, ctx = _get(name)
+    hks = H()
+    ksk = _rand_ksk(pr, 60)
+    dk = dev(ksk)
+    for level in _levels(pr):
+        for k in (1, -3):
+            g = hks.hks_galois_for_rotation(k, pr.log_n)
+            ct = _rand_ct(pr, level, 61 + level)
+            out = hks.empty((2, level, pr.n))
+            hks.hks_rotate(ctx, dev(ct), level, g, dk, out)
+            assert np.array_equal(host(out), O.rotate(pr, ct, level, g, ksk)), (level, k)
+
+
+def test_rotate_config1_valid_key_decrypts():
+    """config 1: N=2^12, 4 limbs, 2 special primes, dnum=2, ternary secret,
+    rotation index 1; GPU output equals the oracle and decrypts to the
+    rotated message within the key-switching noise bound."""
+    pr, ctx = _get("cfg1")
+    hks = H()
+    g = synth.rng(synth.seed_for(1, synth.KIND_SECRET))
+    s = synth.ternary(g, pr.n)
+    gal = hks.hks_galois_for_rotation(1, pr.log_n)
+    ksk = O.rotation_key(pr, s, gal, g)
+    ct = O.encrypt(pr, s, synth.small_uniform(g, pr.n, 1 << 40), 4, g)
+    out = hks.empty((2, 4, pr.n))
+    hks.hks_rotate(ctx, dev(ct), 4, gal, dev(ksk), out)
+    got = host(out)
+    assert np.array_equal(got, O.rotate(pr, ct, 4, gal, ksk))
+    mods = pr.q[:4]
+    diff = O.sub_vec(O.decrypt_coef(pr, s, got, 4),
+                     O.automorph(O.decrypt_coef(pr, s, ct, 4), pr.log_n, mods, gal, eval_domain=False),
+                     pr.log_n, mods)
+    assert O.centered_small(diff, mods, O.ks_noise_bound(pr, 4, s)) is not None
+
+
+def test_rotate_config2_valid_key_decrypts():
+    """N=2^16, L=24, K=8, dnum=3 with a valid rotation key: bit-exact vs the
+    oracle and decryption within the noise bound."""
+    pr, ctx = _get("cfg2")
+    hks = H()
+    g = synth.rng(synth.seed_for(2, synth.KIND_SECRET))
+    s = synth.ternary(g, pr.n)
+    gal = hks.hks_galois_for_rotation(1, pr.log_n)
+    ksk = O.rotation_key(pr, s, gal, g)
+    level = 24
+    ct = O.encrypt(pr, s, synth.small_uniform(g, pr.n, 1 << 40), level, g)
+    out = hks.empty((2, level, pr.n))
+    hks.hks_rotate(ctx, dev(ct), level, gal, dev(ksk), out)
+    got = host(out)
+    assert np.array_equal(got, O.rotate(pr, ct, level, gal, ksk))
+    mods = pr.q[:level]
+    diff = O.sub_vec(O.decrypt_coef(pr, s, got, level),
+                     O.automorph(O.decrypt_coef(pr, s, ct, level), pr.log_n, mods, gal, eval_domain=False),
+                     pr.log_n, mods)
+    assert O.centered_small(diff, mods, O.ks_noise_bound(pr, level, s)) is not None
+
+
+@pytest.mark.parametrize("name", ["n10", "cfg1", "cfg2"])
+def test_hrotate(name):
+    pr, ctx = _get(name)
+    hks = H()
+    level = pr.L
+    ks = (1, 2, -5)
+    gals = [hks.hks_galois_for_rotation(k, pr.log_n) for k in ks]
+    ksks = [_rand_ksk(pr, 70 + i) for i in range(len(ks))]
+    ct = _rand_ct(pr, level, 75)
+    outs = [hks.empty((2, level, pr.n)) for _ in ks]
+    hks.hks_hrotate(ctx, dev(ct), level, gals, [dev(k) for k in ksks], outs)
+    refs = O.hrotate(pr, ct, level, gals, ksks)
+    for o, r in zip(outs, refs):
+        assert np.array_equal(host(o), r)
+
+
+@pytest.mark.parametrize("name", ["cfg1", "cfg2"])
+def test_batch_rotate_equals_single(name):
+    pr, ctx = _get(name)
+    hks = H()
+    level = pr.L
+    ksk = _rand_ksk(pr, 80)
+    dk = dev(ksk)
+    cts = [_rand_ct(pr, level, 81 + i) for i in range(3)]
+    gals = [hks.hks_galois_for_rotation(k, pr.log_n) for k in (1, 1, 4)]
+    outs = [hks.empty((2, level, pr.n)) for _ in cts]
+    hks.hks_batch_rotate(ctx, [dev(c) for c in cts], level, gals, [dk] * 3, outs)
+    for c, gl, o in zip(cts, gals, outs):
+        assert np.array_equal(host(o), O.rotate(pr, c, level, gl, ksk))
+
+
+@pytest.mark.parametrize("name", ["n10", "cfg1", "cfg2"])
+def test_rescale_ptmult(name):
+    pr, ctx = _get(name)
+    hks = H()
+    for level in sorted({2, pr.L}):
+        ct = _rand_ct(pr, level, 90 + level)
+        pt = synth.uniform_residues(synth.rng(91), pr.q[:level], pr.n)
+        out = hks.empty((2, level - 1, pr.n))
+        hks.hks_rescale(ctx, dev(ct), level, out)
+        assert np.array_equal(host(out), O.rescale(pr, ct, level))
+        for rs in (False, True):
+            o = hks.empty((2, level - (1 if rs else 0), pr.n))
+            hks.hks_ptmult(ctx, dev(ct), dev(pt), level, rs, o)
+            assert np.array_equal(host(o), O.ptmult(pr, ct, pt, level, rs))
+
+
+@pytest.mark.parametrize("name", ["n10", "cfg1", "cfg2"])
+def test_mult_relin(name):
+    pr, ctx = _get(name)
+    hks = H()
+    rlk = _rand_ksk(pr, 100)
+    level = pr.L
+    c1, c2 = _rand_ct(pr, level, 101), _rand_ct(pr, level, 102)
+    for rs in (False, True):
+        o = hks.empty((2, level - (1 if rs else 0), pr.n))
+        hks.hks_mult_relin(ctx, dev(c1), dev(c2), level, dev(rlk), rs, o)
+        assert np.array_equal(host(o), O.mult_relin(pr, c1, c2, level, rlk, rs))
+
+
+def test_max_level_config4_shape():
+    """N=2^16 at the top of the bootstrapping-shaped trace: L=35, K=12, dnum=3."""
+    pr, ctx = _get((16, 35, 12, 3))
+    hks = H()
+    ksk = _rand_ksk(pr, 110)
+    for level in (35, 10):
+        ct = _rand_ct(pr, level, 111)
+        g = hks.hks_galois_for_rotation(32, pr.log_n)
+        out = hks.empty((2, level, pr.n))
+        hks.hks_rotate(ctx, dev(ct), level, g, dev(ksk), out)
+        assert np.array_equal(host(out), O.rotate(pr, ct, level, g, ksk)), level
+
+
+def test_invalid_arguments_are_rejected():
+    pr, ctx = _get("cfg1")
+    hks = H()
+    ct = dev(_rand_ct(pr, 4, 1))
+    ksk = dev(_rand_ksk(pr, 2))
+    out = hks.empty((2, 4, pr.n))
+    for level, g in ((0, 5), (5, 5), (4, 4), (4, 2 * pr.n + 1)):
+        with pytest.raises(hks.HksError) as e:
+            hks.hks_rotate(ctx, ct, level, g, ksk, out)
+        assert e.value.status == hks.HKS_EINVAL
+    with pytest.raises(hks.HksError):
+        hks.hks_rotate(ctx, ct, 4, 5, ksk, ct)  # output aliases input
+    with pytest.raises(hks.HksError):
+        hks.hks_rescale(ctx, ct, 1, out)
+
+
+def test_deterministic_repeat():
+    pr, ctx = _get("cfg2")
+    hks = H()
+    ct, ksk = dev(_rand_ct(pr, 24, 5)), dev(_rand_ksk(pr, 6))
+    o1, o2 = hks.empty((2, 24, pr.n)), hks.empty((2, 24, pr.n))
+    g = hks.hks_galois_for_rotation(1, pr.log_n)
+    hks.hks_rotate(ctx, ct, 24, g, ksk, o1)
+    hks.hks_rotate(ctx, ct, 24, g, ksk, o2)
+    assert torch.equal(o1.view(torch.int64), o2.view(torch.int64))
