@@ -1,0 +1,305 @@
+#!/usr/bin/env python3
+"""Key-switching benchmark on one MI355X.
+
+Step = one Rotate (Algorithm 3: automorph, Decomp, ModUp, KSKInnerProd,
+ModDown x2, add) of an N = 2^16 ciphertext at level L = 24 with K = 8 special
+primes and dnum = 3 (one 96 MiB rotation key), through the C ABI.  Inputs are
+seeded synthetic uniform residues resident in HBM; the timed loop cycles over
+a pool of distinct (ciphertext, key) pairs larger than the 256 MB Infinity
+Cache so that every step streams its key from HBM.
+
+Prints ONE JSON line (stdout).  Progress and the per-kernel breakdown go to
+stderr.
+
+  python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "key-switch ops/s @N=2^16,L=24 (batched vs plain); achieved HBM GB/s; p99 ms"
+LOG_N, L, K, DNUM, LEVEL = 16, 24, 8, 3, 24
+WORKLOAD = 2  # seed family of this workload
+
+HBM_PEAK_GBS = 8000.0
+# int32 VALU lane-ops/s: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (gfx950 issues the
+# 32-bit multiply-class ops of a 64-bit modmul at full rate)
+VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
+# multiply-class 32-bit ops of one 64-bit Shoup modular multiplication
+# (high half of x*w': 4 partial products; low halves of x*w and q_est*q: 3 each)
+MULS_PER_MODMUL = 10
+MODMUL_PEAK = VALU_PEAK_OPS / MULS_PER_MODMUL
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_work(cls: int, n: int, level: int, k: int, alpha: int, beta: int):
+    """Algorithmic modular multiplications of one Rotate done by kernel class
+    `cls` (butterflies for NTT passes, multiply-accumulates for conversion and
+    KSKInnerProd) and the algorithmic HBM bytes it moves (8 B words)."""
+    n1 = LOG_N // 2
+    n2 = LOG_N - n1
+    E = level + k
+    own = level  # limbs copied from the input, one per digit member
+    new_limbs = beta * E - own
+    fwd_limbs = new_limbs + 2 * level
+    inv_limbs = level + 2 * k
+    half = n // 2
+    if cls == 0:  # forward NTT, column pass
+        return fwd_limbs * half * n1, fwd_limbs * n * 16
+    if cls == 1:  # forward NTT, row pass
+        return fwd_limbs * half * n2, fwd_limbs * n * 16
+    if cls == 2:  # inverse NTT, row pass
+        return inv_limbs * half * n2, inv_limbs * n * 16
+    if cls == 3:  # inverse NTT, column pass (+ folded scale on half the outputs)
+        return inv_limbs * half * (n1 + 1), inv_limbs * n * 16
+    if cls == 4:  # conversion: ModUp sum_j |I_j| (E - |I_j|) + ModDown 2 K level
+        macs = 0
+        for j in range(beta):
+            sz = min(alpha, level - j * alpha)
+            macs += sz * (E - sz)
+        macs += 2 * k * level
+        return macs * n, (level + new_limbs + 2 * k + 2 * level) * n * 8
+    if cls == 5:  # KSKInnerProd: 2 rows x beta digits x E limbs
+        return 2 * beta * E * n, (beta * E + 2 * beta * E + 2 * E) * n * 8
+    return 0, 0
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "modarith.h", "hks_internal.h", "abi.cpp"):
+        h.update(open(os.path.join(ROOT, "paper_2112_06396_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(kernel_name: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", f"{kernel_name}_rotate_n16_l24_counters.md")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m = re.search(r"source_hash:\s*([0-9a-f]+)", txt)
+    t = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if not m or not t or m.group(1) != source_hash():
+        return None
+    return float(t.group(1))
+
+
+def cpu_baseline(sample: int):
+    import numpy as np
+    from oracle import oracle as O
+    from paper_2112_06396_amd import synth
+    pr = O.make_params(LOG_N, L, K, DNUM)
+    g = synth.rng(synth.seed_for(WORKLOAD, synth.KIND_CT, 999))
+    ct = np.stack([synth.uniform_residues(g, pr.q[:LEVEL], pr.n) for _ in range(2)])
+    ksk = np.stack([np.stack([synth.uniform_residues(g, pr.key_mods(), pr.n) for _ in range(2)])
+                    for _ in range(DNUM)])
+    gal = pow(5, -1, 2 * pr.n)
+    t0 = time.perf_counter()
+    for _ in range(sample):
+        O.rotate(pr, ct, LEVEL, gal, ksk)
+    dt = time.perf_counter() - t0
+    return {"value": sample / dt, "unit": "key-switch/s", "cores": 1, "kind": "oracle",
+            "sample": f"{sample} Rotate calls of the single-threaded C oracle at N=2^16, L=24, K=8, dnum=3 "
+                      f"({dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--pool", type=int, default=8)
+    ap.add_argument("--cpu-sample", type=int, default=4)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="also run one plain copy of this many MiB (counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the key-switching path here runs on a single MI355X "
+              "(multi-GPU sharding is a design note, not part of this build). Run with --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2112_06396_amd import hks, synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.init()
+    pq = hks.hks_gen_primes(50, LOG_N + 1, L + K)
+    q, p = pq[:L], pq[L:]
+    ctx = hks.Context(LOG_N, q, p, DNUM)
+    n = 1 << LOG_N
+    alpha = ctx.alpha
+    beta = ctx.beta(LEVEL)
+    key_mods = q + p
+
+    log(f"[bench] building pool of {args.pool} (ciphertext, key) pairs")
+    cts, ksks, outs = [], [], []
+    for i in range(args.pool):
+        g = synth.rng(synth.seed_for(WORKLOAD, synth.KIND_CT, i))
+        ct = np.stack([synth.uniform_residues(g, q[:LEVEL], n) for _ in range(2)])
+        gk = synth.rng(synth.seed_for(WORKLOAD, synth.KIND_KEY, i))
+        kk = np.stack([np.stack([synth.uniform_residues(gk, key_mods, n) for _ in range(2)]) for _ in range(DNUM)])
+        cts.append(hks.to_device(ct))
+        ksks.append(hks.to_device(kk))
+        outs.append(hks.empty((2, LEVEL, n)))
+    torch.cuda.synchronize()
+    pool_bytes = sum(t.numel() * 8 for t in cts + ksks + outs)
+    log(f"[bench] pool resident: {pool_bytes / 2**30:.2f} GiB")
+    gal = hks.hks_galois_for_rotation(1, LOG_N)
+    stream = torch.cuda.current_stream()
+
+    def step(i):
+        j = i % args.pool
+        hks.hks_rotate(ctx, cts[j], LEVEL, gal, ksks[j], outs[j], stream)
+
+    # warmup
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    log(f"[bench] warmup done ({args.warmup} steps)")
+
+    # per-kernel breakdown (untimed pass, all classes recorded)
+    hks.hks_prof_enable(ctx, (1 << 9) - 1)
+    nb = min(20, max(4, args.steps // 10))
+    for i in range(nb):
+        step(i)
+    torch.cuda.synchronize()
+    breakdown = {}
+    for cls, name in enumerate(hks.HKS_K_NAMES):
+        ms, cnt = hks.hks_prof_read(ctx, cls)
+        if cnt:
+            breakdown[name] = {"ms_per_step": ms / nb, "launches_per_step": cnt / nb}
+    hks.hks_prof_enable(ctx, 0)
+    dom_name = max(breakdown, key=lambda k: breakdown[k]["ms_per_step"])
+    dom_cls = hks.HKS_K_NAMES.index(dom_name)
+    tot = sum(v["ms_per_step"] for v in breakdown.values())
+    for k_, v in sorted(breakdown.items(), key=lambda kv: -kv[1]["ms_per_step"]):
+        log(f"[bench]   {k_:14s} {v['ms_per_step'] * 1e3:8.1f} us/step  {v['launches_per_step']:.0f} launches"
+            f"  ({100 * v['ms_per_step'] / tot:.0f}%)")
+    log(f"[bench] dominant kernel class: {dom_name}")
+
+    # timed region: per-step events, dominant-kernel events recorded by the library
+    hks.hks_prof_enable(ctx, 1 << dom_cls)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    for i in range(args.steps):
+        step(i)
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    dom_ms, dom_launches = hks.hks_prof_read(ctx, dom_cls)
+    hks.hks_prof_enable(ctx, 0)
+    gpu_ms = ev[0].elapsed_time(ev[-1])
+    per = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps)])
+    ms_per_step = gpu_ms / args.steps
+    value = args.steps / (gpu_ms / 1e3)
+    log(f"[bench] timed {args.steps} steps: {ms_per_step * 1e3:.1f} us/step, {value:.0f} ks/s "
+        f"(host wall {wall * 1e3 / args.steps:.1f} us/step)")
+
+    # roofline of the dominant kernel
+    mm, byt = kernel_work(dom_cls, n, LEVEL, K, alpha, beta)
+    launches_per_step = dom_launches / args.steps
+    avg_launch_s = dom_ms / 1e3 / dom_launches
+    per_launch_mm = mm / launches_per_step
+    per_launch_bytes = byt / launches_per_step
+    if dom_cls <= 4:
+        achieved = per_launch_mm / avg_launch_s / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": MODMUL_PEAK / 1e12, "unit": "Tmodmul/s",
+                "frac": achieved / (MODMUL_PEAK / 1e12)}
+    else:
+        achieved = per_launch_bytes / avg_launch_s / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS}
+    roof["kernel"] = dom_name
+    roof["avg_launch_us"] = avg_launch_s * 1e6
+    roof["launches_per_step"] = launches_per_step
+    roof["algorithmic_per_launch"] = {"modmul": per_launch_mm, "bytes": per_launch_bytes}
+    tr = read_traffic(dom_name)
+    roof["traffic"] = tr
+
+    # compulsory HBM bytes of one Rotate: a, b, key (digits < beta, limbs [0,level) U P), output
+    key_bytes = beta * 2 * (LEVEL + K) * n * 8
+    comp_bytes = 2 * LEVEL * n * 8 + key_bytes + 2 * LEVEL * n * 8
+    result = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "key-switch/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": "Rotate (key-switch) N=2^16 L=24 K=8 dnum=3 level=24, one 96 MiB key, "
+                               f"pool of {args.pool} (ciphertext, key) pairs",
+                   "log_n": LOG_N, "L": L, "K": K, "dnum": DNUM, "level": LEVEL, "batch": 1},
+        "p50_ms": float(np.percentile(per, 50)),
+        "p99_ms": float(np.percentile(per, 99)),
+        "hbm_compulsory_bytes_per_step": comp_bytes,
+        "hbm_algorithmic_GBps": comp_bytes / (ms_per_step / 1e3) / 1e9,
+        "roofline": roof,
+        "kernel_breakdown_us": {k_: v["ms_per_step"] * 1e3 for k_, v in breakdown.items()},
+    }
+
+    if not args.no_extras:
+        # hoisted rotations (Algorithm 4): one ModUp shared by r rotations
+        r = min(args.pool, 8)
+        gals = [hks.hks_galois_for_rotation(k_ + 1, LOG_N) for k_ in range(r)]
+        hks.hks_hrotate(ctx, cts[0], LEVEL, gals, ksks[:r], outs[:r], stream)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = max(2, args.steps // (4 * r))
+        e0.record(stream)
+        for i in range(reps):
+            hks.hks_hrotate(ctx, cts[i % args.pool], LEVEL, gals, ksks[:r], outs[:r], stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        result["hrotate_r8_ks_per_s"] = reps * r / (e0.elapsed_time(e1) / 1e3)
+        # batch of ciphertexts sharing one key
+        nb_ct = args.pool
+        e0.record(stream)
+        for i in range(reps):
+            hks.hks_batch_rotate(ctx, cts, LEVEL, [gal] * nb_ct, [ksks[0]] * nb_ct, outs, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        result[f"batch{nb_ct}_shared_key_ks_per_s"] = reps * nb_ct / (e0.elapsed_time(e1) / 1e3)
+
+    if args.calib_copy_mib:
+        nw = args.calib_copy_mib * (1 << 20) // 8
+        src = torch.ones(nw, dtype=torch.int64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy of {args.calib_copy_mib} MiB done")
+
+    if not args.no_cpu_baseline:
+        log(f"[bench] timing the CPU oracle on {args.cpu_sample} rotations")
+        result["cpu_baseline"] = cpu_baseline(args.cpu_sample)
+
+    ctx.close()
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

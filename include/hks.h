@@ -184,6 +184,29 @@ int hks_ptmult(hks_ctx *ctx, const uint64_t *ct, const uint64_t *pt, uint32_t le
 int hks_mult_relin(hks_ctx *ctx, const uint64_t *ct1, const uint64_t *ct2, uint32_t level,
                    const uint64_t *rlk, int rescale, uint64_t *ct_out, void *stream);
 
+/* ---------------------------------------------------------------- kernel timing */
+
+/* Kernel classes for hks_prof_* (bit i of a mask selects class i). */
+#define HKS_K_NTT_FWD_COLS 0 /* forward NTT, column pass (stages 0..n1-1) */
+#define HKS_K_NTT_FWD_ROWS 1 /* forward NTT, row pass (stages n1..n-1) */
+#define HKS_K_NTT_INV_ROWS 2 /* inverse NTT, row pass (+ automorph gather) */
+#define HKS_K_NTT_INV_COLS 3 /* inverse NTT, column pass (+ folded scale) */
+#define HKS_K_CONV 4         /* basis conversion (NewLimb) */
+#define HKS_K_KSK 5          /* KSKInnerProd */
+#define HKS_K_MODDOWN_EPI 6  /* ModDown final step */
+#define HKS_K_AUTOMORPH 7    /* standalone automorph / limb copy */
+#define HKS_K_ELEMENTWISE 8  /* PtMult, tensor, Rescale steps */
+#define HKS_K_COUNT 9
+
+/* Measurement aid.  While bit k of `mask` is set, every launch of kernel
+ * class k records a hipEvent pair on the launch stream; hks_prof_read()
+ * waits for the recorded events and returns the summed milliseconds and the
+ * launch count of class k since the last hks_prof_enable() call.  mask = 0
+ * turns recording off.  Events are created on the host side only; no device
+ * memory is allocated. */
+int hks_prof_enable(hks_ctx *ctx, uint32_t mask);
+int hks_prof_read(hks_ctx *ctx, int kernel_class, double *ms, uint64_t *launches);
+
 #ifdef __cplusplus
 }
 #endif

@@ -517,4 +517,31 @@ int hks_mult_relin(hks_ctx *h, const uint64_t *ct1, const uint64_t *ct2, uint32_
     GUARD_END
 }
 
+int hks_prof_enable(hks_ctx *h, uint32_t mask) {
+    GUARD_BEGIN
+    if (!h) return HKS_EINVAL;
+    if (hipDeviceSynchronize() != hipSuccess) return HKS_EHIP;
+    prof_reset(h->c);
+    h->c.prof_mask = mask & ((1u << HKS_K_COUNT) - 1u);
+    return HKS_OK;
+    GUARD_END
+}
+
+int hks_prof_read(hks_ctx *h, int kernel_class, double *ms, uint64_t *launches) {
+    GUARD_BEGIN
+    if (!h || !ms || !launches || kernel_class < 0 || kernel_class >= HKS_K_COUNT) return HKS_EINVAL;
+    const Ctx &c = h->c;
+    double total = 0.0;
+    for (auto &p : c.prof_ev[kernel_class]) {
+        if (hipEventSynchronize(p.second) != hipSuccess) return HKS_EHIP;
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, p.first, p.second) != hipSuccess) return HKS_EHIP;
+        total += t;
+    }
+    *ms = total;
+    *launches = c.prof_ev[kernel_class].size();
+    return HKS_OK;
+    GUARD_END
+}
+
 }  // extern "C"

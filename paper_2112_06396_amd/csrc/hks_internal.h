@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/hks.h"
@@ -76,8 +77,25 @@ struct Ctx {
     uint64_t *ws_r = nullptr;    // [cap][2][N]          Rescale: coefficient-form last limbs
     uint64_t *ws_w = nullptr;    // [cap][2][L][N]       Rescale: rounding correction
 
+    // kernel timing (hks_prof_*): event pairs per kernel class
+    mutable uint32_t prof_mask = 0;
+    mutable std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev[HKS_K_COUNT];
+    mutable std::vector<hipEvent_t> prof_pool;
+
     size_t ksk_words() const { return (size_t)dnum * 2 * M * n; }
 };
+
+// Records a hipEvent pair around the launches in its scope when the class is
+// selected by the context's timing mask.
+struct ProfScope {
+    const Ctx &c;
+    int cls;
+    hipStream_t s;
+    bool on;
+    ProfScope(const Ctx &ctx, int k, hipStream_t st);
+    ~ProfScope();
+};
+void prof_reset(const Ctx &c);
 
 // ---------------------------------------------------------------- tables (host)
 int build_tables(Ctx &c);

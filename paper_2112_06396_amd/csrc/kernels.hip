@@ -25,6 +25,42 @@
 
 namespace hks {
 
+// ------------------------------------------------------------------ timing
+
+static hipEvent_t prof_event(const Ctx &c) {
+    if (!c.prof_pool.empty()) {
+        hipEvent_t e = c.prof_pool.back();
+        c.prof_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+ProfScope::ProfScope(const Ctx &ctx, int k, hipStream_t st) : c(ctx), cls(k), s(st), on(false) {
+    if (!((c.prof_mask >> cls) & 1u)) return;
+    hipEvent_t a = prof_event(c), b = prof_event(c);
+    if (!a || !b) return;
+    if (hipEventRecord(a, s) != hipSuccess) return;
+    c.prof_ev[cls].push_back({a, b});
+    on = true;
+}
+
+ProfScope::~ProfScope() {
+    if (on) (void)hipEventRecord(c.prof_ev[cls].back().second, s);
+}
+
+void prof_reset(const Ctx &c) {
+    for (int k = 0; k < HKS_K_COUNT; ++k) {
+        for (auto &p : c.prof_ev[k]) {
+            c.prof_pool.push_back(p.first);
+            c.prof_pool.push_back(p.second);
+        }
+        c.prof_ev[k].clear();
+    }
+}
+
 // ------------------------------------------------------------------ helpers
 
 __device__ __forceinline__ uint32_t brev_n(uint32_t x, uint32_t n) { return __brev(x) >> (32 - n); }
@@ -136,6 +172,7 @@ __device__ __forceinline__ void ntt_all_phases(uint64_t *lds, int line, int t, u
 }
 
 struct NttArgs {
+    const Ctx *ctx;  // host-side only (timing); not read by kernels
     const uint64_t *in;
     uint64_t *out;
     const Shoup *tw;       // [M][N] forward or inverse table
@@ -225,6 +262,8 @@ ntt_pass_kernel(const NttArgs a) {
 template <int LOGS, int LINES, bool COLS, bool FWD, int IO>
 static hipError_t launch_pass(const NttArgs &a, uint32_t count, uint32_t batch, hipStream_t s) {
     using TL = Tile<LOGS, LINES, COLS>;
+    ProfScope ps(*a.ctx, FWD ? (COLS ? HKS_K_NTT_FWD_COLS : HKS_K_NTT_FWD_ROWS)
+                             : (COLS ? HKS_K_NTT_INV_COLS : HKS_K_NTT_INV_ROWS), s);
     uint32_t lines_per_limb = 1u << (COLS ? a.n2 : a.n1);
     dim3 grid(count * (lines_per_limb / LINES), batch);
     hipLaunchKernelGGL((ntt_pass_kernel<LOGS, LINES, COLS, FWD, IO>), grid, dim3(TL::NT), 0, s, a);
@@ -256,6 +295,7 @@ hipError_t launch_ntt_fwd(const Ctx &c, const LimbMap &m, const uint64_t *in, ui
                           uint32_t batch, size_t in_bstride, size_t out_bstride, hipStream_t s) {
     if (m.count == 0 || batch == 0) return hipSuccess;
     NttArgs a{};
+    a.ctx = &c;
     a.tw = c.tw_fwd;
     a.mc = c.mc;
     a.li = c.li_plain;
@@ -283,6 +323,7 @@ hipError_t launch_ntt_inv(const Ctx &c, const LimbMap &m, const uint64_t *in, ui
                           size_t out_bstride, hipStream_t s) {
     if (m.count == 0 || batch == 0) return hipSuccess;
     NttArgs a{};
+    a.ctx = &c;
     a.tw = c.tw_inv;
     a.mc = c.mc;
     a.li = li;
@@ -357,6 +398,7 @@ hipError_t launch_conv_map(const Ctx &c, const uint64_t *in, uint32_t n_src, con
     a.stride = stride;
     a.m = m;
     dim3 grid((c.n + 255) / 256, batch);
+    ProfScope ps(c, HKS_K_CONV, s);
     if (n_src <= 4) hipLaunchKernelGGL(conv_kernel<4>, grid, dim3(256), 0, s, a);
     else if (n_src <= 8) hipLaunchKernelGGL(conv_kernel<8>, grid, dim3(256), 0, s, a);
     else if (n_src <= 12) hipLaunchKernelGGL(conv_kernel<12>, grid, dim3(256), 0, s, a);
@@ -417,6 +459,7 @@ hipError_t launch_automorph(const Ctx &c, const LimbMap &m, const uint64_t *in, 
     a.ginv = (uint32_t)h_powmod(galois, (two_n / 2) - 1, two_n);  // g^(N-1) = g^-1 in (Z/2N)^*
     a.m = m;
     dim3 grid((c.n + 255) / 256, batch, m.count);
+    ProfScope ps(c, HKS_K_AUTOMORPH, s);
     if (eval_domain) hipLaunchKernelGGL(automorph_kernel<true>, grid, dim3(256), 0, s, a);
     else hipLaunchKernelGGL(automorph_kernel<false>, grid, dim3(256), 0, s, a);
     return hipGetLastError();
@@ -477,6 +520,7 @@ hipError_t launch_ksk(const Ctx &c, const uint64_t *ext, uint32_t level, uint32_
     a.beta = beta;
     a.galois = galois;
     dim3 grid((c.n + 255) / 256, batch, a.E);
+    ProfScope ps(c, HKS_K_KSK, s);
     hipLaunchKernelGGL(ksk_kernel, grid, dim3(256), 0, s, a);
     return hipGetLastError();
 }
@@ -530,6 +574,7 @@ hipError_t launch_moddown_epi(const Ctx &c, const uint64_t *x, const uint64_t *z
     a.add_galois = add_galois;
     a.add_mask = add_mask;
     dim3 grid((c.n + 255) / 256, batch, level);
+    ProfScope ps(c, HKS_K_MODDOWN_EPI, s);
     hipLaunchKernelGGL(moddown_epi_kernel, grid, dim3(256), 0, s, a);
     return hipGetLastError();
 }
@@ -625,6 +670,7 @@ hipError_t launch_mulpt(const Ctx &c, const uint64_t *ct, const uint64_t *pt, ui
     a.mc = c.mc;
     a.n = c.log_n;
     a.level = level;
+    ProfScope ps(c, HKS_K_ELEMENTWISE, s);
     hipLaunchKernelGGL(mulpt_kernel, dim3((c.n + 255) / 256, n_poly, level), dim3(256), 0, s, a);
     return hipGetLastError();
 }
@@ -638,6 +684,7 @@ hipError_t launch_tensor(const Ctx &c, const uint64_t *ct1, const uint64_t *ct2,
     a.mc = c.mc;
     a.n = c.log_n;
     a.level = level;
+    ProfScope ps(c, HKS_K_ELEMENTWISE, s);
     hipLaunchKernelGGL(tensor_kernel, dim3((c.n + 255) / 256, 1, level), dim3(256), 0, s, a);
     return hipGetLastError();
 }
@@ -651,6 +698,7 @@ hipError_t launch_add(const Ctx &c, const uint64_t *x, const uint64_t *y, uint64
     a.mc = c.mc;
     a.n = c.log_n;
     a.level = level;
+    ProfScope ps(c, HKS_K_ELEMENTWISE, s);
     hipLaunchKernelGGL(add_kernel, dim3((c.n + 255) / 256, 1, n_limbs_total), dim3(256), 0, s, a);
     return hipGetLastError();
 }
@@ -667,6 +715,7 @@ hipError_t launch_rescale_prep(const Ctx &c, const uint64_t *rlast, uint64_t *w,
     a.n_poly = c.L;  // row stride of the per-level table
     a.xs = r_bstride;
     a.outs = w_bstride;
+    ProfScope ps(c, HKS_K_ELEMENTWISE, s);
     hipLaunchKernelGGL(rescale_prep_kernel, dim3((c.n + 255) / 256, n_poly, level - 1), dim3(256), 0,
                        s, a);
     return hipGetLastError();
@@ -687,6 +736,7 @@ hipError_t launch_rescale_epi(const Ctx &c, const uint64_t *x, const uint64_t *w
     a.xs = x_bstride;
     a.ys = w_bstride;
     a.outs = out_bstride;
+    ProfScope ps(c, HKS_K_ELEMENTWISE, s);
     hipLaunchKernelGGL(rescale_epi_kernel, dim3((c.n + 255) / 256, n_poly, level - 1), dim3(256), 0,
                        s, a);
     return hipGetLastError();

@@ -41,8 +41,20 @@ EXPORTS = (
     "hks_gen_primes", "hks_galois_for_rotation", "hks_galois_conjugate", "hks_strerror",
     "hks_create", "hks_destroy", "hks_query", "hks_ntt", "hks_intt", "hks_automorph",
     "hks_modup", "hks_ksk_inner", "hks_moddown", "hks_keyswitch", "hks_rotate", "hks_hrotate",
-    "hks_batch_rotate", "hks_rescale", "hks_ptmult", "hks_mult_relin",
+    "hks_batch_rotate", "hks_rescale", "hks_ptmult", "hks_mult_relin", "hks_prof_enable", "hks_prof_read",
 )
+
+HKS_K_NTT_FWD_COLS = 0
+HKS_K_NTT_FWD_ROWS = 1
+HKS_K_NTT_INV_ROWS = 2
+HKS_K_NTT_INV_COLS = 3
+HKS_K_CONV = 4
+HKS_K_KSK = 5
+HKS_K_MODDOWN_EPI = 6
+HKS_K_AUTOMORPH = 7
+HKS_K_ELEMENTWISE = 8
+HKS_K_NAMES = ("ntt_fwd_cols", "ntt_fwd_rows", "ntt_inv_rows", "ntt_inv_cols", "conv", "ksk",
+               "moddown_epi", "automorph", "elementwise")
 
 
 class HksError(RuntimeError):
@@ -102,6 +114,8 @@ def lib():
             "hks_rescale": (_i32, [_vp, _vp, _u32, _vp, _vp]),
             "hks_ptmult": (_i32, [_vp, _vp, _vp, _u32, _i32, _vp, _vp]),
             "hks_mult_relin": (_i32, [_vp, _vp, _vp, _u32, _vp, _i32, _vp, _vp]),
+            "hks_prof_enable": (_i32, [_vp, _u32]),
+            "hks_prof_read": (_i32, [_vp, _i32, ctypes.POINTER(ctypes.c_double), u64p]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -289,6 +303,18 @@ def hks_ptmult(ctx, ct, pt, level: int, rescale: bool, ct_out, stream=None):
 def hks_mult_relin(ctx, ct1, ct2, level: int, rlk, rescale: bool, ct_out, stream=None):
     _check("hks_mult_relin", lib().hks_mult_relin(ctx.handle, _ptr(ct1), _ptr(ct2), level, _ptr(rlk),
                                                   1 if rescale else 0, _ptr(ct_out), _stream(stream)))
+
+
+def hks_prof_enable(ctx, mask: int):
+    _check("hks_prof_enable", lib().hks_prof_enable(ctx.handle, int(mask)))
+
+
+def hks_prof_read(ctx, kernel_class: int):
+    """(milliseconds summed over launches, launch count) for one kernel class."""
+    ms = ctypes.c_double()
+    n = ctypes.c_uint64()
+    _check("hks_prof_read", lib().hks_prof_read(ctx.handle, int(kernel_class), ctypes.byref(ms), ctypes.byref(n)))
+    return float(ms.value), int(n.value)
 
 
 # ---------------------------------------------------------------- tensor helpers
