@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhks.so")
-SOURCES = ["kernels.hip", "tables.cpp", "abi.cpp"]
+SOURCES = ["ntt.hip", "kernels.hip", "tables.cpp", "abi.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
@@ -20,35 +20,36 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False, jobs: int = 4) -> str:
-    bdir = os.path.join(HERE, "_build")
+def build(verbose: bool = False, out: str = LIB, src_dir: str = CSRC, extra_flags=()) -> str:
+    """Compile SOURCES from src_dir into the shared library `out`."""
+    bdir = os.path.join(os.path.dirname(os.path.abspath(out)), "_build", os.path.basename(out) + ".d")
     os.makedirs(bdir, exist_ok=True)
     objs, procs = [], []
     for src in SOURCES:
         obj = os.path.join(bdir, os.path.splitext(src)[0] + ".o")
         lang = ["-x", "hip"]
-        cmd = [HIPCC, *FLAGS, *lang, "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [HIPCC, *FLAGS, *extra_flags, *lang, "-c", os.path.join(src_dir, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)))
         objs.append(obj)
     failed = False
     for src, p in procs:
-        out, _ = p.communicate()
+        log, _ = p.communicate()
         if p.returncode != 0:
             failed = True
-            sys.stderr.write(f"--- {src}\n{out}\n")
-        elif verbose and out.strip():
-            sys.stderr.write(out)
+            sys.stderr.write(f"--- {src}\n{log}\n")
+        elif verbose and log.strip():
+            sys.stderr.write(log)
     if failed:
         raise RuntimeError("hipcc failed")
-    tmp = LIB + ".tmp"
+    tmp = out + ".tmp"
     cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp, *objs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

@@ -36,144 +36,130 @@ bool aligned(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 
 uint32_t ext_mod(const Ctx &c, uint32_t level, uint32_t t) { return t < level ? t : c.L + (t - level); }
 
-// Run `fn(chunk)` over a limb list in chunks of at most MAXL entries.
-template <typename F>
-hipError_t chunked(const std::vector<uint32_t> &in_off, const std::vector<uint32_t> &out_off,
-                   const std::vector<uint32_t> &mod, const std::vector<uint32_t> &cidx, F fn) {
-    LimbMap m;
-    size_t total = in_off.size();
-    for (size_t s = 0; s < total; s += MAXL) {
-        size_t cnt = std::min<size_t>(MAXL, total - s);
-        std::memset(&m, 0, sizeof(m));
-        m.count = (uint32_t)cnt;
-        for (size_t i = 0; i < cnt; ++i) {
-            m.in_off[i] = (uint16_t)in_off[s + i];
-            m.out_off[i] = (uint16_t)out_off[s + i];
-            m.mod[i] = (uint8_t)mod[s + i];
-            m.cidx[i] = (uint16_t)cidx[s + i];
-        }
-        hipError_t e = fn(m);
-        if (e != hipSuccess) return e;
+struct Lists {
+    std::vector<uint32_t> io, oo, md, ci, ns;
+    void add(uint32_t in_off, uint32_t out_off, uint32_t mod, uint32_t cidx, uint32_t nsrc = 0) {
+        io.push_back(in_off);
+        oo.push_back(out_off);
+        md.push_back(mod);
+        ci.push_back(cidx);
+        ns.push_back(nsrc);
     }
-    return hipSuccess;
-}
-
-// ModUp of all digits of `a` (level limbs, evaluation form, optionally
-// gathered through the automorph `galois`) into ext [beta][level+K][N].
-int do_modup(Ctx &c, const uint64_t *a, uint32_t level, uint32_t galois, uint64_t *ext, hipStream_t s) {
-    const uint32_t N = c.n, A = c.alpha, E = level + c.K, beta = (level + A - 1) / A;
-    std::vector<uint32_t> io, oo, md, ci;
-    // 1. iNTT with hat scaling (and automorph gather)
-    for (uint32_t i = 0; i < level; ++i) {
-        io.push_back(i);
-        oo.push_back(i);
-        md.push_back(i);
-        ci.push_back(level * c.L + i);
-    }
-    HKS_TRY(chunked(io, oo, md, ci, [&](const LimbMap &m) {
-        return launch_ntt_inv(c, m, a, c.ws_y, c.li_modup, galois, 1, 0, 0, s);
-    }));
-    // 2. NewLimb per digit; 3. NTT of new limbs; own limbs copied
-    std::vector<uint32_t> nio, noo, nmd, nci, cio, coo, cmd, cci;
-    for (uint32_t j = 0; j < beta; ++j) {
-        uint32_t lo = j * A, hi = std::min((j + 1) * A, level);
-        std::vector<uint32_t> vio, voo, vmd, vci;
-        for (uint32_t t = 0; t < E; ++t) {
-            if (t >= lo && t < hi) {
-                cio.push_back(t);
-                coo.push_back(j * E + t);
-                cmd.push_back(t);
-                cci.push_back(0);
-                continue;
+    template <typename F>
+    hipError_t run(F fn) const {
+        LimbMap m;
+        for (size_t s = 0; s < io.size(); s += MAXL) {
+            size_t cnt = std::min<size_t>(MAXL, io.size() - s);
+            std::memset(&m, 0, sizeof(m));
+            m.count = (uint32_t)cnt;
+            for (size_t i = 0; i < cnt; ++i) {
+                m.in_off[i] = (uint16_t)io[s + i];
+                m.out_off[i] = (uint16_t)oo[s + i];
+                m.mod[i] = (uint8_t)md[s + i];
+                m.cidx[i] = (uint16_t)ci[s + i];
+                m.nsrc[i] = (uint8_t)ns[s + i];
             }
-            vio.push_back(0);
-            voo.push_back(j * E + t);
-            vmd.push_back(ext_mod(c, level, t));
-            vci.push_back(t);
-            nio.push_back(j * E + t);
-            noo.push_back(j * E + t);
-            nmd.push_back(ext_mod(c, level, t));
-            nci.push_back(0);
+            hipError_t e = fn(m);
+            if (e != hipSuccess) return e;
         }
-        const uint64_t *conv = c.conv_modup + c.conv_modup_off[level] + (size_t)j * A * E;
-        HKS_TRY(chunked(vio, voo, vmd, vci, [&](const LimbMap &m) {
-            return launch_conv_map(c, c.ws_y + (size_t)lo * N, hi - lo, conv, E, ext, m, 1, 0, 0, s);
-        }));
+        return hipSuccess;
     }
-    HKS_TRY(chunked(nio, noo, nmd, nci, [&](const LimbMap &m) {
-        return launch_ntt_fwd(c, m, ext, ext, 1, 0, 0, s);
-    }));
-    HKS_TRY(chunked(cio, coo, cmd, cci, [&](const LimbMap &m) {
-        return launch_automorph(c, m, a, ext, galois, 1, 1, 0, 0, s);
-    }));
-    return HKS_OK;
-}
-
-// ModDown of `batch` polynomials x [E][N] (stride x_bstride) into out [level][N]
-// (stride out_bstride), with the optional additions of launch_moddown_epi.
-int do_moddown(Ctx &c, const uint64_t *x, uint32_t level, uint64_t *out, uint32_t batch, size_t x_bstride,
-               size_t out_bstride, const uint64_t *add, uint32_t add_galois, uint32_t add_mask,
-               size_t add_pstride, hipStream_t s) {
-    const uint32_t N = c.n, K = c.K, L = c.L;
-    std::vector<uint32_t> io, oo, md, ci;
-    for (uint32_t k = 0; k < K; ++k) {
-        io.push_back(level + k);
-        oo.push_back(k);
-        md.push_back(L + k);
-        ci.push_back(k);
-    }
-    HKS_TRY(chunked(io, oo, md, ci, [&](const LimbMap &m) {
-        return launch_ntt_inv(c, m, x, c.ws_p, c.li_moddown, 1, batch, x_bstride, (size_t)K * N, s);
-    }));
-    std::vector<uint32_t> vio, voo, vmd, vci;
-    for (uint32_t i = 0; i < level; ++i) {
-        vio.push_back(i);
-        voo.push_back(i);
-        vmd.push_back(i);
-        vci.push_back(i);
-    }
-    HKS_TRY(chunked(vio, voo, vmd, vci, [&](const LimbMap &m) {
-        return launch_conv_map(c, c.ws_p, K, c.conv_moddown, L, c.ws_z, m, batch, (size_t)K * N,
-                               (size_t)L * N, s);
-    }));
-    HKS_TRY(chunked(vio, voo, vmd, vci, [&](const LimbMap &m) {
-        return launch_ntt_fwd(c, m, c.ws_z, c.ws_z, batch, (size_t)L * N, (size_t)L * N, s);
-    }));
-    HKS_TRY(launch_moddown_epi(c, x, c.ws_z, out, level, add, add_galois, add_mask, batch, x_bstride,
-                               (size_t)L * N, out_bstride, add_pstride, s));
-    return HKS_OK;
-}
+};
 
 uint32_t beta_of(const Ctx &c, uint32_t level) { return (level + c.alpha - 1) / c.alpha; }
 
-// KeySwitch of d (level limbs; gathered through `galois`), results into
-// uv [2][level][N] with the ModDown additions.
+// ModUp up to the column pass of the forward NTT (Algorithm "ModUp"):
+//   iNTT of the level limbs of `a` (gathered through the automorph `galois`),
+//   scaled by N^-1 [(Qt_j/q_i)^-1]_{q_i} -> ws_y (coefficient form);
+//   NewLimb of every digit into every other limb of Q_level U P, fused with
+//   the forward column pass -> col[j][t] (lazy; own-digit slots untouched).
+int do_modup_cols(Ctx &c, const uint64_t *a, uint32_t level, uint32_t galois, uint64_t *col, hipStream_t s) {
+    const uint32_t A = c.alpha, E = level + c.K, beta = beta_of(c, level);
+    Lists inv, cv;
+    for (uint32_t i = 0; i < level; ++i) inv.add(i, i, i, level * c.L + i);
+    HKS_TRY(inv.run([&](const LimbMap &m) {
+        return launch_ntt_inv(c, m, a, c.ws_y, c.li_modup, galois, 1, 0, 0, s);
+    }));
+    for (uint32_t j = 0; j < beta; ++j) {
+        const uint32_t lo = j * A, hi = std::min((j + 1) * A, level);
+        for (uint32_t t = 0; t < E; ++t)
+            if (t < lo || t >= hi) cv.add(lo, j * E + t, ext_mod(c, level, t), j * E + t, hi - lo);
+    }
+    const uint64_t *conv = c.conv_modup + c.conv_modup_off[level];
+    HKS_TRY(cv.run([&](const LimbMap &m) {
+        return launch_conv_cols(c, m, c.ws_y, conv, A, col, 1, 0, 0, s);
+    }));
+    return HKS_OK;
+}
+
+// Finish ModUp into evaluation form: row pass of the converted limbs in place
+// and the digits' own limbs copied (automorph `galois` applied) from `a`.
+int do_modup_finish(Ctx &c, const uint64_t *a, uint32_t level, uint32_t galois, uint64_t *ext, hipStream_t s) {
+    const uint32_t A = c.alpha, E = level + c.K, beta = beta_of(c, level);
+    Lists rows, own;
+    for (uint32_t j = 0; j < beta; ++j) {
+        const uint32_t lo = j * A, hi = std::min((j + 1) * A, level);
+        for (uint32_t t = 0; t < E; ++t) {
+            if (t < lo || t >= hi) rows.add(j * E + t, j * E + t, ext_mod(c, level, t), 0);
+            else own.add(t, j * E + t, t, 0);
+        }
+    }
+    HKS_TRY(rows.run([&](const LimbMap &m) { return launch_ntt_fwd_rows(c, m, ext, ext, 1, 0, 0, s); }));
+    HKS_TRY(own.run([&](const LimbMap &m) { return launch_automorph(c, m, a, ext, galois, 1, 1, 0, 0, s); }));
+    return HKS_OK;
+}
+
+// ModDown of two polynomials after rows_ksk: P limbs (already through the
+// inverse row pass, in ws_p) -> inverse column pass scaled by
+// N^-1 [(P/p_k)^-1]_{p_k}; NewLimb into the q limbs fused with the forward
+// column pass; row pass + (u - z) P^-1 (+ add).  u in uq [2][level][N].
+int do_moddown_tail(Ctx &c, const uint64_t *uq, size_t uq_bstride, uint32_t level, uint64_t *out, uint32_t batch,
+                    size_t out_bstride, const uint64_t *add, uint32_t add_galois, uint32_t add_mask,
+                    size_t add_pstride, hipStream_t s) {
+    const uint32_t N = c.n, K = c.K, L = c.L;
+    Lists pl, ql, rl;
+    for (uint32_t k = 0; k < K; ++k) pl.add(k, k, L + k, k);
+    for (uint32_t i = 0; i < level; ++i) {
+        ql.add(0, i, i, i, K);
+        rl.add(i, i, i, i);
+    }
+    HKS_TRY(pl.run([&](const LimbMap &m) {
+        return launch_ntt_inv_cols(c, m, c.ws_p, c.ws_p, c.li_moddown, batch, (size_t)K * N, (size_t)K * N, s);
+    }));
+    HKS_TRY(ql.run([&](const LimbMap &m) {
+        return launch_conv_cols(c, m, c.ws_p, c.conv_moddown, K, c.ws_z, batch, (size_t)K * N, (size_t)L * N, s);
+    }));
+    HKS_TRY(rl.run([&](const LimbMap &m) {
+        return launch_rows_mdepi(c, m, c.ws_z, out, uq, uq_bstride, add, add_galois, add_mask, add_pstride, batch,
+                                 (size_t)L * N, out_bstride, s);
+    }));
+    return HKS_OK;
+}
+
+// KeySwitch of d (level limbs, gathered through `galois`) into uv [2][level][N]
+// with the ModDown additions: 7 launches, extended digits never stored in
+// evaluation form.
 int do_keyswitch(Ctx &c, const uint64_t *d, uint32_t level, uint32_t galois, const uint64_t *ksk,
                  uint64_t *uv, const uint64_t *add, uint32_t add_galois, uint32_t add_mask,
                  size_t add_pstride, hipStream_t s) {
-    const uint32_t N = c.n, E = level + c.K;
-    int rc = do_modup(c, d, level, galois, c.ws_ext, s);
+    const uint32_t N = c.n;
+    int rc = do_modup_cols(c, d, level, galois, c.ws_ext, s);
     if (rc) return rc;
-    HKS_TRY(launch_ksk(c, c.ws_ext, level, beta_of(c, level), ksk, c.ws_uv, 1, 1, 0, 0, s));
-    return do_moddown(c, c.ws_uv, level, uv, 2, (size_t)E * N, (size_t)level * N, add, add_galois, add_mask,
-                      add_pstride, s);
+    HKS_TRY(launch_rows_ksk(c, c.ws_ext, d, 0, 0, ksk, level, galois, c.ws_uv, c.ws_p, s));
+    return do_moddown_tail(c, c.ws_uv, (size_t)level * N, level, uv, 2, (size_t)level * N, add, add_galois,
+                           add_mask, add_pstride, s);
 }
 
 int do_rescale(Ctx &c, const uint64_t *ct, uint32_t level, uint64_t *out, hipStream_t s) {
     const uint32_t N = c.n;
-    std::vector<uint32_t> io{level - 1}, oo{0}, md{level - 1}, ci{level - 1};
-    HKS_TRY(chunked(io, oo, md, ci, [&](const LimbMap &m) {
+    Lists last, rest;
+    last.add(level - 1, 0, level - 1, level - 1);
+    for (uint32_t i = 0; i + 1 < level; ++i) rest.add(i, i, i, 0);
+    HKS_TRY(last.run([&](const LimbMap &m) {
         return launch_ntt_inv(c, m, ct, c.ws_r, c.li_plain, 1, 2, (size_t)level * N, N, s);
     }));
     HKS_TRY(launch_rescale_prep(c, c.ws_r, c.ws_w, level, 2, N, (size_t)(level - 1) * N, s));
-    std::vector<uint32_t> vio, voo, vmd, vci;
-    for (uint32_t i = 0; i + 1 < level; ++i) {
-        vio.push_back(i);
-        voo.push_back(i);
-        vmd.push_back(i);
-        vci.push_back(0);
-    }
-    HKS_TRY(chunked(vio, voo, vmd, vci, [&](const LimbMap &m) {
+    HKS_TRY(rest.run([&](const LimbMap &m) {
         return launch_ntt_fwd(c, m, c.ws_w, c.ws_w, 2, (size_t)(level - 1) * N, (size_t)(level - 1) * N, s);
     }));
     HKS_TRY(launch_rescale_epi(c, ct, c.ws_w, out, level, 2, (size_t)level * N, (size_t)(level - 1) * N,
@@ -340,15 +326,9 @@ int hks_ntt(hks_ctx *h, uint64_t *x, uint32_t first_mod, uint32_t n_limbs, void 
     GUARD_BEGIN
     if (!h || !x || !aligned(x) || n_limbs == 0 || first_mod + n_limbs > h->c.M) return HKS_EINVAL;
     Ctx &c = h->c;
-    std::vector<uint32_t> io, md, ci;
-    for (uint32_t i = 0; i < n_limbs; ++i) {
-        io.push_back(i);
-        md.push_back(first_mod + i);
-        ci.push_back(0);
-    }
-    return hip_status(chunked(io, io, md, ci, [&](const LimbMap &m) {
-        return launch_ntt_fwd(c, m, x, x, 1, 0, 0, (hipStream_t)stream);
-    }));
+    Lists ls;
+    for (uint32_t i = 0; i < n_limbs; ++i) ls.add(i, i, first_mod + i, first_mod + i);
+    return hip_status(ls.run([&](const LimbMap &m) { return launch_ntt_fwd(c, m, x, x, 1, 0, 0, (hipStream_t)stream); }));
     GUARD_END
 }
 
@@ -356,15 +336,9 @@ int hks_intt(hks_ctx *h, uint64_t *x, uint32_t first_mod, uint32_t n_limbs, void
     GUARD_BEGIN
     if (!h || !x || !aligned(x) || n_limbs == 0 || first_mod + n_limbs > h->c.M) return HKS_EINVAL;
     Ctx &c = h->c;
-    std::vector<uint32_t> io, md, ci;
-    for (uint32_t i = 0; i < n_limbs; ++i) {
-        io.push_back(i);
-        md.push_back(first_mod + i);
-        ci.push_back(first_mod + i);
-    }
-    return hip_status(chunked(io, io, md, ci, [&](const LimbMap &m) {
-        return launch_ntt_inv(c, m, x, x, c.li_plain, 1, 1, 0, 0, (hipStream_t)stream);
-    }));
+    Lists ls;
+    for (uint32_t i = 0; i < n_limbs; ++i) ls.add(i, i, first_mod + i, first_mod + i);
+    return hip_status(ls.run([&](const LimbMap &m) { return launch_ntt_inv(c, m, x, x, c.li_plain, 1, 1, 0, 0, (hipStream_t)stream); }));
     GUARD_END
 }
 
@@ -378,13 +352,9 @@ int hks_automorph(hks_ctx *h, const uint64_t *x, uint64_t *y, uint32_t first_mod
     const uint64_t *xe = x + (size_t)n_limbs * c.n;
     const uint64_t *ye = y + (size_t)n_limbs * c.n;
     if (x < ye && y < xe) return HKS_EINVAL;
-    std::vector<uint32_t> io, md, ci;
-    for (uint32_t i = 0; i < n_limbs; ++i) {
-        io.push_back(i);
-        md.push_back(first_mod + i);
-        ci.push_back(0);
-    }
-    return hip_status(chunked(io, io, md, ci, [&](const LimbMap &m) {
+    Lists ls;
+    for (uint32_t i = 0; i < n_limbs; ++i) ls.add(i, i, first_mod + i, 0);
+    return hip_status(ls.run([&](const LimbMap &m) {
         return launch_automorph(c, m, x, y, galois, eval_domain ? 1 : 0, 1, 0, 0, (hipStream_t)stream);
     }));
     GUARD_END
@@ -393,7 +363,9 @@ int hks_automorph(hks_ctx *h, const uint64_t *x, uint64_t *y, uint32_t first_mod
 int hks_modup(hks_ctx *h, const uint64_t *a, uint32_t level, uint64_t *ext, void *stream) {
     GUARD_BEGIN
     if (!h || !a || !ext || !aligned(a) || !aligned(ext) || level < 1 || level > h->c.L) return HKS_EINVAL;
-    return do_modup(h->c, a, level, 1, ext, (hipStream_t)stream);
+    hipStream_t s = (hipStream_t)stream;
+    int rc = do_modup_cols(h->c, a, level, 1, ext, s);
+    return rc ? rc : do_modup_finish(h->c, a, level, 1, ext, s);
     GUARD_END
 }
 
@@ -412,7 +384,12 @@ int hks_moddown(hks_ctx *h, const uint64_t *x, uint32_t level, uint64_t *y, void
     GUARD_BEGIN
     if (!h || !x || !y || !aligned(x) || !aligned(y) || level < 1 || level > h->c.L) return HKS_EINVAL;
     Ctx &c = h->c;
-    return do_moddown(c, x, level, y, 1, 0, 0, nullptr, 1, 0, 0, (hipStream_t)stream);
+    hipStream_t s = (hipStream_t)stream;
+    // P limbs: inverse row pass into ws_p (the column pass runs in the tail)
+    Lists pl;
+    for (uint32_t k = 0; k < c.K; ++k) pl.add(level + k, k, c.L + k, k);
+    HKS_TRY(pl.run([&](const LimbMap &m) { return launch_ntt_inv_rows(c, m, x, c.ws_p, 1, 0, 0, s); }));
+    return do_moddown_tail(c, x, 0, level, y, 1, 0, nullptr, 1, 0, 0, s);
     GUARD_END
 }
 
@@ -453,12 +430,14 @@ int hks_hrotate(hks_ctx *h, const uint64_t *ct, uint32_t level, uint32_t r, cons
             return HKS_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     const uint32_t N = c.n, E = level + c.K;
-    int rc = do_modup(c, ct, level, 1, c.ws_ext, s);
+    int rc = do_modup_cols(c, ct, level, 1, c.ws_ext, s);
+    if (!rc) rc = do_modup_finish(c, ct, level, 1, c.ws_ext, s);
     if (rc) return rc;
     for (uint32_t i = 0; i < r; ++i) {
-        HKS_TRY(launch_ksk(c, c.ws_ext, level, beta_of(c, level), ksk[i], c.ws_uv, galois[i], 1, 0, 0, s));
-        rc = do_moddown(c, c.ws_uv, level, ct_out[i], 2, (size_t)E * N, (size_t)level * N, ct, galois[i], 2u,
-                        (size_t)level * N, s);
+        HKS_TRY(launch_rows_ksk(c, nullptr, c.ws_ext, (size_t)E * N, 1, ksk[i], level, galois[i], c.ws_uv, c.ws_p,
+                                s));
+        rc = do_moddown_tail(c, c.ws_uv, (size_t)level * N, level, ct_out[i], 2, (size_t)level * N, ct, galois[i],
+                             2u, (size_t)level * N, s);
         if (rc) return rc;
     }
     return HKS_OK;

@@ -22,6 +22,7 @@ struct LimbMap {
     uint16_t in_off[MAXL];
     uint16_t out_off[MAXL];
     uint8_t mod[MAXL];
+    uint8_t nsrc[MAXL];  // conversion: number of source limbs
     uint16_t cidx[MAXL];
 };
 
@@ -55,9 +56,9 @@ struct Ctx {
     LastInv *li_plain = nullptr;  // [M]: scale 1
     LastInv *li_modup = nullptr;  // [L+1][L]: level l, limb i: scale (Qt_j/q_i)^-1 mod q_i
     LastInv *li_moddown = nullptr;  // [K]: scale (P/p_k)^-1 mod p_k
-    uint64_t *conv_modup = nullptr;  // per level: [beta][alpha][l+K] of [Qt_j/q_i]_t
+    uint64_t *conv_modup = nullptr;  // per level: [beta][l+K][alpha] of [Qt_j/q_i]_t (row j*E+t)
     std::vector<size_t> conv_modup_off;  // [L+1]
-    uint64_t *conv_moddown = nullptr;  // [K][L]: [P/p_k]_{q_i}
+    uint64_t *conv_moddown = nullptr;  // [L][K]: [P/p_k]_{q_i} (row i)
     Shoup *pinv = nullptr;             // [L]: P^-1 mod q_i
     Shoup *rs_qinv = nullptr;          // [L+1][L]: q_{l-1}^-1 mod q_i
     uint64_t *rs_h = nullptr;          // [L+1][L]: ((q_{l-1}-1)/2) mod q_i
@@ -113,12 +114,35 @@ hipError_t launch_ntt_fwd(const Ctx &c, const LimbMap &m, const uint64_t *in, ui
 hipError_t launch_ntt_inv(const Ctx &c, const LimbMap &m, const uint64_t *in, uint64_t *out,
                           const LastInv *li, uint32_t galois, uint32_t batch, size_t in_bstride,
                           size_t out_bstride, hipStream_t s);
-// Basis conversion (NewLimb): for output o of `m`, out[out_off[o]] =
-// sum_i in[i] * conv[i * stride + cidx[o]] mod mods[mod[o]]; in holds n_src
-// consecutive canonical limbs.
-hipError_t launch_conv_map(const Ctx &c, const uint64_t *in, uint32_t n_src, const uint64_t *conv,
-                           uint32_t stride, uint64_t *out, const LimbMap &m, uint32_t batch,
-                           size_t in_bstride, size_t out_bstride, hipStream_t s);
+// Forward NTT row pass only (input: column-pass output), canonical output.
+hipError_t launch_ntt_fwd_rows(const Ctx &c, const LimbMap &m, const uint64_t *in, uint64_t *out,
+                               uint32_t batch, size_t in_bstride, size_t out_bstride, hipStream_t s);
+// Inverse NTT row pass only (lazy output in [0, 2q)).
+hipError_t launch_ntt_inv_rows(const Ctx &c, const LimbMap &m, const uint64_t *in, uint64_t *out,
+                               uint32_t batch, size_t in_bstride, size_t out_bstride, hipStream_t s);
+// Inverse NTT column pass only, with the folded last stage li[cidx].
+hipError_t launch_ntt_inv_cols(const Ctx &c, const LimbMap &m, const uint64_t *in, uint64_t *out,
+                               const LastInv *li, uint32_t batch, size_t in_bstride, size_t out_bstride,
+                               hipStream_t s);
+// NewLimb fused into the forward column pass: output limb o (out_off[o]) =
+// column pass of sum_{i < nsrc[o]} y[in_off[o] + i] * conv[cidx[o]*cstride + i]
+// mod mods[mod[o]].  Lazy output (input of launch_rows_ksk / launch_rows_mdepi).
+hipError_t launch_conv_cols(const Ctx &c, const LimbMap &m, const uint64_t *y, const uint64_t *conv,
+                            uint32_t cstride, uint64_t *out, uint32_t batch, size_t in_bstride,
+                            size_t out_bstride, hipStream_t s);
+// Forward row pass of the ModDown correction z followed by
+// out = (u - z) * P^-1 (+ add gathered by add_galois for polys in add_mask);
+// u limb cidx[o] at uq + b*uq_bstride.
+hipError_t launch_rows_mdepi(const Ctx &c, const LimbMap &m, const uint64_t *zc, uint64_t *out,
+                             const uint64_t *uq, size_t uq_bstride, const uint64_t *add, uint32_t add_galois,
+                             uint32_t add_mask, size_t add_pstride, uint32_t batch, size_t in_bstride,
+                             size_t out_bstride, hipStream_t s);
+// Row pass of every converted digit limb + KSKInnerProd (+ ModDown inverse row
+// pass for the P limbs).  Digit j's own limb t is read in evaluation form at
+// direct + j*dstride + t*N, gathered by `galois`; all digits if all_direct.
+hipError_t launch_rows_ksk(const Ctx &c, const uint64_t *colout, const uint64_t *direct, size_t dstride,
+                           uint32_t all_direct, const uint64_t *ksk, uint32_t level, uint32_t galois,
+                           uint64_t *uq, uint64_t *pc, hipStream_t s);
 // Eval-domain automorph (gather) of limbs; or coefficient-domain map with negation.
 hipError_t launch_automorph(const Ctx &c, const LimbMap &m, const uint64_t *in, uint64_t *out,
                             uint32_t galois, int eval_domain, uint32_t batch, size_t in_bstride,
@@ -127,13 +151,6 @@ hipError_t launch_automorph(const Ctx &c, const LimbMap &m, const uint64_t *in, 
 hipError_t launch_ksk(const Ctx &c, const uint64_t *ext, uint32_t level, uint32_t beta,
                       const uint64_t *ksk, uint64_t *uv, uint32_t galois, uint32_t batch,
                       size_t ext_bstride, size_t uv_bstride, hipStream_t s);
-// ModDown final step over `batch` polynomials p: out_p,i = (x_p,i - z_p,i) * P^-1,
-// plus add[p * add_pstride][i][slot gathered by add_galois] when bit p of
-// add_mask is set (Rotate adds b_rot to v; Mult adds (b3, c3)).
-hipError_t launch_moddown_epi(const Ctx &c, const uint64_t *x, const uint64_t *z, uint64_t *out,
-                              uint32_t level, const uint64_t *add, uint32_t add_galois,
-                              uint32_t add_mask, uint32_t batch, size_t x_bstride, size_t z_bstride,
-                              size_t out_bstride, size_t add_pstride, hipStream_t s);
 // Elementwise: out[l] = x[l] * y[l] mod q_l (pt mult) for n_poly polys of level limbs.
 hipError_t launch_mulpt(const Ctx &c, const uint64_t *ct, const uint64_t *pt, uint64_t *out,
                         uint32_t level, uint32_t n_poly, hipStream_t s);

@@ -57,7 +57,7 @@ struct Acc128 {
     __device__ __forceinline__ uint64_t reduce(uint64_t q, uint64_t mu) const { return reduce128(hi, lo, q, mu); }
 };
 
-// Generic x * y mod q for two variables (< 2^52 each): 128-bit product then Barrett.
+// Generic x * y mod q for two variables (x * y < 2^111): 128-bit product then Barrett.
 __device__ __forceinline__ uint64_t mul_mod(uint64_t x, uint64_t y, uint64_t q, uint64_t mu) {
     u128 p = (u128)x * y;
     return reduce128((uint64_t)(p >> 64), (uint64_t)p, q, mu);

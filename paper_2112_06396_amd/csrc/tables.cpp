@@ -144,7 +144,7 @@ int build_tables(Ctx &c) {
                     uint64_t v = 1;
                     for (uint32_t k = lo; k < hi; ++k)
                         if (k != i) v = h_mulmod(v, c.mods[k] % mt, mt);
-                    tab[((size_t)j * A + (i - lo)) * E + t] = v;
+                    tab[((size_t)j * E + t) * A + (i - lo)] = v;
                 }
             }
         }
@@ -163,7 +163,7 @@ int build_tables(Ctx &c) {
             uint64_t qi = c.mods[i], v = 1;
             for (uint32_t kk = 0; kk < K; ++kk)
                 if (kk != k) v = h_mulmod(v, c.mods[L + kk] % qi, qi);
-            convd[(size_t)k * L + i] = v;
+            convd[(size_t)i * K + k] = v;
         }
     }
     for (uint32_t i = 0; i < L; ++i) {

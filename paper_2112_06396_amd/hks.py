@@ -17,7 +17,8 @@ import os
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libhks.so")
+# HKS_LIBRARY may name another build of the same library (e.g. an A/B variant)
+LIB_PATH = os.environ.get("HKS_LIBRARY") or os.path.join(_HERE, "libhks.so")
 
 HKS_OK = 0
 HKS_EINVAL = -1
