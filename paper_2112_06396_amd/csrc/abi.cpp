@@ -68,68 +68,59 @@ struct Lists {
 
 uint32_t beta_of(const Ctx &c, uint32_t level) { return (level + c.alpha - 1) / c.alpha; }
 
-// ModUp up to the column pass of the forward NTT (Algorithm "ModUp"):
+// ModUp of the converted limbs (Algorithm "ModUp"):
 //   iNTT of the level limbs of `a` (gathered through the automorph `galois`),
 //   scaled by N^-1 [(Qt_j/q_i)^-1]_{q_i} -> ws_y (coefficient form);
-//   NewLimb of every digit into every other limb of Q_level U P, fused with
-//   the forward column pass -> col[j][t] (lazy; own-digit slots untouched).
-int do_modup_cols(Ctx &c, const uint64_t *a, uint32_t level, uint32_t galois, uint64_t *col, hipStream_t s) {
+//   NewLimb of every digit into every other limb of Q_level U P -> ext[j][t];
+//   forward NTT of those limbs in place (own-digit slots untouched).
+int do_modup_new(Ctx &c, const uint64_t *a, uint32_t level, uint32_t galois, uint64_t *ext, hipStream_t s) {
     const uint32_t A = c.alpha, E = level + c.K, beta = beta_of(c, level);
-    Lists inv, cv;
+    Lists inv, nl;
     for (uint32_t i = 0; i < level; ++i) inv.add(i, i, i, level * c.L + i);
     HKS_TRY(inv.run([&](const LimbMap &m) {
         return launch_ntt_inv(c, m, a, c.ws_y, c.li_modup, galois, 1, 0, 0, s);
     }));
+    HKS_TRY(launch_conv_modup(c, c.ws_y, level, ext, s));
     for (uint32_t j = 0; j < beta; ++j) {
         const uint32_t lo = j * A, hi = std::min((j + 1) * A, level);
         for (uint32_t t = 0; t < E; ++t)
-            if (t < lo || t >= hi) cv.add(lo, j * E + t, ext_mod(c, level, t), j * E + t, hi - lo);
+            if (t < lo || t >= hi) nl.add(j * E + t, j * E + t, ext_mod(c, level, t), 0);
     }
-    const uint64_t *conv = c.conv_modup + c.conv_modup_off[level];
-    HKS_TRY(cv.run([&](const LimbMap &m) {
-        return launch_conv_cols(c, m, c.ws_y, conv, A, col, 1, 0, 0, s);
-    }));
+    HKS_TRY(nl.run([&](const LimbMap &m) { return launch_ntt_fwd(c, m, ext, ext, 1, 0, 0, s); }));
     return HKS_OK;
 }
 
-// Finish ModUp into evaluation form: row pass of the converted limbs in place
-// and the digits' own limbs copied (automorph `galois` applied) from `a`.
-int do_modup_finish(Ctx &c, const uint64_t *a, uint32_t level, uint32_t galois, uint64_t *ext, hipStream_t s) {
+// The digits' own limbs of ext, copied (automorph `galois` applied) from `a`.
+int do_modup_own(Ctx &c, const uint64_t *a, uint32_t level, uint32_t galois, uint64_t *ext, hipStream_t s) {
     const uint32_t A = c.alpha, E = level + c.K, beta = beta_of(c, level);
-    Lists rows, own;
+    Lists own;
     for (uint32_t j = 0; j < beta; ++j) {
         const uint32_t lo = j * A, hi = std::min((j + 1) * A, level);
-        for (uint32_t t = 0; t < E; ++t) {
-            if (t < lo || t >= hi) rows.add(j * E + t, j * E + t, ext_mod(c, level, t), 0);
-            else own.add(t, j * E + t, t, 0);
-        }
+        for (uint32_t t = lo; t < hi; ++t) own.add(t, j * E + t, t, 0);
     }
-    HKS_TRY(rows.run([&](const LimbMap &m) { return launch_ntt_fwd_rows(c, m, ext, ext, 1, 0, 0, s); }));
     HKS_TRY(own.run([&](const LimbMap &m) { return launch_automorph(c, m, a, ext, galois, 1, 1, 0, 0, s); }));
     return HKS_OK;
 }
 
-// ModDown of two polynomials after rows_ksk: P limbs (already through the
-// inverse row pass, in ws_p) -> inverse column pass scaled by
-// N^-1 [(P/p_k)^-1]_{p_k}; NewLimb into the q limbs fused with the forward
-// column pass; row pass + (u - z) P^-1 (+ add).  u in uq [2][level][N].
+// ModDown of `batch` polynomials after ksk_rows: P limbs (already through
+// the inverse row pass, in ws_p) -> inverse column pass scaled by
+// N^-1 [(P/p_k)^-1]_{p_k}; NewLimb into the q limbs; forward column pass;
+// row pass + (u - z) P^-1 (+ add).  u in uq [batch][level][N].
 int do_moddown_tail(Ctx &c, const uint64_t *uq, size_t uq_bstride, uint32_t level, uint64_t *out, uint32_t batch,
                     size_t out_bstride, const uint64_t *add, uint32_t add_galois, uint32_t add_mask,
                     size_t add_pstride, hipStream_t s) {
     const uint32_t N = c.n, K = c.K, L = c.L;
-    Lists pl, ql, rl;
+    Lists pl, ql;
     for (uint32_t k = 0; k < K; ++k) pl.add(k, k, L + k, k);
-    for (uint32_t i = 0; i < level; ++i) {
-        ql.add(0, i, i, i, K);
-        rl.add(i, i, i, i);
-    }
+    for (uint32_t i = 0; i < level; ++i) ql.add(i, i, i, i);
     HKS_TRY(pl.run([&](const LimbMap &m) {
         return launch_ntt_inv_cols(c, m, c.ws_p, c.ws_p, c.li_moddown, batch, (size_t)K * N, (size_t)K * N, s);
     }));
+    HKS_TRY(launch_conv_moddown(c, c.ws_p, level, c.ws_z, batch, (size_t)K * N, (size_t)L * N, s));
     HKS_TRY(ql.run([&](const LimbMap &m) {
-        return launch_conv_cols(c, m, c.ws_p, c.conv_moddown, K, c.ws_z, batch, (size_t)K * N, (size_t)L * N, s);
+        return launch_ntt_fwd_cols(c, m, c.ws_z, c.ws_z, batch, (size_t)L * N, (size_t)L * N, s);
     }));
-    HKS_TRY(rl.run([&](const LimbMap &m) {
+    HKS_TRY(ql.run([&](const LimbMap &m) {
         return launch_rows_mdepi(c, m, c.ws_z, out, uq, uq_bstride, add, add_galois, add_mask, add_pstride, batch,
                                  (size_t)L * N, out_bstride, s);
     }));
@@ -137,15 +128,15 @@ int do_moddown_tail(Ctx &c, const uint64_t *uq, size_t uq_bstride, uint32_t leve
 }
 
 // KeySwitch of d (level limbs, gathered through `galois`) into uv [2][level][N]
-// with the ModDown additions: 7 launches, extended digits never stored in
-// evaluation form.
+// with the ModDown additions (10 launches); the digits' own limbs are read
+// from d in the KSKInnerProd kernel (never copied).
 int do_keyswitch(Ctx &c, const uint64_t *d, uint32_t level, uint32_t galois, const uint64_t *ksk,
                  uint64_t *uv, const uint64_t *add, uint32_t add_galois, uint32_t add_mask,
                  size_t add_pstride, hipStream_t s) {
     const uint32_t N = c.n;
-    int rc = do_modup_cols(c, d, level, galois, c.ws_ext, s);
+    int rc = do_modup_new(c, d, level, galois, c.ws_ext, s);
     if (rc) return rc;
-    HKS_TRY(launch_rows_ksk(c, c.ws_ext, d, 0, 0, ksk, level, galois, c.ws_uv, c.ws_p, s));
+    HKS_TRY(launch_ksk_rows(c, c.ws_ext, d, 0, 0, ksk, level, galois, c.ws_uv, c.ws_p, s));
     return do_moddown_tail(c, c.ws_uv, (size_t)level * N, level, uv, 2, (size_t)level * N, add, add_galois,
                            add_mask, add_pstride, s);
 }
@@ -364,8 +355,8 @@ int hks_modup(hks_ctx *h, const uint64_t *a, uint32_t level, uint64_t *ext, void
     GUARD_BEGIN
     if (!h || !a || !ext || !aligned(a) || !aligned(ext) || level < 1 || level > h->c.L) return HKS_EINVAL;
     hipStream_t s = (hipStream_t)stream;
-    int rc = do_modup_cols(h->c, a, level, 1, ext, s);
-    return rc ? rc : do_modup_finish(h->c, a, level, 1, ext, s);
+    int rc = do_modup_new(h->c, a, level, 1, ext, s);
+    return rc ? rc : do_modup_own(h->c, a, level, 1, ext, s);
     GUARD_END
 }
 
@@ -430,11 +421,11 @@ int hks_hrotate(hks_ctx *h, const uint64_t *ct, uint32_t level, uint32_t r, cons
             return HKS_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     const uint32_t N = c.n, E = level + c.K;
-    int rc = do_modup_cols(c, ct, level, 1, c.ws_ext, s);
-    if (!rc) rc = do_modup_finish(c, ct, level, 1, c.ws_ext, s);
+    int rc = do_modup_new(c, ct, level, 1, c.ws_ext, s);
+    if (!rc) rc = do_modup_own(c, ct, level, 1, c.ws_ext, s);
     if (rc) return rc;
     for (uint32_t i = 0; i < r; ++i) {
-        HKS_TRY(launch_rows_ksk(c, nullptr, c.ws_ext, (size_t)E * N, 1, ksk[i], level, galois[i], c.ws_uv, c.ws_p,
+        HKS_TRY(launch_ksk_rows(c, c.ws_ext, c.ws_ext, (size_t)E * N, 1, ksk[i], level, galois[i], c.ws_uv, c.ws_p,
                                 s));
         rc = do_moddown_tail(c, c.ws_uv, (size_t)level * N, level, ct_out[i], 2, (size_t)level * N, ct, galois[i],
                              2u, (size_t)level * N, s);

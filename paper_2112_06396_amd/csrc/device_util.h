@@ -46,4 +46,34 @@ struct MacAcc {
     }
 };
 
+// Sum of products y_i * k_i of canonical 50-bit residues with y and k split
+// into 25-bit halves: each product adds y0 k0, y0 k1 + y1 k0 and y1 k1 to
+// three 64-bit sums (one v_mad_u64_u32 each, no carries for up to 16 terms:
+// every partial product is < 2^50).  k comes pre-split as k0 | (k1 << 32).
+struct Mac25 {
+    uint64_t a0, a1, a2;
+    __device__ __forceinline__ Mac25() : a0(0), a1(0), a2(0) {}
+    __device__ __forceinline__ void mac(uint32_t y0, uint32_t y1, uint64_t ksplit) {
+        const uint32_t k0 = (uint32_t)ksplit, k1 = (uint32_t)(ksplit >> 32);
+        a0 += (uint64_t)y0 * k0;
+        a1 += (uint64_t)y0 * k1;
+        a1 += (uint64_t)y1 * k0;
+        a2 += (uint64_t)y1 * k1;
+    }
+    // a0 + a1 2^25 + a2 2^50 (< 2^105) reduced modulo q (mu = floor(2^112 / q))
+    __device__ __forceinline__ uint64_t reduce(uint64_t q, uint64_t mu) const {
+        const uint64_t l1 = a1 << 25, l2 = a2 << 50;
+        uint64_t lo = a0 + l1;
+        uint64_t hi = (a1 >> 39) + (a2 >> 14) + ((lo < l1) ? 1u : 0u);
+        const uint64_t lo2 = lo + l2;
+        hi += (lo2 < l2) ? 1u : 0u;
+        return reduce128(hi, lo2, q, mu);
+    }
+};
+
+__device__ __forceinline__ void split25(uint64_t y, uint32_t &y0, uint32_t &y1) {
+    y0 = (uint32_t)y & 0x1FFFFFFu;
+    y1 = (uint32_t)(y >> 25);
+}
+
 }  // namespace hks

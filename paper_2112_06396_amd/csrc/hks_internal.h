@@ -56,9 +56,9 @@ struct Ctx {
     LastInv *li_plain = nullptr;  // [M]: scale 1
     LastInv *li_modup = nullptr;  // [L+1][L]: level l, limb i: scale (Qt_j/q_i)^-1 mod q_i
     LastInv *li_moddown = nullptr;  // [K]: scale (P/p_k)^-1 mod p_k
-    uint64_t *conv_modup = nullptr;  // per level: [beta][l+K][alpha] of [Qt_j/q_i]_t (row j*E+t)
+    uint64_t *conv_modup = nullptr;  // per level: [beta][l+K][alpha] of [Qt_j/q_i]_t (row j*E+t), split 25/25
     std::vector<size_t> conv_modup_off;  // [L+1]
-    uint64_t *conv_moddown = nullptr;  // [L][K]: [P/p_k]_{q_i} (row i)
+    uint64_t *conv_moddown = nullptr;  // [L][K]: [P/p_k]_{q_i} (row i), split 25/25
     Shoup *pinv = nullptr;             // [L]: P^-1 mod q_i
     Shoup *rs_qinv = nullptr;          // [L+1][L]: q_{l-1}^-1 mod q_i
     uint64_t *rs_h = nullptr;          // [L+1][L]: ((q_{l-1}-1)/2) mod q_i
@@ -124,12 +124,17 @@ hipError_t launch_ntt_inv_rows(const Ctx &c, const LimbMap &m, const uint64_t *i
 hipError_t launch_ntt_inv_cols(const Ctx &c, const LimbMap &m, const uint64_t *in, uint64_t *out,
                                const LastInv *li, uint32_t batch, size_t in_bstride, size_t out_bstride,
                                hipStream_t s);
-// NewLimb fused into the forward column pass: output limb o (out_off[o]) =
-// column pass of sum_{i < nsrc[o]} y[in_off[o] + i] * conv[cidx[o]*cstride + i]
-// mod mods[mod[o]].  Lazy output (input of launch_rows_ksk / launch_rows_mdepi).
-hipError_t launch_conv_cols(const Ctx &c, const LimbMap &m, const uint64_t *y, const uint64_t *conv,
-                            uint32_t cstride, uint64_t *out, uint32_t batch, size_t in_bstride,
-                            size_t out_bstride, hipStream_t s);
+// Forward NTT column pass only (lazy output for a row pass).
+hipError_t launch_ntt_fwd_cols(const Ctx &c, const LimbMap &m, const uint64_t *in, uint64_t *out,
+                               uint32_t batch, size_t in_bstride, size_t out_bstride, hipStream_t s);
+// NewLimb of every digit of the coefficient-form y [level][N] into the other
+// limbs of Q_level U P: ext[j][t] (coefficient form, canonical) for t outside
+// digit j.
+hipError_t launch_conv_modup(const Ctx &c, const uint64_t *y, uint32_t level, uint64_t *ext, hipStream_t s);
+// NewLimb of ModDown: the K coefficient-form P limbs p [K][N] (scaled by
+// [(P/p_k)^-1]) into the level q limbs z [level][N], for `batch` polynomials.
+hipError_t launch_conv_moddown(const Ctx &c, const uint64_t *p, uint32_t level, uint64_t *z, uint32_t batch,
+                               size_t p_bstride, size_t z_bstride, hipStream_t s);
 // Forward row pass of the ModDown correction z followed by
 // out = (u - z) * P^-1 (+ add gathered by add_galois for polys in add_mask);
 // u limb cidx[o] at uq + b*uq_bstride.
@@ -137,10 +142,12 @@ hipError_t launch_rows_mdepi(const Ctx &c, const LimbMap &m, const uint64_t *zc,
                              const uint64_t *uq, size_t uq_bstride, const uint64_t *add, uint32_t add_galois,
                              uint32_t add_mask, size_t add_pstride, uint32_t batch, size_t in_bstride,
                              size_t out_bstride, hipStream_t s);
-// Row pass of every converted digit limb + KSKInnerProd (+ ModDown inverse row
-// pass for the P limbs).  Digit j's own limb t is read in evaluation form at
-// direct + j*dstride + t*N, gathered by `galois`; all digits if all_direct.
-hipError_t launch_rows_ksk(const Ctx &c, const uint64_t *colout, const uint64_t *direct, size_t dstride,
+// KSKInnerProd per target limb and row tile (+ ModDown's inverse row pass for
+// the P limbs, into pc [2][K][N]); q limbs into uq [2][level][N].  Converted
+// limb t of digit j is read in evaluation form at ext + (j*E + t)*N; digit j's
+// own limb (all digits if all_direct) at direct + j*dstride + t*N, gathered
+// through `galois`.
+hipError_t launch_ksk_rows(const Ctx &c, const uint64_t *ext, const uint64_t *direct, size_t dstride,
                            uint32_t all_direct, const uint64_t *ksk, uint32_t level, uint32_t galois,
                            uint64_t *uq, uint64_t *pc, hipStream_t s);
 // Eval-domain automorph (gather) of limbs; or coefficient-domain map with negation.

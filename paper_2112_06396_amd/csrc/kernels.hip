@@ -47,6 +47,113 @@ void prof_reset(const Ctx &c) {
     }
 }
 
+// ------------------------------------------------------------------ NewLimb (basis conversion)
+
+struct ConvArgs {
+    const uint64_t *in;    // coefficient-form source limbs
+    uint64_t *out;
+    const uint64_t *conv;  // split constants
+    const ModC *mc;
+    size_t in_bstride, out_bstride;
+    uint32_t n, level, L, K, alpha;
+};
+
+// Fast basis conversion (NewLimb, Algorithm "ModUp"; also ModDown's step).
+// One thread = one coefficient of one digit: its n_src source residues are
+// loaded once (split into 25-bit halves) and every target limb of the digit
+// is produced from them (the alpha limbs stay on chip for all new limbs).
+//   MODUP:   digit j = blockIdx.y, sources y[j*alpha .. +n_src), targets t of
+//            Q_level U P outside the digit, out[j*E + t], constants row j*E+t;
+//   ModDown: sources the K P limbs, targets the level q limbs, out[t],
+//            constants row t.
+template <bool MODUP, int MAXS>
+__global__ void __launch_bounds__(256) conv_kernel(const ConvArgs a) {
+    constexpr int MAXT = 80;  // targets of one digit: level + K <= 64
+    __shared__ uint64_t kc[MAXT * MAXS];
+    __shared__ ModC mt[MAXT];
+    const uint32_t N = 1u << a.n;
+    const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t j = blockIdx.y, b = blockIdx.z;
+    const uint32_t lo = MODUP ? j * a.alpha : 0;
+    const uint32_t ns = MODUP ? min(a.alpha, a.level - lo) : a.K;
+    const uint32_t E = a.level + a.K;
+    const uint32_t nt = MODUP ? E : a.level;
+    const uint32_t cstride = MODUP ? a.alpha : a.K;
+    // the digit's constant rows and target moduli, staged once per block
+    const uint64_t *rows = a.conv + (size_t)(MODUP ? j * E : 0) * cstride;
+    for (uint32_t i = threadIdx.x; i < nt * MAXS; i += blockDim.x) {
+        const uint32_t t = i / MAXS, s = i % MAXS;
+        kc[i] = (s < ns) ? rows[(size_t)t * cstride + s] : 0;
+    }
+    for (uint32_t t = threadIdx.x; t < nt; t += blockDim.x) {
+        const uint32_t mod = MODUP ? (t < a.level ? t : a.L + (t - a.level)) : t;
+        mt[t] = a.mc[mod];
+    }
+    const uint64_t *src = a.in + b * a.in_bstride + (size_t)lo * N + c;
+    uint32_t y0[MAXS], y1[MAXS];
+#pragma unroll
+    for (int i = 0; i < MAXS; ++i) {
+        const uint64_t y = (i < (int)ns) ? src[(size_t)i * N] : 0;
+        split25(y, y0[i], y1[i]);
+    }
+    __syncthreads();
+    uint64_t *dst = a.out + b * a.out_bstride + c;
+#pragma unroll 2
+    for (uint32_t t = 0; t < nt; ++t) {
+        if (MODUP && t >= lo && t < lo + ns) continue;
+        const ModC m = mt[t];
+        const uint64_t *kr = kc + t * MAXS;
+        Mac25 acc;
+#pragma unroll
+        for (int i = 0; i < MAXS; ++i) acc.mac(y0[i], y1[i], kr[i]);
+        dst[(size_t)(MODUP ? j * E + t : t) * N] = acc.reduce(m.q, m.mu);
+    }
+}
+
+template <bool MODUP>
+static hipError_t launch_conv_t(const ConvArgs &a, uint32_t ns_max, dim3 grid, hipStream_t s) {
+    if (ns_max <= 4) hipLaunchKernelGGL((conv_kernel<MODUP, 4>), grid, dim3(256), 0, s, a);
+    else if (ns_max <= 8) hipLaunchKernelGGL((conv_kernel<MODUP, 8>), grid, dim3(256), 0, s, a);
+    else if (ns_max <= 12) hipLaunchKernelGGL((conv_kernel<MODUP, 12>), grid, dim3(256), 0, s, a);
+    else if (ns_max <= 16) hipLaunchKernelGGL((conv_kernel<MODUP, 16>), grid, dim3(256), 0, s, a);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_conv_modup(const Ctx &c, const uint64_t *y, uint32_t level, uint64_t *ext, hipStream_t s) {
+    ConvArgs a{};
+    a.in = y;
+    a.out = ext;
+    a.conv = c.conv_modup + c.conv_modup_off[level];
+    a.mc = c.mc;
+    a.n = c.log_n;
+    a.level = level;
+    a.L = c.L;
+    a.K = c.K;
+    a.alpha = c.alpha;
+    const uint32_t beta = (level + c.alpha - 1) / c.alpha;
+    ProfScope ps(c, HKS_K_CONV, s);
+    return launch_conv_t<true>(a, c.alpha, dim3((c.n + 255) / 256, beta, 1), s);
+}
+
+hipError_t launch_conv_moddown(const Ctx &c, const uint64_t *p, uint32_t level, uint64_t *z, uint32_t batch,
+                               size_t p_bstride, size_t z_bstride, hipStream_t s) {
+    ConvArgs a{};
+    a.in = p;
+    a.out = z;
+    a.conv = c.conv_moddown;
+    a.mc = c.mc;
+    a.in_bstride = p_bstride;
+    a.out_bstride = z_bstride;
+    a.n = c.log_n;
+    a.level = level;
+    a.L = c.L;
+    a.K = c.K;
+    a.alpha = c.alpha;
+    ProfScope ps(c, HKS_K_CONV, s);
+    return launch_conv_t<false>(a, c.K, dim3((c.n + 255) / 256, 1, batch), s);
+}
+
 // ------------------------------------------------------------------ automorph
 
 struct AutArgs {

@@ -19,14 +19,9 @@
 // inverse values stay in [0, 2q).
 //
 // Fusions (cache-oriented ideas of the paper, Sec. 4, recast for LDS):
-//   IO_CONV   column pass whose load computes NewLimb (the basis conversion
-//             of ModUp / ModDown) from the digit's coefficient-form limbs, so
-//             the converted limb is produced on chip and goes straight into
-//             its NTT (alpha-limb caching);
-//   rows_ksk  row pass of every digit of one target limb followed by
-//             KSKInnerProd against the key, so extended digits never reach
-//             HBM in evaluation form; for the special-prime limbs it then
-//             runs the inverse row pass of ModDown (P limbs first);
+//   ksk_rows  KSKInnerProd streamed per target limb and row tile; for the
+//             special-prime limbs it goes on with the inverse row pass of
+//             ModDown on chip (P limbs first);
 //   IO_MDEPI  row pass of the ModDown correction followed by
 //             (u - z) * P^-1 (+ the automorphed b of Rotate).
 #include <hip/hip_runtime.h>
@@ -51,29 +46,41 @@ struct Tile {
     }
 };
 
-// One phase over bits [LO, HI) of the sub-index k.  Twiddle of the butterfly
-// on bit `bit` for lower element k:
+// Phases of a pass over the LOGS bits of the sub-index k: P0 = [LOGS-4, LOGS),
+// P1 = [max(LOGS-8, 0), LOGS-4), P2 = [0, LOGS-8) when LOGS > 8.  The forward
+// pass runs P0, P1, P2 (high bits first); the inverse runs them in reverse.
+template <int LOGS>
+struct Phases {
+    static constexpr int P0L = LOGS - 4, P0H = LOGS;
+    static constexpr int P1L = (LOGS - 8) > 0 ? (LOGS - 8) : 0, P1H = LOGS - 4;
+    static constexpr int P2L = 0, P2H = (LOGS - 8) > 0 ? (LOGS - 8) : 0;
+    static constexpr bool THREE = LOGS > 8;
+};
+
+// Element e (0..15) of thread t in the layout of phase [LO, HI): the thread
+// holds every value of bits [LO, HI) of k for 16 >> (HI-LO) values of the
+// other bits.  [LOGS-4, LOGS) gives k = e*T + t (consecutive threads on
+// consecutive k); [0, b) gives k = 16t + e (each thread a contiguous run).
+template <int LO, int HI>
+__device__ __forceinline__ int k_of(int t, int e) {
+    constexpr int B = HI - LO, G = 16 >> B;
+    const int v = e & ((1 << B) - 1), g = e >> B;
+    const int r = t * G + g;
+    return ((r >> LO) << HI) | (v << LO) | (r & ((1 << LO) - 1));
+}
+
+// The butterflies of one phase on the thread's 16 registers (layout [LO, HI)).
+// Twiddle of the butterfly on bit `bit` for lower element k:
 //   column pass: index 2^s + (k >> (bit+1)),           s = LOGS-1-bit;
 //   row pass:    index 2^s + (r << (LOGS-1-bit)) + (k >> (bit+1)),
 //                s = n1 + LOGS-1-bit, r the row.
 // Elements whose k agree above `bit` share the twiddle, so each stage loads
-// 16 >> (vb+1) twiddles per thread.
-template <int LOGS, int LINES, bool COLS, bool FWD, int LO, int HI>
-__device__ __forceinline__ void ntt_phase(uint64_t *lds, int line, int t, uint32_t row, uint32_t n1, uint64_t q,
-                                          const Shoup *__restrict__ tw, const LastInv &fold) {
-    using TL = Tile<LOGS, LINES, COLS>;
+// 16 >> (vb+1) twiddles.  The global stage 0 of the inverse (only in the
+// column pass) multiplies by the folded constants instead.
+template <int LOGS, bool COLS, bool FWD, int LO, int HI>
+__device__ __forceinline__ void phase_regs(uint64_t (&x)[16], int t, uint32_t row, uint32_t n1, uint64_t q,
+                                           const Shoup *__restrict__ tw, const LastInv &fold) {
     constexpr int B = HI - LO;
-    constexpr int G = 16 >> B;
-    uint64_t x[16];
-    int kk[16];
-#pragma unroll
-    for (int e = 0; e < 16; ++e) {
-        int v = e & ((1 << B) - 1), g = e >> B;
-        int r = t * G + g;
-        int k = ((r >> LO) << HI) | (v << LO) | (r & ((1 << LO) - 1));
-        kk[e] = k;
-        x[e] = lds[TL::idx(line, k)];
-    }
     const uint64_t q2 = 2 * q;
 #pragma unroll
     for (int st = 0; st < B; ++st) {
@@ -86,9 +93,8 @@ __device__ __forceinline__ void ntt_phase(uint64_t *lds, int line, int t, uint32
 #pragma unroll
         for (int key = 0; key < 8; ++key) {
             if (key < (16 >> (vb + 1)) && !fold_stage) {
-                const uint32_t k = (uint32_t)kk[key << (vb + 1)];
-                const uint32_t ix = COLS ? (sbase + (k >> (bit + 1)))
-                                         : (sbase + (row << ls) + (k >> (bit + 1)));
+                const uint32_t k = (uint32_t)k_of<LO, HI>(t, key << (vb + 1));
+                const uint32_t ix = COLS ? (sbase + (k >> (bit + 1))) : (sbase + (row << ls) + (k >> (bit + 1)));
                 wc[key] = tw[ix];
             }
         }
@@ -114,67 +120,122 @@ __device__ __forceinline__ void ntt_phase(uint64_t *lds, int line, int t, uint32
             }
         }
     }
+}
+
+template <int LOGS, int LINES, bool COLS, int LO, int HI>
+__device__ __forceinline__ void lds_put(uint64_t *lds, const uint64_t (&x)[16], int line, int t) {
+    using TL = Tile<LOGS, LINES, COLS>;
 #pragma unroll
-    for (int e = 0; e < 16; ++e) lds[TL::idx(line, kk[e])] = x[e];
+    for (int e = 0; e < 16; ++e) lds[TL::idx(line, k_of<LO, HI>(t, e))] = x[e];
 }
 
-// All phases of one pass on the LDS tile (caller synchronizes before/after).
+template <int LOGS, int LINES, bool COLS, int LO, int HI>
+__device__ __forceinline__ void lds_get(const uint64_t *lds, uint64_t (&x)[16], int line, int t) {
+    using TL = Tile<LOGS, LINES, COLS>;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) x[e] = lds[TL::idx(line, k_of<LO, HI>(t, e))];
+}
+
+// A whole pass on registers.  On entry x is in the first phase's layout
+// (forward: P0, inverse: P2 or P1), on exit in the last one's (forward: P1 or
+// P2, inverse: P0).  The LDS tile carries the exchanges between phases; the
+// caller synchronizes before this tile is written again.  Work is done only
+// where `active` holds, but every thread reaches every barrier.
 template <int LOGS, int LINES, bool COLS, bool FWD>
-__device__ __forceinline__ void ntt_tile(uint64_t *lds, int line, int t, uint32_t row, uint32_t n1, uint64_t q,
-                                         const Shoup *__restrict__ tw, const LastInv &fold) {
-    constexpr int P0L = LOGS - 4;
-    constexpr int P1H = P0L, P1L = (P0L - 4) > 0 ? (P0L - 4) : 0;
-    constexpr int P2H = P1L, P2L = 0;
-    static_assert(LOGS >= 5 && LOGS <= 12, "sub-transform size");
+__device__ __forceinline__ void pass_regs(bool active, uint64_t (&x)[16], uint64_t *lds, int line, int t,
+                                          uint32_t row, uint32_t n1, uint64_t q, const Shoup *__restrict__ tw,
+                                          const LastInv &fold) {
+    using P = Phases<LOGS>;
     if (FWD) {
-        ntt_phase<LOGS, LINES, COLS, true, P0L, LOGS>(lds, line, t, row, n1, q, tw, fold);
+        if (active) {
+            phase_regs<LOGS, COLS, true, P::P0L, P::P0H>(x, t, row, n1, q, tw, fold);
+            lds_put<LOGS, LINES, COLS, P::P0L, P::P0H>(lds, x, line, t);
+        }
         __syncthreads();
-        ntt_phase<LOGS, LINES, COLS, true, P1L, P1H>(lds, line, t, row, n1, q, tw, fold);
-        if constexpr (P2H > P2L) {
+        if (active) {
+            lds_get<LOGS, LINES, COLS, P::P1L, P::P1H>(lds, x, line, t);
+            phase_regs<LOGS, COLS, true, P::P1L, P::P1H>(x, t, row, n1, q, tw, fold);
+        }
+        if constexpr (P::THREE) {
             __syncthreads();
-            ntt_phase<LOGS, LINES, COLS, true, P2L, P2H>(lds, line, t, row, n1, q, tw, fold);
+            if (active) lds_put<LOGS, LINES, COLS, P::P1L, P::P1H>(lds, x, line, t);
+            __syncthreads();
+            if (active) {
+                lds_get<LOGS, LINES, COLS, P::P2L, P::P2H>(lds, x, line, t);
+                phase_regs<LOGS, COLS, true, P::P2L, P::P2H>(x, t, row, n1, q, tw, fold);
+            }
         }
     } else {
-        if constexpr (P2H > P2L) {
-            ntt_phase<LOGS, LINES, COLS, false, P2L, P2H>(lds, line, t, row, n1, q, tw, fold);
+        if constexpr (P::THREE) {
+            if (active) {
+                phase_regs<LOGS, COLS, false, P::P2L, P::P2H>(x, t, row, n1, q, tw, fold);
+                lds_put<LOGS, LINES, COLS, P::P2L, P::P2H>(lds, x, line, t);
+            }
+            __syncthreads();
+            if (active) lds_get<LOGS, LINES, COLS, P::P1L, P::P1H>(lds, x, line, t);
             __syncthreads();
         }
-        ntt_phase<LOGS, LINES, COLS, false, P1L, P1H>(lds, line, t, row, n1, q, tw, fold);
+        if (active) {
+            phase_regs<LOGS, COLS, false, P::P1L, P::P1H>(x, t, row, n1, q, tw, fold);
+            lds_put<LOGS, LINES, COLS, P::P1L, P::P1H>(lds, x, line, t);
+        }
         __syncthreads();
-        ntt_phase<LOGS, LINES, COLS, false, P0L, LOGS>(lds, line, t, row, n1, q, tw, fold);
+        if (active) {
+            lds_get<LOGS, LINES, COLS, P::P0L, P::P0H>(lds, x, line, t);
+            phase_regs<LOGS, COLS, false, P::P0L, P::P0H>(x, t, row, n1, q, tw, fold);
+        }
     }
 }
 
-// All phases of one pass with the work of each phase done only where
-// `active` holds; every thread of the block reaches every barrier, so thread
-// groups of one block may run passes on different tiles (or sit one out).
-template <int LOGS, int LINES, bool COLS, bool FWD>
-__device__ __forceinline__ void ntt_tile_guarded(bool active, uint64_t *lds, int line, int t, uint32_t row,
-                                                 uint32_t n1, uint64_t q, const Shoup *__restrict__ tw,
-                                                 const LastInv &fold) {
-    constexpr int P0L = LOGS - 4;
-    constexpr int P1H = P0L, P1L = (P0L - 4) > 0 ? (P0L - 4) : 0;
-    constexpr int P2H = P1L, P2L = 0;
-    if (FWD) {
-        if (active) ntt_phase<LOGS, LINES, COLS, true, P0L, LOGS>(lds, line, t, row, n1, q, tw, fold);
-        __syncthreads();
-        if (active) ntt_phase<LOGS, LINES, COLS, true, P1L, P1H>(lds, line, t, row, n1, q, tw, fold);
-        if constexpr (P2H > P2L) {
-            __syncthreads();
-            if (active) ntt_phase<LOGS, LINES, COLS, true, P2L, P2H>(lds, line, t, row, n1, q, tw, fold);
+// first / last phase layouts of a pass
+template <int LOGS, bool FWD>
+struct IoLayout {
+    using P = Phases<LOGS>;
+    static constexpr int IN_LO = FWD ? P::P0L : (P::THREE ? P::P2L : P::P1L);
+    static constexpr int IN_HI = FWD ? P::P0H : (P::THREE ? P::P2H : P::P1H);
+    static constexpr int OUT_LO = FWD ? (P::THREE ? P::P2L : P::P1L) : P::P0L;
+    static constexpr int OUT_HI = FWD ? (P::THREE ? P::P2H : P::P1H) : P::P0H;
+};
+
+// global index of sub-index k of line `lg` (a column, or a row)
+template <bool COLS>
+__device__ __forceinline__ uint32_t jdx(uint32_t lg, int k, uint32_t n2) {
+    return COLS ? (((uint32_t)k << n2) + lg) : ((lg << n2) + (uint32_t)k);
+}
+
+// Load / store the thread's 16 elements of line `lg` in layout [LO, HI).  A
+// row pass in a [0, b) layout owns 16 consecutive words: 16-byte accesses.
+template <int LOGS, bool COLS, int LO, int HI>
+__device__ __forceinline__ void gload(uint64_t (&x)[16], const uint64_t *__restrict__ src, int t, uint32_t lg,
+                                      uint32_t n2) {
+    if (!COLS && LO == 0) {
+        const ulonglong2 *p = reinterpret_cast<const ulonglong2 *>(src + (lg << n2) + 16 * t);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const ulonglong2 v = p[i];
+            x[2 * i] = v.x;
+            x[2 * i + 1] = v.y;
         }
     } else {
-        if constexpr (P2H > P2L) {
-            if (active) ntt_phase<LOGS, LINES, COLS, false, P2L, P2H>(lds, line, t, row, n1, q, tw, fold);
-            __syncthreads();
-        }
-        if (active) ntt_phase<LOGS, LINES, COLS, false, P1L, P1H>(lds, line, t, row, n1, q, tw, fold);
-        __syncthreads();
-        if (active) ntt_phase<LOGS, LINES, COLS, false, P0L, LOGS>(lds, line, t, row, n1, q, tw, fold);
+#pragma unroll
+        for (int e = 0; e < 16; ++e) x[e] = src[jdx<COLS>(lg, k_of<LO, HI>(t, e), n2)];
     }
 }
 
-// thread -> (line, t): column tiles put lines fastest (LDS rows contiguous),
+template <int LOGS, bool COLS, int LO, int HI>
+__device__ __forceinline__ void gstore(const uint64_t (&x)[16], uint64_t *__restrict__ dst, int t, uint32_t lg,
+                                       uint32_t n2) {
+    if (!COLS && LO == 0) {
+        ulonglong2 *p = reinterpret_cast<ulonglong2 *>(dst + (lg << n2) + 16 * t);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) p[i] = make_ulonglong2(x[2 * i], x[2 * i + 1]);
+    } else {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) dst[jdx<COLS>(lg, k_of<LO, HI>(t, e), n2)] = x[e];
+    }
+}
+
+// thread -> (line, t): column tiles put lines fastest (coalesced columns),
 // row tiles put the threads of one line together.
 template <int LOGS, int LINES, bool COLS>
 __device__ __forceinline__ void thread_coords(int tid, int &line, int &t) {
@@ -210,20 +271,20 @@ struct NttArgs {
     const Shoup *tw;      // [M][N] forward or inverse table
     const ModC *mc;
     const LastInv *li;    // folded last inverse stage, indexed by cidx
-    const uint64_t *conv; // IO_CONV: constant rows, row cidx at conv + cidx * cstride
     const uint64_t *uq;   // IO_MDEPI: u limbs (limb cidx), batch stride uq_bstride
     const Shoup *pinv;    // IO_MDEPI: P^-1 mod q_i
     const uint64_t *add;  // IO_MDEPI: addend (limb cidx) for polys selected by add_mask
     size_t in_bstride, out_bstride, uq_bstride, add_pstride;
-    uint32_t n, n1, n2, galois, cstride, add_galois, add_mask;
+    uint32_t n, n1, n2, galois, add_galois, add_mask;
     LimbMap m;
 };
 
-enum { IO_PLAIN = 0, IO_GATHER = 1, IO_REDUCE = 2, IO_CONV = 3, IO_MDEPI = 4 };
+enum { IO_PLAIN = 0, IO_GATHER = 1, IO_REDUCE = 2, IO_MDEPI = 4 };
 
 template <int LOGS, int LINES, bool COLS, bool FWD, int IO>
 __global__ void __launch_bounds__((Tile<LOGS, LINES, COLS>::NT)) ntt_pass_kernel(const NttArgs a) {
     using TL = Tile<LOGS, LINES, COLS>;
+    using IOL = IoLayout<LOGS, FWD>;
     __shared__ uint64_t lds[TL::WORDS];
     const uint32_t lines_per_limb = 1u << (COLS ? a.n2 : a.n1);
     const uint32_t tiles = lines_per_limb / LINES;
@@ -237,67 +298,21 @@ __global__ void __launch_bounds__((Tile<LOGS, LINES, COLS>::NT)) ntt_pass_kernel
     const uint64_t *src = a.in + b * a.in_bstride + (size_t)a.m.in_off[li] * N;
     uint64_t *dst = a.out + b * a.out_bstride + (size_t)a.m.out_off[li] * N;
     const Shoup *tw = a.tw + (size_t)mod * N;
-    const int tid = threadIdx.x;
-    const uint32_t line0 = tile * LINES;
-
-    if (IO == IO_CONV) {
-        // NewLimb: out = sum_i y_i * K_i mod q over the digit's n_src limbs,
-        // CH elements at a time so that their source loads overlap
-        constexpr int MAXS = 16, CH = 4;
-        const uint32_t ns = a.m.nsrc[li];
-        const uint64_t *kr = a.conv + (size_t)a.m.cidx[li] * a.cstride;
-        uint64_t kc[MAXS];
-#pragma unroll
-        for (int i = 0; i < MAXS; ++i) kc[i] = (i < (int)ns) ? kr[i] : 0;
-#pragma unroll 1
-        for (int i0 = 0; i0 < TL::EPT; i0 += CH) {
-            uint32_t jj[CH];
-            int ii[CH];
-            MacAcc acc[CH];
-#pragma unroll
-            for (int c = 0; c < CH; ++c) {
-                int line, k;
-                elem_coords<LOGS, LINES, COLS>(tid + (i0 + c) * TL::NT, line0, a.n2, line, k, jj[c]);
-                ii[c] = TL::idx(line, k);
-            }
-#pragma unroll
-            for (int i = 0; i < MAXS; ++i) {
-                if (i < (int)ns) {
-                    uint64_t yv[CH];
-#pragma unroll
-                    for (int c = 0; c < CH; ++c) yv[c] = src[(size_t)i * N + jj[c]];
-#pragma unroll
-                    for (int c = 0; c < CH; ++c) acc[c].mac(yv[c], kc[i]);
-                }
-            }
-#pragma unroll
-            for (int c = 0; c < CH; ++c) lds[ii[c]] = acc[c].reduce(q, mcv.mu);
-        }
-    } else {
-        uint64_t v[TL::EPT];
-#pragma unroll
-        for (int i = 0; i < TL::EPT; ++i) {
-            int line, k;
-            uint32_t j;
-            elem_coords<LOGS, LINES, COLS>(tid + i * TL::NT, line0, a.n2, line, k, j);
-            const uint32_t sj = (IO == IO_GATHER) ? aut_eval_src(j, a.galois, a.n) : j;
-            v[i] = src[sj];
-        }
-#pragma unroll
-        for (int i = 0; i < TL::EPT; ++i) {
-            int line, k;
-            uint32_t j;
-            elem_coords<LOGS, LINES, COLS>(tid + i * TL::NT, line0, a.n2, line, k, j);
-            lds[TL::idx(line, k)] = v[i];
-        }
-    }
-    __syncthreads();
-
     int line, t;
-    thread_coords<LOGS, LINES, COLS>(tid, line, t);
+    thread_coords<LOGS, LINES, COLS>(threadIdx.x, line, t);
+    const uint32_t lg = tile * LINES + line;  // this thread's column or row
+
+    uint64_t x[16];
+    if (IO == IO_GATHER) {
+#pragma unroll
+        for (int e = 0; e < 16; ++e)
+            x[e] = src[aut_eval_src(jdx<COLS>(lg, k_of<IOL::IN_LO, IOL::IN_HI>(t, e), a.n2), a.galois, a.n)];
+    } else {
+        gload<LOGS, COLS, IOL::IN_LO, IOL::IN_HI>(x, src, t, lg, a.n2);
+    }
+
     const LastInv fold = (!FWD && COLS) ? a.li[a.m.cidx[li]] : LastInv{};
-    ntt_tile<LOGS, LINES, COLS, FWD>(lds, line, t, line0 + line, a.n1, q, tw, fold);
-    __syncthreads();
+    pass_regs<LOGS, LINES, COLS, FWD>(true, x, lds, line, t, lg, a.n1, q, tw, fold);
 
     if (IO == IO_MDEPI) {
         const uint32_t ui = a.m.cidx[li];
@@ -305,27 +320,23 @@ __global__ void __launch_bounds__((Tile<LOGS, LINES, COLS>::NT)) ntt_pass_kernel
         const Shoup pi = a.pinv[ui];
         const bool do_add = a.add && ((a.add_mask >> b) & 1u);
         const uint64_t *ad = do_add ? a.add + b * a.add_pstride + (size_t)ui * N : nullptr;
-#pragma unroll 4
-        for (int i = 0; i < TL::EPT; ++i) {
-            int ln, k;
-            uint32_t j;
-            elem_coords<LOGS, LINES, COLS>(tid + i * TL::NT, line0, a.n2, ln, k, j);
-            const uint64_t z = reduce64(lds[TL::idx(ln, k)], q, mcv.mu);
-            uint64_t r = mul_shoup(u[j] + q - z, pi.w, pi.wp, q);
-            if (do_add) r = add_mod(r, ad[a.add_galois != 1 ? aut_eval_src(j, a.add_galois, a.n) : j], q);
-            dst[j] = r;
-        }
-    } else {
+        uint64_t uv[16];
+        gload<LOGS, COLS, IOL::OUT_LO, IOL::OUT_HI>(uv, u, t, lg, a.n2);
 #pragma unroll
-        for (int i = 0; i < TL::EPT; ++i) {
-            int ln, k;
-            uint32_t j;
-            elem_coords<LOGS, LINES, COLS>(tid + i * TL::NT, line0, a.n2, ln, k, j);
-            uint64_t v = lds[TL::idx(ln, k)];
-            if (IO == IO_REDUCE) v = reduce64(v, q, mcv.mu);
-            dst[j] = v;
+        for (int e = 0; e < 16; ++e) {
+            const uint64_t z = reduce64(x[e], q, mcv.mu);
+            uint64_t r = mul_shoup(uv[e] + q - z, pi.w, pi.wp, q);
+            if (do_add) {
+                const uint32_t j = jdx<COLS>(lg, k_of<IOL::OUT_LO, IOL::OUT_HI>(t, e), a.n2);
+                r = add_mod(r, ad[a.add_galois != 1 ? aut_eval_src(j, a.add_galois, a.n) : j], q);
+            }
+            x[e] = r;
         }
+    } else if (IO == IO_REDUCE) {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) x[e] = reduce64(x[e], q, mcv.mu);
     }
+    gstore<LOGS, COLS, IOL::OUT_LO, IOL::OUT_HI>(x, dst, t, lg, a.n2);
 }
 
 constexpr int COL_LINES = 16;
@@ -443,18 +454,15 @@ hipError_t launch_ntt_inv_cols(const Ctx &c, const LimbMap &m, const uint64_t *i
     return dispatch_pass<true, false, IO_PLAIN>(a, c.n1, m.count, batch, s);
 }
 
-hipError_t launch_conv_cols(const Ctx &c, const LimbMap &m, const uint64_t *y, const uint64_t *conv,
-                            uint32_t cstride, uint64_t *out, uint32_t batch, size_t in_bstride,
-                            size_t out_bstride, hipStream_t s) {
+hipError_t launch_ntt_fwd_cols(const Ctx &c, const LimbMap &m, const uint64_t *in, uint64_t *out,
+                               uint32_t batch, size_t in_bstride, size_t out_bstride, hipStream_t s) {
     if (m.count == 0 || batch == 0) return hipSuccess;
     NttArgs a = base_args(c, m, true);
-    a.in = y;
+    a.in = in;
     a.out = out;
-    a.conv = conv;
-    a.cstride = cstride;
     a.in_bstride = in_bstride;
     a.out_bstride = out_bstride;
-    return dispatch_pass<true, true, IO_CONV>(a, c.n1, m.count, batch, s);
+    return dispatch_pass<true, true, IO_PLAIN>(a, c.n1, m.count, batch, s);
 }
 
 hipError_t launch_rows_mdepi(const Ctx &c, const LimbMap &m, const uint64_t *zc, uint64_t *out,
@@ -477,37 +485,33 @@ hipError_t launch_rows_mdepi(const Ctx &c, const LimbMap &m, const uint64_t *zc,
     return dispatch_pass<false, true, IO_MDEPI>(a, c.n2, m.count, batch, s);
 }
 
-// ------------------------------------------------------------------ row pass + KSKInnerProd
+// ------------------------------------------------------------------ KSKInnerProd (+ ModDown's first P pass)
 
 struct KskRowArgs {
-    const uint64_t *colout;  // [beta][E][N] column-pass outputs of the new limbs
-    const uint64_t *direct;  // evaluation-form digits: limb t of digit j at direct + j*dstride + t*N
+    const uint64_t *ext;     // [beta][E][N] extended digits in evaluation form (converted limbs)
+    const uint64_t *direct;  // digit j's own limb t at direct + j*dstride + t*N (gathered by `galois`)
     const uint64_t *ksk;     // [dnum][2][L+K][N]
     uint64_t *uq;            // [2][level][N] KSKInnerProd on the q limbs
     uint64_t *pc;            // [2][K][N] P limbs after the inverse row pass
-    const Shoup *twf, *twi;
+    const Shoup *twi;
     const ModC *mc;
     size_t dstride;
     uint32_t n, n1, n2, level, L, K, E, alpha, beta, galois, all_direct;
 };
 
-// One block = one target limb t of Q_level U P and ROW_LINES rows, DG thread
-// groups.  A round handles digits j0..j0+DG-1: group g runs the row pass of
-// the converted limb of digit j0+g in its LDS tile (the digit's own limb is
-// instead read in evaluation form, gathered through the automorph).  Then
-// every thread accumulates, per element, u_t = sum_j x_j ksk[j][0] and
-// v_t = sum_j x_j ksk[j][1] (products reduced by Barrett into canonical
-// sums; partial sums of earlier rounds come from the output buffers when
-// beta > DG).  q limbs store (u_t, v_t).  Special-prime limbs put (u, v) back
-// into LDS tiles 0 and 1 at the element's own slot (only the thread that read
-// the slot writes it) and run ModDown's inverse row pass on both.
-template <int LOGS, int DG>
-__global__ void __launch_bounds__((DG * Tile<LOGS, ROW_LINES, false>::NT)) rows_ksk_kernel(const KskRowArgs a) {
+// One block = one target limb t of Q_level U P and ROW_LINES rows.  Each
+// thread streams its elements (coalesced): u_t = sum_j x_j ksk[j][0][t],
+// v_t = sum_j x_j ksk[j][1][t] over the beta digits (products reduced by
+// Barrett into canonical sums), x_j from the extended digit (evaluation form)
+// or, for the digit's own limb, from the input gathered through the
+// automorph.  q limbs store (u_t, v_t); special-prime limbs keep (u, v) in LDS
+// and run ModDown's inverse row pass on both before storing.
+template <int LOGS>
+__global__ void __launch_bounds__((Tile<LOGS, ROW_LINES, false>::NT)) ksk_rows_kernel(const KskRowArgs a) {
     using TL = Tile<LOGS, ROW_LINES, false>;
-    constexpr int TW = ROW_LINES * TL::S;  // elements of the tile
-    constexpr int BT = DG * TL::NT;        // threads of the block
-    constexpr int NTILE = DG < 2 ? 2 : DG;
-    __shared__ uint64_t lds[NTILE][TL::WORDS];
+    using IOI = IoLayout<LOGS, false>;
+    constexpr int CH = 4;
+    __shared__ uint64_t lds[2][TL::WORDS];
     const uint32_t tiles = (1u << a.n1) / ROW_LINES;
     const uint32_t tgt = blockIdx.x / tiles;
     const uint32_t tile = blockIdx.x % tiles;
@@ -516,7 +520,6 @@ __global__ void __launch_bounds__((DG * Tile<LOGS, ROW_LINES, false>::NT)) rows_
     const ModC mcv = a.mc[mod];
     const uint64_t q = mcv.q;
     const int tid = threadIdx.x;
-    const int grp = tid / TL::NT, ltid = tid % TL::NT;
     const uint32_t line0 = tile * ROW_LINES;
     const size_t KL = (size_t)a.L + a.K;
     const uint32_t own = (tgt < a.level) ? tgt / a.alpha : 0xffffffffu;
@@ -524,111 +527,79 @@ __global__ void __launch_bounds__((DG * Tile<LOGS, ROW_LINES, false>::NT)) rows_
     const uint32_t kp = tgt - a.level;
     uint64_t *ou = is_p ? a.pc + (size_t)kp * N : a.uq + (size_t)tgt * N;
     uint64_t *ov = is_p ? a.pc + ((size_t)a.K + kp) * N : a.uq + ((size_t)a.level + tgt) * N;
-    const Shoup *twf = a.twf + (size_t)mod * N;
-    int line, t;
-    thread_coords<LOGS, ROW_LINES, false>(ltid, line, t);
 
-    for (uint32_t j0 = 0; j0 < a.beta; j0 += DG) {
-        const bool last_round = j0 + DG >= a.beta;
-        const uint32_t jg = j0 + grp;
-        const bool ntt_g = jg < a.beta && !a.all_direct && jg != own;
-        if (ntt_g) {
-            const uint64_t *src = a.colout + ((size_t)jg * a.E + tgt) * N;
-            uint64_t v[TL::EPT];
+#pragma unroll 1
+    for (int i0 = 0; i0 < TL::EPT; i0 += CH) {
+        uint32_t jj[CH];
+        int li[CH];
+        uint64_t u[CH], v[CH];
 #pragma unroll
-            for (int i = 0; i < TL::EPT; ++i) {
-                int ln, k;
-                uint32_t j;
-                elem_coords<LOGS, ROW_LINES, false>(ltid + i * TL::NT, line0, a.n2, ln, k, j);
-                v[i] = src[j];
-            }
-#pragma unroll
-            for (int i = 0; i < TL::EPT; ++i) {
-                int ln, k;
-                uint32_t j;
-                elem_coords<LOGS, ROW_LINES, false>(ltid + i * TL::NT, line0, a.n2, ln, k, j);
-                lds[grp][TL::idx(ln, k)] = v[i];
-            }
-        }
-        __syncthreads();
-        ntt_tile_guarded<LOGS, ROW_LINES, false, true>(ntt_g, lds[grp], line, t, line0 + line, a.n1, q, twf,
-                                                       LastInv{});
-        __syncthreads();
-        // KSKInnerProd of this round's digits
-#pragma unroll 2
-        for (int e = tid; e < TW; e += BT) {
+        for (int c = 0; c < CH; ++c) {
             int ln, k;
-            uint32_t j;
-            elem_coords<LOGS, ROW_LINES, false>(e, line0, a.n2, ln, k, j);
-            const int li = TL::idx(ln, k);
-            uint64_t u = 0, v = 0;
-            if (j0) {
-                u = ou[j];
-                v = ov[j];
+            elem_coords<LOGS, ROW_LINES, false>(tid + (i0 + c) * TL::NT, line0, a.n2, ln, k, jj[c]);
+            li[c] = TL::idx(ln, k);
+            u[c] = v[c] = 0;
+        }
+        for (uint32_t jd = 0; jd < a.beta; ++jd) {
+            const uint64_t *k0 = a.ksk + ((size_t)(2 * jd) * KL + mod) * N;
+            const uint64_t *k1 = k0 + KL * N;
+            const bool dir = a.all_direct || jd == own;
+            const uint64_t *src = dir ? a.direct + jd * a.dstride + (size_t)tgt * N
+                                      : a.ext + ((size_t)jd * a.E + tgt) * N;
+            uint64_t xv[CH], kv0[CH], kv1[CH];
+#pragma unroll
+            for (int c = 0; c < CH; ++c) {
+                const uint32_t sj = (dir && a.galois != 1) ? aut_eval_src(jj[c], a.galois, a.n) : jj[c];
+                xv[c] = src[sj];
+                kv0[c] = k0[jj[c]];
+                kv1[c] = k1[jj[c]];
             }
 #pragma unroll
-            for (int g = 0; g < DG; ++g) {
-                const uint32_t jd = j0 + g;
-                if (jd >= a.beta) break;
-                const uint64_t *k0 = a.ksk + ((size_t)(2 * jd) * KL + mod) * N;
-                const uint64_t *k1 = k0 + KL * N;
-                uint64_t x;
-                if (a.all_direct || jd == own) {
-                    const uint64_t *dsrc = a.direct + jd * a.dstride + (size_t)tgt * N;
-                    x = dsrc[a.galois != 1 ? aut_eval_src(j, a.galois, a.n) : j];
-                } else {
-                    x = lds[g][li];
-                }
-                u = add_mod(u, mul_mod(x, k0[j], q, mcv.mu), q);
-                v = add_mod(v, mul_mod(x, k1[j], q, mcv.mu), q);
-            }
-            if (is_p && last_round) {
-                lds[0][li] = u;
-                lds[1][li] = v;
-            } else {
-                ou[j] = u;
-                ov[j] = v;
+            for (int c = 0; c < CH; ++c) {
+                u[c] = add_mod(u[c], mul_mod(xv[c], kv0[c], q, mcv.mu), q);
+                v[c] = add_mod(v[c], mul_mod(xv[c], kv1[c], q, mcv.mu), q);
             }
         }
-        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            if (is_p) {
+                lds[0][li[c]] = u[c];
+                lds[1][li[c]] = v[c];
+            } else {
+                ou[jj[c]] = u[c];
+                ov[jj[c]] = v[c];
+            }
+        }
     }
     if (!is_p) return;
 
     // special-prime limb: inverse row pass (first pass of ModDown's iNTT) of u and v
-    const Shoup *twi = a.twi + (size_t)mod * N;
-    if (DG >= 2) {
-        ntt_tile_guarded<LOGS, ROW_LINES, false, false>(grp < 2, lds[grp < 2 ? grp : 0], line, t, line0 + line,
-                                                        a.n1, q, twi, LastInv{});
-    } else {
-        ntt_tile_guarded<LOGS, ROW_LINES, false, false>(true, lds[0], line, t, line0 + line, a.n1, q, twi,
-                                                        LastInv{});
-        __syncthreads();
-        ntt_tile_guarded<LOGS, ROW_LINES, false, false>(true, lds[1], line, t, line0 + line, a.n1, q, twi,
-                                                        LastInv{});
-    }
     __syncthreads();
-    for (int e = tid; e < TW; e += BT) {
-        int ln, k;
-        uint32_t j;
-        elem_coords<LOGS, ROW_LINES, false>(e, line0, a.n2, ln, k, j);
-        const int li = TL::idx(ln, k);
-        ou[j] = lds[0][li];
-        ov[j] = lds[1][li];
+    int line, t;
+    thread_coords<LOGS, ROW_LINES, false>(tid, line, t);
+    const uint32_t lg = line0 + line;
+    const Shoup *twi = a.twi + (size_t)mod * N;
+#pragma unroll
+    for (int poly = 0; poly < 2; ++poly) {
+        uint64_t x[16];
+        lds_get<LOGS, ROW_LINES, false, IOI::IN_LO, IOI::IN_HI>(lds[poly], x, line, t);
+        __syncthreads();
+        pass_regs<LOGS, ROW_LINES, false, false>(true, x, lds[poly], line, t, lg, a.n1, q, twi, LastInv{});
+        gstore<LOGS, false, IOI::OUT_LO, IOI::OUT_HI>(x, poly ? ov : ou, t, lg, a.n2);
     }
 }
 
-hipError_t launch_rows_ksk(const Ctx &c, const uint64_t *colout, const uint64_t *direct, size_t dstride,
+hipError_t launch_ksk_rows(const Ctx &c, const uint64_t *ext, const uint64_t *direct, size_t dstride,
                            uint32_t all_direct, const uint64_t *ksk, uint32_t level, uint32_t galois,
                            uint64_t *uq, uint64_t *pc, hipStream_t s) {
     KskRowArgs a{};
-    a.colout = colout;
+    a.ext = ext;
     a.direct = direct;
     a.dstride = dstride;
     a.all_direct = all_direct;
     a.ksk = ksk;
     a.uq = uq;
     a.pc = pc;
-    a.twf = c.tw_fwd;
     a.twi = c.tw_inv;
     a.mc = c.mc;
     a.n = c.log_n;
@@ -644,24 +615,13 @@ hipError_t launch_rows_ksk(const Ctx &c, const uint64_t *colout, const uint64_t 
     ProfScope ps(c, HKS_K_KSK, s);
     const uint32_t tiles = (1u << c.n1) / ROW_LINES;
     dim3 grid(tiles * a.E);
-    const uint32_t dg = a.beta >= 4 ? 4 : a.beta;
-#define HKS_RK(LG, D) hipLaunchKernelGGL((rows_ksk_kernel<LG, D>), grid, dim3(D * Tile<LG, ROW_LINES, false>::NT), 0, s, a)
-#define HKS_RK_DG(LG)       \
-    switch (dg) {           \
-        case 1: HKS_RK(LG, 1); break; \
-        case 2: HKS_RK(LG, 2); break; \
-        case 3: HKS_RK(LG, 3); break; \
-        default: HKS_RK(LG, 4); break; \
-    }
     switch (c.n2) {
-        case 5: HKS_RK_DG(5); break;
-        case 6: HKS_RK_DG(6); break;
-        case 7: HKS_RK_DG(7); break;
-        case 8: HKS_RK_DG(8); break;
+        case 5: hipLaunchKernelGGL(ksk_rows_kernel<5>, grid, dim3(Tile<5, ROW_LINES, false>::NT), 0, s, a); break;
+        case 6: hipLaunchKernelGGL(ksk_rows_kernel<6>, grid, dim3(Tile<6, ROW_LINES, false>::NT), 0, s, a); break;
+        case 7: hipLaunchKernelGGL(ksk_rows_kernel<7>, grid, dim3(Tile<7, ROW_LINES, false>::NT), 0, s, a); break;
+        case 8: hipLaunchKernelGGL(ksk_rows_kernel<8>, grid, dim3(Tile<8, ROW_LINES, false>::NT), 0, s, a); break;
         default: return hipErrorInvalidValue;
     }
-#undef HKS_RK_DG
-#undef HKS_RK
     return hipGetLastError();
 }
 

@@ -86,6 +86,10 @@ static int upload(T **dst, const std::vector<T> &src) {
     return HKS_OK;
 }
 
+// conversion constant in the split form used by the kernels: k0 | (k1 << 32),
+// k = k0 + k1 2^25 with k0 < 2^25
+static uint64_t split25(uint64_t k) { return (k & 0x1FFFFFFull) | ((k >> 25) << 32); }
+
 static LastInv make_last(uint64_t q, uint64_t n_inv, uint64_t scale, uint64_t w0_inv) {
     LastInv li;
     uint64_t c = h_mulmod(n_inv, scale % q, q);
@@ -144,7 +148,7 @@ int build_tables(Ctx &c) {
                     uint64_t v = 1;
                     for (uint32_t k = lo; k < hi; ++k)
                         if (k != i) v = h_mulmod(v, c.mods[k] % mt, mt);
-                    tab[((size_t)j * E + t) * A + (i - lo)] = v;
+                    tab[((size_t)j * E + t) * A + (i - lo)] = split25(v);
                 }
             }
         }
@@ -163,7 +167,7 @@ int build_tables(Ctx &c) {
             uint64_t qi = c.mods[i], v = 1;
             for (uint32_t kk = 0; kk < K; ++kk)
                 if (kk != k) v = h_mulmod(v, c.mods[L + kk] % qi, qi);
-            convd[(size_t)i * K + k] = v;
+            convd[(size_t)i * K + k] = split25(v);
         }
     }
     for (uint32_t i = 0; i < L; ++i) {
