@@ -44,39 +44,40 @@ def log(*a):
 
 def kernel_work(cls: int, n: int, level: int, k: int, alpha: int, beta: int):
     """Algorithmic modular multiplications of one Rotate done by kernel class
-    `cls` (butterflies for NTT passes, multiply-accumulates for conversion and
-    KSKInnerProd) and the algorithmic HBM bytes it moves (8 B words)."""
+    `cls` (butterflies for NTT passes, product terms for the conversion and
+    KSKInnerProd) and the algorithmic HBM bytes it moves (8-byte words: each
+    limb read once and written once per pass)."""
     n1 = LOG_N // 2
     n2 = LOG_N - n1
     E = level + k
     own = level  # limbs copied from the input, one per digit member
     new_limbs = beta * E - own
-    fwd_limbs = new_limbs + 2 * level
-    inv_limbs = level + 2 * k
+    fwd_limbs = new_limbs + 2 * level  # ModUp's new limbs + ModDown's corrections (u and v)
     half = n // 2
     if cls == 0:  # forward NTT, column pass
         return fwd_limbs * half * n1, fwd_limbs * n * 16
-    if cls == 1:  # forward NTT, row pass
-        return fwd_limbs * half * n2, fwd_limbs * n * 16
-    if cls == 2:  # inverse NTT, row pass
-        return inv_limbs * half * n2, inv_limbs * n * 16
-    if cls == 3:  # inverse NTT, column pass (+ folded scale on half the outputs)
-        return inv_limbs * half * (n1 + 1), inv_limbs * n * 16
+    if cls == 1:  # forward NTT, row pass (+ ModDown epilogue on the corrections)
+        return fwd_limbs * half * n2, (fwd_limbs * 16 + 2 * level * 8 * 2 + level * 8) * n
+    if cls == 2:  # inverse NTT, row pass of the input limbs (automorph gathered)
+        return level * half * n2, level * n * 16
+    if cls == 3:  # inverse NTT, column pass (+ folded scale on half the outputs): input + P limbs
+        limbs = level + 2 * k
+        return limbs * half * (n1 + 1), limbs * n * 16
     if cls == 4:  # conversion: ModUp sum_j |I_j| (E - |I_j|) + ModDown 2 K level
-        macs = 0
+        terms = 0
         for j in range(beta):
             sz = min(alpha, level - j * alpha)
-            macs += sz * (E - sz)
-        macs += 2 * k * level
-        return macs * n, (level + new_limbs + 2 * k + 2 * level) * n * 8
-    if cls == 5:  # KSKInnerProd: 2 rows x beta digits x E limbs
-        return 2 * beta * E * n, (beta * E + 2 * beta * E + 2 * E) * n * 8
+            terms += sz * (E - sz)
+        terms += 2 * k * level
+        return terms * n, (level + new_limbs + 2 * k + 2 * level) * n * 8
+    if cls == 5:  # KSKInnerProd: 2 rows x beta digits x E limbs (+ inverse row pass of 2K P limbs)
+        return 2 * beta * E * n + 2 * k * half * n2, (beta * E + 2 * beta * E + 2 * E) * n * 8
     return 0, 0
 
 
 def source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("kernels.hip", "modarith.h", "hks_internal.h", "abi.cpp"):
+    for f in ("ntt.hip", "kernels.hip", "modarith.h", "device_util.h", "hks_internal.h", "abi.cpp"):
         h.update(open(os.path.join(ROOT, "paper_2112_06396_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
