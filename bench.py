@@ -57,7 +57,7 @@ def kernel_work(cls: int, n: int, level: int, k: int, alpha: int, beta: int):
     if cls == 0:  # forward NTT, column pass
         return fwd_limbs * half * n1, fwd_limbs * n * 16
     if cls == 1:  # forward NTT, row pass (+ ModDown epilogue on the corrections)
-        return fwd_limbs * half * n2, (fwd_limbs * 16 + 2 * level * 8 * 2 + level * 8) * n
+        return fwd_limbs * half * n2, (fwd_limbs * 16 + 2 * level * 8 + level * 8) * n
     if cls == 2:  # inverse NTT, row pass of the input limbs (automorph gathered)
         return level * half * n2, level * n * 16
     if cls == 3:  # inverse NTT, column pass (+ folded scale on half the outputs): input + P limbs
