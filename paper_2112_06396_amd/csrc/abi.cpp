@@ -72,8 +72,11 @@ uint32_t beta_of(const Ctx &c, uint32_t level) { return (level + c.alpha - 1) / 
 //   iNTT of the level limbs of `a` (gathered through the automorph `galois`),
 //   scaled by N^-1 [(Qt_j/q_i)^-1]_{q_i} -> ws_y (coefficient form);
 //   NewLimb of every digit into every other limb of Q_level U P -> ext[j][t];
-//   forward NTT of those limbs in place (own-digit slots untouched).
-int do_modup_new(Ctx &c, const uint64_t *a, uint32_t level, uint32_t galois, uint64_t *ext, hipStream_t s) {
+//   forward NTT of those limbs in place (own-digit slots untouched): both
+//   passes, or with cols_only just the column pass (the key-switch kernel
+//   runs the row pass on chip).
+int do_modup_new(Ctx &c, const uint64_t *a, uint32_t level, uint32_t galois, uint64_t *ext, hipStream_t s,
+                 bool cols_only = false) {
     const uint32_t A = c.alpha, E = level + c.K, beta = beta_of(c, level);
     Lists inv, nl;
     for (uint32_t i = 0; i < level; ++i) inv.add(i, i, i, level * c.L + i);
@@ -86,7 +89,9 @@ int do_modup_new(Ctx &c, const uint64_t *a, uint32_t level, uint32_t galois, uin
         for (uint32_t t = 0; t < E; ++t)
             if (t < lo || t >= hi) nl.add(j * E + t, j * E + t, ext_mod(c, level, t), 0);
     }
-    HKS_TRY(nl.run([&](const LimbMap &m) { return launch_ntt_fwd(c, m, ext, ext, 1, 0, 0, s); }));
+    HKS_TRY(nl.run([&](const LimbMap &m) {
+        return cols_only ? launch_ntt_fwd_cols(c, m, ext, ext, 1, 0, 0, s) : launch_ntt_fwd(c, m, ext, ext, 1, 0, 0, s);
+    }));
     return HKS_OK;
 }
 
@@ -128,15 +133,16 @@ int do_moddown_tail(Ctx &c, const uint64_t *uq, size_t uq_bstride, uint32_t leve
 }
 
 // KeySwitch of d (level limbs, gathered through `galois`) into uv [2][level][N]
-// with the ModDown additions (10 launches); the digits' own limbs are read
-// from d in the KSKInnerProd kernel (never copied).
+// with the ModDown additions (9 launches); the digits' own limbs are read
+// from d in the KSKInnerProd kernel (never copied), which also runs the
+// last forward pass of ModUp's NTT.
 int do_keyswitch(Ctx &c, const uint64_t *d, uint32_t level, uint32_t galois, const uint64_t *ksk,
                  uint64_t *uv, const uint64_t *add, uint32_t add_galois, uint32_t add_mask,
                  size_t add_pstride, hipStream_t s) {
     const uint32_t N = c.n;
-    int rc = do_modup_new(c, d, level, galois, c.ws_ext, s);
+    int rc = do_modup_new(c, d, level, galois, c.ws_ext, s, true);
     if (rc) return rc;
-    HKS_TRY(launch_ksk_rows(c, c.ws_ext, d, 0, 0, ksk, level, galois, c.ws_uv, c.ws_p, s));
+    HKS_TRY(launch_ksk_rows(c, c.ws_ext, true, d, 0, 0, ksk, level, galois, c.ws_uv, c.ws_p, s));
     return do_moddown_tail(c, c.ws_uv, (size_t)level * N, level, uv, 2, (size_t)level * N, add, add_galois,
                            add_mask, add_pstride, s);
 }
@@ -425,7 +431,7 @@ int hks_hrotate(hks_ctx *h, const uint64_t *ct, uint32_t level, uint32_t r, cons
     if (!rc) rc = do_modup_own(c, ct, level, 1, c.ws_ext, s);
     if (rc) return rc;
     for (uint32_t i = 0; i < r; ++i) {
-        HKS_TRY(launch_ksk_rows(c, c.ws_ext, c.ws_ext, (size_t)E * N, 1, ksk[i], level, galois[i], c.ws_uv, c.ws_p,
+        HKS_TRY(launch_ksk_rows(c, c.ws_ext, false, c.ws_ext, (size_t)E * N, 1, ksk[i], level, galois[i], c.ws_uv, c.ws_p,
                                 s));
         rc = do_moddown_tail(c, c.ws_uv, (size_t)level * N, level, ct_out[i], 2, (size_t)level * N, ct, galois[i],
                              2u, (size_t)level * N, s);

@@ -144,10 +144,11 @@ hipError_t launch_rows_mdepi(const Ctx &c, const LimbMap &m, const uint64_t *zc,
                              size_t out_bstride, hipStream_t s);
 // KSKInnerProd per target limb and row tile (+ ModDown's inverse row pass for
 // the P limbs, into pc [2][K][N]); q limbs into uq [2][level][N].  Converted
-// limb t of digit j is read in evaluation form at ext + (j*E + t)*N; digit j's
-// own limb (all digits if all_direct) at direct + j*dstride + t*N, gathered
-// through `galois`.
-hipError_t launch_ksk_rows(const Ctx &c, const uint64_t *ext, const uint64_t *direct, size_t dstride,
+// limb t of digit j is read at ext + (j*E + t)*N: after the forward column
+// pass only (rowpass: the kernel runs the row pass) or in evaluation form;
+// digit j's own limb (all digits if all_direct) at direct + j*dstride + t*N,
+// gathered through `galois`.
+hipError_t launch_ksk_rows(const Ctx &c, const uint64_t *ext, bool rowpass, const uint64_t *direct, size_t dstride,
                            uint32_t all_direct, const uint64_t *ksk, uint32_t level, uint32_t galois,
                            uint64_t *uq, uint64_t *pc, hipStream_t s);
 // Eval-domain automorph (gather) of limbs; or coefficient-domain map with negation.

@@ -69,17 +69,28 @@ __device__ __forceinline__ int k_of(int t, int e) {
     return ((r >> LO) << HI) | (v << LO) | (r & ((1 << LO) - 1));
 }
 
+// Twiddle sources.  The butterfly group m = k >> (bit+1) of local stage ls
+// (0-based within the pass) uses
+//   column pass: table index 2^ls + m;
+//   row pass:    table index ((2^n1 + r) << ls) + m for row r.
+// Elements whose k agree above `bit` share the twiddle.
+struct TwCols {
+    const Shoup *tw;
+    __device__ __forceinline__ Shoup operator()(int ls, uint32_t m) const { return tw[(1u << ls) + m]; }
+};
+struct TwRows {
+    const Shoup *tw;
+    uint32_t row, n1;
+    __device__ __forceinline__ Shoup operator()(int ls, uint32_t m) const {
+        return tw[(((1u << n1) + row) << ls) + m];
+    }
+};
 // The butterflies of one phase on the thread's 16 registers (layout [LO, HI)).
-// Twiddle of the butterfly on bit `bit` for lower element k:
-//   column pass: index 2^s + (k >> (bit+1)),           s = LOGS-1-bit;
-//   row pass:    index 2^s + (r << (LOGS-1-bit)) + (k >> (bit+1)),
-//                s = n1 + LOGS-1-bit, r the row.
-// Elements whose k agree above `bit` share the twiddle, so each stage loads
-// 16 >> (vb+1) twiddles.  The global stage 0 of the inverse (only in the
-// column pass) multiplies by the folded constants instead.
-template <int LOGS, bool COLS, bool FWD, int LO, int HI>
-__device__ __forceinline__ void phase_regs(uint64_t (&x)[16], int t, uint32_t row, uint32_t n1, uint64_t q,
-                                           const Shoup *__restrict__ tw, const LastInv &fold) {
+// Each stage loads 16 >> (vb+1) distinct twiddles.  With FOLD (the inverse
+// column pass) the global last inverse stage multiplies by the folded
+// constants instead.
+template <int LOGS, bool FWD, bool FOLD, int LO, int HI, typename TW>
+__device__ __forceinline__ void phase_regs(uint64_t (&x)[16], int t, uint64_t q, const TW &tws, const LastInv &fold) {
     constexpr int B = HI - LO;
     const uint64_t q2 = 2 * q;
 #pragma unroll
@@ -87,15 +98,13 @@ __device__ __forceinline__ void phase_regs(uint64_t (&x)[16], int t, uint32_t ro
         const int bit = FWD ? (HI - 1 - st) : (LO + st);
         const int vb = bit - LO;
         const int ls = LOGS - 1 - bit;  // stage within this pass
-        const bool fold_stage = !FWD && COLS && ls == 0;
-        const uint32_t sbase = COLS ? (1u << ls) : ((1u << n1) << ls);
+        const bool fold_stage = FOLD && ls == 0;
         Shoup wc[8];
 #pragma unroll
         for (int key = 0; key < 8; ++key) {
             if (key < (16 >> (vb + 1)) && !fold_stage) {
                 const uint32_t k = (uint32_t)k_of<LO, HI>(t, key << (vb + 1));
-                const uint32_t ix = COLS ? (sbase + (k >> (bit + 1))) : (sbase + (row << ls) + (k >> (bit + 1)));
-                wc[key] = tw[ix];
+                wc[key] = tws(ls, k >> (bit + 1));
             }
         }
 #pragma unroll
@@ -141,20 +150,20 @@ __device__ __forceinline__ void lds_get(const uint64_t *lds, uint64_t (&x)[16], 
 // P2, inverse: P0).  The LDS tile carries the exchanges between phases; the
 // caller synchronizes before this tile is written again.  Work is done only
 // where `active` holds, but every thread reaches every barrier.
-template <int LOGS, int LINES, bool COLS, bool FWD>
-__device__ __forceinline__ void pass_regs(bool active, uint64_t (&x)[16], uint64_t *lds, int line, int t,
-                                          uint32_t row, uint32_t n1, uint64_t q, const Shoup *__restrict__ tw,
-                                          const LastInv &fold) {
+template <int LOGS, int LINES, bool COLS, bool FWD, typename TW>
+__device__ __forceinline__ void pass_regs(bool active, uint64_t (&x)[16], uint64_t *lds, int line, int t, uint64_t q,
+                                          const TW &tws, const LastInv &fold) {
     using P = Phases<LOGS>;
+    constexpr bool FOLD = !FWD && COLS;
     if (FWD) {
         if (active) {
-            phase_regs<LOGS, COLS, true, P::P0L, P::P0H>(x, t, row, n1, q, tw, fold);
+            phase_regs<LOGS, true, FOLD, P::P0L, P::P0H>(x, t, q, tws, fold);
             lds_put<LOGS, LINES, COLS, P::P0L, P::P0H>(lds, x, line, t);
         }
         __syncthreads();
         if (active) {
             lds_get<LOGS, LINES, COLS, P::P1L, P::P1H>(lds, x, line, t);
-            phase_regs<LOGS, COLS, true, P::P1L, P::P1H>(x, t, row, n1, q, tw, fold);
+            phase_regs<LOGS, true, FOLD, P::P1L, P::P1H>(x, t, q, tws, fold);
         }
         if constexpr (P::THREE) {
             __syncthreads();
@@ -162,13 +171,13 @@ __device__ __forceinline__ void pass_regs(bool active, uint64_t (&x)[16], uint64
             __syncthreads();
             if (active) {
                 lds_get<LOGS, LINES, COLS, P::P2L, P::P2H>(lds, x, line, t);
-                phase_regs<LOGS, COLS, true, P::P2L, P::P2H>(x, t, row, n1, q, tw, fold);
+                phase_regs<LOGS, true, FOLD, P::P2L, P::P2H>(x, t, q, tws, fold);
             }
         }
     } else {
         if constexpr (P::THREE) {
             if (active) {
-                phase_regs<LOGS, COLS, false, P::P2L, P::P2H>(x, t, row, n1, q, tw, fold);
+                phase_regs<LOGS, false, FOLD, P::P2L, P::P2H>(x, t, q, tws, fold);
                 lds_put<LOGS, LINES, COLS, P::P2L, P::P2H>(lds, x, line, t);
             }
             __syncthreads();
@@ -176,13 +185,13 @@ __device__ __forceinline__ void pass_regs(bool active, uint64_t (&x)[16], uint64
             __syncthreads();
         }
         if (active) {
-            phase_regs<LOGS, COLS, false, P::P1L, P::P1H>(x, t, row, n1, q, tw, fold);
+            phase_regs<LOGS, false, FOLD, P::P1L, P::P1H>(x, t, q, tws, fold);
             lds_put<LOGS, LINES, COLS, P::P1L, P::P1H>(lds, x, line, t);
         }
         __syncthreads();
         if (active) {
             lds_get<LOGS, LINES, COLS, P::P0L, P::P0H>(lds, x, line, t);
-            phase_regs<LOGS, COLS, false, P::P0L, P::P0H>(x, t, row, n1, q, tw, fold);
+            phase_regs<LOGS, false, FOLD, P::P0L, P::P0H>(x, t, q, tws, fold);
         }
     }
 }
@@ -312,7 +321,11 @@ __global__ void __launch_bounds__((Tile<LOGS, LINES, COLS>::NT)) ntt_pass_kernel
     }
 
     const LastInv fold = (!FWD && COLS) ? a.li[a.m.cidx[li]] : LastInv{};
-    pass_regs<LOGS, LINES, COLS, FWD>(true, x, lds, line, t, lg, a.n1, q, tw, fold);
+    if constexpr (COLS) {
+        pass_regs<LOGS, LINES, COLS, FWD>(true, x, lds, line, t, q, TwCols{tw}, fold);
+    } else {
+        pass_regs<LOGS, LINES, COLS, FWD>(true, x, lds, line, t, q, TwRows{tw, lg, a.n1}, fold);
+    }
 
     if (IO == IO_MDEPI) {
         const uint32_t ui = a.m.cidx[li];
@@ -485,33 +498,39 @@ hipError_t launch_rows_mdepi(const Ctx &c, const LimbMap &m, const uint64_t *zc,
     return dispatch_pass<false, true, IO_MDEPI>(a, c.n2, m.count, batch, s);
 }
 
-// ------------------------------------------------------------------ KSKInnerProd (+ ModDown's first P pass)
+// ------------------------------------------------------------------ KSKInnerProd (+ ModUp's last pass, + ModDown's first)
 
+#ifndef KSK_WAVES
+#define KSK_WAVES
+#endif
 struct KskRowArgs {
-    const uint64_t *ext;     // [beta][E][N] extended digits in evaluation form (converted limbs)
+    const uint64_t *ext;     // [beta][E][N] converted limbs: after the forward column pass (rowpass) or in evaluation form
     const uint64_t *direct;  // digit j's own limb t at direct + j*dstride + t*N (gathered by `galois`)
     const uint64_t *ksk;     // [dnum][2][L+K][N]
     uint64_t *uq;            // [2][level][N] KSKInnerProd on the q limbs
     uint64_t *pc;            // [2][K][N] P limbs after the inverse row pass
-    const Shoup *twi;
+    const Shoup *twf, *twi;
     const ModC *mc;
     size_t dstride;
     uint32_t n, n1, n2, level, L, K, E, alpha, beta, galois, all_direct;
 };
 
-// One block = one target limb t of Q_level U P and ROW_LINES rows.  Each
-// thread streams its elements (coalesced): u_t = sum_j x_j ksk[j][0][t],
-// v_t = sum_j x_j ksk[j][1][t] over the beta digits (products reduced by
-// Barrett into canonical sums), x_j from the extended digit (evaluation form)
-// or, for the digit's own limb, from the input gathered through the
-// automorph.  q limbs store (u_t, v_t); special-prime limbs keep (u, v) in LDS
-// and run ModDown's inverse row pass on both before storing.
-template <int LOGS>
-__global__ void __launch_bounds__((Tile<LOGS, ROW_LINES, false>::NT)) ksk_rows_kernel(const KskRowArgs a) {
+// One block = one target limb t of Q_level U P and ROW_LINES rows, in the
+// row-pass layout (each thread 16 elements of one row).  For each digit j:
+// the converted limb x_{j,t} gets the forward row pass on chip (ROWPASS: the
+// last pass of ModUp's NTT; lazy values < 2^56), or the digit's own limb is
+// read from the input through the automorph; then u_t += x ksk[j][0][t],
+// v_t += x ksk[j][1][t] (Barrett products of the lazy value and the key,
+// canonical sums).  q limbs store (u_t, v_t); special-prime limbs run
+// ModDown's inverse row pass on both in registers before storing (the
+// forward pass ends in the layout the inverse pass starts from).
+template <int LOGS, bool ROWPASS>
+__global__ void __launch_bounds__((Tile<LOGS, ROW_LINES, false>::NT)) KSK_WAVES ksk_rows_kernel(const KskRowArgs a) {
     using TL = Tile<LOGS, ROW_LINES, false>;
+    using IOF = IoLayout<LOGS, true>;
     using IOI = IoLayout<LOGS, false>;
-    constexpr int CH = 4;
-    __shared__ uint64_t lds[2][TL::WORDS];
+    static_assert(IOF::OUT_LO == IOI::IN_LO && IOF::OUT_HI == IOI::IN_HI, "row-pass layouts must chain");
+    __shared__ uint64_t lds[TL::WORDS];
     const uint32_t tiles = (1u << a.n1) / ROW_LINES;
     const uint32_t tgt = blockIdx.x / tiles;
     const uint32_t tile = blockIdx.x % tiles;
@@ -519,77 +538,82 @@ __global__ void __launch_bounds__((Tile<LOGS, ROW_LINES, false>::NT)) ksk_rows_k
     const uint32_t mod = tgt < a.level ? tgt : a.L + (tgt - a.level);
     const ModC mcv = a.mc[mod];
     const uint64_t q = mcv.q;
-    const int tid = threadIdx.x;
-    const uint32_t line0 = tile * ROW_LINES;
     const size_t KL = (size_t)a.L + a.K;
     const uint32_t own = (tgt < a.level) ? tgt / a.alpha : 0xffffffffu;
     const bool is_p = tgt >= a.level;
     const uint32_t kp = tgt - a.level;
-    uint64_t *ou = is_p ? a.pc + (size_t)kp * N : a.uq + (size_t)tgt * N;
-    uint64_t *ov = is_p ? a.pc + ((size_t)a.K + kp) * N : a.uq + ((size_t)a.level + tgt) * N;
-
-#pragma unroll 1
-    for (int i0 = 0; i0 < TL::EPT; i0 += CH) {
-        uint32_t jj[CH];
-        int li[CH];
-        uint64_t u[CH], v[CH];
-#pragma unroll
-        for (int c = 0; c < CH; ++c) {
-            int ln, k;
-            elem_coords<LOGS, ROW_LINES, false>(tid + (i0 + c) * TL::NT, line0, a.n2, ln, k, jj[c]);
-            li[c] = TL::idx(ln, k);
-            u[c] = v[c] = 0;
-        }
-        for (uint32_t jd = 0; jd < a.beta; ++jd) {
-            const uint64_t *k0 = a.ksk + ((size_t)(2 * jd) * KL + mod) * N;
-            const uint64_t *k1 = k0 + KL * N;
-            const bool dir = a.all_direct || jd == own;
-            const uint64_t *src = dir ? a.direct + jd * a.dstride + (size_t)tgt * N
-                                      : a.ext + ((size_t)jd * a.E + tgt) * N;
-            uint64_t xv[CH], kv0[CH], kv1[CH];
-#pragma unroll
-            for (int c = 0; c < CH; ++c) {
-                const uint32_t sj = (dir && a.galois != 1) ? aut_eval_src(jj[c], a.galois, a.n) : jj[c];
-                xv[c] = src[sj];
-                kv0[c] = k0[jj[c]];
-                kv1[c] = k1[jj[c]];
-            }
-#pragma unroll
-            for (int c = 0; c < CH; ++c) {
-                u[c] = add_mod(u[c], mul_mod(xv[c], kv0[c], q, mcv.mu), q);
-                v[c] = add_mod(v[c], mul_mod(xv[c], kv1[c], q, mcv.mu), q);
-            }
-        }
-#pragma unroll
-        for (int c = 0; c < CH; ++c) {
-            if (is_p) {
-                lds[0][li[c]] = u[c];
-                lds[1][li[c]] = v[c];
-            } else {
-                ou[jj[c]] = u[c];
-                ov[jj[c]] = v[c];
-            }
-        }
-    }
-    if (!is_p) return;
-
-    // special-prime limb: inverse row pass (first pass of ModDown's iNTT) of u and v
-    __syncthreads();
     int line, t;
-    thread_coords<LOGS, ROW_LINES, false>(tid, line, t);
-    const uint32_t lg = line0 + line;
-    const Shoup *twi = a.twi + (size_t)mod * N;
+    thread_coords<LOGS, ROW_LINES, false>(threadIdx.x, line, t);
+    const uint32_t lg = tile * ROW_LINES + line;
+
+    uint64_t u[16], v[16];
 #pragma unroll
-    for (int poly = 0; poly < 2; ++poly) {
+    for (int e = 0; e < 16; ++e) u[e] = v[e] = 0;
+    bool lds_used = false;
+    for (uint32_t jd = 0; jd < a.beta; ++jd) {
+        const bool dir = a.all_direct || jd == own;
         uint64_t x[16];
-        lds_get<LOGS, ROW_LINES, false, IOI::IN_LO, IOI::IN_HI>(lds[poly], x, line, t);
-        __syncthreads();
-        pass_regs<LOGS, ROW_LINES, false, false>(true, x, lds[poly], line, t, lg, a.n1, q, twi, LastInv{});
-        gstore<LOGS, false, IOI::OUT_LO, IOI::OUT_HI>(x, poly ? ov : ou, t, lg, a.n2);
+        if (dir) {
+            const uint64_t *src = a.direct + jd * a.dstride + (size_t)tgt * N;
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const uint32_t j = jdx<false>(lg, k_of<IOF::OUT_LO, IOF::OUT_HI>(t, e), a.n2);
+                x[e] = src[a.galois != 1 ? aut_eval_src(j, a.galois, a.n) : j];
+            }
+        } else {
+            const uint64_t *src = a.ext + ((size_t)jd * a.E + tgt) * N;
+            if (ROWPASS) {
+                gload<LOGS, false, IOF::IN_LO, IOF::IN_HI>(x, src, t, lg, a.n2);
+                if (lds_used) __syncthreads();
+                pass_regs<LOGS, ROW_LINES, false, true>(true, x, lds, line, t, q,
+                                                        TwRows{a.twf + (size_t)mod * N, lg, a.n1}, LastInv{});
+                lds_used = true;
+            } else {
+                gload<LOGS, false, IOF::OUT_LO, IOF::OUT_HI>(x, src, t, lg, a.n2);
+            }
+        }
+        // the key rows in the same layout: 16 consecutive words per thread
+        static_assert(IOF::OUT_LO == 0, "forward row pass ends with 16 consecutive elements per thread");
+        const ulonglong2 *k0 =
+            reinterpret_cast<const ulonglong2 *>(a.ksk + ((size_t)(2 * jd) * KL + mod) * N + (lg << a.n2) + 16 * t);
+        const ulonglong2 *k1 = k0 + KL * N / 2;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const ulonglong2 kv0 = k0[c], kv1 = k1[c];
+            u[2 * c] = add_mod(u[2 * c], mul_mod(x[2 * c], kv0.x, q, mcv.mu), q);
+            u[2 * c + 1] = add_mod(u[2 * c + 1], mul_mod(x[2 * c + 1], kv0.y, q, mcv.mu), q);
+            v[2 * c] = add_mod(v[2 * c], mul_mod(x[2 * c], kv1.x, q, mcv.mu), q);
+            v[2 * c + 1] = add_mod(v[2 * c + 1], mul_mod(x[2 * c + 1], kv1.y, q, mcv.mu), q);
+        }
     }
+    if (!is_p) {
+        gstore<LOGS, false, IOF::OUT_LO, IOF::OUT_HI>(u, a.uq + (size_t)tgt * N, t, lg, a.n2);
+        gstore<LOGS, false, IOF::OUT_LO, IOF::OUT_HI>(v, a.uq + ((size_t)a.level + tgt) * N, t, lg, a.n2);
+        return;
+    }
+    // special-prime limb: inverse row pass (first pass of ModDown's iNTT) of u and v
+    const TwRows twi{a.twi + (size_t)mod * N, lg, a.n1};
+    if (lds_used) __syncthreads();
+    pass_regs<LOGS, ROW_LINES, false, false>(true, u, lds, line, t, q, twi, LastInv{});
+    gstore<LOGS, false, IOI::OUT_LO, IOI::OUT_HI>(u, a.pc + (size_t)kp * N, t, lg, a.n2);
+    __syncthreads();
+    pass_regs<LOGS, ROW_LINES, false, false>(true, v, lds, line, t, q, twi, LastInv{});
+    gstore<LOGS, false, IOI::OUT_LO, IOI::OUT_HI>(v, a.pc + ((size_t)a.K + kp) * N, t, lg, a.n2);
 }
 
-hipError_t launch_ksk_rows(const Ctx &c, const uint64_t *ext, const uint64_t *direct, size_t dstride,
+template <bool ROWPASS>
+static hipError_t launch_ksk_rows_t(const KskRowArgs &a, uint32_t n2, dim3 grid, hipStream_t s) {
+    switch (n2) {
+        case 5: hipLaunchKernelGGL((ksk_rows_kernel<5, ROWPASS>), grid, dim3(Tile<5, ROW_LINES, false>::NT), 0, s, a); break;
+        case 6: hipLaunchKernelGGL((ksk_rows_kernel<6, ROWPASS>), grid, dim3(Tile<6, ROW_LINES, false>::NT), 0, s, a); break;
+        case 7: hipLaunchKernelGGL((ksk_rows_kernel<7, ROWPASS>), grid, dim3(Tile<7, ROW_LINES, false>::NT), 0, s, a); break;
+        case 8: hipLaunchKernelGGL((ksk_rows_kernel<8, ROWPASS>), grid, dim3(Tile<8, ROW_LINES, false>::NT), 0, s, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_ksk_rows(const Ctx &c, const uint64_t *ext, bool rowpass, const uint64_t *direct, size_t dstride,
                            uint32_t all_direct, const uint64_t *ksk, uint32_t level, uint32_t galois,
                            uint64_t *uq, uint64_t *pc, hipStream_t s) {
     KskRowArgs a{};
@@ -600,6 +624,7 @@ hipError_t launch_ksk_rows(const Ctx &c, const uint64_t *ext, const uint64_t *di
     a.ksk = ksk;
     a.uq = uq;
     a.pc = pc;
+    a.twf = c.tw_fwd;
     a.twi = c.tw_inv;
     a.mc = c.mc;
     a.n = c.log_n;
@@ -614,15 +639,8 @@ hipError_t launch_ksk_rows(const Ctx &c, const uint64_t *ext, const uint64_t *di
     a.galois = galois;
     ProfScope ps(c, HKS_K_KSK, s);
     const uint32_t tiles = (1u << c.n1) / ROW_LINES;
-    dim3 grid(tiles * a.E);
-    switch (c.n2) {
-        case 5: hipLaunchKernelGGL(ksk_rows_kernel<5>, grid, dim3(Tile<5, ROW_LINES, false>::NT), 0, s, a); break;
-        case 6: hipLaunchKernelGGL(ksk_rows_kernel<6>, grid, dim3(Tile<6, ROW_LINES, false>::NT), 0, s, a); break;
-        case 7: hipLaunchKernelGGL(ksk_rows_kernel<7>, grid, dim3(Tile<7, ROW_LINES, false>::NT), 0, s, a); break;
-        case 8: hipLaunchKernelGGL(ksk_rows_kernel<8>, grid, dim3(Tile<8, ROW_LINES, false>::NT), 0, s, a); break;
-        default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+    const dim3 grid(tiles * a.E);
+    return rowpass ? launch_ksk_rows_t<true>(a, c.n2, grid, s) : launch_ksk_rows_t<false>(a, c.n2, grid, s);
 }
 
 }  // namespace hks
