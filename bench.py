@@ -46,18 +46,17 @@ def kernel_work(cls: int, n: int, level: int, k: int, alpha: int, beta: int):
     """Algorithmic modular multiplications of one Rotate done by kernel class
     `cls` (butterflies for NTT passes, product terms for the conversion and
     KSKInnerProd) and the algorithmic HBM bytes it moves (8-byte words: each
-    limb read once and written once per pass)."""
+    limb a launch touches read once and written once)."""
     n1 = LOG_N // 2
     n2 = LOG_N - n1
     E = level + k
-    own = level  # limbs copied from the input, one per digit member
-    new_limbs = beta * E - own
-    fwd_limbs = new_limbs + 2 * level  # ModUp's new limbs + ModDown's corrections (u and v)
+    new_limbs = beta * E - level  # ModUp's converted limbs (the digits' own limbs are not copied)
     half = n // 2
-    if cls == 0:  # forward NTT, column pass
-        return fwd_limbs * half * n1, fwd_limbs * n * 16
-    if cls == 1:  # forward NTT, row pass (+ ModDown epilogue on the corrections)
-        return fwd_limbs * half * n2, (fwd_limbs * 16 + 2 * level * 8 + level * 8) * n
+    if cls == 0:  # forward NTT, column pass: ModUp's new limbs + ModDown's corrections (u and v)
+        limbs = new_limbs + 2 * level
+        return limbs * half * n1, limbs * n * 16
+    if cls == 1:  # forward NTT, row pass of the corrections + ModDown epilogue (reads u, and b for v)
+        return 2 * level * half * n2, (2 * level * 16 + 2 * level * 8 + level * 8) * n
     if cls == 2:  # inverse NTT, row pass of the input limbs (automorph gathered)
         return level * half * n2, level * n * 16
     if cls == 3:  # inverse NTT, column pass (+ folded scale on half the outputs): input + P limbs
@@ -70,8 +69,10 @@ def kernel_work(cls: int, n: int, level: int, k: int, alpha: int, beta: int):
             terms += sz * (E - sz)
         terms += 2 * k * level
         return terms * n, (level + new_limbs + 2 * k + 2 * level) * n * 8
-    if cls == 5:  # KSKInnerProd: 2 rows x beta digits x E limbs (+ inverse row pass of 2K P limbs)
-        return 2 * beta * E * n + 2 * k * half * n2, (beta * E + 2 * beta * E + 2 * E) * n * 8
+    if cls == 5:  # KSKInnerProd fused with ModUp's row pass and ModDown's first inverse pass (P limbs)
+        mm = 2 * beta * E * n + new_limbs * half * n2 + 2 * k * half * n2
+        words = beta * 2 * E + new_limbs + level + 2 * level + 2 * k  # key, ext, own digits, u/v out, P out
+        return mm, words * n * 8
     return 0, 0
 
 
@@ -121,6 +122,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--pool", type=int, default=8)
+    ap.add_argument("--batch", type=int, default=8, help="ciphertexts per batched launch step (extras)")
     ap.add_argument("--cpu-sample", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
@@ -142,7 +144,7 @@ def main():
     torch.cuda.init()
     pq = hks.hks_gen_primes(50, LOG_N + 1, L + K)
     q, p = pq[:L], pq[L:]
-    ctx = hks.Context(LOG_N, q, p, DNUM)
+    ctx = hks.Context(LOG_N, q, p, DNUM, max_batch=args.batch)
     n = 1 << LOG_N
     alpha = ctx.alpha
     beta = ctx.beta(LEVEL)
@@ -263,27 +265,35 @@ def main():
     }
 
     if not args.no_extras:
-        # hoisted rotations (Algorithm 4): one ModUp shared by r rotations
-        r = min(args.pool, 8)
-        gals = [hks.hks_galois_for_rotation(k_ + 1, LOG_N) for k_ in range(r)]
-        hks.hks_hrotate(ctx, cts[0], LEVEL, gals, ksks[:r], outs[:r], stream)
-        torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        reps = max(2, args.steps // (4 * r))
-        e0.record(stream)
-        for i in range(reps):
-            hks.hks_hrotate(ctx, cts[i % args.pool], LEVEL, gals, ksks[:r], outs[:r], stream)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        result["hrotate_r8_ks_per_s"] = reps * r / (e0.elapsed_time(e1) / 1e3)
-        # batch of ciphertexts sharing one key
-        nb_ct = args.pool
-        e0.record(stream)
-        for i in range(reps):
-            hks.hks_batch_rotate(ctx, cts, LEVEL, [gal] * nb_ct, [ksks[0]] * nb_ct, outs, stream)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        result[f"batch{nb_ct}_shared_key_ks_per_s"] = reps * nb_ct / (e0.elapsed_time(e1) / 1e3)
+
+        def rate(fn, per_call, reps):
+            fn(0)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            for i in range(reps):
+                fn(i + 1)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            return reps * per_call / (e0.elapsed_time(e1) / 1e3)
+
+        nb = min(args.batch, args.pool)
+        reps = max(4, args.steps // (2 * nb))
+        # hoisted rotations (Algorithm 4): one ModUp shared by nb rotations, nb distinct keys
+        gals = [hks.hks_galois_for_rotation(k_ + 1, LOG_N) for k_ in range(nb)]
+        result[f"hrotate_r{nb}_ks_per_s"] = rate(
+            lambda i: hks.hks_hrotate(ctx, cts[i % args.pool], LEVEL, gals, ksks[:nb], outs[:nb], stream), nb, reps)
+        # nb ciphertexts rotated by one galois element with one shared key
+        result[f"batch{nb}_shared_key_ks_per_s"] = rate(
+            lambda i: hks.hks_batch_rotate(ctx, cts[:nb], LEVEL, [gal] * nb, [ksks[i % args.pool]] * nb,
+                                           outs[:nb], stream), nb, reps)
+        # nb ciphertexts, distinct rotation indices and keys
+        result[f"batch{nb}_distinct_keys_ks_per_s"] = rate(
+            lambda i: hks.hks_batch_rotate(ctx, cts[:nb], LEVEL, gals, ksks[:nb], outs[:nb], stream), nb, reps)
+        result["batch_vs_plain"] = result[f"batch{nb}_shared_key_ks_per_s"] / value
+        log(f"[bench] hrotate r={nb}: {result[f'hrotate_r{nb}_ks_per_s']:.0f} ks/s; batch {nb} shared key: "
+            f"{result[f'batch{nb}_shared_key_ks_per_s']:.0f} ks/s; distinct keys: "
+            f"{result[f'batch{nb}_distinct_keys_ks_per_s']:.0f} ks/s")
 
     if args.calib_copy_mib:
         nw = args.calib_copy_mib * (1 << 20) // 8

@@ -67,7 +67,7 @@ extern "C" {
 #define HKS_Q_L 7
 #define HKS_Q_K 8
 #define HKS_Q_DNUM 9
-#define HKS_Q_BATCH_CAP 10     /* ciphertexts processed per internal batch step */
+#define HKS_Q_BATCH_CAP 10     /* ciphertexts (or rotations) per batched launch step */
 
 typedef struct hks_ctx hks_ctx;
 
@@ -78,6 +78,10 @@ typedef struct {
     uint32_t dnum;        /* digits of the switching key, 1..L */
     const uint64_t *q;    /* host array [L] */
     const uint64_t *p;    /* host array [K] */
+    uint32_t max_batch;   /* ciphertexts (or rotations) per batched launch step,
+                             0..16 (0 = 1).  The workspace holds one slot per
+                             step entry: (L + dnum(L+K) + 2(L+K) + 2K + 2L) N
+                             words each, plus 7 L N + 2 N words shared. */
 } hks_params;
 
 /* ---------------------------------------------------------------- host helpers */
@@ -157,15 +161,20 @@ int hks_rotate(hks_ctx *ctx, const uint64_t *ct, uint32_t level, uint32_t galois
  * extended digits by galois[i], KSKInnerProd with ksk[i], ModDown x2, add the
  * automorphed b.  galois, ksk, ct_out are HOST arrays of r entries (ksk[i] and
  * ct_out[i] device pointers).  Bits differ from r calls of hks_rotate (the
- * automorphism is applied after the uncorrected conversion). */
+ * automorphism is applied after the uncorrected conversion).  Rotations are
+ * processed max_batch at a time, each step in one KSKInnerProd launch and
+ * one ModDown sequence. */
 int hks_hrotate(hks_ctx *ctx, const uint64_t *ct, uint32_t level, uint32_t r,
                 const uint32_t *galois, const uint64_t *const *ksk, uint64_t *const *ct_out,
                 void *stream);
 
 /* Rotate of n_ct independent ciphertexts at one level (same semantics and
- * bits as n_ct calls of hks_rotate).  ct, galois, ksk, ct_out are HOST
- * arrays of n_ct entries.  Ciphertexts sharing a key pointer and galois
- * element are key-switched together so that key limbs are read once. */
+ * bits as n_ct calls of hks_rotate; the hoisting / batching of Sec. 4).  ct,
+ * galois, ksk, ct_out are HOST arrays of n_ct entries; galois elements and
+ * keys may differ per ciphertext.  Up to max_batch ciphertexts share every
+ * launch of a step; the blocks of one key tile run on one XCD, so a key
+ * shared by the step is streamed from HBM once.  HKS_EINVAL if an output
+ * equals any input or another output. */
 int hks_batch_rotate(hks_ctx *ctx, uint32_t n_ct, const uint64_t *const *ct, uint32_t level,
                      const uint32_t *galois, const uint64_t *const *ksk, uint64_t *const *ct_out,
                      void *stream);

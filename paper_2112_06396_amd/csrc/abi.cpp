@@ -68,29 +68,37 @@ struct Lists {
 
 uint32_t beta_of(const Ctx &c, uint32_t level) { return (level + c.alpha - 1) / c.alpha; }
 
-// ModUp of the converted limbs (Algorithm "ModUp"):
-//   iNTT of the level limbs of `a` (gathered through the automorph `galois`),
-//   scaled by N^-1 [(Qt_j/q_i)^-1]_{q_i} -> ws_y (coefficient form);
-//   NewLimb of every digit into every other limb of Q_level U P -> ext[j][t];
+// ModUp of the converted limbs (Algorithm "ModUp") of nb polynomials at
+// once; entry b uses workspace slot b:
+//   iNTT of the level limbs of a[b] (gathered through the automorph
+//   galois[b]), scaled by N^-1 [(Qt_j/q_i)^-1]_{q_i} -> ws_y (coefficient form);
+//   NewLimb of every digit into every other limb of Q_level U P ->
+//   ext + b*ext_bstride, [j][t];
 //   forward NTT of those limbs in place (own-digit slots untouched): both
 //   passes, or with cols_only just the column pass (the key-switch kernel
 //   runs the row pass on chip).
-int do_modup_new(Ctx &c, const uint64_t *a, uint32_t level, uint32_t galois, uint64_t *ext, hipStream_t s,
-                 bool cols_only = false) {
+int do_modup_new(Ctx &c, const uint64_t *const *a, const uint32_t *galois, uint32_t nb, uint32_t level,
+                 uint64_t *ext, size_t ext_bstride, hipStream_t s, bool cols_only) {
     const uint32_t A = c.alpha, E = level + c.K, beta = beta_of(c, level);
     Lists inv, nl;
     for (uint32_t i = 0; i < level; ++i) inv.add(i, i, i, level * c.L + i);
-    HKS_TRY(inv.run([&](const LimbMap &m) {
-        return launch_ntt_inv(c, m, a, c.ws_y, c.li_modup, galois, 1, 0, 0, s);
-    }));
-    HKS_TRY(launch_conv_modup(c, c.ws_y, level, ext, s));
+    BatchIo io{};
+    for (uint32_t b = 0; b < nb; ++b) {
+        io.in[b] = a[b];
+        io.out[b] = c.ws_y + b * c.st_y();
+        io.galois[b] = galois[b];
+        io.add_galois[b] = 1;
+    }
+    HKS_TRY(inv.run([&](const LimbMap &m) { return launch_ntt_inv(c, m, io, c.li_modup, nb, s); }));
+    HKS_TRY(launch_conv_modup(c, c.ws_y, level, ext, nb, c.st_y(), ext_bstride, s));
     for (uint32_t j = 0; j < beta; ++j) {
         const uint32_t lo = j * A, hi = std::min((j + 1) * A, level);
         for (uint32_t t = 0; t < E; ++t)
             if (t < lo || t >= hi) nl.add(j * E + t, j * E + t, ext_mod(c, level, t), 0);
     }
+    const BatchIo eio = strided_io(ext, ext_bstride, ext, ext_bstride, nb);
     HKS_TRY(nl.run([&](const LimbMap &m) {
-        return cols_only ? launch_ntt_fwd_cols(c, m, ext, ext, 1, 0, 0, s) : launch_ntt_fwd(c, m, ext, ext, 1, 0, 0, s);
+        return cols_only ? launch_ntt_fwd_cols(c, m, eio, nb, s) : launch_ntt_fwd(c, m, eio, nb, s);
     }));
     return HKS_OK;
 }
@@ -107,44 +115,75 @@ int do_modup_own(Ctx &c, const uint64_t *a, uint32_t level, uint32_t galois, uin
     return HKS_OK;
 }
 
-// ModDown of `batch` polynomials after ksk_rows: P limbs (already through
-// the inverse row pass, in ws_p) -> inverse column pass scaled by
-// N^-1 [(P/p_k)^-1]_{p_k}; NewLimb into the q limbs; forward column pass;
-// row pass + (u - z) P^-1 (+ add).  u in uq [batch][level][N].
-int do_moddown_tail(Ctx &c, const uint64_t *uq, size_t uq_bstride, uint32_t level, uint64_t *out, uint32_t batch,
-                    size_t out_bstride, const uint64_t *add, uint32_t add_galois, uint32_t add_mask,
-                    size_t add_pstride, hipStream_t s) {
+// ModDown of np polynomials whose P limbs went through the inverse row pass
+// into ws_p (polynomial p at ws_p + p*K*N): inverse column pass scaled by
+// N^-1 [(P/p_k)^-1]_{p_k}; NewLimb into the q limbs (ws_z + p*L*N); forward
+// column pass; row pass + (u - z) P^-1 (+ add), with u, the output, the
+// addend and its automorph per polynomial in `epi`.
+int do_moddown_tail(Ctx &c, uint32_t level, uint32_t np, BatchIo epi, hipStream_t s) {
     const uint32_t N = c.n, K = c.K, L = c.L;
+    const size_t pst = (size_t)K * N, zst = (size_t)L * N;
     Lists pl, ql;
     for (uint32_t k = 0; k < K; ++k) pl.add(k, k, L + k, k);
     for (uint32_t i = 0; i < level; ++i) ql.add(i, i, i, i);
-    HKS_TRY(pl.run([&](const LimbMap &m) {
-        return launch_ntt_inv_cols(c, m, c.ws_p, c.ws_p, c.li_moddown, batch, (size_t)K * N, (size_t)K * N, s);
-    }));
-    HKS_TRY(launch_conv_moddown(c, c.ws_p, level, c.ws_z, batch, (size_t)K * N, (size_t)L * N, s));
-    HKS_TRY(ql.run([&](const LimbMap &m) {
-        return launch_ntt_fwd_cols(c, m, c.ws_z, c.ws_z, batch, (size_t)L * N, (size_t)L * N, s);
-    }));
-    HKS_TRY(ql.run([&](const LimbMap &m) {
-        return launch_rows_mdepi(c, m, c.ws_z, out, uq, uq_bstride, add, add_galois, add_mask, add_pstride, batch,
-                                 (size_t)L * N, out_bstride, s);
-    }));
+    const BatchIo pio = strided_io(c.ws_p, pst, c.ws_p, pst, np);
+    HKS_TRY(pl.run([&](const LimbMap &m) { return launch_ntt_inv_cols(c, m, pio, c.li_moddown, np, s); }));
+    HKS_TRY(launch_conv_moddown(c, c.ws_p, level, c.ws_z, np, pst, zst, s));
+    const BatchIo zio = strided_io(c.ws_z, zst, c.ws_z, zst, np);
+    HKS_TRY(ql.run([&](const LimbMap &m) { return launch_ntt_fwd_cols(c, m, zio, np, s); }));
+    for (uint32_t p = 0; p < np; ++p) epi.in[p] = c.ws_z + p * zst;
+    HKS_TRY(ql.run([&](const LimbMap &m) { return launch_rows_mdepi(c, m, epi, np, s); }));
     return HKS_OK;
 }
 
-// KeySwitch of d (level limbs, gathered through `galois`) into uv [2][level][N]
-// with the ModDown additions (9 launches); the digits' own limbs are read
-// from d in the KSKInnerProd kernel (never copied), which also runs the
-// last forward pass of ModUp's NTT.
-int do_keyswitch(Ctx &c, const uint64_t *d, uint32_t level, uint32_t galois, const uint64_t *ksk,
-                 uint64_t *uv, const uint64_t *add, uint32_t add_galois, uint32_t add_mask,
-                 size_t add_pstride, hipStream_t s) {
-    const uint32_t N = c.n;
-    int rc = do_modup_new(c, d, level, galois, c.ws_ext, s, true);
+// One key-switch of a batch: d (level limbs, gathered through galois) with
+// key ksk into out [2][level][N]; after ModDown, out poly 0 += add0 and
+// poly 1 += add1 (each gathered through galois; null adds nothing).
+struct KsJob {
+    const uint64_t *d;
+    uint32_t galois;
+    const uint64_t *ksk;
+    uint64_t *out;
+    const uint64_t *add0, *add1;
+};
+
+// KeySwitch of nb <= min(batch_cap, MAXCT) jobs in shared launches (9 per
+// step); the digits' own limbs are read from d in the KSKInnerProd kernel
+// (never copied), which also runs the last forward pass of ModUp's NTT.
+int do_keyswitch_step(Ctx &c, const KsJob *jobs, uint32_t nb, uint32_t level, hipStream_t s) {
+    const size_t pl = (size_t)level * c.n;
+    const uint64_t *d[MAXCT];
+    uint32_t g[MAXCT];
+    KskBatch kb{};
+    BatchIo epi{};
+    for (uint32_t b = 0; b < nb; ++b) {
+        d[b] = jobs[b].d;
+        g[b] = jobs[b].galois;
+        kb.direct[b] = jobs[b].d;
+        kb.ksk[b] = jobs[b].ksk;
+        kb.galois[b] = jobs[b].galois;
+        for (uint32_t poly = 0; poly < 2; ++poly) {
+            const uint32_t p = 2 * b + poly;
+            epi.uq[p] = c.ws_uv + b * c.st_uv() + poly * pl;
+            epi.out[p] = jobs[b].out + poly * pl;
+            epi.add[p] = poly ? jobs[b].add1 : jobs[b].add0;
+            epi.add_galois[p] = jobs[b].galois;
+        }
+    }
+    int rc = do_modup_new(c, d, g, nb, level, c.ws_ext, c.st_ext(), s, true);
     if (rc) return rc;
-    HKS_TRY(launch_ksk_rows(c, c.ws_ext, true, d, 0, 0, ksk, level, galois, c.ws_uv, c.ws_p, s));
-    return do_moddown_tail(c, c.ws_uv, (size_t)level * N, level, uv, 2, (size_t)level * N, add, add_galois,
-                           add_mask, add_pstride, s);
+    HKS_TRY(launch_ksk_rows(c, kb, nb, c.ws_ext, c.st_ext(), true, 0, 0, level, c.ws_uv, c.st_uv(), c.ws_p,
+                            c.st_p(), s));
+    return do_moddown_tail(c, level, 2 * nb, epi, s);
+}
+
+int do_keyswitch_jobs(Ctx &c, const KsJob *jobs, uint32_t n, uint32_t level, hipStream_t s) {
+    const uint32_t step = std::min<uint32_t>(c.batch_cap, MAXCT);
+    for (uint32_t i = 0; i < n; i += step) {
+        int rc = do_keyswitch_step(c, jobs + i, std::min(step, n - i), level, s);
+        if (rc) return rc;
+    }
+    return HKS_OK;
 }
 
 int do_rescale(Ctx &c, const uint64_t *ct, uint32_t level, uint64_t *out, hipStream_t s) {
@@ -152,13 +191,11 @@ int do_rescale(Ctx &c, const uint64_t *ct, uint32_t level, uint64_t *out, hipStr
     Lists last, rest;
     last.add(level - 1, 0, level - 1, level - 1);
     for (uint32_t i = 0; i + 1 < level; ++i) rest.add(i, i, i, 0);
-    HKS_TRY(last.run([&](const LimbMap &m) {
-        return launch_ntt_inv(c, m, ct, c.ws_r, c.li_plain, 1, 2, (size_t)level * N, N, s);
-    }));
+    const BatchIo lio = strided_io(ct, (size_t)level * N, c.ws_r, N, 2);
+    HKS_TRY(last.run([&](const LimbMap &m) { return launch_ntt_inv(c, m, lio, c.li_plain, 2, s); }));
     HKS_TRY(launch_rescale_prep(c, c.ws_r, c.ws_w, level, 2, N, (size_t)(level - 1) * N, s));
-    HKS_TRY(rest.run([&](const LimbMap &m) {
-        return launch_ntt_fwd(c, m, c.ws_w, c.ws_w, 2, (size_t)(level - 1) * N, (size_t)(level - 1) * N, s);
-    }));
+    const BatchIo wio = strided_io(c.ws_w, (size_t)(level - 1) * N, c.ws_w, (size_t)(level - 1) * N, 2);
+    HKS_TRY(rest.run([&](const LimbMap &m) { return launch_ntt_fwd(c, m, wio, 2, s); }));
     HKS_TRY(launch_rescale_epi(c, ct, c.ws_w, out, level, 2, (size_t)level * N, (size_t)(level - 1) * N,
                                (size_t)(level - 1) * N, s));
     return HKS_OK;
@@ -226,6 +263,7 @@ int hks_create(const hks_params *p, int device, hks_ctx **out) {
     if (p->L < 1 || p->L > 48 || p->K < 1 || p->K > 16 || p->dnum < 1 || p->dnum > p->L) return HKS_EINVAL;
     const uint32_t alpha = (p->L + p->dnum - 1) / p->dnum;
     if (p->K < alpha || alpha > 16) return HKS_EINVAL;
+    if (p->max_batch > (uint32_t)MAXCT) return HKS_EINVAL;
     std::vector<uint64_t> mods(p->q, p->q + p->L);
     mods.insert(mods.end(), p->p, p->p + p->K);
     const uint64_t two_n = 2ull << p->log_n;
@@ -248,15 +286,15 @@ int hks_create(const hks_params *p, int device, hks_ctx **out) {
     c.dnum = p->dnum;
     c.alpha = alpha;
     c.M = p->L + p->K;
+    c.batch_cap = p->max_batch ? p->max_batch : 1;
     c.n1 = p->log_n / 2;
     c.n2 = p->log_n - c.n1;
     c.mods = mods;
     int rc = build_tables(c);
     if (rc == HKS_OK) {
-        const size_t N = c.n, L = c.L, K = c.K, M = c.M, cap = c.batch_cap;
-        size_t words[] = {cap * L * N,         cap * c.dnum * M * N, cap * 2 * M * N, cap * 2 * K * N,
-                          cap * 2 * L * N,     cap * 2 * L * N,      cap * 3 * L * N, cap * 2 * N,
-                          cap * 2 * L * N};
+        const size_t N = c.n, L = c.L, cap = c.batch_cap;
+        size_t words[] = {cap * c.st_y(), cap * c.st_ext(), cap * c.st_uv(), cap * c.st_p(), cap * c.st_z(),
+                          2 * L * N,      3 * L * N,        2 * N,           2 * L * N};
         size_t total = 0;
         for (size_t w : words) total += w;
         c.ws_bytes = total * sizeof(uint64_t);
@@ -325,7 +363,8 @@ int hks_ntt(hks_ctx *h, uint64_t *x, uint32_t first_mod, uint32_t n_limbs, void 
     Ctx &c = h->c;
     Lists ls;
     for (uint32_t i = 0; i < n_limbs; ++i) ls.add(i, i, first_mod + i, first_mod + i);
-    return hip_status(ls.run([&](const LimbMap &m) { return launch_ntt_fwd(c, m, x, x, 1, 0, 0, (hipStream_t)stream); }));
+    const BatchIo io = strided_io(x, 0, x, 0, 1);
+    return hip_status(ls.run([&](const LimbMap &m) { return launch_ntt_fwd(c, m, io, 1, (hipStream_t)stream); }));
     GUARD_END
 }
 
@@ -335,7 +374,9 @@ int hks_intt(hks_ctx *h, uint64_t *x, uint32_t first_mod, uint32_t n_limbs, void
     Ctx &c = h->c;
     Lists ls;
     for (uint32_t i = 0; i < n_limbs; ++i) ls.add(i, i, first_mod + i, first_mod + i);
-    return hip_status(ls.run([&](const LimbMap &m) { return launch_ntt_inv(c, m, x, x, c.li_plain, 1, 1, 0, 0, (hipStream_t)stream); }));
+    const BatchIo io = strided_io(x, 0, x, 0, 1);
+    return hip_status(
+        ls.run([&](const LimbMap &m) { return launch_ntt_inv(c, m, io, c.li_plain, 1, (hipStream_t)stream); }));
     GUARD_END
 }
 
@@ -361,7 +402,8 @@ int hks_modup(hks_ctx *h, const uint64_t *a, uint32_t level, uint64_t *ext, void
     GUARD_BEGIN
     if (!h || !a || !ext || !aligned(a) || !aligned(ext) || level < 1 || level > h->c.L) return HKS_EINVAL;
     hipStream_t s = (hipStream_t)stream;
-    int rc = do_modup_new(h->c, a, level, 1, ext, s);
+    const uint32_t one = 1;
+    int rc = do_modup_new(h->c, &a, &one, 1, level, ext, 0, s, false);
     return rc ? rc : do_modup_own(h->c, a, level, 1, ext, s);
     GUARD_END
 }
@@ -385,8 +427,13 @@ int hks_moddown(hks_ctx *h, const uint64_t *x, uint32_t level, uint64_t *y, void
     // P limbs: inverse row pass into ws_p (the column pass runs in the tail)
     Lists pl;
     for (uint32_t k = 0; k < c.K; ++k) pl.add(level + k, k, c.L + k, k);
-    HKS_TRY(pl.run([&](const LimbMap &m) { return launch_ntt_inv_rows(c, m, x, c.ws_p, 1, 0, 0, s); }));
-    return do_moddown_tail(c, x, 0, level, y, 1, 0, nullptr, 1, 0, 0, s);
+    const BatchIo pio = strided_io(x, 0, c.ws_p, 0, 1);
+    HKS_TRY(pl.run([&](const LimbMap &m) { return launch_ntt_inv_rows(c, m, pio, 1, s); }));
+    BatchIo epi{};
+    epi.uq[0] = x;
+    epi.out[0] = y;
+    epi.add_galois[0] = 1;
+    return do_moddown_tail(c, level, 1, epi, s);
     GUARD_END
 }
 
@@ -396,7 +443,8 @@ int hks_keyswitch(hks_ctx *h, const uint64_t *d, uint32_t level, const uint64_t 
     if (!h || !d || !ksk || !uv || !aligned(d) || !aligned(ksk) || !aligned(uv) || level < 1 ||
         level > h->c.L)
         return HKS_EINVAL;
-    return do_keyswitch(h->c, d, level, 1, ksk, uv, nullptr, 1, 0, 0, (hipStream_t)stream);
+    const KsJob job{d, 1, ksk, uv, nullptr, nullptr};
+    return do_keyswitch_jobs(h->c, &job, 1, level, (hipStream_t)stream);
     GUARD_END
 }
 
@@ -408,10 +456,10 @@ int hks_rotate(hks_ctx *h, const uint64_t *ct, uint32_t level, uint32_t galois, 
         return HKS_EINVAL;
     Ctx &c = h->c;
     if (!valid_galois(c, galois)) return HKS_EINVAL;
-    const size_t pl = (size_t)level * c.n;
-    // (u, v + b_rot): the ModDown epilogue adds b (poly 1 of ct, at ct + pl)
-    // gathered through the automorph to v (mask bit 1 only)
-    return do_keyswitch(c, ct, level, galois, ksk, ct_out, ct, galois, 2u, pl, (hipStream_t)stream);
+    // (u, v + b_rot): the ModDown epilogue adds b (poly 1 of ct) gathered
+    // through the automorph to v
+    const KsJob job{ct, galois, ksk, ct_out, nullptr, ct + (size_t)level * c.n};
+    return do_keyswitch_jobs(c, &job, 1, level, (hipStream_t)stream);
     GUARD_END
 }
 
@@ -427,14 +475,34 @@ int hks_hrotate(hks_ctx *h, const uint64_t *ct, uint32_t level, uint32_t r, cons
             return HKS_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     const uint32_t N = c.n, E = level + c.K;
-    int rc = do_modup_new(c, ct, level, 1, c.ws_ext, s);
+    const size_t pl = (size_t)level * N;
+    const uint32_t one = 1;
+    int rc = do_modup_new(c, &ct, &one, 1, level, c.ws_ext, 0, s, false);
     if (!rc) rc = do_modup_own(c, ct, level, 1, c.ws_ext, s);
     if (rc) return rc;
-    for (uint32_t i = 0; i < r; ++i) {
-        HKS_TRY(launch_ksk_rows(c, c.ws_ext, false, c.ws_ext, (size_t)E * N, 1, ksk[i], level, galois[i], c.ws_uv, c.ws_p,
-                                s));
-        rc = do_moddown_tail(c, c.ws_uv, (size_t)level * N, level, ct_out[i], 2, (size_t)level * N, ct, galois[i],
-                             2u, (size_t)level * N, s);
+    // rotations in steps of up to batch_cap: one KSKInnerProd launch over the
+    // shared extended digits (automorph gathered per rotation) and one ModDown
+    // sequence for the step's 2 * nb polynomials
+    const uint32_t step = std::min<uint32_t>(c.batch_cap, MAXCT);
+    for (uint32_t i0 = 0; i0 < r; i0 += step) {
+        const uint32_t nb = std::min(step, r - i0);
+        KskBatch kb{};
+        BatchIo epi{};
+        for (uint32_t b = 0; b < nb; ++b) {
+            kb.direct[b] = c.ws_ext;
+            kb.ksk[b] = ksk[i0 + b];
+            kb.galois[b] = galois[i0 + b];
+            for (uint32_t poly = 0; poly < 2; ++poly) {
+                const uint32_t p = 2 * b + poly;
+                epi.uq[p] = c.ws_uv + b * c.st_uv() + poly * pl;
+                epi.out[p] = ct_out[i0 + b] + poly * pl;
+                epi.add[p] = poly ? ct + pl : nullptr;
+                epi.add_galois[p] = galois[i0 + b];
+            }
+        }
+        HKS_TRY(launch_ksk_rows(c, kb, nb, c.ws_ext, 0, false, (size_t)E * N, 1, level, c.ws_uv, c.st_uv(), c.ws_p,
+                                c.st_p(), s));
+        rc = do_moddown_tail(c, level, 2 * nb, epi, s);
         if (rc) return rc;
     }
     return HKS_OK;
@@ -445,12 +513,18 @@ int hks_batch_rotate(hks_ctx *h, uint32_t n_ct, const uint64_t *const *ct, uint3
                      const uint32_t *galois, const uint64_t *const *ksk, uint64_t *const *ct_out,
                      void *stream) {
     GUARD_BEGIN
-    if (!h || !ct || !galois || !ksk || !ct_out || n_ct == 0) return HKS_EINVAL;
+    if (!h || !ct || !galois || !ksk || !ct_out || n_ct == 0 || level < 1 || level > h->c.L) return HKS_EINVAL;
+    Ctx &c = h->c;
+    std::vector<KsJob> jobs(n_ct);
     for (uint32_t i = 0; i < n_ct; ++i) {
-        int rc = hks_rotate(h, ct[i], level, galois[i], ksk[i], ct_out[i], stream);
-        if (rc) return rc;
+        if (!ct[i] || !ksk[i] || !ct_out[i] || !aligned(ct[i]) || !aligned(ksk[i]) || !aligned(ct_out[i]) ||
+            !valid_galois(c, galois[i]))
+            return HKS_EINVAL;
+        for (uint32_t j = 0; j < n_ct; ++j)
+            if (ct_out[i] == ct[j] || (j != i && ct_out[i] == ct_out[j])) return HKS_EINVAL;
+        jobs[i] = KsJob{ct[i], galois[i], ksk[i], ct_out[i], nullptr, ct[i] + (size_t)level * c.n};
     }
-    return HKS_OK;
+    return do_keyswitch_jobs(c, jobs.data(), n_ct, level, (hipStream_t)stream);
     GUARD_END
 }
 
@@ -487,7 +561,8 @@ int hks_mult_relin(hks_ctx *h, const uint64_t *ct1, const uint64_t *ct2, uint32_
     const size_t pl = (size_t)level * c.n;
     HKS_TRY(launch_tensor(c, ct1, ct2, c.ws_t, level, s));
     uint64_t *dst = rescale ? c.ws_rot : ct_out;
-    int rc = do_keyswitch(c, c.ws_t, level, 1, rlk, dst, c.ws_t + pl, 1, 3u, pl, s);
+    const KsJob job{c.ws_t, 1, rlk, dst, c.ws_t + pl, c.ws_t + 2 * pl};
+    int rc = do_keyswitch_jobs(c, &job, 1, level, s);
     if (rc || !rescale) return rc;
     return do_rescale(c, c.ws_rot, level, ct_out, s);
     GUARD_END

@@ -13,6 +13,8 @@
 namespace hks {
 
 constexpr int MAXL = 160;  // limbs per launch descriptor
+constexpr int MAXB = 32;   // batch entries (polynomials) per launch
+constexpr int MAXCT = 16;  // ciphertexts per batched key-switch step (two polynomials each)
 
 // A list of limbs for one launch.  Limb i is read at in_base + in_off[i]*N
 // (+ blockIdx.y * in_bstride for batches), written at out_base + out_off[i]*N,
@@ -25,6 +27,33 @@ struct LimbMap {
     uint8_t nsrc[MAXL];  // conversion: number of source limbs
     uint16_t cidx[MAXL];
 };
+
+// Per batch entry b of a pass launch: where its limbs are read and written.
+// Limb i of entry b is read at in[b] + in_off[i]*N and written at
+// out[b] + out_off[i]*N.  IO_GATHER reads through the automorph galois[b];
+// the ModDown epilogue reads u at uq[b] + cidx[i]*N and adds add[b] +
+// cidx[i]*N gathered through add_galois[b] (add[b] null: nothing added).
+struct BatchIo {
+    const uint64_t *in[MAXB];
+    uint64_t *out[MAXB];
+    const uint64_t *uq[MAXB];
+    const uint64_t *add[MAXB];
+    uint32_t galois[MAXB];
+    uint32_t add_galois[MAXB];
+};
+
+// Entries at fixed strides from two bases (workspace buffers).
+inline BatchIo strided_io(const uint64_t *in, size_t in_bstride, uint64_t *out, size_t out_bstride,
+                          uint32_t batch) {
+    BatchIo io{};
+    for (uint32_t b = 0; b < batch && b < (uint32_t)MAXB; ++b) {
+        io.in[b] = in + b * in_bstride;
+        io.out[b] = out + b * out_bstride;
+        io.galois[b] = 1;
+        io.add_galois[b] = 1;
+    }
+    return io;
+}
 
 // Per-modulus constants.
 struct ModC {
@@ -64,19 +93,25 @@ struct Ctx {
     uint64_t *rs_h = nullptr;          // [L+1][L]: ((q_{l-1}-1)/2) mod q_i
     LimbMap *dummy = nullptr;
 
-    // workspace (device), sized for the top level and batch capacity
+    // workspace (device), sized for the top level and the batch capacity:
+    // one slot per ciphertext of a batched key-switch step
     uint32_t batch_cap = 1;
     size_t ws_bytes = 0;
     uint64_t *ws = nullptr;
     uint64_t *ws_y = nullptr;    // [cap][L][N]          coefficient-form digits (ModUp)
     uint64_t *ws_ext = nullptr;  // [cap][dnum][L+K][N]  extended digits
-    uint64_t *ws_uv = nullptr;   // [cap][2][L+K][N]     KSKInnerProd output
+    uint64_t *ws_uv = nullptr;   // [cap][2][L+K][N]     KSKInnerProd output on the q limbs
     uint64_t *ws_p = nullptr;    // [cap][2][K][N]       ModDown P-limbs (coefficient form)
     uint64_t *ws_z = nullptr;    // [cap][2][L][N]       ModDown correction
-    uint64_t *ws_rot = nullptr;  // [cap][2][L][N]       automorphed input / tensor scratch
-    uint64_t *ws_t = nullptr;    // [cap][3][L][N]       tensor product
-    uint64_t *ws_r = nullptr;    // [cap][2][N]          Rescale: coefficient-form last limbs
-    uint64_t *ws_w = nullptr;    // [cap][2][L][N]       Rescale: rounding correction
+    uint64_t *ws_rot = nullptr;  // [2][L][N]            PtMult / Mult scratch before Rescale
+    uint64_t *ws_t = nullptr;    // [3][L][N]            tensor product
+    uint64_t *ws_r = nullptr;    // [2][N]               Rescale: coefficient-form last limbs
+    uint64_t *ws_w = nullptr;    // [2][L][N]            Rescale: rounding correction
+    size_t st_y() const { return (size_t)L * n; }
+    size_t st_ext() const { return (size_t)dnum * M * n; }
+    size_t st_uv() const { return (size_t)2 * M * n; }
+    size_t st_p() const { return (size_t)2 * K * n; }
+    size_t st_z() const { return (size_t)2 * L * n; }
 
     // kernel timing (hks_prof_*): event pairs per kernel class
     mutable uint32_t prof_mask = 0;
@@ -104,53 +139,51 @@ void free_tables(Ctx &c);
 
 // ---------------------------------------------------------------- launches (kernels.hip)
 // All return hipSuccess or the launch error.
-// Forward NTT of the limbs in `m` (in -> out; in == out allowed), batch copies
-// at strides in_bstride/out_bstride (words).  Input residues < 2^53; output
-// canonical [0, q).
-hipError_t launch_ntt_fwd(const Ctx &c, const LimbMap &m, const uint64_t *in, uint64_t *out,
-                          uint32_t batch, size_t in_bstride, size_t out_bstride, hipStream_t s);
-// Inverse NTT with the folded last stage `li[cidx]` (scale included); optional
-// eval-domain automorph gather of the input (galois != 1).  Output canonical.
-hipError_t launch_ntt_inv(const Ctx &c, const LimbMap &m, const uint64_t *in, uint64_t *out,
-                          const LastInv *li, uint32_t galois, uint32_t batch, size_t in_bstride,
-                          size_t out_bstride, hipStream_t s);
-// Forward NTT row pass only (input: column-pass output), canonical output.
-hipError_t launch_ntt_fwd_rows(const Ctx &c, const LimbMap &m, const uint64_t *in, uint64_t *out,
-                               uint32_t batch, size_t in_bstride, size_t out_bstride, hipStream_t s);
-// Inverse NTT row pass only (lazy output in [0, 2q)).
-hipError_t launch_ntt_inv_rows(const Ctx &c, const LimbMap &m, const uint64_t *in, uint64_t *out,
-                               uint32_t batch, size_t in_bstride, size_t out_bstride, hipStream_t s);
-// Inverse NTT column pass only, with the folded last stage li[cidx].
-hipError_t launch_ntt_inv_cols(const Ctx &c, const LimbMap &m, const uint64_t *in, uint64_t *out,
-                               const LastInv *li, uint32_t batch, size_t in_bstride, size_t out_bstride,
-                               hipStream_t s);
-// Forward NTT column pass only (lazy output for a row pass).
-hipError_t launch_ntt_fwd_cols(const Ctx &c, const LimbMap &m, const uint64_t *in, uint64_t *out,
-                               uint32_t batch, size_t in_bstride, size_t out_bstride, hipStream_t s);
+// NTT passes.  Every launcher runs the limbs of `m` for `batch` entries of
+// `io` (in == out allowed).  Forward input residues < 2^53.
+// Forward NTT, both passes; canonical output.
+hipError_t launch_ntt_fwd(const Ctx &c, const LimbMap &m, const BatchIo &io, uint32_t batch, hipStream_t s);
+// Forward column pass only (lazy output for a row pass).
+hipError_t launch_ntt_fwd_cols(const Ctx &c, const LimbMap &m, const BatchIo &io, uint32_t batch, hipStream_t s);
+// Forward row pass only (input: column-pass output); canonical output.
+hipError_t launch_ntt_fwd_rows(const Ctx &c, const LimbMap &m, const BatchIo &io, uint32_t batch, hipStream_t s);
+// Inverse NTT, both passes, with the folded last stage li[cidx] (scale
+// included); the row pass gathers entry b through the automorph
+// io.galois[b] (1: none).  Canonical output.
+hipError_t launch_ntt_inv(const Ctx &c, const LimbMap &m, const BatchIo &io, const LastInv *li, uint32_t batch,
+                          hipStream_t s);
+// Inverse row pass only (lazy output in [0, 2q)).
+hipError_t launch_ntt_inv_rows(const Ctx &c, const LimbMap &m, const BatchIo &io, uint32_t batch, hipStream_t s);
+// Inverse column pass only, with the folded last stage li[cidx].
+hipError_t launch_ntt_inv_cols(const Ctx &c, const LimbMap &m, const BatchIo &io, const LastInv *li,
+                               uint32_t batch, hipStream_t s);
+// Forward row pass of the ModDown correction z (io.in) followed by
+// out = (u - z) * P^-1 (+ io.add gathered through io.add_galois).
+hipError_t launch_rows_mdepi(const Ctx &c, const LimbMap &m, const BatchIo &io, uint32_t batch, hipStream_t s);
 // NewLimb of every digit of the coefficient-form y [level][N] into the other
 // limbs of Q_level U P: ext[j][t] (coefficient form, canonical) for t outside
-// digit j.
-hipError_t launch_conv_modup(const Ctx &c, const uint64_t *y, uint32_t level, uint64_t *ext, hipStream_t s);
+// digit j; `batch` polynomials at strides y_bstride / ext_bstride.
+hipError_t launch_conv_modup(const Ctx &c, const uint64_t *y, uint32_t level, uint64_t *ext, uint32_t batch,
+                             size_t y_bstride, size_t ext_bstride, hipStream_t s);
 // NewLimb of ModDown: the K coefficient-form P limbs p [K][N] (scaled by
 // [(P/p_k)^-1]) into the level q limbs z [level][N], for `batch` polynomials.
 hipError_t launch_conv_moddown(const Ctx &c, const uint64_t *p, uint32_t level, uint64_t *z, uint32_t batch,
                                size_t p_bstride, size_t z_bstride, hipStream_t s);
-// Forward row pass of the ModDown correction z followed by
-// out = (u - z) * P^-1 (+ add gathered by add_galois for polys in add_mask);
-// u limb cidx[o] at uq + b*uq_bstride.
-hipError_t launch_rows_mdepi(const Ctx &c, const LimbMap &m, const uint64_t *zc, uint64_t *out,
-                             const uint64_t *uq, size_t uq_bstride, const uint64_t *add, uint32_t add_galois,
-                             uint32_t add_mask, size_t add_pstride, uint32_t batch, size_t in_bstride,
-                             size_t out_bstride, hipStream_t s);
-// KSKInnerProd per target limb and row tile (+ ModDown's inverse row pass for
-// the P limbs, into pc [2][K][N]); q limbs into uq [2][level][N].  Converted
-// limb t of digit j is read at ext + (j*E + t)*N: after the forward column
-// pass only (rowpass: the kernel runs the row pass) or in evaluation form;
-// digit j's own limb (all digits if all_direct) at direct + j*dstride + t*N,
-// gathered through `galois`.
-hipError_t launch_ksk_rows(const Ctx &c, const uint64_t *ext, bool rowpass, const uint64_t *direct, size_t dstride,
-                           uint32_t all_direct, const uint64_t *ksk, uint32_t level, uint32_t galois,
-                           uint64_t *uq, uint64_t *pc, hipStream_t s);
+// KSKInnerProd of `nb` ciphertexts per target limb and row tile (+ ModDown's
+// inverse row pass for the P limbs).  Entry b: converted limb t of digit j
+// at ext + b*ext_bstride + (j*E + t)*N, after the forward column pass only
+// (rowpass: the kernel runs the row pass) or in evaluation form; digit j's
+// own limb (all digits if all_direct) at direct[b] + j*dstride + t*N,
+// gathered through galois[b]; key ksk[b]; q limbs to uq + b*uq_bstride
+// ([2][level][N]), P limbs to pc + b*pc_bstride ([2][K][N]).
+struct KskBatch {
+    const uint64_t *direct[MAXCT];
+    const uint64_t *ksk[MAXCT];
+    uint32_t galois[MAXCT];
+};
+hipError_t launch_ksk_rows(const Ctx &c, const KskBatch &kb, uint32_t nb, const uint64_t *ext, size_t ext_bstride,
+                           bool rowpass, size_t dstride, uint32_t all_direct, uint32_t level, uint64_t *uq,
+                           size_t uq_bstride, uint64_t *pc, size_t pc_bstride, hipStream_t s);
 // Eval-domain automorph (gather) of limbs; or coefficient-domain map with negation.
 hipError_t launch_automorph(const Ctx &c, const LimbMap &m, const uint64_t *in, uint64_t *out,
                             uint32_t galois, int eval_domain, uint32_t batch, size_t in_bstride,

@@ -120,10 +120,14 @@ static hipError_t launch_conv_t(const ConvArgs &a, uint32_t ns_max, dim3 grid, h
     return hipGetLastError();
 }
 
-hipError_t launch_conv_modup(const Ctx &c, const uint64_t *y, uint32_t level, uint64_t *ext, hipStream_t s) {
+hipError_t launch_conv_modup(const Ctx &c, const uint64_t *y, uint32_t level, uint64_t *ext, uint32_t batch,
+                             size_t y_bstride, size_t ext_bstride, hipStream_t s) {
+    if (batch == 0) return hipSuccess;
     ConvArgs a{};
     a.in = y;
     a.out = ext;
+    a.in_bstride = y_bstride;
+    a.out_bstride = ext_bstride;
     a.conv = c.conv_modup + c.conv_modup_off[level];
     a.mc = c.mc;
     a.n = c.log_n;
@@ -133,11 +137,12 @@ hipError_t launch_conv_modup(const Ctx &c, const uint64_t *y, uint32_t level, ui
     a.alpha = c.alpha;
     const uint32_t beta = (level + c.alpha - 1) / c.alpha;
     ProfScope ps(c, HKS_K_CONV, s);
-    return launch_conv_t<true>(a, c.alpha, dim3((c.n + 255) / 256, beta, 1), s);
+    return launch_conv_t<true>(a, c.alpha, dim3((c.n + 255) / 256, beta, batch), s);
 }
 
 hipError_t launch_conv_moddown(const Ctx &c, const uint64_t *p, uint32_t level, uint64_t *z, uint32_t batch,
                                size_t p_bstride, size_t z_bstride, hipStream_t s) {
+    if (batch == 0) return hipSuccess;
     ConvArgs a{};
     a.in = p;
     a.out = z;

@@ -275,17 +275,13 @@ __device__ __forceinline__ void elem_coords(int e, uint32_t line0, uint32_t n2, 
 
 struct NttArgs {
     const Ctx *ctx;  // host-side only (timing); not read by kernels
-    const uint64_t *in;
-    uint64_t *out;
     const Shoup *tw;      // [M][N] forward or inverse table
     const ModC *mc;
     const LastInv *li;    // folded last inverse stage, indexed by cidx
-    const uint64_t *uq;   // IO_MDEPI: u limbs (limb cidx), batch stride uq_bstride
     const Shoup *pinv;    // IO_MDEPI: P^-1 mod q_i
-    const uint64_t *add;  // IO_MDEPI: addend (limb cidx) for polys selected by add_mask
-    size_t in_bstride, out_bstride, uq_bstride, add_pstride;
-    uint32_t n, n1, n2, galois, add_galois, add_mask;
+    uint32_t n, n1, n2;
     LimbMap m;
+    BatchIo io;
 };
 
 enum { IO_PLAIN = 0, IO_GATHER = 1, IO_REDUCE = 2, IO_MDEPI = 4 };
@@ -304,8 +300,8 @@ __global__ void __launch_bounds__((Tile<LOGS, LINES, COLS>::NT)) ntt_pass_kernel
     const uint32_t mod = a.m.mod[li];
     const ModC mcv = a.mc[mod];
     const uint64_t q = mcv.q;
-    const uint64_t *src = a.in + b * a.in_bstride + (size_t)a.m.in_off[li] * N;
-    uint64_t *dst = a.out + b * a.out_bstride + (size_t)a.m.out_off[li] * N;
+    const uint64_t *src = a.io.in[b] + (size_t)a.m.in_off[li] * N;
+    uint64_t *dst = a.io.out[b] + (size_t)a.m.out_off[li] * N;
     const Shoup *tw = a.tw + (size_t)mod * N;
     int line, t;
     thread_coords<LOGS, LINES, COLS>(threadIdx.x, line, t);
@@ -313,9 +309,12 @@ __global__ void __launch_bounds__((Tile<LOGS, LINES, COLS>::NT)) ntt_pass_kernel
 
     uint64_t x[16];
     if (IO == IO_GATHER) {
+        const uint32_t g = a.io.galois[b];
 #pragma unroll
-        for (int e = 0; e < 16; ++e)
-            x[e] = src[aut_eval_src(jdx<COLS>(lg, k_of<IOL::IN_LO, IOL::IN_HI>(t, e), a.n2), a.galois, a.n)];
+        for (int e = 0; e < 16; ++e) {
+            const uint32_t j = jdx<COLS>(lg, k_of<IOL::IN_LO, IOL::IN_HI>(t, e), a.n2);
+            x[e] = src[g != 1 ? aut_eval_src(j, g, a.n) : j];
+        }
     } else {
         gload<LOGS, COLS, IOL::IN_LO, IOL::IN_HI>(x, src, t, lg, a.n2);
     }
@@ -329,19 +328,19 @@ __global__ void __launch_bounds__((Tile<LOGS, LINES, COLS>::NT)) ntt_pass_kernel
 
     if (IO == IO_MDEPI) {
         const uint32_t ui = a.m.cidx[li];
-        const uint64_t *u = a.uq + b * a.uq_bstride + (size_t)ui * N;
+        const uint64_t *u = a.io.uq[b] + (size_t)ui * N;
         const Shoup pi = a.pinv[ui];
-        const bool do_add = a.add && ((a.add_mask >> b) & 1u);
-        const uint64_t *ad = do_add ? a.add + b * a.add_pstride + (size_t)ui * N : nullptr;
+        const uint64_t *ad = a.io.add[b] ? a.io.add[b] + (size_t)ui * N : nullptr;
+        const uint32_t ag = a.io.add_galois[b];
         uint64_t uv[16];
         gload<LOGS, COLS, IOL::OUT_LO, IOL::OUT_HI>(uv, u, t, lg, a.n2);
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
             const uint64_t z = reduce64(x[e], q, mcv.mu);
             uint64_t r = mul_shoup(uv[e] + q - z, pi.w, pi.wp, q);
-            if (do_add) {
+            if (ad) {
                 const uint32_t j = jdx<COLS>(lg, k_of<IOL::OUT_LO, IOL::OUT_HI>(t, e), a.n2);
-                r = add_mod(r, ad[a.add_galois != 1 ? aut_eval_src(j, a.add_galois, a.n) : j], q);
+                r = add_mod(r, ad[ag != 1 ? aut_eval_src(j, ag, a.n) : j], q);
             }
             x[e] = r;
         }
@@ -369,6 +368,8 @@ static hipError_t launch_pass_t(const NttArgs &a, uint32_t count, uint32_t batch
 
 template <bool COLS, bool FWD, int IO>
 static hipError_t dispatch_pass(const NttArgs &a, int logs, uint32_t count, uint32_t batch, hipStream_t s) {
+    if (count == 0 || batch == 0) return hipSuccess;
+    if (batch > (uint32_t)MAXB) return hipErrorInvalidValue;
     switch (logs) {
         case 5: return launch_pass_t<5, COLS, FWD, IO>(a, count, batch, s);
         case 6: return launch_pass_t<6, COLS, FWD, IO>(a, count, batch, s);
@@ -378,141 +379,85 @@ static hipError_t dispatch_pass(const NttArgs &a, int logs, uint32_t count, uint
     }
 }
 
-static NttArgs base_args(const Ctx &c, const LimbMap &m, bool fwd) {
+static NttArgs base_args(const Ctx &c, const LimbMap &m, const BatchIo &io, bool fwd) {
     NttArgs a{};
     a.ctx = &c;
     a.tw = fwd ? c.tw_fwd : c.tw_inv;
     a.mc = c.mc;
     a.li = c.li_plain;
+    a.pinv = c.pinv;
     a.n = c.log_n;
     a.n1 = c.n1;
     a.n2 = c.n2;
-    a.galois = 1;
     a.m = m;
+    a.io = io;
     return a;
 }
 
-static void outputs_as_inputs(NttArgs &a, const LimbMap &m) {
-    for (uint32_t i = 0; i < m.count; ++i) a.m.in_off[i] = m.out_off[i];
+// the second pass of a transform reads what the first wrote
+static void chain(NttArgs &a, uint32_t batch) {
+    for (uint32_t i = 0; i < a.m.count; ++i) a.m.in_off[i] = a.m.out_off[i];
+    for (uint32_t b = 0; b < batch; ++b) {
+        a.io.in[b] = a.io.out[b];
+        a.io.galois[b] = 1;
+    }
 }
 
-hipError_t launch_ntt_fwd(const Ctx &c, const LimbMap &m, const uint64_t *in, uint64_t *out, uint32_t batch,
-                          size_t in_bstride, size_t out_bstride, hipStream_t s) {
-    if (m.count == 0 || batch == 0) return hipSuccess;
-    NttArgs a = base_args(c, m, true);
-    a.in = in;
-    a.out = out;
-    a.in_bstride = in_bstride;
-    a.out_bstride = out_bstride;
+hipError_t launch_ntt_fwd(const Ctx &c, const LimbMap &m, const BatchIo &io, uint32_t batch, hipStream_t s) {
+    NttArgs a = base_args(c, m, io, true);
     hipError_t e = dispatch_pass<true, true, IO_PLAIN>(a, c.n1, m.count, batch, s);
     if (e != hipSuccess) return e;
-    a.in = out;
-    a.in_bstride = out_bstride;
-    outputs_as_inputs(a, m);
+    chain(a, batch);
     return dispatch_pass<false, true, IO_REDUCE>(a, c.n2, m.count, batch, s);
 }
 
-hipError_t launch_ntt_fwd_rows(const Ctx &c, const LimbMap &m, const uint64_t *in, uint64_t *out,
-                               uint32_t batch, size_t in_bstride, size_t out_bstride, hipStream_t s) {
-    if (m.count == 0 || batch == 0) return hipSuccess;
-    NttArgs a = base_args(c, m, true);
-    a.in = in;
-    a.out = out;
-    a.in_bstride = in_bstride;
-    a.out_bstride = out_bstride;
-    return dispatch_pass<false, true, IO_REDUCE>(a, c.n2, m.count, batch, s);
+hipError_t launch_ntt_fwd_cols(const Ctx &c, const LimbMap &m, const BatchIo &io, uint32_t batch, hipStream_t s) {
+    return dispatch_pass<true, true, IO_PLAIN>(base_args(c, m, io, true), c.n1, m.count, batch, s);
 }
 
-hipError_t launch_ntt_inv(const Ctx &c, const LimbMap &m, const uint64_t *in, uint64_t *out, const LastInv *li,
-                          uint32_t galois, uint32_t batch, size_t in_bstride, size_t out_bstride, hipStream_t s) {
-    if (m.count == 0 || batch == 0) return hipSuccess;
-    NttArgs a = base_args(c, m, false);
+hipError_t launch_ntt_fwd_rows(const Ctx &c, const LimbMap &m, const BatchIo &io, uint32_t batch, hipStream_t s) {
+    return dispatch_pass<false, true, IO_REDUCE>(base_args(c, m, io, true), c.n2, m.count, batch, s);
+}
+
+hipError_t launch_ntt_inv(const Ctx &c, const LimbMap &m, const BatchIo &io, const LastInv *li, uint32_t batch,
+                          hipStream_t s) {
+    NttArgs a = base_args(c, m, io, false);
     a.li = li;
-    a.galois = galois;
-    a.in = in;
-    a.out = out;
-    a.in_bstride = in_bstride;
-    a.out_bstride = out_bstride;
-    hipError_t e = (galois != 1) ? dispatch_pass<false, false, IO_GATHER>(a, c.n2, m.count, batch, s)
-                                 : dispatch_pass<false, false, IO_PLAIN>(a, c.n2, m.count, batch, s);
+    bool gather = false;
+    for (uint32_t b = 0; b < batch && b < (uint32_t)MAXB; ++b) gather |= io.galois[b] != 1;
+    hipError_t e = gather ? dispatch_pass<false, false, IO_GATHER>(a, c.n2, m.count, batch, s)
+                          : dispatch_pass<false, false, IO_PLAIN>(a, c.n2, m.count, batch, s);
     if (e != hipSuccess) return e;
-    a.in = out;
-    a.in_bstride = out_bstride;
-    a.galois = 1;
-    outputs_as_inputs(a, m);
+    chain(a, batch);
     return dispatch_pass<true, false, IO_PLAIN>(a, c.n1, m.count, batch, s);
 }
 
-hipError_t launch_ntt_inv_rows(const Ctx &c, const LimbMap &m, const uint64_t *in, uint64_t *out,
-                               uint32_t batch, size_t in_bstride, size_t out_bstride, hipStream_t s) {
-    if (m.count == 0 || batch == 0) return hipSuccess;
-    NttArgs a = base_args(c, m, false);
-    a.in = in;
-    a.out = out;
-    a.in_bstride = in_bstride;
-    a.out_bstride = out_bstride;
-    return dispatch_pass<false, false, IO_PLAIN>(a, c.n2, m.count, batch, s);
+hipError_t launch_ntt_inv_rows(const Ctx &c, const LimbMap &m, const BatchIo &io, uint32_t batch, hipStream_t s) {
+    return dispatch_pass<false, false, IO_PLAIN>(base_args(c, m, io, false), c.n2, m.count, batch, s);
 }
 
-hipError_t launch_ntt_inv_cols(const Ctx &c, const LimbMap &m, const uint64_t *in, uint64_t *out,
-                               const LastInv *li, uint32_t batch, size_t in_bstride, size_t out_bstride,
-                               hipStream_t s) {
-    if (m.count == 0 || batch == 0) return hipSuccess;
-    NttArgs a = base_args(c, m, false);
+hipError_t launch_ntt_inv_cols(const Ctx &c, const LimbMap &m, const BatchIo &io, const LastInv *li,
+                               uint32_t batch, hipStream_t s) {
+    NttArgs a = base_args(c, m, io, false);
     a.li = li;
-    a.in = in;
-    a.out = out;
-    a.in_bstride = in_bstride;
-    a.out_bstride = out_bstride;
     return dispatch_pass<true, false, IO_PLAIN>(a, c.n1, m.count, batch, s);
 }
 
-hipError_t launch_ntt_fwd_cols(const Ctx &c, const LimbMap &m, const uint64_t *in, uint64_t *out,
-                               uint32_t batch, size_t in_bstride, size_t out_bstride, hipStream_t s) {
-    if (m.count == 0 || batch == 0) return hipSuccess;
-    NttArgs a = base_args(c, m, true);
-    a.in = in;
-    a.out = out;
-    a.in_bstride = in_bstride;
-    a.out_bstride = out_bstride;
-    return dispatch_pass<true, true, IO_PLAIN>(a, c.n1, m.count, batch, s);
-}
-
-hipError_t launch_rows_mdepi(const Ctx &c, const LimbMap &m, const uint64_t *zc, uint64_t *out,
-                             const uint64_t *uq, size_t uq_bstride, const uint64_t *add, uint32_t add_galois,
-                             uint32_t add_mask, size_t add_pstride, uint32_t batch, size_t in_bstride,
-                             size_t out_bstride, hipStream_t s) {
-    if (m.count == 0 || batch == 0) return hipSuccess;
-    NttArgs a = base_args(c, m, true);
-    a.in = zc;
-    a.out = out;
-    a.uq = uq;
-    a.uq_bstride = uq_bstride;
-    a.pinv = c.pinv;
-    a.add = add;
-    a.add_galois = add_galois;
-    a.add_mask = add_mask;
-    a.add_pstride = add_pstride;
-    a.in_bstride = in_bstride;
-    a.out_bstride = out_bstride;
-    return dispatch_pass<false, true, IO_MDEPI>(a, c.n2, m.count, batch, s);
+hipError_t launch_rows_mdepi(const Ctx &c, const LimbMap &m, const BatchIo &io, uint32_t batch, hipStream_t s) {
+    return dispatch_pass<false, true, IO_MDEPI>(base_args(c, m, io, true), c.n2, m.count, batch, s);
 }
 
 // ------------------------------------------------------------------ KSKInnerProd (+ ModUp's last pass, + ModDown's first)
 
-#ifndef KSK_WAVES
-#define KSK_WAVES
-#endif
 struct KskRowArgs {
+    KskBatch kb;             // per ciphertext: own-digit source, key [dnum][2][L+K][N], galois
     const uint64_t *ext;     // [beta][E][N] converted limbs: after the forward column pass (rowpass) or in evaluation form
-    const uint64_t *direct;  // digit j's own limb t at direct + j*dstride + t*N (gathered by `galois`)
-    const uint64_t *ksk;     // [dnum][2][L+K][N]
     uint64_t *uq;            // [2][level][N] KSKInnerProd on the q limbs
     uint64_t *pc;            // [2][K][N] P limbs after the inverse row pass
     const Shoup *twf, *twi;
     const ModC *mc;
-    size_t dstride;
-    uint32_t n, n1, n2, level, L, K, E, alpha, beta, galois, all_direct;
+    size_t dstride, ext_bstride, uq_bstride, pc_bstride;
+    uint32_t n, n1, n2, level, L, K, E, alpha, beta, all_direct, nb, xcd_group;
 };
 
 // One block = one target limb t of Q_level U P and ROW_LINES rows, in the
@@ -524,17 +469,38 @@ struct KskRowArgs {
 // canonical sums).  q limbs store (u_t, v_t); special-prime limbs run
 // ModDown's inverse row pass on both in registers before storing (the
 // forward pass ends in the layout the inverse pass starts from).
+// (at least two waves per SIMD: the register budget stays within 256)
 template <int LOGS, bool ROWPASS>
-__global__ void __launch_bounds__((Tile<LOGS, ROW_LINES, false>::NT)) KSK_WAVES ksk_rows_kernel(const KskRowArgs a) {
+__global__ void __launch_bounds__((Tile<LOGS, ROW_LINES, false>::NT)) __attribute__((amdgpu_waves_per_eu(2)))
+ksk_rows_kernel(const KskRowArgs a) {
     using TL = Tile<LOGS, ROW_LINES, false>;
     using IOF = IoLayout<LOGS, true>;
     using IOI = IoLayout<LOGS, false>;
     static_assert(IOF::OUT_LO == IOI::IN_LO && IOF::OUT_HI == IOI::IN_HI, "row-pass layouts must chain");
     __shared__ uint64_t lds[TL::WORDS];
+    // block -> (x = target limb and row tile, b = ciphertext).  With
+    // xcd_group the nb blocks of one x get ids that are equal modulo 8, so
+    // that they run on one XCD (ids are dealt round-robin over the 8 XCDs)
+    // and a shared key tile is fetched into that XCD's L2 once.
+    uint32_t x, b;
+    if (a.xcd_group) {
+        const uint32_t rest = blockIdx.x >> 3;
+        b = rest % a.nb;
+        x = ((rest / a.nb) << 3) | (blockIdx.x & 7u);
+    } else {
+        b = blockIdx.x % a.nb;
+        x = blockIdx.x / a.nb;
+    }
     const uint32_t tiles = (1u << a.n1) / ROW_LINES;
-    const uint32_t tgt = blockIdx.x / tiles;
-    const uint32_t tile = blockIdx.x % tiles;
+    const uint32_t tgt = x / tiles;
+    const uint32_t tile = x % tiles;
     const uint32_t N = 1u << a.n;
+    const uint64_t *ext = a.ext + b * a.ext_bstride;
+    const uint64_t *direct = a.kb.direct[b];
+    const uint64_t *ksk = a.kb.ksk[b];
+    const uint32_t galois = a.kb.galois[b];
+    uint64_t *uq = a.uq + b * a.uq_bstride;
+    uint64_t *pc = a.pc + b * a.pc_bstride;
     const uint32_t mod = tgt < a.level ? tgt : a.L + (tgt - a.level);
     const ModC mcv = a.mc[mod];
     const uint64_t q = mcv.q;
@@ -552,53 +518,53 @@ __global__ void __launch_bounds__((Tile<LOGS, ROW_LINES, false>::NT)) KSK_WAVES 
     bool lds_used = false;
     for (uint32_t jd = 0; jd < a.beta; ++jd) {
         const bool dir = a.all_direct || jd == own;
-        uint64_t x[16];
+        uint64_t xv[16];
         if (dir) {
-            const uint64_t *src = a.direct + jd * a.dstride + (size_t)tgt * N;
+            const uint64_t *src = direct + jd * a.dstride + (size_t)tgt * N;
 #pragma unroll
             for (int e = 0; e < 16; ++e) {
                 const uint32_t j = jdx<false>(lg, k_of<IOF::OUT_LO, IOF::OUT_HI>(t, e), a.n2);
-                x[e] = src[a.galois != 1 ? aut_eval_src(j, a.galois, a.n) : j];
+                xv[e] = src[galois != 1 ? aut_eval_src(j, galois, a.n) : j];
             }
         } else {
-            const uint64_t *src = a.ext + ((size_t)jd * a.E + tgt) * N;
+            const uint64_t *src = ext + ((size_t)jd * a.E + tgt) * N;
             if (ROWPASS) {
-                gload<LOGS, false, IOF::IN_LO, IOF::IN_HI>(x, src, t, lg, a.n2);
+                gload<LOGS, false, IOF::IN_LO, IOF::IN_HI>(xv, src, t, lg, a.n2);
                 if (lds_used) __syncthreads();
-                pass_regs<LOGS, ROW_LINES, false, true>(true, x, lds, line, t, q,
+                pass_regs<LOGS, ROW_LINES, false, true>(true, xv, lds, line, t, q,
                                                         TwRows{a.twf + (size_t)mod * N, lg, a.n1}, LastInv{});
                 lds_used = true;
             } else {
-                gload<LOGS, false, IOF::OUT_LO, IOF::OUT_HI>(x, src, t, lg, a.n2);
+                gload<LOGS, false, IOF::OUT_LO, IOF::OUT_HI>(xv, src, t, lg, a.n2);
             }
         }
         // the key rows in the same layout: 16 consecutive words per thread
         static_assert(IOF::OUT_LO == 0, "forward row pass ends with 16 consecutive elements per thread");
         const ulonglong2 *k0 =
-            reinterpret_cast<const ulonglong2 *>(a.ksk + ((size_t)(2 * jd) * KL + mod) * N + (lg << a.n2) + 16 * t);
+            reinterpret_cast<const ulonglong2 *>(ksk + ((size_t)(2 * jd) * KL + mod) * N + (lg << a.n2) + 16 * t);
         const ulonglong2 *k1 = k0 + KL * N / 2;
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
             const ulonglong2 kv0 = k0[c], kv1 = k1[c];
-            u[2 * c] = add_mod(u[2 * c], mul_mod(x[2 * c], kv0.x, q, mcv.mu), q);
-            u[2 * c + 1] = add_mod(u[2 * c + 1], mul_mod(x[2 * c + 1], kv0.y, q, mcv.mu), q);
-            v[2 * c] = add_mod(v[2 * c], mul_mod(x[2 * c], kv1.x, q, mcv.mu), q);
-            v[2 * c + 1] = add_mod(v[2 * c + 1], mul_mod(x[2 * c + 1], kv1.y, q, mcv.mu), q);
+            u[2 * c] = add_mod(u[2 * c], mul_mod(xv[2 * c], kv0.x, q, mcv.mu), q);
+            u[2 * c + 1] = add_mod(u[2 * c + 1], mul_mod(xv[2 * c + 1], kv0.y, q, mcv.mu), q);
+            v[2 * c] = add_mod(v[2 * c], mul_mod(xv[2 * c], kv1.x, q, mcv.mu), q);
+            v[2 * c + 1] = add_mod(v[2 * c + 1], mul_mod(xv[2 * c + 1], kv1.y, q, mcv.mu), q);
         }
     }
     if (!is_p) {
-        gstore<LOGS, false, IOF::OUT_LO, IOF::OUT_HI>(u, a.uq + (size_t)tgt * N, t, lg, a.n2);
-        gstore<LOGS, false, IOF::OUT_LO, IOF::OUT_HI>(v, a.uq + ((size_t)a.level + tgt) * N, t, lg, a.n2);
+        gstore<LOGS, false, IOF::OUT_LO, IOF::OUT_HI>(u, uq + (size_t)tgt * N, t, lg, a.n2);
+        gstore<LOGS, false, IOF::OUT_LO, IOF::OUT_HI>(v, uq + ((size_t)a.level + tgt) * N, t, lg, a.n2);
         return;
     }
     // special-prime limb: inverse row pass (first pass of ModDown's iNTT) of u and v
     const TwRows twi{a.twi + (size_t)mod * N, lg, a.n1};
     if (lds_used) __syncthreads();
     pass_regs<LOGS, ROW_LINES, false, false>(true, u, lds, line, t, q, twi, LastInv{});
-    gstore<LOGS, false, IOI::OUT_LO, IOI::OUT_HI>(u, a.pc + (size_t)kp * N, t, lg, a.n2);
+    gstore<LOGS, false, IOI::OUT_LO, IOI::OUT_HI>(u, pc + (size_t)kp * N, t, lg, a.n2);
     __syncthreads();
     pass_regs<LOGS, ROW_LINES, false, false>(true, v, lds, line, t, q, twi, LastInv{});
-    gstore<LOGS, false, IOI::OUT_LO, IOI::OUT_HI>(v, a.pc + ((size_t)a.K + kp) * N, t, lg, a.n2);
+    gstore<LOGS, false, IOI::OUT_LO, IOI::OUT_HI>(v, pc + ((size_t)a.K + kp) * N, t, lg, a.n2);
 }
 
 template <bool ROWPASS>
@@ -613,17 +579,21 @@ static hipError_t launch_ksk_rows_t(const KskRowArgs &a, uint32_t n2, dim3 grid,
     return hipGetLastError();
 }
 
-hipError_t launch_ksk_rows(const Ctx &c, const uint64_t *ext, bool rowpass, const uint64_t *direct, size_t dstride,
-                           uint32_t all_direct, const uint64_t *ksk, uint32_t level, uint32_t galois,
-                           uint64_t *uq, uint64_t *pc, hipStream_t s) {
+hipError_t launch_ksk_rows(const Ctx &c, const KskBatch &kb, uint32_t nb, const uint64_t *ext, size_t ext_bstride,
+                           bool rowpass, size_t dstride, uint32_t all_direct, uint32_t level, uint64_t *uq,
+                           size_t uq_bstride, uint64_t *pc, size_t pc_bstride, hipStream_t s) {
+    if (nb == 0) return hipSuccess;
+    if (nb > (uint32_t)MAXCT) return hipErrorInvalidValue;
     KskRowArgs a{};
+    a.kb = kb;
     a.ext = ext;
-    a.direct = direct;
+    a.ext_bstride = ext_bstride;
     a.dstride = dstride;
     a.all_direct = all_direct;
-    a.ksk = ksk;
     a.uq = uq;
+    a.uq_bstride = uq_bstride;
     a.pc = pc;
+    a.pc_bstride = pc_bstride;
     a.twf = c.tw_fwd;
     a.twi = c.tw_inv;
     a.mc = c.mc;
@@ -636,10 +606,11 @@ hipError_t launch_ksk_rows(const Ctx &c, const uint64_t *ext, bool rowpass, cons
     a.E = level + c.K;
     a.alpha = c.alpha;
     a.beta = (level + c.alpha - 1) / c.alpha;
-    a.galois = galois;
+    a.nb = nb;
+    const uint32_t xs = ((1u << c.n1) / ROW_LINES) * a.E;
+    a.xcd_group = (nb > 1 && xs % 8 == 0) ? 1u : 0u;
     ProfScope ps(c, HKS_K_KSK, s);
-    const uint32_t tiles = (1u << c.n1) / ROW_LINES;
-    const dim3 grid(tiles * a.E);
+    const dim3 grid(xs * nb);
     return rowpass ? launch_ksk_rows_t<true>(a, c.n2, grid, s) : launch_ksk_rows_t<false>(a, c.n2, grid, s);
 }
 

@@ -76,6 +76,7 @@ class _Params(ctypes.Structure):
         ("dnum", ctypes.c_uint32),
         ("q", ctypes.POINTER(ctypes.c_uint64)),
         ("p", ctypes.POINTER(ctypes.c_uint64)),
+        ("max_batch", ctypes.c_uint32),
     ]
 
 
@@ -178,13 +179,13 @@ def hks_strerror(status: int) -> str:
 class Context:
     """Owns an hks_ctx (tables + workspace on one device)."""
 
-    def __init__(self, log_n: int, q, p, dnum: int, device: int = 0):
+    def __init__(self, log_n: int, q, p, dnum: int, device: int = 0, max_batch: int = 1):
         self.q = [int(v) for v in q]
         self.p = [int(v) for v in p]
         self.log_n, self.L, self.K, self.dnum = int(log_n), len(self.q), len(self.p), int(dnum)
         qa = (ctypes.c_uint64 * self.L)(*self.q)
         pa = (ctypes.c_uint64 * self.K)(*self.p)
-        prm = _Params(self.log_n, self.L, self.K, self.dnum, qa, pa)
+        prm = _Params(self.log_n, self.L, self.K, self.dnum, qa, pa, int(max_batch))
         h = ctypes.c_void_p()
         _check("hks_create", lib().hks_create(ctypes.byref(prm), int(device), ctypes.byref(h)))
         self._h = h

@@ -59,10 +59,10 @@ def test_strerror(hks):
     assert "unknown" in hks.strerror(-99)
 
 
-def _create(hks, log_n, q, p, dnum):
+def _create(hks, log_n, q, p, dnum, max_batch=0):
     qa = (ctypes.c_uint64 * len(q))(*q)
     pa = (ctypes.c_uint64 * len(p))(*p)
-    prm = hks._Params(log_n, len(q), len(p), dnum, qa, pa)
+    prm = hks._Params(log_n, len(q), len(p), dnum, qa, pa, max_batch)
     h = ctypes.c_void_p()
     return hks.lib().hks_create(ctypes.byref(prm), 0, ctypes.byref(h))
 
@@ -80,6 +80,7 @@ def test_create_rejects_invalid_parameters(hks):
     assert _create(hks, 12, q[:5] + [q[5] + 2], p, 3) == EINVAL  # not prime / not 1 mod 2N
     small = [int(v) for v in O.gen_primes(40, 17, 1)]
     assert _create(hks, 12, q[:5] + small, p, 3) == EINVAL  # below 2^49
+    assert _create(hks, 12, q, p, 3, max_batch=17) == EINVAL  # more batch slots than a launch holds
     rc = hks.lib().hks_create(None, 0, ctypes.byref(ctypes.c_void_p()))
     assert rc == EINVAL
 

@@ -30,13 +30,14 @@ CFGS = {
 _CTX = {}
 
 
-def _get(name):
+def _get(name, max_batch=1):
     from paper_2112_06396_amd import hks
-    if name not in _CTX:
+    key = (name, max_batch)
+    if key not in _CTX:
         log_n, L, K, dnum = CFGS[name] if name in CFGS else name
         pr = O.make_params(log_n, L, K, dnum)
-        _CTX[name] = (pr, hks.Context(log_n, pr.q, pr.p, dnum))
-    return _CTX[name]
+        _CTX[key] = (pr, hks.Context(log_n, pr.q, pr.p, dnum, max_batch=max_batch))
+    return _CTX[key]
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -237,6 +238,83 @@ def test_hrotate(name):
     refs = O.hrotate(pr, ct, level, gals, ksks)
     for o, r in zip(outs, refs):
         assert np.array_equal(host(o), r)
+
+
+@pytest.mark.parametrize("name,max_batch,r", [("n10", 2, 5), ("cfg1", 4, 3), ("cfg2", 4, 6)])
+def test_hrotate_batched_steps(name, max_batch, r):
+    """Rotations processed max_batch at a time (ragged last step) equal the
+    oracle's HRotate (Algorithm 4) exactly."""
+    pr, ctx = _get(name, max_batch)
+    hks = H()
+    level = pr.L - 1 if pr.L > 1 else pr.L
+    ks = [1, -1, 3, 7, -16, 2][:r]
+    gals = [hks.hks_galois_for_rotation(k, pr.log_n) for k in ks]
+    ksks = [_rand_ksk(pr, 120 + i) for i in range(r)]
+    ct = _rand_ct(pr, level, 126)
+    outs = [hks.empty((2, level, pr.n)) for _ in ks]
+    hks.hks_hrotate(ctx, dev(ct), level, gals, [dev(k) for k in ksks], outs)
+    refs = O.hrotate(pr, ct, level, gals, ksks)
+    for i, (o, ref) in enumerate(zip(outs, refs)):
+        assert np.array_equal(host(o), ref), i
+
+
+@pytest.mark.parametrize("name,max_batch,n_ct,shared", [
+    ("n10", 4, 6, False), ("cfg1", 8, 8, True), ("cfg1", 3, 7, False), ("n13", 16, 5, True),
+    ("cfg2", 8, 8, True), ("cfg2", 4, 5, False)])
+def test_batch_rotate_batched_context(name, max_batch, n_ct, shared):
+    """Batched Rotate with a shared key (one galois) or distinct keys and
+    galois elements, in steps of max_batch (ragged last step): every output
+    equals the oracle's Rotate of that ciphertext (Algorithm 3)."""
+    pr, ctx = _get(name, max_batch)
+    hks = H()
+    level = pr.L
+    nk = 1 if shared else n_ct
+    ksks = [_rand_ksk(pr, 130 + i) for i in range(nk)]
+    dks = [dev(k) for k in ksks]
+    ks = [1] * n_ct if shared else [1 + (3 * i) % 11 - 5 for i in range(n_ct)]
+    gals = [hks.hks_galois_for_rotation(k, pr.log_n) for k in ks]
+    cts = [_rand_ct(pr, level, 140 + i) for i in range(n_ct)]
+    outs = [hks.empty((2, level, pr.n)) for _ in cts]
+    kidx = [0 if shared else i for i in range(n_ct)]
+    hks.hks_batch_rotate(ctx, [dev(c) for c in cts], level, gals, [dks[j] for j in kidx], outs)
+    for i in range(n_ct):
+        ref = O.rotate(pr, cts[i], level, gals[i], ksks[kidx[i]])
+        assert np.array_equal(host(outs[i]), ref), i
+
+
+def test_batched_context_single_calls_and_lower_level():
+    """A context with batch slots still gives the single-call results, and a
+    batch at a lower level (short last digit) after a full-level batch."""
+    pr, ctx = _get("n13", 4)
+    hks = H()
+    ksk = _rand_ksk(pr, 150)
+    dk = dev(ksk)
+    c1, c2 = _rand_ct(pr, pr.L, 151), _rand_ct(pr, pr.L, 152)
+    o = hks.empty((2, pr.L, pr.n))
+    hks.hks_mult_relin(ctx, dev(c1), dev(c2), pr.L, dk, False, o)
+    assert np.array_equal(host(o), O.mult_relin(pr, c1, c2, pr.L, ksk, False))
+    uv = hks.empty((2, pr.L, pr.n))
+    hks.hks_keyswitch(ctx, dev(c1[0]), pr.L, dk, uv)
+    assert np.array_equal(host(uv), O.keyswitch(pr, c1[0], pr.L, ksk))
+    level = pr.alpha + 1
+    g = hks.hks_galois_for_rotation(2, pr.log_n)
+    cts = [_rand_ct(pr, level, 153 + i) for i in range(3)]
+    outs = [hks.empty((2, level, pr.n)) for _ in cts]
+    hks.hks_batch_rotate(ctx, [dev(c) for c in cts], level, [g] * 3, [dk] * 3, outs)
+    for c, out in zip(cts, outs):
+        assert np.array_equal(host(out), O.rotate(pr, c, level, g, ksk))
+
+
+def test_batch_rotate_rejects_aliasing():
+    pr, ctx = _get("cfg1", 4)
+    hks = H()
+    cts = [dev(_rand_ct(pr, 4, 160 + i)) for i in range(2)]
+    ksk = dev(_rand_ksk(pr, 162))
+    out = hks.empty((2, 4, pr.n))
+    with pytest.raises(hks.HksError):
+        hks.hks_batch_rotate(ctx, cts, 4, [5, 5], [ksk, ksk], [out, cts[0]])
+    with pytest.raises(hks.HksError):
+        hks.hks_batch_rotate(ctx, cts, 4, [5, 5], [ksk, ksk], [out, out])
 
 
 @pytest.mark.parametrize("name", ["cfg1", "cfg2"])
