@@ -60,14 +60,15 @@ struct Mac25 {
         a1 += (uint64_t)y1 * k0;
         a2 += (uint64_t)y1 * k1;
     }
-    // a0 + a1 2^25 + a2 2^50 (< 2^105) reduced modulo q (mu = floor(2^112 / q))
-    __device__ __forceinline__ uint64_t reduce(uint64_t q, uint64_t mu) const {
+    // a0 + a1 2^25 + a2 2^50 (< 2^105) reduced modulo q (mu = floor(2^112 / q),
+    // nq = 2^64 - q)
+    __device__ __forceinline__ uint64_t reduce(uint64_t q, uint64_t mu, uint64_t nq) const {
         const uint64_t l1 = a1 << 25, l2 = a2 << 50;
         uint64_t lo = a0 + l1;
         uint64_t hi = (a1 >> 39) + (a2 >> 14) + ((lo < l1) ? 1u : 0u);
         const uint64_t lo2 = lo + l2;
         hi += (lo2 < l2) ? 1u : 0u;
-        return reduce128(hi, lo2, q, mu);
+        return reduce128(hi, lo2, q, mu, nq);
     }
 };
 

@@ -59,6 +59,7 @@ inline BatchIo strided_io(const uint64_t *in, size_t in_bstride, uint64_t *out, 
 struct ModC {
     uint64_t q;
     uint64_t mu;  // floor(2^112 / q), Barrett for 128-bit values
+    uint64_t nq;  // 2^64 - q (held in the table so that products add instead of subtract)
 };
 
 // Constant pair for Shoup multiplication: (w, floor(w * 2^64 / q)).

@@ -106,7 +106,7 @@ __global__ void __launch_bounds__(256) conv_kernel(const ConvArgs a) {
         Mac25 acc;
 #pragma unroll
         for (int i = 0; i < MAXS; ++i) acc.mac(y0[i], y1[i], kr[i]);
-        dst[(size_t)(MODUP ? j * E + t : t) * N] = acc.reduce(m.q, m.mu);
+        dst[(size_t)(MODUP ? j * E + t : t) * N] = acc.reduce(m.q, m.mu, m.nq);
     }
 }
 

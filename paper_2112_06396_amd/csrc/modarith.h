@@ -22,6 +22,14 @@ __device__ __forceinline__ uint64_t mul_shoup_lazy(uint64_t x, uint64_t w, uint6
     return x * w - qh * q;
 }
 
+// The same with nq = 2^64 - q: x*w + qh*nq = x*w - qh*q (mod 2^64), so the
+// product terms accumulate in carry-free 64-bit multiply-adds instead of a
+// subtraction with borrow.
+__device__ __forceinline__ uint64_t mul_shoup_lazy_nq(uint64_t x, uint64_t w, uint64_t wp, uint64_t nq) {
+    uint64_t qh = __umul64hi(x, wp);
+    return x * w + qh * nq;
+}
+
 __device__ __forceinline__ uint64_t csub(uint64_t x, uint64_t m) { return x >= m ? x - m : x; }
 
 __device__ __forceinline__ uint64_t mul_shoup(uint64_t x, uint64_t w, uint64_t wp, uint64_t q) {
@@ -37,6 +45,18 @@ __device__ __forceinline__ uint64_t reduce128(uint64_t hi, uint64_t lo, uint64_t
     uint64_t qh = __umul64hi(xs, mu);
     uint64_t r = lo - qh * q;
     return csub(r, q);
+}
+
+// The same with nq = 2^64 - q: the remainder lo - qh q is formed as
+// lo + qh nq (mod 2^64), a carry-free multiply-add.
+__device__ __forceinline__ uint64_t reduce128(uint64_t hi, uint64_t lo, uint64_t q, uint64_t mu, uint64_t nq) {
+    uint64_t xs = (hi << 16) | (lo >> 48);
+    uint64_t qh = __umul64hi(xs, mu);
+    return csub(lo + qh * nq, q);
+}
+
+__device__ __forceinline__ uint64_t reduce64(uint64_t x, uint64_t q, uint64_t mu, uint64_t nq) {
+    return reduce128(0, x, q, mu, nq);
 }
 
 // Reduction of any 64-bit x to [0, q) (same Barrett with hi = 0).
@@ -61,6 +81,11 @@ struct Acc128 {
 __device__ __forceinline__ uint64_t mul_mod(uint64_t x, uint64_t y, uint64_t q, uint64_t mu) {
     u128 p = (u128)x * y;
     return reduce128((uint64_t)(p >> 64), (uint64_t)p, q, mu);
+}
+
+__device__ __forceinline__ uint64_t mul_mod(uint64_t x, uint64_t y, uint64_t q, uint64_t mu, uint64_t nq) {
+    u128 p = (u128)x * y;
+    return reduce128((uint64_t)(p >> 64), (uint64_t)p, q, mu, nq);
 }
 
 __device__ __forceinline__ uint64_t add_mod(uint64_t x, uint64_t y, uint64_t q) { return csub(x + y, q); }

@@ -90,7 +90,8 @@ struct TwRows {
 // column pass) the global last inverse stage multiplies by the folded
 // constants instead.
 template <int LOGS, bool FWD, bool FOLD, int LO, int HI, typename TW>
-__device__ __forceinline__ void phase_regs(uint64_t (&x)[16], int t, uint64_t q, const TW &tws, const LastInv &fold) {
+__device__ __forceinline__ void phase_regs(uint64_t (&x)[16], int t, uint64_t q, uint64_t nq, const TW &tws,
+                                           const LastInv &fold) {
     constexpr int B = HI - LO;
     const uint64_t q2 = 2 * q;
 #pragma unroll
@@ -114,7 +115,7 @@ __device__ __forceinline__ void phase_regs(uint64_t (&x)[16], int t, uint64_t q,
             const Shoup w = wc[(e >> (vb + 1)) & 7];
             if (FWD) {
                 const uint64_t u = x[e];
-                const uint64_t tv = mul_shoup_lazy(x[e2], w.w, w.wp, q);
+                const uint64_t tv = mul_shoup_lazy_nq(x[e2], w.w, w.wp, nq);
                 x[e] = u + tv;
                 x[e2] = u + q2 - tv;
             } else {
@@ -124,7 +125,7 @@ __device__ __forceinline__ void phase_regs(uint64_t (&x)[16], int t, uint64_t q,
                     x[e2] = mul_shoup(u + q2 - v, fold.cw.w, fold.cw.wp, q);
                 } else {
                     x[e] = csub(u + v, q2);
-                    x[e2] = mul_shoup_lazy(u + q2 - v, w.w, w.wp, q);
+                    x[e2] = mul_shoup_lazy_nq(u + q2 - v, w.w, w.wp, nq);
                 }
             }
         }
@@ -152,18 +153,18 @@ __device__ __forceinline__ void lds_get(const uint64_t *lds, uint64_t (&x)[16], 
 // where `active` holds, but every thread reaches every barrier.
 template <int LOGS, int LINES, bool COLS, bool FWD, typename TW>
 __device__ __forceinline__ void pass_regs(bool active, uint64_t (&x)[16], uint64_t *lds, int line, int t, uint64_t q,
-                                          const TW &tws, const LastInv &fold) {
+                                          uint64_t nq, const TW &tws, const LastInv &fold) {
     using P = Phases<LOGS>;
     constexpr bool FOLD = !FWD && COLS;
     if (FWD) {
         if (active) {
-            phase_regs<LOGS, true, FOLD, P::P0L, P::P0H>(x, t, q, tws, fold);
+            phase_regs<LOGS, true, FOLD, P::P0L, P::P0H>(x, t, q, nq, tws, fold);
             lds_put<LOGS, LINES, COLS, P::P0L, P::P0H>(lds, x, line, t);
         }
         __syncthreads();
         if (active) {
             lds_get<LOGS, LINES, COLS, P::P1L, P::P1H>(lds, x, line, t);
-            phase_regs<LOGS, true, FOLD, P::P1L, P::P1H>(x, t, q, tws, fold);
+            phase_regs<LOGS, true, FOLD, P::P1L, P::P1H>(x, t, q, nq, tws, fold);
         }
         if constexpr (P::THREE) {
             __syncthreads();
@@ -171,13 +172,13 @@ __device__ __forceinline__ void pass_regs(bool active, uint64_t (&x)[16], uint64
             __syncthreads();
             if (active) {
                 lds_get<LOGS, LINES, COLS, P::P2L, P::P2H>(lds, x, line, t);
-                phase_regs<LOGS, true, FOLD, P::P2L, P::P2H>(x, t, q, tws, fold);
+                phase_regs<LOGS, true, FOLD, P::P2L, P::P2H>(x, t, q, nq, tws, fold);
             }
         }
     } else {
         if constexpr (P::THREE) {
             if (active) {
-                phase_regs<LOGS, false, FOLD, P::P2L, P::P2H>(x, t, q, tws, fold);
+                phase_regs<LOGS, false, FOLD, P::P2L, P::P2H>(x, t, q, nq, tws, fold);
                 lds_put<LOGS, LINES, COLS, P::P2L, P::P2H>(lds, x, line, t);
             }
             __syncthreads();
@@ -185,13 +186,13 @@ __device__ __forceinline__ void pass_regs(bool active, uint64_t (&x)[16], uint64
             __syncthreads();
         }
         if (active) {
-            phase_regs<LOGS, false, FOLD, P::P1L, P::P1H>(x, t, q, tws, fold);
+            phase_regs<LOGS, false, FOLD, P::P1L, P::P1H>(x, t, q, nq, tws, fold);
             lds_put<LOGS, LINES, COLS, P::P1L, P::P1H>(lds, x, line, t);
         }
         __syncthreads();
         if (active) {
             lds_get<LOGS, LINES, COLS, P::P0L, P::P0H>(lds, x, line, t);
-            phase_regs<LOGS, false, FOLD, P::P0L, P::P0H>(x, t, q, tws, fold);
+            phase_regs<LOGS, false, FOLD, P::P0L, P::P0H>(x, t, q, nq, tws, fold);
         }
     }
 }
@@ -321,9 +322,9 @@ __global__ void __launch_bounds__((Tile<LOGS, LINES, COLS>::NT)) ntt_pass_kernel
 
     const LastInv fold = (!FWD && COLS) ? a.li[a.m.cidx[li]] : LastInv{};
     if constexpr (COLS) {
-        pass_regs<LOGS, LINES, COLS, FWD>(true, x, lds, line, t, q, TwCols{tw}, fold);
+        pass_regs<LOGS, LINES, COLS, FWD>(true, x, lds, line, t, q, mcv.nq, TwCols{tw}, fold);
     } else {
-        pass_regs<LOGS, LINES, COLS, FWD>(true, x, lds, line, t, q, TwRows{tw, lg, a.n1}, fold);
+        pass_regs<LOGS, LINES, COLS, FWD>(true, x, lds, line, t, q, mcv.nq, TwRows{tw, lg, a.n1}, fold);
     }
 
     if (IO == IO_MDEPI) {
@@ -336,7 +337,7 @@ __global__ void __launch_bounds__((Tile<LOGS, LINES, COLS>::NT)) ntt_pass_kernel
         gload<LOGS, COLS, IOL::OUT_LO, IOL::OUT_HI>(uv, u, t, lg, a.n2);
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
-            const uint64_t z = reduce64(x[e], q, mcv.mu);
+            const uint64_t z = reduce64(x[e], q, mcv.mu, mcv.nq);
             uint64_t r = mul_shoup(uv[e] + q - z, pi.w, pi.wp, q);
             if (ad) {
                 const uint32_t j = jdx<COLS>(lg, k_of<IOL::OUT_LO, IOL::OUT_HI>(t, e), a.n2);
@@ -346,7 +347,7 @@ __global__ void __launch_bounds__((Tile<LOGS, LINES, COLS>::NT)) ntt_pass_kernel
         }
     } else if (IO == IO_REDUCE) {
 #pragma unroll
-        for (int e = 0; e < 16; ++e) x[e] = reduce64(x[e], q, mcv.mu);
+        for (int e = 0; e < 16; ++e) x[e] = reduce64(x[e], q, mcv.mu, mcv.nq);
     }
     gstore<LOGS, COLS, IOL::OUT_LO, IOL::OUT_HI>(x, dst, t, lg, a.n2);
 }
@@ -531,7 +532,7 @@ ksk_rows_kernel(const KskRowArgs a) {
             if (ROWPASS) {
                 gload<LOGS, false, IOF::IN_LO, IOF::IN_HI>(xv, src, t, lg, a.n2);
                 if (lds_used) __syncthreads();
-                pass_regs<LOGS, ROW_LINES, false, true>(true, xv, lds, line, t, q,
+                pass_regs<LOGS, ROW_LINES, false, true>(true, xv, lds, line, t, q, mcv.nq,
                                                         TwRows{a.twf + (size_t)mod * N, lg, a.n1}, LastInv{});
                 lds_used = true;
             } else {
@@ -546,10 +547,10 @@ ksk_rows_kernel(const KskRowArgs a) {
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
             const ulonglong2 kv0 = k0[c], kv1 = k1[c];
-            u[2 * c] = add_mod(u[2 * c], mul_mod(xv[2 * c], kv0.x, q, mcv.mu), q);
-            u[2 * c + 1] = add_mod(u[2 * c + 1], mul_mod(xv[2 * c + 1], kv0.y, q, mcv.mu), q);
-            v[2 * c] = add_mod(v[2 * c], mul_mod(xv[2 * c], kv1.x, q, mcv.mu), q);
-            v[2 * c + 1] = add_mod(v[2 * c + 1], mul_mod(xv[2 * c + 1], kv1.y, q, mcv.mu), q);
+            u[2 * c] = add_mod(u[2 * c], mul_mod(xv[2 * c], kv0.x, q, mcv.mu, mcv.nq), q);
+            u[2 * c + 1] = add_mod(u[2 * c + 1], mul_mod(xv[2 * c + 1], kv0.y, q, mcv.mu, mcv.nq), q);
+            v[2 * c] = add_mod(v[2 * c], mul_mod(xv[2 * c], kv1.x, q, mcv.mu, mcv.nq), q);
+            v[2 * c + 1] = add_mod(v[2 * c + 1], mul_mod(xv[2 * c + 1], kv1.y, q, mcv.mu, mcv.nq), q);
         }
     }
     if (!is_p) {
@@ -560,10 +561,10 @@ ksk_rows_kernel(const KskRowArgs a) {
     // special-prime limb: inverse row pass (first pass of ModDown's iNTT) of u and v
     const TwRows twi{a.twi + (size_t)mod * N, lg, a.n1};
     if (lds_used) __syncthreads();
-    pass_regs<LOGS, ROW_LINES, false, false>(true, u, lds, line, t, q, twi, LastInv{});
+    pass_regs<LOGS, ROW_LINES, false, false>(true, u, lds, line, t, q, mcv.nq, twi, LastInv{});
     gstore<LOGS, false, IOI::OUT_LO, IOI::OUT_HI>(u, pc + (size_t)kp * N, t, lg, a.n2);
     __syncthreads();
-    pass_regs<LOGS, ROW_LINES, false, false>(true, v, lds, line, t, q, twi, LastInv{});
+    pass_regs<LOGS, ROW_LINES, false, false>(true, v, lds, line, t, q, mcv.nq, twi, LastInv{});
     gstore<LOGS, false, IOI::OUT_LO, IOI::OUT_HI>(v, pc + ((size_t)a.K + kp) * N, t, lg, a.n2);
 }
 

@@ -121,6 +121,7 @@ int build_tables(Ctx &c) {
         }
         mc[m].q = q;
         mc[m].mu = (uint64_t)(((u128)1 << 112) / q);
+        mc[m].nq = 0 - q;
         ninv[m] = h_invmod(N, q);
         w0inv[m] = twi[(size_t)m * N + 1].w;
         lip[m] = make_last(q, ninv[m], 1, w0inv[m]);
