@@ -308,6 +308,24 @@ __global__ void __launch_bounds__((Tile<LOGS, LINES, COLS>::NT)) ntt_pass_kernel
     thread_coords<LOGS, LINES, COLS>(threadIdx.x, line, t);
     const uint32_t lg = tile * LINES + line;  // this thread's column or row
 
+    // ModDown epilogue operands (u, and the automorphed addend), issued
+    // before the pass input: loads complete in issue order, so one memory
+    // latency covers all three instead of a second one after the pass
+    uint64_t uv[16], bv[16];
+    const uint32_t ui = a.m.cidx[li];
+    const uint64_t *ad = (IO == IO_MDEPI && a.io.add[b]) ? a.io.add[b] + (size_t)ui * N : nullptr;
+    if (IO == IO_MDEPI) {
+        gload<LOGS, COLS, IOL::OUT_LO, IOL::OUT_HI>(uv, a.io.uq[b] + (size_t)ui * N, t, lg, a.n2);
+        if (ad) {
+            const uint32_t ag = a.io.add_galois[b];
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const uint32_t j = jdx<COLS>(lg, k_of<IOL::OUT_LO, IOL::OUT_HI>(t, e), a.n2);
+                bv[e] = ad[ag != 1 ? aut_eval_src(j, ag, a.n) : j];
+            }
+        }
+    }
+
     uint64_t x[16];
     if (IO == IO_GATHER) {
         const uint32_t g = a.io.galois[b];
@@ -328,21 +346,12 @@ __global__ void __launch_bounds__((Tile<LOGS, LINES, COLS>::NT)) ntt_pass_kernel
     }
 
     if (IO == IO_MDEPI) {
-        const uint32_t ui = a.m.cidx[li];
-        const uint64_t *u = a.io.uq[b] + (size_t)ui * N;
         const Shoup pi = a.pinv[ui];
-        const uint64_t *ad = a.io.add[b] ? a.io.add[b] + (size_t)ui * N : nullptr;
-        const uint32_t ag = a.io.add_galois[b];
-        uint64_t uv[16];
-        gload<LOGS, COLS, IOL::OUT_LO, IOL::OUT_HI>(uv, u, t, lg, a.n2);
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
             const uint64_t z = reduce64(x[e], q, mcv.mu, mcv.nq);
             uint64_t r = mul_shoup(uv[e] + q - z, pi.w, pi.wp, q);
-            if (ad) {
-                const uint32_t j = jdx<COLS>(lg, k_of<IOL::OUT_LO, IOL::OUT_HI>(t, e), a.n2);
-                r = add_mod(r, ad[ag != 1 ? aut_eval_src(j, ag, a.n) : j], q);
-            }
+            if (ad) r = add_mod(r, bv[e], q);
             x[e] = r;
         }
     } else if (IO == IO_REDUCE) {
