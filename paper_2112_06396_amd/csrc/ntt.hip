@@ -69,6 +69,11 @@ __device__ __forceinline__ int k_of(int t, int e) {
     return ((r >> LO) << HI) | (v << LO) | (r & ((1 << LO) - 1));
 }
 
+#ifndef HKS_TW_HOIST
+#define HKS_TW_HOIST 1
+#endif
+constexpr bool TW_HOIST = HKS_TW_HOIST != 0;  // pass kernels load a phase's twiddles up front
+
 // Twiddle sources.  The butterfly group m = k >> (bit+1) of local stage ls
 // (0-based within the pass) uses
 //   column pass: table index 2^ls + m;
@@ -89,11 +94,28 @@ struct TwRows {
 // Each stage loads 16 >> (vb+1) distinct twiddles.  With FOLD (the inverse
 // column pass) the global last inverse stage multiplies by the folded
 // constants instead.
-template <int LOGS, bool FWD, bool FOLD, int LO, int HI, typename TW>
+template <int LOGS, bool FWD, bool FOLD, int LO, int HI, bool HOIST, typename TW>
 __device__ __forceinline__ void phase_regs(uint64_t (&x)[16], int t, uint64_t q, uint64_t nq, const TW &tws,
                                            const LastInv &fold) {
     constexpr int B = HI - LO;
     const uint64_t q2 = 2 * q;
+    // HOIST: every twiddle of the phase loaded up front (16 >> (vb+1) per
+    // stage), one memory latency per phase instead of one per stage, for
+    // more registers
+    Shoup wall[HOIST ? B : 1][8];
+#pragma unroll
+    for (int st = 0; st < (HOIST ? B : 0); ++st) {
+        const int bit = FWD ? (HI - 1 - st) : (LO + st);
+        const int vb = bit - LO;
+        const int ls = LOGS - 1 - bit;
+#pragma unroll
+        for (int key = 0; key < 8; ++key) {
+            if (key < (16 >> (vb + 1)) && !(FOLD && ls == 0)) {
+                const uint32_t k = (uint32_t)k_of<LO, HI>(t, key << (vb + 1));
+                wall[st][key] = tws(ls, k >> (bit + 1));
+            }
+        }
+    }
 #pragma unroll
     for (int st = 0; st < B; ++st) {
         const int bit = FWD ? (HI - 1 - st) : (LO + st);
@@ -103,7 +125,9 @@ __device__ __forceinline__ void phase_regs(uint64_t (&x)[16], int t, uint64_t q,
         Shoup wc[8];
 #pragma unroll
         for (int key = 0; key < 8; ++key) {
-            if (key < (16 >> (vb + 1)) && !fold_stage) {
+            if (HOIST) {
+                wc[key] = wall[HOIST ? st : 0][key];
+            } else if (key < (16 >> (vb + 1)) && !fold_stage) {
                 const uint32_t k = (uint32_t)k_of<LO, HI>(t, key << (vb + 1));
                 wc[key] = tws(ls, k >> (bit + 1));
             }
@@ -151,20 +175,20 @@ __device__ __forceinline__ void lds_get(const uint64_t *lds, uint64_t (&x)[16], 
 // P2, inverse: P0).  The LDS tile carries the exchanges between phases; the
 // caller synchronizes before this tile is written again.  Work is done only
 // where `active` holds, but every thread reaches every barrier.
-template <int LOGS, int LINES, bool COLS, bool FWD, typename TW>
+template <int LOGS, int LINES, bool COLS, bool FWD, bool HOIST, typename TW>
 __device__ __forceinline__ void pass_regs(bool active, uint64_t (&x)[16], uint64_t *lds, int line, int t, uint64_t q,
                                           uint64_t nq, const TW &tws, const LastInv &fold) {
     using P = Phases<LOGS>;
     constexpr bool FOLD = !FWD && COLS;
     if (FWD) {
         if (active) {
-            phase_regs<LOGS, true, FOLD, P::P0L, P::P0H>(x, t, q, nq, tws, fold);
+            phase_regs<LOGS, true, FOLD, P::P0L, P::P0H, HOIST>(x, t, q, nq, tws, fold);
             lds_put<LOGS, LINES, COLS, P::P0L, P::P0H>(lds, x, line, t);
         }
         __syncthreads();
         if (active) {
             lds_get<LOGS, LINES, COLS, P::P1L, P::P1H>(lds, x, line, t);
-            phase_regs<LOGS, true, FOLD, P::P1L, P::P1H>(x, t, q, nq, tws, fold);
+            phase_regs<LOGS, true, FOLD, P::P1L, P::P1H, HOIST>(x, t, q, nq, tws, fold);
         }
         if constexpr (P::THREE) {
             __syncthreads();
@@ -172,13 +196,13 @@ __device__ __forceinline__ void pass_regs(bool active, uint64_t (&x)[16], uint64
             __syncthreads();
             if (active) {
                 lds_get<LOGS, LINES, COLS, P::P2L, P::P2H>(lds, x, line, t);
-                phase_regs<LOGS, true, FOLD, P::P2L, P::P2H>(x, t, q, nq, tws, fold);
+                phase_regs<LOGS, true, FOLD, P::P2L, P::P2H, HOIST>(x, t, q, nq, tws, fold);
             }
         }
     } else {
         if constexpr (P::THREE) {
             if (active) {
-                phase_regs<LOGS, false, FOLD, P::P2L, P::P2H>(x, t, q, nq, tws, fold);
+                phase_regs<LOGS, false, FOLD, P::P2L, P::P2H, HOIST>(x, t, q, nq, tws, fold);
                 lds_put<LOGS, LINES, COLS, P::P2L, P::P2H>(lds, x, line, t);
             }
             __syncthreads();
@@ -186,13 +210,13 @@ __device__ __forceinline__ void pass_regs(bool active, uint64_t (&x)[16], uint64
             __syncthreads();
         }
         if (active) {
-            phase_regs<LOGS, false, FOLD, P::P1L, P::P1H>(x, t, q, nq, tws, fold);
+            phase_regs<LOGS, false, FOLD, P::P1L, P::P1H, HOIST>(x, t, q, nq, tws, fold);
             lds_put<LOGS, LINES, COLS, P::P1L, P::P1H>(lds, x, line, t);
         }
         __syncthreads();
         if (active) {
             lds_get<LOGS, LINES, COLS, P::P0L, P::P0H>(lds, x, line, t);
-            phase_regs<LOGS, false, FOLD, P::P0L, P::P0H>(x, t, q, nq, tws, fold);
+            phase_regs<LOGS, false, FOLD, P::P0L, P::P0H, HOIST>(x, t, q, nq, tws, fold);
         }
     }
 }
@@ -340,9 +364,9 @@ __global__ void __launch_bounds__((Tile<LOGS, LINES, COLS>::NT)) ntt_pass_kernel
 
     const LastInv fold = (!FWD && COLS) ? a.li[a.m.cidx[li]] : LastInv{};
     if constexpr (COLS) {
-        pass_regs<LOGS, LINES, COLS, FWD>(true, x, lds, line, t, q, mcv.nq, TwCols{tw}, fold);
+        pass_regs<LOGS, LINES, COLS, FWD, TW_HOIST>(true, x, lds, line, t, q, mcv.nq, TwCols{tw}, fold);
     } else {
-        pass_regs<LOGS, LINES, COLS, FWD>(true, x, lds, line, t, q, mcv.nq, TwRows{tw, lg, a.n1}, fold);
+        pass_regs<LOGS, LINES, COLS, FWD, TW_HOIST>(true, x, lds, line, t, q, mcv.nq, TwRows{tw, lg, a.n1}, fold);
     }
 
     if (IO == IO_MDEPI) {
@@ -541,7 +565,7 @@ ksk_rows_kernel(const KskRowArgs a) {
             if (ROWPASS) {
                 gload<LOGS, false, IOF::IN_LO, IOF::IN_HI>(xv, src, t, lg, a.n2);
                 if (lds_used) __syncthreads();
-                pass_regs<LOGS, ROW_LINES, false, true>(true, xv, lds, line, t, q, mcv.nq,
+                pass_regs<LOGS, ROW_LINES, false, true, false>(true, xv, lds, line, t, q, mcv.nq,
                                                         TwRows{a.twf + (size_t)mod * N, lg, a.n1}, LastInv{});
                 lds_used = true;
             } else {
@@ -570,10 +594,10 @@ ksk_rows_kernel(const KskRowArgs a) {
     // special-prime limb: inverse row pass (first pass of ModDown's iNTT) of u and v
     const TwRows twi{a.twi + (size_t)mod * N, lg, a.n1};
     if (lds_used) __syncthreads();
-    pass_regs<LOGS, ROW_LINES, false, false>(true, u, lds, line, t, q, mcv.nq, twi, LastInv{});
+    pass_regs<LOGS, ROW_LINES, false, false, false>(true, u, lds, line, t, q, mcv.nq, twi, LastInv{});
     gstore<LOGS, false, IOI::OUT_LO, IOI::OUT_HI>(u, pc + (size_t)kp * N, t, lg, a.n2);
     __syncthreads();
-    pass_regs<LOGS, ROW_LINES, false, false>(true, v, lds, line, t, q, mcv.nq, twi, LastInv{});
+    pass_regs<LOGS, ROW_LINES, false, false, false>(true, v, lds, line, t, q, mcv.nq, twi, LastInv{});
     gstore<LOGS, false, IOI::OUT_LO, IOI::OUT_HI>(v, pc + ((size_t)a.K + kp) * N, t, lg, a.n2);
 }
 
