@@ -116,13 +116,91 @@ def cpu_baseline(sample: int):
                       f"({dt:.1f} s)"}
 
 
+def extras(args, ctx, hks, synth, cts, ksks, outs, gal, key_mods, n, plain_value, stream):
+    """Batched, hoisted, graph-replayed and trace figures beside the plain
+    Rotate: the same N=2^16, L=24, dnum=3 key-switch in the forms of the
+    paper's hoisting / batching and of a bootstrapping-shaped trace."""
+    import torch
+    from paper_2112_06396_amd import trace
+    res = {}
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def rate(fn, per_call, reps):
+        fn(0)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for i in range(reps):
+            fn(i + 1)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return reps * per_call / (e0.elapsed_time(e1) / 1e3)
+
+    # keys and ciphertexts drawn on the GPU (values only need to be residues)
+    nk = 64
+    dkeys = [synth.device_residues(key_mods, (DNUM, 2), n, 5000 + i) for i in range(nk)]
+    dcts = [synth.device_residues(key_mods[:LEVEL], (2,), n, 7000 + i) for i in range(32)]
+    douts = [hks.empty((2, LEVEL, n)) for _ in range(nk)]
+    gals = [hks.hks_galois_for_rotation(k + 1, LOG_N) for k in range(nk)]
+    torch.cuda.synchronize()
+    log(f"[bench] extras: {nk} keys, 32 ciphertexts resident")
+
+    # hoisted rotations (Algorithm 4): one ModUp shared by 64 rotations with distinct keys
+    res["hrotate_r64_ks_per_s"] = rate(
+        lambda i: hks.hks_hrotate(ctx, cts[i % args.pool], LEVEL, gals, dkeys, douts, stream), nk, 4)
+    # 32 ciphertexts rotated once: one shared key (read once per step) / 32 distinct keys and indices
+    res["batch32_shared_key_ks_per_s"] = rate(
+        lambda i: hks.hks_batch_rotate(ctx, dcts, LEVEL, [gal] * 32, [dkeys[i % nk]] * 32, douts[:32], stream),
+        32, 8)
+    res["batch32_distinct_keys_ks_per_s"] = rate(
+        lambda i: hks.hks_batch_rotate(ctx, dcts, LEVEL, gals[:32], dkeys[32 * (i % 2):32 * (i % 2) + 32],
+                                       douts[:32], stream), 32, 8)
+    res["batch_vs_plain"] = res["batch32_shared_key_ks_per_s"] / plain_value
+    # the plain Rotate replayed from hipGraphs (one per pool entry)
+    graphs = []
+    for j in range(args.pool):
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            hks.hks_rotate(ctx, cts[j], LEVEL, gal, ksks[j], outs[j])
+        graphs.append(g)
+    torch.cuda.synchronize()
+    res["graph_rotate_ks_per_s"] = rate(lambda i: graphs[i % args.pool].replay(), 1, max(50, args.steps))
+    del graphs
+    log(f"[bench] hrotate r=64 {res['hrotate_r64_ks_per_s']:.0f} ks/s; batch 32 shared key "
+        f"{res['batch32_shared_key_ks_per_s']:.0f}, distinct keys {res['batch32_distinct_keys_ks_per_s']:.0f}; "
+        f"graph-replayed Rotate {res['graph_rotate_ks_per_s']:.0f}")
+    del dkeys, dcts, douts
+    torch.cuda.empty_cache()
+
+    # bootstrapping-shaped trace: L = 35 -> 9, K = 12, dnum = 3, 120 key-switches
+    pq = hks.hks_gen_primes(50, LOG_N + 1, 47)
+    tctx = hks.Context(LOG_N, pq[:35], pq[35:], 3, max_batch=16)
+    plan = trace.bootstrap_plan(35)
+    bufs = trace.TraceBuffers(plan, n)
+    bufs.view("x0", 35).copy_(synth.device_residues(pq[:35], (2,), n, 11))
+    diag = {d: synth.device_residues(pq[:35], (), n, 100 + i) for i, d in enumerate(plan.diagonals)}
+    tkeys = {k: synth.device_residues(pq, (3, 2), n, 2000 + i) for i, k in enumerate(plan.rotations)}
+    rlk = synth.device_residues(pq, (3, 2), n, 1999)
+    res["trace_ks_per_s_eager"] = rate(lambda i: trace.run_plan(tctx, plan, bufs, diag, tkeys, rlk),
+                                       plan.key_switches, 3)
+    gr = trace.capture(tctx, plan, bufs, diag, tkeys, rlk)
+    res["trace_ks_per_s_graph"] = rate(lambda i: gr.replay(), plan.key_switches, 3)
+    res["trace"] = {"key_switches": plan.key_switches, "rotation_keys": len(plan.rotations), "levels": "35->9",
+                    "ops": len(plan.ops)}
+    log(f"[bench] trace ({plan.key_switches} key-switches, L 35->9): eager {res['trace_ks_per_s_eager']:.0f} ks/s, "
+        f"graph {res['trace_ks_per_s_graph']:.0f} ks/s")
+    del gr
+    torch.cuda.synchronize()
+    tctx.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--pool", type=int, default=8)
-    ap.add_argument("--batch", type=int, default=8, help="ciphertexts per batched launch step (extras)")
+    ap.add_argument("--batch", type=int, default=16, help="ciphertexts per batched launch step (extras)")
     ap.add_argument("--cpu-sample", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
@@ -265,35 +343,7 @@ def main():
     }
 
     if not args.no_extras:
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-
-        def rate(fn, per_call, reps):
-            fn(0)
-            torch.cuda.synchronize()
-            e0.record(stream)
-            for i in range(reps):
-                fn(i + 1)
-            e1.record(stream)
-            torch.cuda.synchronize()
-            return reps * per_call / (e0.elapsed_time(e1) / 1e3)
-
-        nb = min(args.batch, args.pool)
-        reps = max(4, args.steps // (2 * nb))
-        # hoisted rotations (Algorithm 4): one ModUp shared by nb rotations, nb distinct keys
-        gals = [hks.hks_galois_for_rotation(k_ + 1, LOG_N) for k_ in range(nb)]
-        result[f"hrotate_r{nb}_ks_per_s"] = rate(
-            lambda i: hks.hks_hrotate(ctx, cts[i % args.pool], LEVEL, gals, ksks[:nb], outs[:nb], stream), nb, reps)
-        # nb ciphertexts rotated by one galois element with one shared key
-        result[f"batch{nb}_shared_key_ks_per_s"] = rate(
-            lambda i: hks.hks_batch_rotate(ctx, cts[:nb], LEVEL, [gal] * nb, [ksks[i % args.pool]] * nb,
-                                           outs[:nb], stream), nb, reps)
-        # nb ciphertexts, distinct rotation indices and keys
-        result[f"batch{nb}_distinct_keys_ks_per_s"] = rate(
-            lambda i: hks.hks_batch_rotate(ctx, cts[:nb], LEVEL, gals, ksks[:nb], outs[:nb], stream), nb, reps)
-        result["batch_vs_plain"] = result[f"batch{nb}_shared_key_ks_per_s"] / value
-        log(f"[bench] hrotate r={nb}: {result[f'hrotate_r{nb}_ks_per_s']:.0f} ks/s; batch {nb} shared key: "
-            f"{result[f'batch{nb}_shared_key_ks_per_s']:.0f} ks/s; distinct keys: "
-            f"{result[f'batch{nb}_distinct_keys_ks_per_s']:.0f} ks/s")
+        result.update(extras(args, ctx, hks, synth, cts, ksks, outs, gal, key_mods, n, value, stream))
 
     if args.calib_copy_mib:
         nw = args.calib_copy_mib * (1 << 20) // 8

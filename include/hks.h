@@ -193,6 +193,12 @@ int hks_ptmult(hks_ctx *ctx, const uint64_t *ct, const uint64_t *pt, uint32_t le
 int hks_mult_relin(hks_ctx *ctx, const uint64_t *ct1, const uint64_t *ct2, uint32_t level,
                    const uint64_t *rlk, int rescale, uint64_t *ct_out, void *stream);
 
+/* Add (Table "CKKS FHE API"): out = x + y limb-wise for n_poly (1..3)
+ * polynomials of level limbs each, [n_poly][level][N]; out may be x or y
+ * (elementwise, in place allowed). */
+int hks_add(hks_ctx *ctx, const uint64_t *x, const uint64_t *y, uint32_t level, uint32_t n_poly,
+            uint64_t *out, void *stream);
+
 /* ---------------------------------------------------------------- kernel timing */
 
 /* Kernel classes for hks_prof_* (bit i of a mask selects class i). */

@@ -568,6 +568,16 @@ int hks_mult_relin(hks_ctx *h, const uint64_t *ct1, const uint64_t *ct2, uint32_
     GUARD_END
 }
 
+int hks_add(hks_ctx *h, const uint64_t *x, const uint64_t *y, uint32_t level, uint32_t n_poly, uint64_t *out,
+            void *stream) {
+    GUARD_BEGIN
+    if (!h || !x || !y || !out || !aligned(x) || !aligned(y) || !aligned(out) || level < 1 || level > h->c.L ||
+        n_poly < 1 || n_poly > 3)
+        return HKS_EINVAL;
+    return hip_status(launch_add(h->c, x, y, out, n_poly * level, level, (hipStream_t)stream));
+    GUARD_END
+}
+
 int hks_prof_enable(hks_ctx *h, uint32_t mask) {
     GUARD_BEGIN
     if (!h) return HKS_EINVAL;

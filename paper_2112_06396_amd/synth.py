@@ -54,3 +54,16 @@ def cbd(g: np.random.Generator, n: int, eta: int = 21) -> np.ndarray:
 def small_uniform(g: np.random.Generator, n: int, bound: int) -> np.ndarray:
     """n coefficients uniform in [-bound, bound) (int64)."""
     return g.integers(-bound, bound, size=n, dtype=np.int64)
+
+
+def device_residues(mods, lead_shape, n: int, seed: int, device="cuda"):
+    """[*lead_shape][len(mods)][n] residues drawn on the GPU (torch's seeded
+    generator): for benchmark-scale keys and ciphertexts whose values only
+    need to be valid residues of the right moduli.  Values are 62-bit
+    uniform words reduced mod q (relative bias below 2^-12)."""
+    import torch
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed)
+    qs = torch.tensor([int(m) for m in mods], dtype=torch.int64, device=device).view(-1, 1)
+    x = torch.randint(0, 1 << 62, (*lead_shape, len(mods), n), generator=gen, dtype=torch.int64, device=device)
+    return (x % qs).view(torch.uint64)

@@ -399,3 +399,102 @@ def test_deterministic_repeat():
     hks.hks_rotate(ctx, ct, 24, g, ksk, o1)
     hks.hks_rotate(ctx, ct, 24, g, ksk, o2)
     assert torch.equal(o1.view(torch.int64), o2.view(torch.int64))
+
+
+# ------------------------------------------------------------------ bootstrapping-shaped trace, hipGraph
+
+
+def _oracle_plan(pr, plan, x0, diag, keys, rlk):
+    """The plan's ops through the oracle (Algorithms 1, 2, 4 and Rescale)."""
+    bufs = {"x0": x0}
+    for op in plan.ops:
+        kind = op[0]
+        if kind == "hrotate":
+            _, src, level, ks, dsts = op
+            gals = [pow(5, -k, 2 * pr.n) for k in ks]
+            outs = O.hrotate(pr, bufs[src], level, gals, [keys[k] for k in ks])
+            for d, o in zip(dsts, outs):
+                bufs[d] = o
+        elif kind == "ptmult":
+            _, src, d, level, dst = op
+            bufs[dst] = O.ptmult(pr, bufs[src], diag[d][:level], level, False)
+        elif kind == "add":
+            _, a, b, level, dst = op
+            bufs[dst] = np.stack([O.add_vec(bufs[a][i], bufs[b][i], pr.log_n, pr.q[:level]) for i in range(2)])
+        elif kind == "rescale":
+            _, src, level, dst = op
+            bufs[dst] = O.rescale(pr, bufs[src], level)
+        elif kind == "mult":
+            _, a, b, level, dst = op
+            bufs[dst] = O.mult_relin(pr, bufs[a], bufs[b], level, rlk, True)
+    return bufs[plan.out]
+
+
+def test_trace_eager_and_graph_replays_match_oracle():
+    """A small bootstrapping-shaped trace (hoisted stages, PtMult sums,
+    Rescale, Mult + relin at falling levels, mirrored stages) run eagerly and
+    as one captured hipGraph replayed three times, with eager library work
+    and buffer clearing between replays: every result equals the oracle's."""
+    from paper_2112_06396_amd import trace
+    pr, ctx = _get((12, 10, 4, 3), 4)
+    hks = H()
+    plan = trace.bootstrap_plan(pr.L, counts=(2, 2, 3), strides=(1, 4, 16), evalmod_levels=3)
+    g = synth.rng(200)
+    x0 = _rand_ct(pr, pr.L, 201)
+    diag = {d: synth.uniform_residues(g, pr.q, pr.n) for d in plan.diagonals}
+    keys = {k: _rand_ksk(pr, 300 + i) for i, k in enumerate(plan.rotations)}
+    rlk = _rand_ksk(pr, 299)
+    ref = _oracle_plan(pr, plan, x0, diag, keys, rlk)
+
+    bufs = trace.TraceBuffers(plan, pr.n)
+    bufs.view("x0", pr.L).copy_(dev(x0))
+    ddiag = {d: dev(v) for d, v in diag.items()}
+    dkeys = {k: dev(v) for k, v in keys.items()}
+    drlk = dev(rlk)
+    out = trace.run_plan(ctx, plan, bufs, ddiag, dkeys, drlk)
+    assert np.array_equal(host(out), ref)
+
+    gr = trace.capture(ctx, plan, bufs, ddiag, dkeys, drlk)
+    other = dev(_rand_ct(pr, pr.L, 202))
+    other_out = hks.empty((2, pr.L, pr.n))
+    for rep in range(3):
+        for name, t in bufs.ct.items():
+            if name != "x0":
+                t.zero_()
+        hks.hks_rotate(ctx, other, pr.L, hks.hks_galois_for_rotation(3, pr.log_n), dkeys[plan.rotations[0]],
+                       other_out)
+        torch.cuda.synchronize()
+        gr.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(host(bufs.view(plan.out, plan.out_level)), ref), rep
+
+
+def test_full_trace_graph_equals_eager():
+    """The bootstrapping-shaped trace at N=2^16, L=35 -> 9, K=12, dnum=3
+    (120 key-switches, 80 rotation keys + one relinearization key): the
+    captured hipGraph's output equals the eager run's, twice in a row."""
+    from paper_2112_06396_amd import trace
+    hks = H()
+    pq = hks.hks_gen_primes(50, 17, 47)
+    ctx = hks.Context(16, pq[:35], pq[35:], 3, max_batch=16)
+    try:
+        plan = trace.bootstrap_plan(35)
+        n = ctx.n
+        keymods = pq
+        bufs = trace.TraceBuffers(plan, n)
+        bufs.view("x0", 35).copy_(synth.device_residues(pq[:35], (2,), n, 1))
+        diag = {d: synth.device_residues(pq[:35], (), n, 10 + i) for i, d in enumerate(plan.diagonals)}
+        keys = {k: synth.device_residues(keymods, (3, 2), n, 1000 + i) for i, k in enumerate(plan.rotations)}
+        rlk = synth.device_residues(keymods, (3, 2), n, 999)
+        eager = trace.run_plan(ctx, plan, bufs, diag, keys, rlk).clone()
+        gr = trace.capture(ctx, plan, bufs, diag, keys, rlk)
+        for rep in range(2):
+            bufs.view(plan.out, plan.out_level).zero_()
+            torch.cuda.synchronize()
+            gr.replay()
+            torch.cuda.synchronize()
+            assert torch.equal(bufs.view(plan.out, plan.out_level).view(torch.int64), eager.view(torch.int64)), rep
+        del gr
+    finally:
+        torch.cuda.synchronize()
+        ctx.close()
