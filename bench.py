@@ -188,10 +188,65 @@ def extras(args, ctx, hks, synth, cts, ksks, outs, gal, key_mods, n, plain_value
                     "ops": len(plan.ops)}
     log(f"[bench] trace ({plan.key_switches} key-switches, L 35->9): eager {res['trace_ks_per_s_eager']:.0f} ks/s, "
         f"graph {res['trace_ks_per_s_graph']:.0f} ks/s")
-    del gr
+    del gr, bufs, diag, tkeys, rlk
     torch.cuda.synchronize()
     tctx.close()
+    torch.cuda.empty_cache()
+    res["serving"] = serving_extra(args, hks, synth)
     return res
+
+
+def serving_extra(args, hks, synth):
+    """Continuous batching vs one request at a time for Poisson arrivals of
+    Rotate / Mult+relin requests from per-client keys at N in {2^15, 2^16},
+    level uniform in [3, 35], L_max = 35, K = 12, dnum = 3, keys resident up
+    to a budget (LRU, re-upload from pinned host memory)."""
+    import torch
+    from paper_2112_06396_amd import serving
+    n_clients, budget_gib, n_req = args.serving_clients, args.serving_budget_gib, args.serving_requests
+    params = {}
+    for ln in (15, 16):
+        pq = hks.hks_gen_primes(50, ln + 1, 47)
+        params[ln] = (pq[:35], pq[35:], 3)
+    host_keys = {}
+    for c in range(n_clients):
+        ln = 15 if c % 2 == 0 else 16
+        q, p, _ = params[ln]
+        for j, kind in enumerate(("rot", "rlk")):
+            d = synth.device_residues(q + p, (3, 2), 1 << ln, 30000 + 2 * c + j)
+            h = torch.empty(d.shape, dtype=torch.int64, pin_memory=True).view(torch.uint64)
+            h.copy_(d)
+            host_keys[(c, kind, ln)] = h
+            del d
+    inputs = {(ln, lv): [synth.device_residues(params[ln][0][:lv], (2,), 1 << ln, 40000 + 100 * lv + 10 * ln + i)
+                         for i in range(2)] for ln in (15, 16) for lv in range(3, 36)}
+    torch.cuda.synchronize()
+    key_bytes = sum(t.numel() * 8 for t in host_keys.values())
+    ks = serving.KeyStore(host_keys, budget=budget_gib << 30)
+    ex = serving.HksExecutor(params, lanes=args.serving_lanes, max_batch=args.batch, slots_per_n=64, keystore=ks,
+                             inputs=inputs)
+    eng = serving.Engine(ex, lanes=args.serving_lanes, max_batch=args.batch)
+    log(f"[bench] serving: {n_clients} clients, {key_bytes / 2**30:.1f} GiB of keys, budget {budget_gib} GiB")
+    # capacity of the plain loop: everything arrives at once, one request at a time
+    sat = serving.poisson_requests(min(n_req, 2000), rate=1e9, n_clients=n_clients, seed=1)
+    cap = eng.run(sat, one_at_a_time=True)["throughput_per_s"]
+    out = {"clients": n_clients, "key_gib": round(key_bytes / 2**30, 1), "key_budget_gib": budget_gib,
+           "requests_per_run": n_req, "plain_capacity_per_s": cap, "runs": []}
+    for f in (0.5, 0.8, 1.0, 1.2):
+        row = {"load": f}
+        for mode in ("plain", "batched"):
+            reqs = serving.poisson_requests(n_req, rate=f * cap, n_clients=n_clients, seed=int(100 * f))
+            up0 = ks.uploads
+            st = eng.run(reqs, one_at_a_time=(mode == "plain"))
+            st["key_uploads"] = ks.uploads - up0
+            row[mode] = st
+        out["runs"].append(row)
+        log(f"[bench] serving load {f}: plain {row['plain']['throughput_per_s']:.0f}/s p50 "
+            f"{row['plain']['p50_ms']:.2f} p99 {row['plain']['p99_ms']:.2f} ms | batched "
+            f"{row['batched']['throughput_per_s']:.0f}/s p50 {row['batched']['p50_ms']:.2f} p99 "
+            f"{row['batched']['p99_ms']:.2f} ms")
+    ex.close()
+    return out
 
 
 def main():
@@ -201,6 +256,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--pool", type=int, default=8)
     ap.add_argument("--batch", type=int, default=16, help="ciphertexts per batched launch step (extras)")
+    ap.add_argument("--serving-clients", type=int, default=64)
+    ap.add_argument("--serving-budget-gib", type=int, default=8)
+    ap.add_argument("--serving-requests", type=int, default=4000)
+    ap.add_argument("--serving-lanes", type=int, default=2)
     ap.add_argument("--cpu-sample", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")

@@ -80,8 +80,8 @@ typedef struct {
     const uint64_t *p;    /* host array [K] */
     uint32_t max_batch;   /* ciphertexts (or rotations) per batched launch step,
                              0..16 (0 = 1).  The workspace holds one slot per
-                             step entry: (L + dnum(L+K) + 2(L+K) + 2K + 2L) N
-                             words each, plus 7 L N + 2 N words shared. */
+                             step entry: (6L + dnum(L+K) + 2(L+K) + 2K + 2L) N
+                             words each, plus 2 L N + 2 N words shared. */
 } hks_params;
 
 /* ---------------------------------------------------------------- host helpers */
@@ -192,6 +192,14 @@ int hks_ptmult(hks_ctx *ctx, const uint64_t *ct, const uint64_t *pt, uint32_t le
  * KeySwitch(a3, rlk); (b3 + u, c3 + v); then Rescale if rescale != 0. */
 int hks_mult_relin(hks_ctx *ctx, const uint64_t *ct1, const uint64_t *ct2, uint32_t level,
                    const uint64_t *rlk, int rescale, uint64_t *ct_out, void *stream);
+
+/* Mult (Algorithm 2) of n independent pairs at one level (same semantics and
+ * bits as n calls of hks_mult_relin).  ct1, ct2, rlk, ct_out are HOST arrays
+ * of n device pointers; up to max_batch pairs share the key-switch launches
+ * of a step.  HKS_EINVAL if an output equals any input or another output. */
+int hks_batch_mult_relin(hks_ctx *ctx, uint32_t n, const uint64_t *const *ct1, const uint64_t *const *ct2,
+                         uint32_t level, const uint64_t *const *rlk, int rescale, uint64_t *const *ct_out,
+                         void *stream);
 
 /* Add (Table "CKKS FHE API"): out = x + y limb-wise for n_poly (1..3)
  * polynomials of level limbs each, [n_poly][level][N]; out may be x or y

@@ -294,7 +294,7 @@ int hks_create(const hks_params *p, int device, hks_ctx **out) {
     if (rc == HKS_OK) {
         const size_t N = c.n, L = c.L, cap = c.batch_cap;
         size_t words[] = {cap * c.st_y(), cap * c.st_ext(), cap * c.st_uv(), cap * c.st_p(), cap * c.st_z(),
-                          2 * L * N,      3 * L * N,        2 * N,           2 * L * N};
+                          cap * c.st_rot(), cap * c.st_t(), 2 * N,         2 * L * N};
         size_t total = 0;
         for (size_t w : words) total += w;
         c.ws_bytes = total * sizeof(uint64_t);
@@ -550,21 +550,55 @@ int hks_ptmult(hks_ctx *h, const uint64_t *ct, const uint64_t *pt, uint32_t leve
     GUARD_END
 }
 
+// Mult (Algorithm 2) of n pairs at one level in steps of batch_cap: per pair
+// the tensor product into its workspace slot, then one batched key-switch of
+// the a1 a2 terms with the (b3, c3) additions, then Rescale per pair.
+int do_mult_relin(Ctx &c, uint32_t n, const uint64_t *const *ct1, const uint64_t *const *ct2, uint32_t level,
+                  const uint64_t *const *rlk, int rescale, uint64_t *const *out, hipStream_t s) {
+    const size_t pl = (size_t)level * c.n;
+    const uint32_t step = std::min<uint32_t>(c.batch_cap, MAXCT);
+    for (uint32_t i0 = 0; i0 < n; i0 += step) {
+        const uint32_t nb = std::min(step, n - i0);
+        KsJob jobs[MAXCT];
+        for (uint32_t b = 0; b < nb; ++b) {
+            uint64_t *t = c.ws_t + b * c.st_t();
+            HKS_TRY(launch_tensor(c, ct1[i0 + b], ct2[i0 + b], t, level, s));
+            jobs[b] = KsJob{t, 1, rlk[i0 + b], rescale ? c.ws_rot + b * c.st_rot() : out[i0 + b], t + pl, t + 2 * pl};
+        }
+        int rc = do_keyswitch_step(c, jobs, nb, level, s);
+        if (rc) return rc;
+        for (uint32_t b = 0; b < nb && rescale; ++b) {
+            rc = do_rescale(c, c.ws_rot + b * c.st_rot(), level, out[i0 + b], s);
+            if (rc) return rc;
+        }
+    }
+    return HKS_OK;
+}
+
 int hks_mult_relin(hks_ctx *h, const uint64_t *ct1, const uint64_t *ct2, uint32_t level, const uint64_t *rlk,
                    int rescale, uint64_t *ct_out, void *stream) {
     GUARD_BEGIN
     if (!h || !ct1 || !ct2 || !rlk || !ct_out || !aligned(ct1) || !aligned(ct2) || !aligned(rlk) ||
         !aligned(ct_out) || level < 1 || level > h->c.L || (rescale && level < 2))
         return HKS_EINVAL;
-    Ctx &c = h->c;
-    hipStream_t s = (hipStream_t)stream;
-    const size_t pl = (size_t)level * c.n;
-    HKS_TRY(launch_tensor(c, ct1, ct2, c.ws_t, level, s));
-    uint64_t *dst = rescale ? c.ws_rot : ct_out;
-    const KsJob job{c.ws_t, 1, rlk, dst, c.ws_t + pl, c.ws_t + 2 * pl};
-    int rc = do_keyswitch_jobs(c, &job, 1, level, s);
-    if (rc || !rescale) return rc;
-    return do_rescale(c, c.ws_rot, level, ct_out, s);
+    return do_mult_relin(h->c, 1, &ct1, &ct2, level, &rlk, rescale, &ct_out, (hipStream_t)stream);
+    GUARD_END
+}
+
+int hks_batch_mult_relin(hks_ctx *h, uint32_t n, const uint64_t *const *ct1, const uint64_t *const *ct2,
+                         uint32_t level, const uint64_t *const *rlk, int rescale, uint64_t *const *ct_out,
+                         void *stream) {
+    GUARD_BEGIN
+    if (!h || !ct1 || !ct2 || !rlk || !ct_out || n == 0 || level < 1 || level > h->c.L || (rescale && level < 2))
+        return HKS_EINVAL;
+    for (uint32_t i = 0; i < n; ++i) {
+        if (!ct1[i] || !ct2[i] || !rlk[i] || !ct_out[i] || !aligned(ct1[i]) || !aligned(ct2[i]) ||
+            !aligned(rlk[i]) || !aligned(ct_out[i]))
+            return HKS_EINVAL;
+        for (uint32_t j = 0; j < n; ++j)
+            if (ct_out[i] == ct1[j] || ct_out[i] == ct2[j] || (j != i && ct_out[i] == ct_out[j])) return HKS_EINVAL;
+    }
+    return do_mult_relin(h->c, n, ct1, ct2, level, rlk, rescale, ct_out, (hipStream_t)stream);
     GUARD_END
 }
 

@@ -104,8 +104,8 @@ struct Ctx {
     uint64_t *ws_uv = nullptr;   // [cap][2][L+K][N]     KSKInnerProd output on the q limbs
     uint64_t *ws_p = nullptr;    // [cap][2][K][N]       ModDown P-limbs (coefficient form)
     uint64_t *ws_z = nullptr;    // [cap][2][L][N]       ModDown correction
-    uint64_t *ws_rot = nullptr;  // [2][L][N]            PtMult / Mult scratch before Rescale
-    uint64_t *ws_t = nullptr;    // [3][L][N]            tensor product
+    uint64_t *ws_rot = nullptr;  // [cap][2][L][N]       PtMult / Mult output before Rescale
+    uint64_t *ws_t = nullptr;    // [cap][3][L][N]       tensor product
     uint64_t *ws_r = nullptr;    // [2][N]               Rescale: coefficient-form last limbs
     uint64_t *ws_w = nullptr;    // [2][L][N]            Rescale: rounding correction
     size_t st_y() const { return (size_t)L * n; }
@@ -113,6 +113,8 @@ struct Ctx {
     size_t st_uv() const { return (size_t)2 * M * n; }
     size_t st_p() const { return (size_t)2 * K * n; }
     size_t st_z() const { return (size_t)2 * L * n; }
+    size_t st_rot() const { return (size_t)2 * L * n; }
+    size_t st_t() const { return (size_t)3 * L * n; }
 
     // kernel timing (hks_prof_*): event pairs per kernel class
     mutable uint32_t prof_mask = 0;

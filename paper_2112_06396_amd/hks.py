@@ -42,7 +42,8 @@ EXPORTS = (
     "hks_gen_primes", "hks_galois_for_rotation", "hks_galois_conjugate", "hks_strerror",
     "hks_create", "hks_destroy", "hks_query", "hks_ntt", "hks_intt", "hks_automorph",
     "hks_modup", "hks_ksk_inner", "hks_moddown", "hks_keyswitch", "hks_rotate", "hks_hrotate",
-    "hks_batch_rotate", "hks_rescale", "hks_ptmult", "hks_mult_relin", "hks_add", "hks_prof_enable",
+    "hks_batch_rotate", "hks_rescale", "hks_ptmult", "hks_mult_relin", "hks_batch_mult_relin", "hks_add",
+    "hks_prof_enable",
     "hks_prof_read",
 )
 
@@ -117,6 +118,8 @@ def lib():
             "hks_rescale": (_i32, [_vp, _vp, _u32, _vp, _vp]),
             "hks_ptmult": (_i32, [_vp, _vp, _vp, _u32, _i32, _vp, _vp]),
             "hks_mult_relin": (_i32, [_vp, _vp, _vp, _u32, _vp, _i32, _vp, _vp]),
+            "hks_batch_mult_relin": (_i32, [_vp, _u32, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _u32,
+                                            ctypes.POINTER(_vp), _i32, ctypes.POINTER(_vp), _vp]),
             "hks_add": (_i32, [_vp, _vp, _vp, _u32, _u32, _vp, _vp]),
             "hks_prof_enable": (_i32, [_vp, _u32]),
             "hks_prof_read": (_i32, [_vp, _i32, ctypes.POINTER(ctypes.c_double), u64p]),
@@ -302,6 +305,18 @@ def hks_rescale(ctx, ct, level: int, ct_out, stream=None):
 def hks_ptmult(ctx, ct, pt, level: int, rescale: bool, ct_out, stream=None):
     _check("hks_ptmult", lib().hks_ptmult(ctx.handle, _ptr(ct), _ptr(pt), level, 1 if rescale else 0, _ptr(ct_out),
                                           _stream(stream)))
+
+
+def hks_batch_mult_relin(ctx, ct1s, ct2s, level: int, rlks, rescale: bool, outs, stream=None):
+    n = len(ct1s)
+    if len(ct2s) != n or len(rlks) != n or len(outs) != n:
+        raise ValueError("ct1s, ct2s, rlks and outs must have the same length")
+    a = (_vp * n)(*[_ptr(c) for c in ct1s])
+    b = (_vp * n)(*[_ptr(c) for c in ct2s])
+    k = (_vp * n)(*[_ptr(r) for r in rlks])
+    o = (_vp * n)(*[_ptr(x) for x in outs])
+    _check("hks_batch_mult_relin", lib().hks_batch_mult_relin(ctx.handle, n, a, b, level, k, 1 if rescale else 0, o,
+                                                              _stream(stream)))
 
 
 def hks_add(ctx, x, y, level: int, n_poly: int, out, stream=None):

@@ -498,3 +498,73 @@ def test_full_trace_graph_equals_eager():
     finally:
         torch.cuda.synchronize()
         ctx.close()
+
+
+# ------------------------------------------------------------------ serving loop
+
+
+def test_serving_results_same_alone_and_in_the_mix():
+    """Requests of two ring degrees and mixed levels and ops, served with
+    continuous batching on two lanes under a key budget that forces
+    evictions, give exactly the bits of the same requests served one at a
+    time; a sample of them also equals the oracle (Algorithms 2 and 3)."""
+    import copy
+    from paper_2112_06396_amd import serving
+    hks = H()
+    prs = {12: O.make_params(12, 8, 3, 3), 13: O.make_params(13, 8, 3, 3)}
+    n_clients = 6
+    reqs = serving.poisson_requests(48, rate=2e5, n_clients=n_clients, log_ns=(12, 13), levels=(3, 8), seed=5)
+    host_np, host_keys = {}, {}
+    for c in range(n_clients):
+        ln = 12 if c % 2 == 0 else 13
+        for j, kind in enumerate(("rot", "rlk")):
+            k = _rand_ksk(prs[ln], 400 + 2 * c + j)
+            host_np[(c, kind, ln)] = k
+            host_keys[(c, kind, ln)] = torch.from_numpy(k.view(np.int64)).view(torch.uint64).pin_memory()
+    inputs_np, inputs = {}, {}
+    for ln, pr in prs.items():
+        for level in range(3, 9):
+            cts = [_rand_ct(pr, level, 500 + 10 * level + i + ln) for i in range(2)]
+            inputs_np[(ln, level)] = cts
+            inputs[(ln, level)] = [dev(c) for c in cts]
+    params = {ln: (pr.q, pr.p, 3) for ln, pr in prs.items()}
+    ks = serving.KeyStore(host_keys, budget=9 * max(t.numel() for t in host_keys.values()) * 8)
+    ex = serving.HksExecutor(params, lanes=2, max_batch=4, slots_per_n=len(reqs), keystore=ks, inputs=inputs)
+    try:
+        eng = serving.Engine(ex, lanes=2, max_batch=4)
+        alone_reqs = copy.deepcopy(reqs)
+        eng.run(reqs)
+        torch.cuda.synchronize()
+        mix = {r.rid: host(ex.out_view(r)) for r in reqs}
+        assert ks.uploads > len(host_keys)  # some keys were evicted and uploaded again
+        eng.run(alone_reqs, one_at_a_time=True)
+        torch.cuda.synchronize()
+        for r in alone_reqs:
+            assert np.array_equal(host(ex.out_view(r)), mix[r.rid]), r
+        for r in reqs[:6]:
+            pr = prs[r.log_n]
+            pool = inputs_np[(r.log_n, r.level)]
+            a = pool[r.rid % len(pool)]
+            if r.op == "rotate":
+                ref = O.rotate(pr, a, r.level, pow(5, -r.k, 2 * pr.n), host_np[(r.client, "rot", r.log_n)])
+            else:
+                b = pool[(r.rid + 1) % len(pool)]
+                ref = O.mult_relin(pr, a, b, r.level, host_np[(r.client, "rlk", r.log_n)], True)
+            assert np.array_equal(mix[r.rid], ref), r
+    finally:
+        ex.close()
+
+
+@pytest.mark.parametrize("name,max_batch,n", [("cfg1", 4, 6), ("n13", 3, 4)])
+def test_batch_mult_relin_equals_oracle(name, max_batch, n):
+    pr, ctx = _get(name, max_batch)
+    hks = H()
+    for rs, level in ((True, pr.L), (False, pr.L - 1)):
+        c1 = [_rand_ct(pr, level, 600 + i) for i in range(n)]
+        c2 = [_rand_ct(pr, level, 620 + i) for i in range(n)]
+        rlks = [_rand_ksk(pr, 640 + (i % 2)) for i in range(n)]
+        drl = [dev(k) for k in rlks]
+        outs = [hks.empty((2, level - (1 if rs else 0), pr.n)) for _ in range(n)]
+        hks.hks_batch_mult_relin(ctx, [dev(c) for c in c1], [dev(c) for c in c2], level, drl, rs, outs)
+        for i in range(n):
+            assert np.array_equal(host(outs[i]), O.mult_relin(pr, c1[i], c2[i], level, rlks[i], rs)), (rs, i)
