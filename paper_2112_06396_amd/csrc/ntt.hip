@@ -32,12 +32,12 @@
 
 namespace hks {
 
-template <int LOGS, int LINES, bool COLS>
+template <int LOGS, int LINES, bool COLS, int E = 16>
 struct Tile {
     static constexpr int S = 1 << LOGS;
-    static constexpr int T = S / 16;         // threads per line
+    static constexpr int T = S / E;          // threads per line
     static constexpr int NT = LINES * T;     // threads per block
-    static constexpr int EPT = 16;           // elements per thread
+    static constexpr int EPT = E;            // elements per thread
     static constexpr int ROWP = S + S / 16;  // padded row length (row tiles)
     static constexpr int COLP = LINES + 1;   // padded k-row length (column tiles)
     static constexpr int WORDS = COLS ? S * COLP : LINES * ROWP;
@@ -46,24 +46,32 @@ struct Tile {
     }
 };
 
-// Phases of a pass over the LOGS bits of the sub-index k: P0 = [LOGS-4, LOGS),
-// P1 = [max(LOGS-8, 0), LOGS-4), P2 = [0, LOGS-8) when LOGS > 8.  The forward
-// pass runs P0, P1, P2 (high bits first); the inverse runs them in reverse.
-template <int LOGS>
+// Phases of a pass over the LOGS bits of the sub-index k with R = log2 of
+// the elements per thread: P0 = [LOGS-R, LOGS), P1 = [max(LOGS-2R, 0),
+// LOGS-R), P2 = [0, LOGS-2R) when LOGS > 2R.  The forward pass runs P0, P1,
+// P2 (high bits first); the inverse runs them in reverse.
+template <int LOGS, int R = 4>
 struct Phases {
-    static constexpr int P0L = LOGS - 4, P0H = LOGS;
-    static constexpr int P1L = (LOGS - 8) > 0 ? (LOGS - 8) : 0, P1H = LOGS - 4;
-    static constexpr int P2L = 0, P2H = (LOGS - 8) > 0 ? (LOGS - 8) : 0;
-    static constexpr bool THREE = LOGS > 8;
+    static_assert(LOGS > R && LOGS <= 3 * R, "a pass has two or three phases");
+    static constexpr int P0L = LOGS - R, P0H = LOGS;
+    static constexpr int P1L = (LOGS - 2 * R) > 0 ? (LOGS - 2 * R) : 0, P1H = LOGS - R;
+    static constexpr int P2L = 0, P2H = (LOGS - 2 * R) > 0 ? (LOGS - 2 * R) : 0;
+    static constexpr bool THREE = LOGS > 2 * R;
 };
 
-// Element e (0..15) of thread t in the layout of phase [LO, HI): the thread
-// holds every value of bits [LO, HI) of k for 16 >> (HI-LO) values of the
-// other bits.  [LOGS-4, LOGS) gives k = e*T + t (consecutive threads on
-// consecutive k); [0, b) gives k = 16t + e (each thread a contiguous run).
-template <int LO, int HI>
+template <int E>
+struct Log2 {
+    static constexpr int value = E == 8 ? 3 : 4;
+    static_assert(E == 8 || E == 16, "8 or 16 elements per thread");
+};
+
+// Element e (0..E-1) of thread t in the layout of phase [LO, HI): the
+// thread holds every value of bits [LO, HI) of k for E >> (HI-LO) values of
+// the other bits.  [LOGS-R, LOGS) gives k = e*T + t (consecutive threads on
+// consecutive k); [0, b) gives k = E t + e (each thread a contiguous run).
+template <int LO, int HI, int E = 16>
 __device__ __forceinline__ int k_of(int t, int e) {
-    constexpr int B = HI - LO, G = 16 >> B;
+    constexpr int B = HI - LO, G = E >> B;
     const int v = e & ((1 << B) - 1), g = e >> B;
     const int r = t * G + g;
     return ((r >> LO) << HI) | (v << LO) | (r & ((1 << LO) - 1));
@@ -90,28 +98,28 @@ struct TwRows {
         return tw[(((1u << n1) + row) << ls) + m];
     }
 };
-// The butterflies of one phase on the thread's 16 registers (layout [LO, HI)).
-// Each stage loads 16 >> (vb+1) distinct twiddles.  With FOLD (the inverse
+// The butterflies of one phase on the thread's E registers (layout [LO, HI)).
+// Each stage loads E >> (vb+1) distinct twiddles.  With FOLD (the inverse
 // column pass) the global last inverse stage multiplies by the folded
 // constants instead.
-template <int LOGS, bool FWD, bool FOLD, int LO, int HI, bool HOIST, typename TW>
-__device__ __forceinline__ void phase_regs(uint64_t (&x)[16], int t, uint64_t q, uint64_t nq, const TW &tws,
+template <int LOGS, bool FWD, bool FOLD, int LO, int HI, bool HOIST, int E, typename TW>
+__device__ __forceinline__ void phase_regs(uint64_t (&x)[E], int t, uint64_t q, uint64_t nq, const TW &tws,
                                            const LastInv &fold) {
-    constexpr int B = HI - LO;
+    constexpr int B = HI - LO, H = E / 2;
     const uint64_t q2 = 2 * q;
-    // HOIST: every twiddle of the phase loaded up front (16 >> (vb+1) per
+    // HOIST: every twiddle of the phase loaded up front (E >> (vb+1) per
     // stage), one memory latency per phase instead of one per stage, for
     // more registers
-    Shoup wall[HOIST ? B : 1][8];
+    Shoup wall[HOIST ? B : 1][H];
 #pragma unroll
     for (int st = 0; st < (HOIST ? B : 0); ++st) {
         const int bit = FWD ? (HI - 1 - st) : (LO + st);
         const int vb = bit - LO;
         const int ls = LOGS - 1 - bit;
 #pragma unroll
-        for (int key = 0; key < 8; ++key) {
-            if (key < (16 >> (vb + 1)) && !(FOLD && ls == 0)) {
-                const uint32_t k = (uint32_t)k_of<LO, HI>(t, key << (vb + 1));
+        for (int key = 0; key < H; ++key) {
+            if (key < (E >> (vb + 1)) && !(FOLD && ls == 0)) {
+                const uint32_t k = (uint32_t)k_of<LO, HI, E>(t, key << (vb + 1));
                 wall[st][key] = tws(ls, k >> (bit + 1));
             }
         }
@@ -122,21 +130,21 @@ __device__ __forceinline__ void phase_regs(uint64_t (&x)[16], int t, uint64_t q,
         const int vb = bit - LO;
         const int ls = LOGS - 1 - bit;  // stage within this pass
         const bool fold_stage = FOLD && ls == 0;
-        Shoup wc[8];
+        Shoup wc[H];
 #pragma unroll
-        for (int key = 0; key < 8; ++key) {
+        for (int key = 0; key < H; ++key) {
             if (HOIST) {
                 wc[key] = wall[HOIST ? st : 0][key];
-            } else if (key < (16 >> (vb + 1)) && !fold_stage) {
-                const uint32_t k = (uint32_t)k_of<LO, HI>(t, key << (vb + 1));
+            } else if (key < (E >> (vb + 1)) && !fold_stage) {
+                const uint32_t k = (uint32_t)k_of<LO, HI, E>(t, key << (vb + 1));
                 wc[key] = tws(ls, k >> (bit + 1));
             }
         }
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
+        for (int e = 0; e < E; ++e) {
             if ((e >> vb) & 1) continue;
             const int e2 = e + (1 << vb);
-            const Shoup w = wc[(e >> (vb + 1)) & 7];
+            const Shoup w = wc[(e >> (vb + 1)) & (H - 1)];
             if (FWD) {
                 const uint64_t u = x[e];
                 const uint64_t tv = mul_shoup_lazy_nq(x[e2], w.w, w.wp, nq);
@@ -156,18 +164,18 @@ __device__ __forceinline__ void phase_regs(uint64_t (&x)[16], int t, uint64_t q,
     }
 }
 
-template <int LOGS, int LINES, bool COLS, int LO, int HI>
-__device__ __forceinline__ void lds_put(uint64_t *lds, const uint64_t (&x)[16], int line, int t) {
-    using TL = Tile<LOGS, LINES, COLS>;
+template <int LOGS, int LINES, bool COLS, int LO, int HI, int E>
+__device__ __forceinline__ void lds_put(uint64_t *lds, const uint64_t (&x)[E], int line, int t) {
+    using TL = Tile<LOGS, LINES, COLS, E>;
 #pragma unroll
-    for (int e = 0; e < 16; ++e) lds[TL::idx(line, k_of<LO, HI>(t, e))] = x[e];
+    for (int e = 0; e < E; ++e) lds[TL::idx(line, k_of<LO, HI, E>(t, e))] = x[e];
 }
 
-template <int LOGS, int LINES, bool COLS, int LO, int HI>
-__device__ __forceinline__ void lds_get(const uint64_t *lds, uint64_t (&x)[16], int line, int t) {
-    using TL = Tile<LOGS, LINES, COLS>;
+template <int LOGS, int LINES, bool COLS, int LO, int HI, int E>
+__device__ __forceinline__ void lds_get(const uint64_t *lds, uint64_t (&x)[E], int line, int t) {
+    using TL = Tile<LOGS, LINES, COLS, E>;
 #pragma unroll
-    for (int e = 0; e < 16; ++e) x[e] = lds[TL::idx(line, k_of<LO, HI>(t, e))];
+    for (int e = 0; e < E; ++e) x[e] = lds[TL::idx(line, k_of<LO, HI, E>(t, e))];
 }
 
 // A whole pass on registers.  On entry x is in the first phase's layout
@@ -175,56 +183,56 @@ __device__ __forceinline__ void lds_get(const uint64_t *lds, uint64_t (&x)[16], 
 // P2, inverse: P0).  The LDS tile carries the exchanges between phases; the
 // caller synchronizes before this tile is written again.  Work is done only
 // where `active` holds, but every thread reaches every barrier.
-template <int LOGS, int LINES, bool COLS, bool FWD, bool HOIST, typename TW>
-__device__ __forceinline__ void pass_regs(bool active, uint64_t (&x)[16], uint64_t *lds, int line, int t, uint64_t q,
+template <int LOGS, int LINES, bool COLS, bool FWD, bool HOIST, int E = 16, typename TW>
+__device__ __forceinline__ void pass_regs(bool active, uint64_t (&x)[E], uint64_t *lds, int line, int t, uint64_t q,
                                           uint64_t nq, const TW &tws, const LastInv &fold) {
-    using P = Phases<LOGS>;
+    using P = Phases<LOGS, Log2<E>::value>;
     constexpr bool FOLD = !FWD && COLS;
     if (FWD) {
         if (active) {
-            phase_regs<LOGS, true, FOLD, P::P0L, P::P0H, HOIST>(x, t, q, nq, tws, fold);
-            lds_put<LOGS, LINES, COLS, P::P0L, P::P0H>(lds, x, line, t);
+            phase_regs<LOGS, true, FOLD, P::P0L, P::P0H, HOIST, E>(x, t, q, nq, tws, fold);
+            lds_put<LOGS, LINES, COLS, P::P0L, P::P0H, E>(lds, x, line, t);
         }
         __syncthreads();
         if (active) {
-            lds_get<LOGS, LINES, COLS, P::P1L, P::P1H>(lds, x, line, t);
-            phase_regs<LOGS, true, FOLD, P::P1L, P::P1H, HOIST>(x, t, q, nq, tws, fold);
+            lds_get<LOGS, LINES, COLS, P::P1L, P::P1H, E>(lds, x, line, t);
+            phase_regs<LOGS, true, FOLD, P::P1L, P::P1H, HOIST, E>(x, t, q, nq, tws, fold);
         }
         if constexpr (P::THREE) {
             __syncthreads();
-            if (active) lds_put<LOGS, LINES, COLS, P::P1L, P::P1H>(lds, x, line, t);
+            if (active) lds_put<LOGS, LINES, COLS, P::P1L, P::P1H, E>(lds, x, line, t);
             __syncthreads();
             if (active) {
-                lds_get<LOGS, LINES, COLS, P::P2L, P::P2H>(lds, x, line, t);
-                phase_regs<LOGS, true, FOLD, P::P2L, P::P2H, HOIST>(x, t, q, nq, tws, fold);
+                lds_get<LOGS, LINES, COLS, P::P2L, P::P2H, E>(lds, x, line, t);
+                phase_regs<LOGS, true, FOLD, P::P2L, P::P2H, HOIST, E>(x, t, q, nq, tws, fold);
             }
         }
     } else {
         if constexpr (P::THREE) {
             if (active) {
-                phase_regs<LOGS, false, FOLD, P::P2L, P::P2H, HOIST>(x, t, q, nq, tws, fold);
-                lds_put<LOGS, LINES, COLS, P::P2L, P::P2H>(lds, x, line, t);
+                phase_regs<LOGS, false, FOLD, P::P2L, P::P2H, HOIST, E>(x, t, q, nq, tws, fold);
+                lds_put<LOGS, LINES, COLS, P::P2L, P::P2H, E>(lds, x, line, t);
             }
             __syncthreads();
-            if (active) lds_get<LOGS, LINES, COLS, P::P1L, P::P1H>(lds, x, line, t);
+            if (active) lds_get<LOGS, LINES, COLS, P::P1L, P::P1H, E>(lds, x, line, t);
             __syncthreads();
         }
         if (active) {
-            phase_regs<LOGS, false, FOLD, P::P1L, P::P1H, HOIST>(x, t, q, nq, tws, fold);
-            lds_put<LOGS, LINES, COLS, P::P1L, P::P1H>(lds, x, line, t);
+            phase_regs<LOGS, false, FOLD, P::P1L, P::P1H, HOIST, E>(x, t, q, nq, tws, fold);
+            lds_put<LOGS, LINES, COLS, P::P1L, P::P1H, E>(lds, x, line, t);
         }
         __syncthreads();
         if (active) {
-            lds_get<LOGS, LINES, COLS, P::P0L, P::P0H>(lds, x, line, t);
-            phase_regs<LOGS, false, FOLD, P::P0L, P::P0H, HOIST>(x, t, q, nq, tws, fold);
+            lds_get<LOGS, LINES, COLS, P::P0L, P::P0H, E>(lds, x, line, t);
+            phase_regs<LOGS, false, FOLD, P::P0L, P::P0H, HOIST, E>(x, t, q, nq, tws, fold);
         }
     }
 }
 
 // first / last phase layouts of a pass
-template <int LOGS, bool FWD>
+template <int LOGS, bool FWD, int E = 16>
 struct IoLayout {
-    using P = Phases<LOGS>;
+    using P = Phases<LOGS, Log2<E>::value>;
     static constexpr int IN_LO = FWD ? P::P0L : (P::THREE ? P::P2L : P::P1L);
     static constexpr int IN_HI = FWD ? P::P0H : (P::THREE ? P::P2H : P::P1H);
     static constexpr int OUT_LO = FWD ? (P::THREE ? P::P2L : P::P1L) : P::P0L;
@@ -237,64 +245,49 @@ __device__ __forceinline__ uint32_t jdx(uint32_t lg, int k, uint32_t n2) {
     return COLS ? (((uint32_t)k << n2) + lg) : ((lg << n2) + (uint32_t)k);
 }
 
-// Load / store the thread's 16 elements of line `lg` in layout [LO, HI).  A
-// row pass in a [0, b) layout owns 16 consecutive words: 16-byte accesses.
-template <int LOGS, bool COLS, int LO, int HI>
-__device__ __forceinline__ void gload(uint64_t (&x)[16], const uint64_t *__restrict__ src, int t, uint32_t lg,
+// Load / store the thread's E elements of line `lg` in layout [LO, HI).  A
+// row pass in a [0, b) layout owns E consecutive words: 16-byte accesses.
+template <int LOGS, bool COLS, int LO, int HI, int E = 16>
+__device__ __forceinline__ void gload(uint64_t (&x)[E], const uint64_t *__restrict__ src, int t, uint32_t lg,
                                       uint32_t n2) {
     if (!COLS && LO == 0) {
-        const ulonglong2 *p = reinterpret_cast<const ulonglong2 *>(src + (lg << n2) + 16 * t);
+        const ulonglong2 *p = reinterpret_cast<const ulonglong2 *>(src + (lg << n2) + E * t);
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
+        for (int i = 0; i < E / 2; ++i) {
             const ulonglong2 v = p[i];
             x[2 * i] = v.x;
             x[2 * i + 1] = v.y;
         }
     } else {
 #pragma unroll
-        for (int e = 0; e < 16; ++e) x[e] = src[jdx<COLS>(lg, k_of<LO, HI>(t, e), n2)];
+        for (int e = 0; e < E; ++e) x[e] = src[jdx<COLS>(lg, k_of<LO, HI, E>(t, e), n2)];
     }
 }
 
-template <int LOGS, bool COLS, int LO, int HI>
-__device__ __forceinline__ void gstore(const uint64_t (&x)[16], uint64_t *__restrict__ dst, int t, uint32_t lg,
+template <int LOGS, bool COLS, int LO, int HI, int E = 16>
+__device__ __forceinline__ void gstore(const uint64_t (&x)[E], uint64_t *__restrict__ dst, int t, uint32_t lg,
                                        uint32_t n2) {
     if (!COLS && LO == 0) {
-        ulonglong2 *p = reinterpret_cast<ulonglong2 *>(dst + (lg << n2) + 16 * t);
+        ulonglong2 *p = reinterpret_cast<ulonglong2 *>(dst + (lg << n2) + E * t);
 #pragma unroll
-        for (int i = 0; i < 8; ++i) p[i] = make_ulonglong2(x[2 * i], x[2 * i + 1]);
+        for (int i = 0; i < E / 2; ++i) p[i] = make_ulonglong2(x[2 * i], x[2 * i + 1]);
     } else {
 #pragma unroll
-        for (int e = 0; e < 16; ++e) dst[jdx<COLS>(lg, k_of<LO, HI>(t, e), n2)] = x[e];
+        for (int e = 0; e < E; ++e) dst[jdx<COLS>(lg, k_of<LO, HI, E>(t, e), n2)] = x[e];
     }
 }
 
 // thread -> (line, t): column tiles put lines fastest (coalesced columns),
 // row tiles put the threads of one line together.
-template <int LOGS, int LINES, bool COLS>
+template <int LOGS, int LINES, bool COLS, int E = 16>
 __device__ __forceinline__ void thread_coords(int tid, int &line, int &t) {
-    using TL = Tile<LOGS, LINES, COLS>;
+    using TL = Tile<LOGS, LINES, COLS, E>;
     if (COLS) {
         line = tid % LINES;
         t = tid / LINES;
     } else {
         t = tid % TL::T;
         line = tid / TL::T;
-    }
-}
-
-// element e of the tile (cooperative, coalesced pattern) -> (line, k, j)
-template <int LOGS, int LINES, bool COLS>
-__device__ __forceinline__ void elem_coords(int e, uint32_t line0, uint32_t n2, int &line, int &k, uint32_t &j) {
-    using TL = Tile<LOGS, LINES, COLS>;
-    if (COLS) {
-        k = e / LINES;
-        line = e % LINES;
-        j = ((uint32_t)k << n2) + line0 + line;
-    } else {
-        line = e / TL::S;
-        k = e % TL::S;
-        j = ((line0 + line) << n2) + k;
     }
 }
 
@@ -311,10 +304,10 @@ struct NttArgs {
 
 enum { IO_PLAIN = 0, IO_GATHER = 1, IO_REDUCE = 2, IO_MDEPI = 4 };
 
-template <int LOGS, int LINES, bool COLS, bool FWD, int IO>
-__global__ void __launch_bounds__((Tile<LOGS, LINES, COLS>::NT)) ntt_pass_kernel(const NttArgs a) {
-    using TL = Tile<LOGS, LINES, COLS>;
-    using IOL = IoLayout<LOGS, FWD>;
+template <int LOGS, int LINES, bool COLS, bool FWD, int IO, int E>
+__global__ void __launch_bounds__((Tile<LOGS, LINES, COLS, E>::NT)) ntt_pass_kernel(const NttArgs a) {
+    using TL = Tile<LOGS, LINES, COLS, E>;
+    using IOL = IoLayout<LOGS, FWD, E>;
     __shared__ uint64_t lds[TL::WORDS];
     const uint32_t lines_per_limb = 1u << (COLS ? a.n2 : a.n1);
     const uint32_t tiles = lines_per_limb / LINES;
@@ -329,50 +322,50 @@ __global__ void __launch_bounds__((Tile<LOGS, LINES, COLS>::NT)) ntt_pass_kernel
     uint64_t *dst = a.io.out[b] + (size_t)a.m.out_off[li] * N;
     const Shoup *tw = a.tw + (size_t)mod * N;
     int line, t;
-    thread_coords<LOGS, LINES, COLS>(threadIdx.x, line, t);
+    thread_coords<LOGS, LINES, COLS, E>(threadIdx.x, line, t);
     const uint32_t lg = tile * LINES + line;  // this thread's column or row
 
     // ModDown epilogue operands (u, and the automorphed addend), issued
     // before the pass input: loads complete in issue order, so one memory
     // latency covers all three instead of a second one after the pass
-    uint64_t uv[16], bv[16];
+    uint64_t uv[E], bv[E];
     const uint32_t ui = a.m.cidx[li];
     const uint64_t *ad = (IO == IO_MDEPI && a.io.add[b]) ? a.io.add[b] + (size_t)ui * N : nullptr;
     if (IO == IO_MDEPI) {
-        gload<LOGS, COLS, IOL::OUT_LO, IOL::OUT_HI>(uv, a.io.uq[b] + (size_t)ui * N, t, lg, a.n2);
+        gload<LOGS, COLS, IOL::OUT_LO, IOL::OUT_HI, E>(uv, a.io.uq[b] + (size_t)ui * N, t, lg, a.n2);
         if (ad) {
             const uint32_t ag = a.io.add_galois[b];
 #pragma unroll
-            for (int e = 0; e < 16; ++e) {
-                const uint32_t j = jdx<COLS>(lg, k_of<IOL::OUT_LO, IOL::OUT_HI>(t, e), a.n2);
+            for (int e = 0; e < E; ++e) {
+                const uint32_t j = jdx<COLS>(lg, k_of<IOL::OUT_LO, IOL::OUT_HI, E>(t, e), a.n2);
                 bv[e] = ad[ag != 1 ? aut_eval_src(j, ag, a.n) : j];
             }
         }
     }
 
-    uint64_t x[16];
+    uint64_t x[E];
     if (IO == IO_GATHER) {
         const uint32_t g = a.io.galois[b];
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            const uint32_t j = jdx<COLS>(lg, k_of<IOL::IN_LO, IOL::IN_HI>(t, e), a.n2);
+        for (int e = 0; e < E; ++e) {
+            const uint32_t j = jdx<COLS>(lg, k_of<IOL::IN_LO, IOL::IN_HI, E>(t, e), a.n2);
             x[e] = src[g != 1 ? aut_eval_src(j, g, a.n) : j];
         }
     } else {
-        gload<LOGS, COLS, IOL::IN_LO, IOL::IN_HI>(x, src, t, lg, a.n2);
+        gload<LOGS, COLS, IOL::IN_LO, IOL::IN_HI, E>(x, src, t, lg, a.n2);
     }
 
     const LastInv fold = (!FWD && COLS) ? a.li[a.m.cidx[li]] : LastInv{};
     if constexpr (COLS) {
-        pass_regs<LOGS, LINES, COLS, FWD, TW_HOIST>(true, x, lds, line, t, q, mcv.nq, TwCols{tw}, fold);
+        pass_regs<LOGS, LINES, COLS, FWD, TW_HOIST, E>(true, x, lds, line, t, q, mcv.nq, TwCols{tw}, fold);
     } else {
-        pass_regs<LOGS, LINES, COLS, FWD, TW_HOIST>(true, x, lds, line, t, q, mcv.nq, TwRows{tw, lg, a.n1}, fold);
+        pass_regs<LOGS, LINES, COLS, FWD, TW_HOIST, E>(true, x, lds, line, t, q, mcv.nq, TwRows{tw, lg, a.n1}, fold);
     }
 
     if (IO == IO_MDEPI) {
         const Shoup pi = a.pinv[ui];
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
+        for (int e = 0; e < E; ++e) {
             const uint64_t z = reduce64(x[e], q, mcv.mu, mcv.nq);
             uint64_t r = mul_shoup(uv[e] + q - z, pi.w, pi.wp, q);
             if (ad) r = add_mod(r, bv[e], q);
@@ -380,37 +373,50 @@ __global__ void __launch_bounds__((Tile<LOGS, LINES, COLS>::NT)) ntt_pass_kernel
         }
     } else if (IO == IO_REDUCE) {
 #pragma unroll
-        for (int e = 0; e < 16; ++e) x[e] = reduce64(x[e], q, mcv.mu, mcv.nq);
+        for (int e = 0; e < E; ++e) x[e] = reduce64(x[e], q, mcv.mu, mcv.nq);
     }
-    gstore<LOGS, COLS, IOL::OUT_LO, IOL::OUT_HI>(x, dst, t, lg, a.n2);
+    gstore<LOGS, COLS, IOL::OUT_LO, IOL::OUT_HI, E>(x, dst, t, lg, a.n2);
 }
 
 constexpr int COL_LINES = 16;
 constexpr int ROW_LINES = 8;
 
-template <int LOGS, bool COLS, bool FWD, int IO>
+template <int LOGS, bool COLS, bool FWD, int IO, int E>
 static hipError_t launch_pass_t(const NttArgs &a, uint32_t count, uint32_t batch, hipStream_t s) {
     constexpr int LINES = COLS ? COL_LINES : ROW_LINES;
-    using TL = Tile<LOGS, LINES, COLS>;
+    using TL = Tile<LOGS, LINES, COLS, E>;
     ProfScope ps(*a.ctx, FWD ? (COLS ? HKS_K_NTT_FWD_COLS : HKS_K_NTT_FWD_ROWS)
                              : (COLS ? HKS_K_NTT_INV_COLS : HKS_K_NTT_INV_ROWS), s);
     const uint32_t lines_per_limb = 1u << (COLS ? a.n2 : a.n1);
     dim3 grid(count * (lines_per_limb / LINES), batch);
-    hipLaunchKernelGGL((ntt_pass_kernel<LOGS, LINES, COLS, FWD, IO>), grid, dim3(TL::NT), 0, s, a);
+    hipLaunchKernelGGL((ntt_pass_kernel<LOGS, LINES, COLS, FWD, IO, E>), grid, dim3(TL::NT), 0, s, a);
     return hipGetLastError();
+}
+
+// Elements per thread: 16 (radix-16 phases) when the launch has enough
+// waves to fill the chip several times over, else 8 (radix-8 phases, one
+// more LDS exchange, twice the waves with half the work each), so that a
+// small launch still hides its memory latency.
+constexpr uint32_t WAVES_FOR_E16 = 6 * 1024;
+
+template <bool COLS, bool FWD, int IO, int E>
+static hipError_t dispatch_pass_e(const NttArgs &a, int logs, uint32_t count, uint32_t batch, hipStream_t s) {
+    switch (logs) {
+        case 5: return launch_pass_t<5, COLS, FWD, IO, E>(a, count, batch, s);
+        case 6: return launch_pass_t<6, COLS, FWD, IO, E>(a, count, batch, s);
+        case 7: return launch_pass_t<7, COLS, FWD, IO, E>(a, count, batch, s);
+        case 8: return launch_pass_t<8, COLS, FWD, IO, E>(a, count, batch, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 template <bool COLS, bool FWD, int IO>
 static hipError_t dispatch_pass(const NttArgs &a, int logs, uint32_t count, uint32_t batch, hipStream_t s) {
     if (count == 0 || batch == 0) return hipSuccess;
     if (batch > (uint32_t)MAXB) return hipErrorInvalidValue;
-    switch (logs) {
-        case 5: return launch_pass_t<5, COLS, FWD, IO>(a, count, batch, s);
-        case 6: return launch_pass_t<6, COLS, FWD, IO>(a, count, batch, s);
-        case 7: return launch_pass_t<7, COLS, FWD, IO>(a, count, batch, s);
-        case 8: return launch_pass_t<8, COLS, FWD, IO>(a, count, batch, s);
-        default: return hipErrorInvalidValue;
-    }
+    const uint64_t waves16 = (uint64_t)count * batch * ((1ull << a.n) / 16) / 64;
+    return waves16 >= WAVES_FOR_E16 ? dispatch_pass_e<COLS, FWD, IO, 16>(a, logs, count, batch, s)
+                                    : dispatch_pass_e<COLS, FWD, IO, 8>(a, logs, count, batch, s);
 }
 
 static NttArgs base_args(const Ctx &c, const LimbMap &m, const BatchIo &io, bool fwd) {
