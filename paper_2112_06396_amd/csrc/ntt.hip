@@ -489,6 +489,11 @@ hipError_t launch_rows_mdepi(const Ctx &c, const LimbMap &m, const BatchIo &io, 
 
 // ------------------------------------------------------------------ KSKInnerProd (+ ModUp's last pass, + ModDown's first)
 
+constexpr uint64_t KSK_WAVES_FOR_E16 = 6 * 1024;
+#ifndef KSK_E8_WAVES
+#define KSK_E8_WAVES 2
+#endif
+
 struct KskRowArgs {
     KskBatch kb;             // per ciphertext: own-digit source, key [dnum][2][L+K][N], galois
     const uint64_t *ext;     // [beta][E][N] converted limbs: after the forward column pass (rowpass) or in evaluation form
@@ -510,12 +515,12 @@ struct KskRowArgs {
 // ModDown's inverse row pass on both in registers before storing (the
 // forward pass ends in the layout the inverse pass starts from).
 // (at least two waves per SIMD: the register budget stays within 256)
-template <int LOGS, bool ROWPASS>
-__global__ void __launch_bounds__((Tile<LOGS, ROW_LINES, false>::NT)) __attribute__((amdgpu_waves_per_eu(2)))
+template <int LOGS, bool ROWPASS, int E>
+__global__ void __launch_bounds__((Tile<LOGS, ROW_LINES, false, E>::NT)) __attribute__((amdgpu_waves_per_eu(E == 8 ? KSK_E8_WAVES : 2)))
 ksk_rows_kernel(const KskRowArgs a) {
-    using TL = Tile<LOGS, ROW_LINES, false>;
-    using IOF = IoLayout<LOGS, true>;
-    using IOI = IoLayout<LOGS, false>;
+    using TL = Tile<LOGS, ROW_LINES, false, E>;
+    using IOF = IoLayout<LOGS, true, E>;
+    using IOI = IoLayout<LOGS, false, E>;
     static_assert(IOF::OUT_LO == IOI::IN_LO && IOF::OUT_HI == IOI::IN_HI, "row-pass layouts must chain");
     __shared__ uint64_t lds[TL::WORDS];
     // block -> (x = target limb and row tile, b = ciphertext).  With
@@ -549,42 +554,42 @@ ksk_rows_kernel(const KskRowArgs a) {
     const bool is_p = tgt >= a.level;
     const uint32_t kp = tgt - a.level;
     int line, t;
-    thread_coords<LOGS, ROW_LINES, false>(threadIdx.x, line, t);
+    thread_coords<LOGS, ROW_LINES, false, E>(threadIdx.x, line, t);
     const uint32_t lg = tile * ROW_LINES + line;
 
-    uint64_t u[16], v[16];
+    uint64_t u[E], v[E];
 #pragma unroll
-    for (int e = 0; e < 16; ++e) u[e] = v[e] = 0;
+    for (int e = 0; e < E; ++e) u[e] = v[e] = 0;
     bool lds_used = false;
     for (uint32_t jd = 0; jd < a.beta; ++jd) {
         const bool dir = a.all_direct || jd == own;
-        uint64_t xv[16];
+        uint64_t xv[E];
         if (dir) {
             const uint64_t *src = direct + jd * a.dstride + (size_t)tgt * N;
 #pragma unroll
-            for (int e = 0; e < 16; ++e) {
-                const uint32_t j = jdx<false>(lg, k_of<IOF::OUT_LO, IOF::OUT_HI>(t, e), a.n2);
+            for (int e = 0; e < E; ++e) {
+                const uint32_t j = jdx<false>(lg, k_of<IOF::OUT_LO, IOF::OUT_HI, E>(t, e), a.n2);
                 xv[e] = src[galois != 1 ? aut_eval_src(j, galois, a.n) : j];
             }
         } else {
             const uint64_t *src = ext + ((size_t)jd * a.E + tgt) * N;
             if (ROWPASS) {
-                gload<LOGS, false, IOF::IN_LO, IOF::IN_HI>(xv, src, t, lg, a.n2);
+                gload<LOGS, false, IOF::IN_LO, IOF::IN_HI, E>(xv, src, t, lg, a.n2);
                 if (lds_used) __syncthreads();
-                pass_regs<LOGS, ROW_LINES, false, true, false>(true, xv, lds, line, t, q, mcv.nq,
+                pass_regs<LOGS, ROW_LINES, false, true, false, E>(true, xv, lds, line, t, q, mcv.nq,
                                                         TwRows{a.twf + (size_t)mod * N, lg, a.n1}, LastInv{});
                 lds_used = true;
             } else {
-                gload<LOGS, false, IOF::OUT_LO, IOF::OUT_HI>(xv, src, t, lg, a.n2);
+                gload<LOGS, false, IOF::OUT_LO, IOF::OUT_HI, E>(xv, src, t, lg, a.n2);
             }
         }
-        // the key rows in the same layout: 16 consecutive words per thread
-        static_assert(IOF::OUT_LO == 0, "forward row pass ends with 16 consecutive elements per thread");
+        // the key rows in the same layout: E consecutive words per thread
+        static_assert(IOF::OUT_LO == 0, "forward row pass ends with E consecutive elements per thread");
         const ulonglong2 *k0 =
-            reinterpret_cast<const ulonglong2 *>(ksk + ((size_t)(2 * jd) * KL + mod) * N + (lg << a.n2) + 16 * t);
+            reinterpret_cast<const ulonglong2 *>(ksk + ((size_t)(2 * jd) * KL + mod) * N + (lg << a.n2) + E * t);
         const ulonglong2 *k1 = k0 + KL * N / 2;
 #pragma unroll
-        for (int c = 0; c < 8; ++c) {
+        for (int c = 0; c < E / 2; ++c) {
             const ulonglong2 kv0 = k0[c], kv1 = k1[c];
             u[2 * c] = add_mod(u[2 * c], mul_mod(xv[2 * c], kv0.x, q, mcv.mu, mcv.nq), q);
             u[2 * c + 1] = add_mod(u[2 * c + 1], mul_mod(xv[2 * c + 1], kv0.y, q, mcv.mu, mcv.nq), q);
@@ -593,27 +598,27 @@ ksk_rows_kernel(const KskRowArgs a) {
         }
     }
     if (!is_p) {
-        gstore<LOGS, false, IOF::OUT_LO, IOF::OUT_HI>(u, uq + (size_t)tgt * N, t, lg, a.n2);
-        gstore<LOGS, false, IOF::OUT_LO, IOF::OUT_HI>(v, uq + ((size_t)a.level + tgt) * N, t, lg, a.n2);
+        gstore<LOGS, false, IOF::OUT_LO, IOF::OUT_HI, E>(u, uq + (size_t)tgt * N, t, lg, a.n2);
+        gstore<LOGS, false, IOF::OUT_LO, IOF::OUT_HI, E>(v, uq + ((size_t)a.level + tgt) * N, t, lg, a.n2);
         return;
     }
     // special-prime limb: inverse row pass (first pass of ModDown's iNTT) of u and v
     const TwRows twi{a.twi + (size_t)mod * N, lg, a.n1};
     if (lds_used) __syncthreads();
-    pass_regs<LOGS, ROW_LINES, false, false, false>(true, u, lds, line, t, q, mcv.nq, twi, LastInv{});
-    gstore<LOGS, false, IOI::OUT_LO, IOI::OUT_HI>(u, pc + (size_t)kp * N, t, lg, a.n2);
+    pass_regs<LOGS, ROW_LINES, false, false, false, E>(true, u, lds, line, t, q, mcv.nq, twi, LastInv{});
+    gstore<LOGS, false, IOI::OUT_LO, IOI::OUT_HI, E>(u, pc + (size_t)kp * N, t, lg, a.n2);
     __syncthreads();
-    pass_regs<LOGS, ROW_LINES, false, false, false>(true, v, lds, line, t, q, mcv.nq, twi, LastInv{});
-    gstore<LOGS, false, IOI::OUT_LO, IOI::OUT_HI>(v, pc + ((size_t)a.K + kp) * N, t, lg, a.n2);
+    pass_regs<LOGS, ROW_LINES, false, false, false, E>(true, v, lds, line, t, q, mcv.nq, twi, LastInv{});
+    gstore<LOGS, false, IOI::OUT_LO, IOI::OUT_HI, E>(v, pc + ((size_t)a.K + kp) * N, t, lg, a.n2);
 }
 
-template <bool ROWPASS>
+template <bool ROWPASS, int E>
 static hipError_t launch_ksk_rows_t(const KskRowArgs &a, uint32_t n2, dim3 grid, hipStream_t s) {
     switch (n2) {
-        case 5: hipLaunchKernelGGL((ksk_rows_kernel<5, ROWPASS>), grid, dim3(Tile<5, ROW_LINES, false>::NT), 0, s, a); break;
-        case 6: hipLaunchKernelGGL((ksk_rows_kernel<6, ROWPASS>), grid, dim3(Tile<6, ROW_LINES, false>::NT), 0, s, a); break;
-        case 7: hipLaunchKernelGGL((ksk_rows_kernel<7, ROWPASS>), grid, dim3(Tile<7, ROW_LINES, false>::NT), 0, s, a); break;
-        case 8: hipLaunchKernelGGL((ksk_rows_kernel<8, ROWPASS>), grid, dim3(Tile<8, ROW_LINES, false>::NT), 0, s, a); break;
+        case 5: hipLaunchKernelGGL((ksk_rows_kernel<5, ROWPASS, E>), grid, dim3(Tile<5, ROW_LINES, false, E>::NT), 0, s, a); break;
+        case 6: hipLaunchKernelGGL((ksk_rows_kernel<6, ROWPASS, E>), grid, dim3(Tile<6, ROW_LINES, false, E>::NT), 0, s, a); break;
+        case 7: hipLaunchKernelGGL((ksk_rows_kernel<7, ROWPASS, E>), grid, dim3(Tile<7, ROW_LINES, false, E>::NT), 0, s, a); break;
+        case 8: hipLaunchKernelGGL((ksk_rows_kernel<8, ROWPASS, E>), grid, dim3(Tile<8, ROW_LINES, false, E>::NT), 0, s, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -651,7 +656,13 @@ hipError_t launch_ksk_rows(const Ctx &c, const KskBatch &kb, uint32_t nb, const 
     a.xcd_group = (nb > 1 && xs % 8 == 0) ? 1u : 0u;
     ProfScope ps(c, HKS_K_KSK, s);
     const dim3 grid(xs * nb);
-    return rowpass ? launch_ksk_rows_t<true>(a, c.n2, grid, s) : launch_ksk_rows_t<false>(a, c.n2, grid, s);
+    // elements per thread as for the pass kernels: 8 unless the launch
+    // already holds many waves at 16
+    const uint64_t thr16 = (uint64_t)ROW_LINES * (1u << c.n2) / 16;  // threads per block at 16
+    const uint64_t waves16 = (uint64_t)xs * nb * ((thr16 + 63) / 64);
+    if (waves16 >= KSK_WAVES_FOR_E16)
+        return rowpass ? launch_ksk_rows_t<true, 16>(a, c.n2, grid, s) : launch_ksk_rows_t<false, 16>(a, c.n2, grid, s);
+    return rowpass ? launch_ksk_rows_t<true, 8>(a, c.n2, grid, s) : launch_ksk_rows_t<false, 8>(a, c.n2, grid, s);
 }
 
 }  // namespace hks
