@@ -73,6 +73,8 @@ def lib():
             "oref_sub_vec": (None, [_u64p, _u64p, _u64p, u32, _u64p, u32]),
             "oref_scale_vec": (None, [_u64p, _u64p, _u64p, u32, _u64p, u32]),
             "oref_lift_signed": (None, [ctypes.POINTER(ctypes.c_int64), _u64p, u32, _u64p, u32]),
+            "oref_philox4x32_10": (None, [ctypes.POINTER(u32), ctypes.POINTER(u32), ctypes.POINTER(u32)]),
+            "oref_expand_key_a": (None, [P, u64, _u64p]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -296,13 +298,32 @@ def secret_eval(pr: Params, s: np.ndarray) -> np.ndarray:
     return ntt(lift_signed(s, pr.log_n, mods), pr.log_n, mods)
 
 
+def philox4x32_10(ctr, key):
+    """Philox4x32-10 of a 4-word counter and 2-word key -> 4 words."""
+    c = (ctypes.c_uint32 * 4)(*[int(v) & 0xFFFFFFFF for v in ctr])
+    k = (ctypes.c_uint32 * 2)(*[int(v) & 0xFFFFFFFF for v in key])
+    o = (ctypes.c_uint32 * 4)()
+    lib().oref_philox4x32_10(c, k, o)
+    return [int(v) for v in o]
+
+
+def expand_key_a(pr: Params, seed: int) -> np.ndarray:
+    """The uniform rows a_j of a seeded switching key, [dnum][L+K][N]."""
+    a = np.zeros((pr.dnum, pr.L + pr.K, pr.n), dtype=np.uint64)
+    ref, keep = pr.c()
+    lib().oref_expand_key_a(ref, int(seed), _p(a))
+    del keep
+    return a
+
+
 def switch_key(pr: Params, s_hat: np.ndarray, s_from_hat: np.ndarray, g: np.random.Generator,
-               uniform_a: bool = True) -> np.ndarray:
+               uniform_a: bool = True, seed=None) -> np.ndarray:
     """Switching key from s_from to s in the Han-Ki gadget form (Eq. kskShape).
 
     ksk[j] = (a_j, b_j) with b_j = -a_j*s + e_j + [P]_{q_i} * s_from on the
     limbs q_i of digit j (i in [j*alpha, (j+1)*alpha)), over Q_L U P.
-    Layout [dnum][2][L+K][N].
+    Layout [dnum][2][L+K][N].  With `seed`, a_j are the seeded rows
+    expand_key_a(seed)[j] (a seeded key: only the b rows need storing).
     """
     mods = pr.key_mods()
     kl = pr.L + pr.K
@@ -310,8 +331,9 @@ def switch_key(pr: Params, s_hat: np.ndarray, s_from_hat: np.ndarray, g: np.rand
     P = 1
     for pk in pr.p:
         P *= int(pk)
+    a_seeded = expand_key_a(pr, seed) if seed is not None else None
     for j in range(pr.dnum):
-        a = synth.uniform_residues(g, mods, pr.n)
+        a = a_seeded[j] if a_seeded is not None else synth.uniform_residues(g, mods, pr.n)
         e = ntt(lift_signed(synth.cbd(g, pr.n), pr.log_n, mods), pr.log_n, mods)
         b = sub_vec(e, mul_vec(a, s_hat, pr.log_n, mods), pr.log_n, mods)
         lo, hi = j * pr.alpha, min((j + 1) * pr.alpha, pr.L)
@@ -323,10 +345,10 @@ def switch_key(pr: Params, s_hat: np.ndarray, s_from_hat: np.ndarray, g: np.rand
     return ksk
 
 
-def rotation_key(pr: Params, s: np.ndarray, gal: int, g: np.random.Generator) -> np.ndarray:
+def rotation_key(pr: Params, s: np.ndarray, gal: int, g: np.random.Generator, seed=None) -> np.ndarray:
     s_hat = secret_eval(pr, s)
     s_rot = automorph(s_hat, pr.log_n, pr.key_mods(), gal, eval_domain=True)
-    return switch_key(pr, s_hat, s_rot, g)
+    return switch_key(pr, s_hat, s_rot, g, seed=seed)
 
 
 def relin_key(pr: Params, s: np.ndarray, g: np.random.Generator) -> np.ndarray:

@@ -595,3 +595,59 @@ void oref_lift_signed(const int64_t *v, uint64_t *out, uint32_t log_n, const uin
             out[l * n + c] = r;
         }
 }
+
+/* ---------------------------------------------------------------------------
+ * Seeded switching keys (the paper's key compression, Sec. 6: the uniform
+ * row a_j of a switching key is regenerated from a short seed instead of
+ * being stored).  The generator is Philox4x32-10 (Salmon, Moraes, Dror and
+ * Shaw, "Parallel Random Numbers: As Easy as 1, 2, 3", SC 2011), written
+ * here from its published definition: ten rounds of
+ *   (c0, c1, c2, c3) <- (hi(M1 c2) ^ c1 ^ k0, lo(M1 c2), hi(M0 c0) ^ c3 ^ k1, lo(M0 c0))
+ * with M0 = 0xD2511F53, M1 = 0xCD9E8D57, the key (k0, k1) advanced by
+ * (0x9E3779B9, 0xBB67AE85) before every round after the first.
+ * ------------------------------------------------------------------------- */
+void oref_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        uint32_t n1 = (uint32_t)p1;
+        uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        uint32_t n3 = (uint32_t)p0;
+        c0 = n0;
+        c1 = n1;
+        c2 = n2;
+        c3 = n3;
+    }
+    out[0] = c0;
+    out[1] = c1;
+    out[2] = c2;
+    out[3] = c3;
+}
+
+/* The uniform rows of a seeded key, [dnum][L+K][N]: entry (j, kappa, i), for
+ * key limb kappa (q_kappa for kappa < L, p_(kappa-L) after), is the 96-bit
+ * number c0 + c1 2^32 + c2 2^64 reduced mod that limb's prime, where
+ * (c0, c1, c2, c3) = Philox4x32-10(counter (i, kappa, j, 0x4B53),
+ * key (seed mod 2^32, seed >> 32)).  (Reduction bias below 2^-46.) */
+void oref_expand_key_a(const oref_params *pr, uint64_t seed, uint64_t *a) {
+    const uint32_t n = 1u << pr->log_n, KL = pr->L + pr->K;
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    for (uint32_t j = 0; j < pr->dnum; ++j)
+        for (uint32_t kappa = 0; kappa < KL; ++kappa) {
+            const uint64_t m = kappa < pr->L ? pr->q[kappa] : pr->p[kappa - pr->L];
+            for (uint32_t i = 0; i < n; ++i) {
+                const uint32_t ctr[4] = {i, kappa, j, 0x4B53u};
+                uint32_t o[4];
+                oref_philox4x32_10(ctr, key, o);
+                const u128 y = ((u128)o[2] << 64) | ((u128)o[1] << 32) | o[0];
+                a[((size_t)j * KL + kappa) * n + i] = (uint64_t)(y % m);
+            }
+        }
+}

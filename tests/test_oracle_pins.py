@@ -361,3 +361,57 @@ def test_noise_bound_config2_is_far_below_q():
     pr = _pr(16, 24, 8, 3)
     s = np.ones(pr.n, dtype=np.int64)
     assert O.ks_noise_bound(pr, 24, s) < (1 << 27)
+
+
+# ------------------------------------------------------------------ seeded keys (key compression, Sec. 6)
+
+
+def test_philox_known_answers():
+    """Philox4x32-10 against the published known-answer vectors
+    (tests/golden/philox_kat.json)."""
+    import json
+    kat = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "philox_kat.json")))
+    for v in kat["vectors"]:
+        ctr = [int(x, 16) for x in v["ctr"]]
+        key = [int(x, 16) for x in v["key"]]
+        assert O.philox4x32_10(ctr, key) == [int(x, 16) for x in v["out"]]
+
+
+def test_seeded_key_rows_are_uniform_residues():
+    pr = O.make_params(10, 6, 2, 3)
+    a = O.expand_key_a(pr, 0x1234_5678_9ABC_DEF0)
+    mods = pr.key_mods()
+    assert a.shape == (pr.dnum, pr.L + pr.K, pr.n)
+    assert np.all(a < mods[None, :, None])
+    assert np.array_equal(a, O.expand_key_a(pr, 0x1234_5678_9ABC_DEF0))
+    assert not np.array_equal(a, O.expand_key_a(pr, 0x1234_5678_9ABC_DEF1))
+    # entry (j, kappa, i) is the 96-bit Philox word reduced mod the limb's prime
+    for j, kappa, i in ((0, 0, 0), (2, pr.L + 1, 777), (1, 3, 1023)):
+        o = O.philox4x32_10([i, kappa, j, 0x4B53], [0x9ABC_DEF0, 0x1234_5678])
+        y = o[0] + (o[1] << 32) + (o[2] << 64)
+        assert int(a[j, kappa, i]) == y % int(mods[kappa])
+    # uniform: 16 equal bins of [0, q) per limb, chi-square well inside its range
+    for kappa in (0, pr.L + pr.K - 1):
+        x = a[:, kappa, :].ravel().astype(np.float64) / float(mods[kappa])
+        h, _ = np.histogram(x, bins=16, range=(0.0, 1.0))
+        e = x.size / 16
+        chi2 = float(((h - e) ** 2 / e).sum())
+        assert chi2 < 50.0  # 15 degrees of freedom: p < 1e-5 beyond 50
+
+
+def test_seeded_rotation_key_decrypts():
+    """A rotation key whose uniform rows come from a seed is a valid
+    switching key: Rotate with it decrypts to the rotated message."""
+    pr = O.make_params(10, 6, 2, 3)
+    g = synth.rng(77)
+    s = synth.ternary(g, pr.n)
+    gal = pow(5, -1, 2 * pr.n)
+    ksk = O.rotation_key(pr, s, gal, g, seed=0xC0FFEE)
+    assert np.array_equal(ksk[:, 0], O.expand_key_a(pr, 0xC0FFEE))
+    m = synth.small_uniform(g, pr.n, 1 << 30)
+    ct = O.encrypt(pr, s, m, pr.L, g)
+    out = O.rotate(pr, ct, pr.L, gal, ksk)
+    d_in = O.decrypt_coef(pr, s, ct, pr.L)
+    d_out = O.decrypt_coef(pr, s, out, pr.L)
+    diff = O.sub_vec(d_out, O.automorph(d_in, pr.log_n, pr.q, gal, eval_domain=False), pr.log_n, pr.q)
+    assert O.centered_small(diff, pr.q, O.ks_noise_bound(pr, pr.L, s)) is not None
