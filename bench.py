@@ -156,6 +156,15 @@ def extras(args, ctx, hks, synth, cts, ksks, outs, gal, key_mods, n, plain_value
         lambda i: hks.hks_batch_rotate(ctx, dcts, LEVEL, gals[:32], dkeys[32 * (i % 2):32 * (i % 2) + 32],
                                        douts[:32], stream), 32, 8)
     res["batch_vs_plain"] = res["batch32_shared_key_ks_per_s"] / plain_value
+    # seeded keys (rows a_j regenerated on chip, half the key bytes)
+    b_rows = [k[:, 1].contiguous() for k in dkeys[:32]]
+    res["rotate_seeded_ks_per_s"] = rate(
+        lambda i: hks.hks_rotate_seeded(ctx, cts[i % args.pool], LEVEL, gal, 77 + i % 32, b_rows[i % 32],
+                                        outs[i % args.pool], stream), 1, max(50, args.steps))
+    res["batch32_seeded_keys_ks_per_s"] = rate(
+        lambda i: hks.hks_batch_rotate_seeded(ctx, dcts, LEVEL, gals[:32], [77 + j for j in range(32)], b_rows,
+                                              douts[:32], stream), 32, 8)
+    del b_rows
     # the plain Rotate replayed from hipGraphs (one per pool entry)
     graphs = []
     for j in range(args.pool):
@@ -167,7 +176,9 @@ def extras(args, ctx, hks, synth, cts, ksks, outs, gal, key_mods, n, plain_value
     res["graph_rotate_ks_per_s"] = rate(lambda i: graphs[i % args.pool].replay(), 1, max(50, args.steps))
     del graphs
     log(f"[bench] hrotate r=64 {res['hrotate_r64_ks_per_s']:.0f} ks/s; batch 32 shared key "
-        f"{res['batch32_shared_key_ks_per_s']:.0f}, distinct keys {res['batch32_distinct_keys_ks_per_s']:.0f}; "
+        f"{res['batch32_shared_key_ks_per_s']:.0f}, distinct keys {res['batch32_distinct_keys_ks_per_s']:.0f}, "
+        f"distinct seeded keys {res['batch32_seeded_keys_ks_per_s']:.0f}; seeded Rotate "
+        f"{res['rotate_seeded_ks_per_s']:.0f}; "
         f"graph-replayed Rotate {res['graph_rotate_ks_per_s']:.0f}")
     del dkeys, dcts, douts
     torch.cuda.empty_cache()

@@ -179,6 +179,29 @@ int hks_batch_rotate(hks_ctx *ctx, uint32_t n_ct, const uint64_t *const *ct, uin
                      const uint32_t *galois, const uint64_t *const *ksk, uint64_t *const *ct_out,
                      void *stream);
 
+/* ---------------------------------------------------------------- seeded keys
+ * Key compression (Sec. 6): a seeded switching key stores only its rows b_j,
+ * ksk_b [dnum][L+K][N]; the uniform rows a_j are regenerated on the device
+ * from a 64-bit seed.  Entry (j, kappa, i) of a_j, for key limb kappa and
+ * slot i, is the low 96 bits c0 + c1 2^32 + c2 2^64 of Philox4x32-10 (Salmon
+ * et al., SC 2011) at counter (i, kappa, j, 0x4B53) and key (seed mod 2^32,
+ * seed >> 32), reduced mod the limb's prime.  Halves the key bytes a
+ * key-switch streams. */
+
+/* The rows a_j of the seeded key `seed`: a [dnum][L+K][N] (device). */
+int hks_expand_key_a(hks_ctx *ctx, uint64_t seed, uint64_t *a, void *stream);
+
+/* hks_rotate with the seeded key (seed, ksk_b); same bits as hks_rotate with
+ * the full key whose rows are (hks_expand_key_a(seed), ksk_b). */
+int hks_rotate_seeded(hks_ctx *ctx, const uint64_t *ct, uint32_t level, uint32_t galois, uint64_t seed,
+                      const uint64_t *ksk_b, uint64_t *ct_out, void *stream);
+
+/* hks_batch_rotate with seeded keys: seeds and ksk_b are HOST arrays of n_ct
+ * entries (ksk_b[i] a device pointer). */
+int hks_batch_rotate_seeded(hks_ctx *ctx, uint32_t n_ct, const uint64_t *const *ct, uint32_t level,
+                            const uint32_t *galois, const uint64_t *seeds, const uint64_t *const *ksk_b,
+                            uint64_t *const *ct_out, void *stream);
+
 /* Rescale = ModDown_{B,1} (Sec. 2.4, rounding to nearest): divide by
  * q_{level-1}.  ct [2][level][N] -> ct_out [2][level-1][N], level >= 2. */
 int hks_rescale(hks_ctx *ctx, const uint64_t *ct, uint32_t level, uint64_t *ct_out, void *stream);

@@ -142,9 +142,11 @@ int do_moddown_tail(Ctx &c, uint32_t level, uint32_t np, BatchIo epi, hipStream_
 struct KsJob {
     const uint64_t *d;
     uint32_t galois;
-    const uint64_t *ksk;
+    const uint64_t *ksk;  // full key [dnum][2][L+K][N], or the rows b_j [dnum][L+K][N] of a seeded key
     uint64_t *out;
     const uint64_t *add0, *add1;
+    uint64_t seed = 0;
+    bool seeded = false;
 };
 
 // KeySwitch of nb <= min(batch_cap, MAXCT) jobs in shared launches (9 per
@@ -161,7 +163,9 @@ int do_keyswitch_step(Ctx &c, const KsJob *jobs, uint32_t nb, uint32_t level, hi
         g[b] = jobs[b].galois;
         kb.direct[b] = jobs[b].d;
         kb.ksk[b] = jobs[b].ksk;
+        kb.seed[b] = jobs[b].seed;
         kb.galois[b] = jobs[b].galois;
+        kb.seeded = jobs[b].seeded ? 1u : 0u;  // one kind per step (the entry points never mix them)
         for (uint32_t poly = 0; poly < 2; ++poly) {
             const uint32_t p = 2 * b + poly;
             epi.uq[p] = c.ws_uv + b * c.st_uv() + poly * pl;
@@ -525,6 +529,46 @@ int hks_batch_rotate(hks_ctx *h, uint32_t n_ct, const uint64_t *const *ct, uint3
         jobs[i] = KsJob{ct[i], galois[i], ksk[i], ct_out[i], nullptr, ct[i] + (size_t)level * c.n};
     }
     return do_keyswitch_jobs(c, jobs.data(), n_ct, level, (hipStream_t)stream);
+    GUARD_END
+}
+
+int hks_expand_key_a(hks_ctx *h, uint64_t seed, uint64_t *a, void *stream) {
+    GUARD_BEGIN
+    if (!h || !a || !aligned(a)) return HKS_EINVAL;
+    return hip_status(launch_expand_key_a(h->c, seed, a, (hipStream_t)stream));
+    GUARD_END
+}
+
+int hks_batch_rotate_seeded(hks_ctx *h, uint32_t n_ct, const uint64_t *const *ct, uint32_t level,
+                            const uint32_t *galois, const uint64_t *seeds, const uint64_t *const *ksk_b,
+                            uint64_t *const *ct_out, void *stream) {
+    GUARD_BEGIN
+    if (!h || !ct || !galois || !seeds || !ksk_b || !ct_out || n_ct == 0 || level < 1 || level > h->c.L)
+        return HKS_EINVAL;
+    Ctx &c = h->c;
+    std::vector<KsJob> jobs(n_ct);
+    for (uint32_t i = 0; i < n_ct; ++i) {
+        if (!ct[i] || !ksk_b[i] || !ct_out[i] || !aligned(ct[i]) || !aligned(ksk_b[i]) || !aligned(ct_out[i]) ||
+            !valid_galois(c, galois[i]))
+            return HKS_EINVAL;
+        for (uint32_t j = 0; j < n_ct; ++j)
+            if (ct_out[i] == ct[j] || (j != i && ct_out[i] == ct_out[j])) return HKS_EINVAL;
+        jobs[i] = KsJob{ct[i], galois[i], ksk_b[i], ct_out[i], nullptr, ct[i] + (size_t)level * c.n, seeds[i], true};
+    }
+    return do_keyswitch_jobs(c, jobs.data(), n_ct, level, (hipStream_t)stream);
+    GUARD_END
+}
+
+int hks_rotate_seeded(hks_ctx *h, const uint64_t *ct, uint32_t level, uint32_t galois, uint64_t seed,
+                      const uint64_t *ksk_b, uint64_t *ct_out, void *stream) {
+    GUARD_BEGIN
+    if (!h || !ct || !ksk_b || !ct_out || !aligned(ct) || !aligned(ksk_b) || !aligned(ct_out) || level < 1 ||
+        level > h->c.L || ct == ct_out)
+        return HKS_EINVAL;
+    Ctx &c = h->c;
+    if (!valid_galois(c, galois)) return HKS_EINVAL;
+    const KsJob job{ct, galois, ksk_b, ct_out, nullptr, ct + (size_t)level * c.n, seed, true};
+    return do_keyswitch_jobs(c, &job, 1, level, (hipStream_t)stream);
     GUARD_END
 }
 

@@ -72,6 +72,39 @@ struct Mac25 {
     }
 };
 
+// Counter-based generator Philox4x32-10 (Salmon et al., SC 2011): ten
+// rounds, each multiplying words 0 and 2 by the round constants and mixing
+// the products' halves with words 1 and 3 and the round key; the key grows
+// by the Weyl increments between rounds.  Returns words 0..2 of the output.
+__device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                              uint32_t k1, uint32_t &o0, uint32_t &o1, uint32_t &o2) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+        c0 = hi1 ^ c1 ^ k0;
+        c1 = lo1;
+        c2 = hi0 ^ c3 ^ k1;
+        c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    o0 = c0;
+    o1 = c1;
+    o2 = c2;
+}
+
+// Entry (digit j, key limb kappa, slot i) of a seeded key's uniform rows:
+// the generator's low 96 bits for counter (i, kappa, j, 0x4B53) and key
+// (seed mod 2^32, seed >> 32), reduced mod the limb's prime (Barrett on a
+// value below 2^96).
+__device__ __forceinline__ uint64_t seeded_key_a(uint64_t seed, uint32_t j, uint32_t kappa, uint32_t i, uint64_t q,
+                                                 uint64_t mu, uint64_t nq) {
+    uint32_t o0, o1, o2;
+    philox4x32_10(i, kappa, j, 0x4B53u, (uint32_t)seed, (uint32_t)(seed >> 32), o0, o1, o2);
+    return reduce128(o2, ((uint64_t)o1 << 32) | o0, q, mu, nq);
+}
+
 __device__ __forceinline__ void split25(uint64_t y, uint32_t &y0, uint32_t &y1) {
     y0 = (uint32_t)y & 0x1FFFFFFu;
     y1 = (uint32_t)(y >> 25);

@@ -179,14 +179,20 @@ hipError_t launch_conv_moddown(const Ctx &c, const uint64_t *p, uint32_t level, 
 // own limb (all digits if all_direct) at direct[b] + j*dstride + t*N,
 // gathered through galois[b]; key ksk[b]; q limbs to uq + b*uq_bstride
 // ([2][level][N]), P limbs to pc + b*pc_bstride ([2][K][N]).
+// With `seeded`, ksk[b] holds only the rows b_j ([dnum][L+K][N]) and the
+// rows a_j are regenerated from seed[b] (Philox4x32-10, see seeded_key_a).
 struct KskBatch {
     const uint64_t *direct[MAXCT];
     const uint64_t *ksk[MAXCT];
+    uint64_t seed[MAXCT];
     uint32_t galois[MAXCT];
+    uint32_t seeded;
 };
 hipError_t launch_ksk_rows(const Ctx &c, const KskBatch &kb, uint32_t nb, const uint64_t *ext, size_t ext_bstride,
                            bool rowpass, size_t dstride, uint32_t all_direct, uint32_t level, uint64_t *uq,
                            size_t uq_bstride, uint64_t *pc, size_t pc_bstride, hipStream_t s);
+// The rows a_j of the seeded key `seed`: a [dnum][L+K][N].
+hipError_t launch_expand_key_a(const Ctx &c, uint64_t seed, uint64_t *a, hipStream_t s);
 // Eval-domain automorph (gather) of limbs; or coefficient-domain map with negation.
 hipError_t launch_automorph(const Ctx &c, const LimbMap &m, const uint64_t *in, uint64_t *out,
                             uint32_t galois, int eval_domain, uint32_t batch, size_t in_bstride,

@@ -159,6 +159,25 @@ hipError_t launch_conv_moddown(const Ctx &c, const uint64_t *p, uint32_t level, 
     return launch_conv_t<false>(a, c.K, dim3((c.n + 255) / 256, 1, batch), s);
 }
 
+// ------------------------------------------------------------------ seeded key rows
+
+// a[j][kappa][i] for the seeded key `seed`: grid (N/256, L+K, dnum).
+__global__ void __launch_bounds__(256) expand_key_a_kernel(uint64_t seed, const ModC *mc, uint64_t *a, uint32_t n,
+                                                           uint32_t KL) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t kappa = blockIdx.y, j = blockIdx.z;
+    if (i >= n) return;
+    const ModC m = mc[kappa];
+    a[((size_t)j * KL + kappa) * n + i] = seeded_key_a(seed, j, kappa, i, m.q, m.mu, m.nq);
+}
+
+hipError_t launch_expand_key_a(const Ctx &c, uint64_t seed, uint64_t *a, hipStream_t s) {
+    ProfScope ps(c, HKS_K_ELEMENTWISE, s);
+    hipLaunchKernelGGL(expand_key_a_kernel, dim3((c.n + 255) / 256, c.M, c.dnum), dim3(256), 0, s, seed, c.mc, a,
+                       c.n, c.M);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ automorph
 
 struct AutArgs {

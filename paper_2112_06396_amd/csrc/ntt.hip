@@ -515,7 +515,7 @@ struct KskRowArgs {
 // ModDown's inverse row pass on both in registers before storing (the
 // forward pass ends in the layout the inverse pass starts from).
 // (at least two waves per SIMD: the register budget stays within 256)
-template <int LOGS, bool ROWPASS, int E>
+template <int LOGS, bool ROWPASS, int E, bool SEEDED>
 __global__ void __launch_bounds__((Tile<LOGS, ROW_LINES, false, E>::NT)) __attribute__((amdgpu_waves_per_eu(E == 8 ? KSK_E8_WAVES : 2)))
 ksk_rows_kernel(const KskRowArgs a) {
     using TL = Tile<LOGS, ROW_LINES, false, E>;
@@ -543,6 +543,7 @@ ksk_rows_kernel(const KskRowArgs a) {
     const uint64_t *ext = a.ext + b * a.ext_bstride;
     const uint64_t *direct = a.kb.direct[b];
     const uint64_t *ksk = a.kb.ksk[b];
+    const uint64_t seed = a.kb.seed[b];
     const uint32_t galois = a.kb.galois[b];
     uint64_t *uq = a.uq + b * a.uq_bstride;
     uint64_t *pc = a.pc + b * a.pc_bstride;
@@ -584,13 +585,25 @@ ksk_rows_kernel(const KskRowArgs a) {
             }
         }
         // the key rows in the same layout: E consecutive words per thread
+        // (slots (lg << n2) + E t + e); a seeded key stores only the rows b_j
+        // and regenerates a_j
         static_assert(IOF::OUT_LO == 0, "forward row pass ends with E consecutive elements per thread");
+        const uint32_t slot0 = (lg << a.n2) + E * t;
         const ulonglong2 *k0 =
-            reinterpret_cast<const ulonglong2 *>(ksk + ((size_t)(2 * jd) * KL + mod) * N + (lg << a.n2) + E * t);
-        const ulonglong2 *k1 = k0 + KL * N / 2;
+            reinterpret_cast<const ulonglong2 *>(ksk + ((size_t)(2 * jd) * KL + mod) * N + slot0);
+        const ulonglong2 *k1 = SEEDED
+            ? reinterpret_cast<const ulonglong2 *>(ksk + ((size_t)jd * KL + mod) * N + slot0)
+            : k0 + KL * N / 2;
 #pragma unroll
         for (int c = 0; c < E / 2; ++c) {
-            const ulonglong2 kv0 = k0[c], kv1 = k1[c];
+            ulonglong2 kv0;
+            if constexpr (SEEDED) {
+                kv0.x = seeded_key_a(seed, jd, mod, slot0 + 2 * c, q, mcv.mu, mcv.nq);
+                kv0.y = seeded_key_a(seed, jd, mod, slot0 + 2 * c + 1, q, mcv.mu, mcv.nq);
+            } else {
+                kv0 = k0[c];
+            }
+            const ulonglong2 kv1 = k1[c];
             u[2 * c] = add_mod(u[2 * c], mul_mod(xv[2 * c], kv0.x, q, mcv.mu, mcv.nq), q);
             u[2 * c + 1] = add_mod(u[2 * c + 1], mul_mod(xv[2 * c + 1], kv0.y, q, mcv.mu, mcv.nq), q);
             v[2 * c] = add_mod(v[2 * c], mul_mod(xv[2 * c], kv1.x, q, mcv.mu, mcv.nq), q);
@@ -612,13 +625,13 @@ ksk_rows_kernel(const KskRowArgs a) {
     gstore<LOGS, false, IOI::OUT_LO, IOI::OUT_HI, E>(v, pc + ((size_t)a.K + kp) * N, t, lg, a.n2);
 }
 
-template <bool ROWPASS, int E>
+template <bool ROWPASS, int E, bool SEEDED>
 static hipError_t launch_ksk_rows_t(const KskRowArgs &a, uint32_t n2, dim3 grid, hipStream_t s) {
     switch (n2) {
-        case 5: hipLaunchKernelGGL((ksk_rows_kernel<5, ROWPASS, E>), grid, dim3(Tile<5, ROW_LINES, false, E>::NT), 0, s, a); break;
-        case 6: hipLaunchKernelGGL((ksk_rows_kernel<6, ROWPASS, E>), grid, dim3(Tile<6, ROW_LINES, false, E>::NT), 0, s, a); break;
-        case 7: hipLaunchKernelGGL((ksk_rows_kernel<7, ROWPASS, E>), grid, dim3(Tile<7, ROW_LINES, false, E>::NT), 0, s, a); break;
-        case 8: hipLaunchKernelGGL((ksk_rows_kernel<8, ROWPASS, E>), grid, dim3(Tile<8, ROW_LINES, false, E>::NT), 0, s, a); break;
+        case 5: hipLaunchKernelGGL((ksk_rows_kernel<5, ROWPASS, E, SEEDED>), grid, dim3(Tile<5, ROW_LINES, false, E>::NT), 0, s, a); break;
+        case 6: hipLaunchKernelGGL((ksk_rows_kernel<6, ROWPASS, E, SEEDED>), grid, dim3(Tile<6, ROW_LINES, false, E>::NT), 0, s, a); break;
+        case 7: hipLaunchKernelGGL((ksk_rows_kernel<7, ROWPASS, E, SEEDED>), grid, dim3(Tile<7, ROW_LINES, false, E>::NT), 0, s, a); break;
+        case 8: hipLaunchKernelGGL((ksk_rows_kernel<8, ROWPASS, E, SEEDED>), grid, dim3(Tile<8, ROW_LINES, false, E>::NT), 0, s, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -660,9 +673,16 @@ hipError_t launch_ksk_rows(const Ctx &c, const KskBatch &kb, uint32_t nb, const 
     // already holds many waves at 16
     const uint64_t thr16 = (uint64_t)ROW_LINES * (1u << c.n2) / 16;  // threads per block at 16
     const uint64_t waves16 = (uint64_t)xs * nb * ((thr16 + 63) / 64);
+    // a seeded key's rows a_j are generated in the kernel: always 8 elements
+    // per thread there (the generator's registers on top of 16 would spill)
+    if (kb.seeded)
+        return rowpass ? launch_ksk_rows_t<true, 8, true>(a, c.n2, grid, s)
+                       : launch_ksk_rows_t<false, 8, true>(a, c.n2, grid, s);
     if (waves16 >= KSK_WAVES_FOR_E16)
-        return rowpass ? launch_ksk_rows_t<true, 16>(a, c.n2, grid, s) : launch_ksk_rows_t<false, 16>(a, c.n2, grid, s);
-    return rowpass ? launch_ksk_rows_t<true, 8>(a, c.n2, grid, s) : launch_ksk_rows_t<false, 8>(a, c.n2, grid, s);
+        return rowpass ? launch_ksk_rows_t<true, 16, false>(a, c.n2, grid, s)
+                       : launch_ksk_rows_t<false, 16, false>(a, c.n2, grid, s);
+    return rowpass ? launch_ksk_rows_t<true, 8, false>(a, c.n2, grid, s)
+                   : launch_ksk_rows_t<false, 8, false>(a, c.n2, grid, s);
 }
 
 }  // namespace hks

@@ -43,7 +43,7 @@ EXPORTS = (
     "hks_create", "hks_destroy", "hks_query", "hks_ntt", "hks_intt", "hks_automorph",
     "hks_modup", "hks_ksk_inner", "hks_moddown", "hks_keyswitch", "hks_rotate", "hks_hrotate",
     "hks_batch_rotate", "hks_rescale", "hks_ptmult", "hks_mult_relin", "hks_batch_mult_relin", "hks_add",
-    "hks_prof_enable",
+    "hks_expand_key_a", "hks_rotate_seeded", "hks_batch_rotate_seeded", "hks_prof_enable",
     "hks_prof_read",
 )
 
@@ -121,6 +121,10 @@ def lib():
             "hks_batch_mult_relin": (_i32, [_vp, _u32, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _u32,
                                             ctypes.POINTER(_vp), _i32, ctypes.POINTER(_vp), _vp]),
             "hks_add": (_i32, [_vp, _vp, _vp, _u32, _u32, _vp, _vp]),
+            "hks_expand_key_a": (_i32, [_vp, ctypes.c_uint64, _vp, _vp]),
+            "hks_rotate_seeded": (_i32, [_vp, _vp, _u32, _u32, ctypes.c_uint64, _vp, _vp, _vp]),
+            "hks_batch_rotate_seeded": (_i32, [_vp, _u32, ctypes.POINTER(_vp), _u32, ctypes.POINTER(_u32), u64p,
+                                               ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp]),
             "hks_prof_enable": (_i32, [_vp, _u32]),
             "hks_prof_read": (_i32, [_vp, _i32, ctypes.POINTER(ctypes.c_double), u64p]),
         }
@@ -317,6 +321,28 @@ def hks_batch_mult_relin(ctx, ct1s, ct2s, level: int, rlks, rescale: bool, outs,
     o = (_vp * n)(*[_ptr(x) for x in outs])
     _check("hks_batch_mult_relin", lib().hks_batch_mult_relin(ctx.handle, n, a, b, level, k, 1 if rescale else 0, o,
                                                               _stream(stream)))
+
+
+def hks_expand_key_a(ctx, seed: int, a, stream=None):
+    _check("hks_expand_key_a", lib().hks_expand_key_a(ctx.handle, int(seed), _ptr(a), _stream(stream)))
+
+
+def hks_rotate_seeded(ctx, ct, level: int, galois: int, seed: int, ksk_b, ct_out, stream=None):
+    _check("hks_rotate_seeded", lib().hks_rotate_seeded(ctx.handle, _ptr(ct), level, galois, int(seed), _ptr(ksk_b),
+                                                        _ptr(ct_out), _stream(stream)))
+
+
+def hks_batch_rotate_seeded(ctx, cts, level: int, galois, seeds, ksk_bs, outs, stream=None):
+    n = len(cts)
+    if len(galois) != n or len(seeds) != n or len(ksk_bs) != n or len(outs) != n:
+        raise ValueError("cts, galois, seeds, ksk_bs and outs must have the same length")
+    ca = (_vp * n)(*[_ptr(c) for c in cts])
+    ga = (_u32 * n)(*[int(g) for g in galois])
+    sa = (ctypes.c_uint64 * n)(*[int(x) for x in seeds])
+    ka = (_vp * n)(*[_ptr(k) for k in ksk_bs])
+    oa = (_vp * n)(*[_ptr(o) for o in outs])
+    _check("hks_batch_rotate_seeded", lib().hks_batch_rotate_seeded(ctx.handle, n, ca, level, ga, sa, ka, oa,
+                                                                    _stream(stream)))
 
 
 def hks_add(ctx, x, y, level: int, n_poly: int, out, stream=None):

@@ -568,3 +568,49 @@ def test_batch_mult_relin_equals_oracle(name, max_batch, n):
         hks.hks_batch_mult_relin(ctx, [dev(c) for c in c1], [dev(c) for c in c2], level, drl, rs, outs)
         for i in range(n):
             assert np.array_equal(host(outs[i]), O.mult_relin(pr, c1[i], c2[i], level, rlks[i], rs)), (rs, i)
+
+
+# ------------------------------------------------------------------ seeded keys
+
+
+@pytest.mark.parametrize("name", ["n10", "cfg1", "cfg2"])
+def test_expand_key_a_equals_oracle(name):
+    pr, ctx = _get(name)
+    hks = H()
+    for seed in (0, 0xC0FFEE, (1 << 64) - 1):
+        a = hks.empty((pr.dnum, pr.L + pr.K, pr.n))
+        hks.hks_expand_key_a(ctx, seed, a)
+        assert np.array_equal(host(a), O.expand_key_a(pr, seed)), seed
+
+
+@pytest.mark.parametrize("name", ["n10", "cfg1", "n13", "cfg2"])
+def test_rotate_seeded_equals_oracle(name):
+    """Rotate with a seeded key (rows a_j regenerated in the key-switch
+    kernel) equals the oracle's Rotate with the full key."""
+    pr, ctx = _get(name)
+    hks = H()
+    seed = 0x5EED_0000 + pr.log_n
+    b_rows = _rand_ksk(pr, 700)[:, 1].copy()
+    full = np.stack([O.expand_key_a(pr, seed), b_rows], axis=1)
+    for level in sorted({pr.L, pr.alpha + 1, 1}):
+        ct = _rand_ct(pr, level, 701 + level)
+        g = hks.hks_galois_for_rotation(3, pr.log_n)
+        out = hks.empty((2, level, pr.n))
+        hks.hks_rotate_seeded(ctx, dev(ct), level, g, seed, dev(b_rows), out)
+        assert np.array_equal(host(out), O.rotate(pr, ct, level, g, full)), level
+
+
+@pytest.mark.parametrize("name,max_batch", [("cfg1", 4), ("cfg2", 8)])
+def test_batch_rotate_seeded_equals_oracle(name, max_batch):
+    pr, ctx = _get(name, max_batch)
+    hks = H()
+    n_ct, level = 5, pr.L
+    seeds = [0xABC0 + i for i in range(n_ct)]
+    b_rows = [_rand_ksk(pr, 710 + i)[:, 1].copy() for i in range(n_ct)]
+    cts = [_rand_ct(pr, level, 720 + i) for i in range(n_ct)]
+    gals = [hks.hks_galois_for_rotation(1 + i, pr.log_n) for i in range(n_ct)]
+    outs = [hks.empty((2, level, pr.n)) for _ in range(n_ct)]
+    hks.hks_batch_rotate_seeded(ctx, [dev(c) for c in cts], level, gals, seeds, [dev(b) for b in b_rows], outs)
+    for i in range(n_ct):
+        full = np.stack([O.expand_key_a(pr, seeds[i]), b_rows[i]], axis=1)
+        assert np.array_equal(host(outs[i]), O.rotate(pr, cts[i], level, gals[i], full)), i
