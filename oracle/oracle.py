@@ -75,6 +75,8 @@ def lib():
             "oref_lift_signed": (None, [ctypes.POINTER(ctypes.c_int64), _u64p, u32, _u64p, u32]),
             "oref_philox4x32_10": (None, [ctypes.POINTER(u32), ctypes.POINTER(u32), ctypes.POINTER(u32)]),
             "oref_expand_key_a": (None, [P, u64, _u64p]),
+            "oref_ptmatvec": (i32, [P, _u64p, u32, u32, ctypes.POINTER(u32), ctypes.POINTER(_u64p),
+                                    ctypes.POINTER(_u64p), _u64p]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -229,6 +231,21 @@ def hrotate(pr: Params, ct: np.ndarray, level: int, gs, ksks) -> list:
     oarr = (_u64p * r)(*[_p(o) for o in outs])
     _call("oref_hrotate", pr, _p(ct), level, r, garr, karr, oarr)
     return outs
+
+
+def ptmatvec(pr: Params, ct: np.ndarray, level: int, gs, ksks, pts) -> np.ndarray:
+    """sum_i M_i * Rotate_{g_i}(ct) with one ModDown (hoisted PtMatVecMult);
+    pts[i] is M_i over Q_level U P, [level + K][N] evaluation form."""
+    ct = _u64(ct)
+    ksks = [_u64(k) for k in ksks]
+    pts = [_u64(p) for p in pts]
+    r = len(gs)
+    out = np.zeros((2, level, pr.n), dtype=np.uint64)
+    ga = (ctypes.c_uint32 * r)(*[int(g) for g in gs])
+    ka = (_u64p * r)(*[_p(k) for k in ksks])
+    pa = (_u64p * r)(*[_p(p) for p in pts])
+    _call("oref_ptmatvec", pr, _p(ct), level, r, ga, ka, pa, _p(out))
+    return out
 
 
 def rescale(pr: Params, ct: np.ndarray, level: int) -> np.ndarray:

@@ -651,3 +651,65 @@ void oref_expand_key_a(const oref_params *pr, uint64_t seed, uint64_t *a) {
             }
         }
 }
+
+/* ---------------------------------------------------------------------------
+ * PtMatVecMult with the ModDown hoisted out of the rotation loop (the
+ * paper's Algorithm "PtMatVecMult", Sec. "Hoisting the ModDown in
+ * PtMatVecMult"): sum_i M_i * Rotate_{g_i}(x) with one ModDown.
+ *   ModUp of a_x once; for each i: automorph the extended digits by g_i,
+ *   KSKInnerProd with ksk_i -> (u, v) over Q_level U P; b_rot = automorph of
+ *   b_x; PModUp(b_rot) = P * b_rot on the q limbs, 0 on the P limbs;
+ *   accumulate (a_y, b_y) += M_i * (u, v + PModUp(b_rot)) limb-wise; finally
+ *   out = (ModDown(a_y), ModDown(b_y)).
+ * pts[i] is the diagonal M_i given over the extended basis ([level + K][N],
+ * evaluation form, residues mod q_0..q_{level-1}, p_0..p_{K-1}): the
+ * plaintext itself, not multiplied by P (a factor P on it would survive the
+ * single ModDown).
+ * ------------------------------------------------------------------------- */
+int oref_ptmatvec(const oref_params *pr, const uint64_t *ct, uint32_t level, uint32_t r, const uint32_t *gs,
+                  const uint64_t *const *ksks, const uint64_t *const *pts, uint64_t *out) {
+    if (check(pr, level)) return -1;
+    size_t n = (size_t)1 << pr->log_n;
+    size_t pl = (size_t)level * n;
+    uint32_t beta = beta_of(pr, level), next = level + pr->K;
+    if (beta > pr->dnum) return -1;
+    uint64_t *ext = (uint64_t *)malloc(sizeof(uint64_t) * n * next * beta);
+    uint64_t *erot = (uint64_t *)malloc(sizeof(uint64_t) * n * next * beta);
+    uint64_t *hat = (uint64_t *)malloc(sizeof(uint64_t) * n * next * 2);
+    uint64_t *acc = (uint64_t *)calloc(n * next * 2, sizeof(uint64_t));
+    uint64_t *brot = (uint64_t *)malloc(sizeof(uint64_t) * pl);
+    uint64_t *emods = (uint64_t *)malloc(sizeof(uint64_t) * next);
+    for (uint32_t t = 0; t < next; t++) emods[t] = ext_mod(pr, level, t);
+    int rc = oref_modup(pr, ct, level, ext);
+    for (uint32_t i = 0; !rc && i < r; i++) {
+        if ((gs[i] & 1) == 0) { rc = -1; break; }
+        for (uint32_t j = 0; j < beta; j++)
+            oref_automorph(ext + (size_t)j * next * n, erot + (size_t)j * next * n, pr->log_n,
+                           emods, next, gs[i], 1);
+        rc = oref_ksk_inner(pr, erot, level, ksks[i], hat);
+        if (rc) break;
+        oref_automorph(ct + pl, brot, pr->log_n, pr->q, level, gs[i], 1);
+        for (uint32_t t = 0; t < next; t++) {
+            uint64_t m = emods[t];
+            uint64_t pmod = 1;  /* [P]_m on q limbs; PModUp is 0 on the P limbs */
+            for (uint32_t k = 0; k < pr->K; k++) pmod = mulmod(pmod, pr->p[k] % m, m);
+            for (size_t c = 0; c < n; c++) {
+                uint64_t mi = pts[i][t * n + c];
+                uint64_t u = hat[t * n + c], v = hat[((size_t)next + t) * n + c];
+                uint64_t bh = t < level ? mulmod(pmod, brot[t * n + c], m) : 0;
+                acc[t * n + c] = addmod(acc[t * n + c], mulmod(mi, u, m), m);
+                acc[((size_t)next + t) * n + c] = addmod(acc[((size_t)next + t) * n + c],
+                                                         mulmod(mi, addmod(v, bh, m), m), m);
+            }
+        }
+    }
+    if (!rc) rc = oref_moddown(pr, acc, level, out);
+    if (!rc) rc = oref_moddown(pr, acc + (size_t)next * n, level, out + pl);
+    free(emods);
+    free(brot);
+    free(acc);
+    free(hat);
+    free(erot);
+    free(ext);
+    return rc;
+}

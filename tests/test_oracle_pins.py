@@ -415,3 +415,48 @@ def test_seeded_rotation_key_decrypts():
     d_out = O.decrypt_coef(pr, s, out, pr.L)
     diff = O.sub_vec(d_out, O.automorph(d_in, pr.log_n, pr.q, gal, eval_domain=False), pr.log_n, pr.q)
     assert O.centered_small(diff, pr.q, O.ks_noise_bound(pr, pr.L, s)) is not None
+
+
+# ------------------------------------------------------------------ hoisted PtMatVecMult (one ModDown)
+
+
+def _negacyclic_int(a, b):
+    """integer negacyclic product of int64 coefficient vectors (small values)"""
+    n = len(a)
+    full = np.convolve(np.asarray(a, dtype=np.int64), np.asarray(b, dtype=np.int64))
+    out = full[:n].copy()
+    out[: n - 1] -= full[n:]
+    return out
+
+
+@pytest.mark.parametrize("cfg", [(10, 6, 2, 3, 6, (1, 2, -5)), (10, 7, 3, 3, 5, (3, 7, 11, -1))])
+def test_ptmatvec_decrypts_to_sum_of_rotated_products(cfg):
+    """PtMatVecMult with the ModDown hoisted out of the rotation loop:
+    decrypting the result gives sum_i M_i * phi_{k_i}(m) (negacyclic products
+    of the diagonals with the rotated message) up to key-switching noise."""
+    log_n, L, K, dnum, level, ks = cfg
+    pr, g, s = _setup(log_n, L, K, dnum, 4321 + level)
+    gals = [pow(5, -k, 2 * pr.n) for k in ks]
+    keys = [O.rotation_key(pr, s, gl, g) for gl in gals]
+    m = synth.small_uniform(g, pr.n, 1 << 20)
+    ct = O.encrypt(pr, s, m, level, g)
+    emods = pr.ext_mods(level)
+    Ms = [synth.ternary(g, pr.n) for _ in ks]
+    pts = [O.ntt(O.lift_signed(M, pr.log_n, emods), pr.log_n, emods) for M in Ms]
+    out = O.ptmatvec(pr, ct, level, gals, keys, pts)
+    mods = pr.q[:level]
+    dec = O.decrypt_coef(pr, s, out, level)
+    want = np.zeros(pr.n, dtype=np.int64)
+    for M, gl in zip(Ms, gals):
+        want += _negacyclic_int(M, np.array(B.automorph_int(m, gl), dtype=np.int64))
+    diff = O.sub_vec(dec, O.lift_signed(want, pr.log_n, mods), pr.log_n, mods)
+    bound = len(ks) * pr.n * O.ks_noise_bound(pr, level, s)
+    assert bound < int(mods[0]) // 1024
+    assert O.centered_small(diff, mods, bound) is not None
+    # the diagonals must be taken as themselves over P, not multiplied by P
+    bad = [O.ntt(O.lift_signed(M, pr.log_n, emods), pr.log_n, emods) for M in Ms]
+    for b_ in bad:
+        b_[level:] = 0
+    dec_bad = O.decrypt_coef(pr, s, O.ptmatvec(pr, ct, level, gals, keys, bad), level)
+    assert O.centered_small(O.sub_vec(dec_bad, O.lift_signed(want, pr.log_n, mods), pr.log_n, mods), mods,
+                            bound) is None
