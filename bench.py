@@ -165,6 +165,25 @@ def extras(args, ctx, hks, synth, cts, ksks, outs, gal, key_mods, n, plain_value
         lambda i: hks.hks_batch_rotate_seeded(ctx, dcts, LEVEL, gals[:32], [77 + j for j in range(32)], b_rows,
                                               douts[:32], stream), 32, 8)
     del b_rows
+    # PtMatVecMult over 12 rotations: the ModDown hoisted (one fused launch, one ModDown) vs
+    # HRotate + PtMult + Add (a ModDown per rotation)
+    r = 12
+    pts = [synth.device_residues(key_mods[:LEVEL] + key_mods[L:], (), n, 9000 + i) for i in range(r)]
+    pts_q = [p_[:LEVEL].contiguous() for p_ in pts]
+    mv_out = hks.empty((2, LEVEL, n))
+    tmp = [hks.empty((2, LEVEL, n)) for _ in range(2)]
+
+    def unhoisted(i):
+        hks.hks_hrotate(ctx, cts[i % args.pool], LEVEL, gals[:r], dkeys[:r], douts[:r], stream)
+        hks.hks_ptmult(ctx, douts[0], pts_q[0], LEVEL, False, tmp[0], stream)
+        for j in range(1, r):
+            hks.hks_ptmult(ctx, douts[j], pts_q[j], LEVEL, False, tmp[1], stream)
+            hks.hks_add(ctx, tmp[0], tmp[1], LEVEL, 2, tmp[0], stream)
+
+    res["ptmatvec_r12_rot_per_s"] = rate(
+        lambda i: hks.hks_ptmatvec(ctx, cts[i % args.pool], LEVEL, gals[:r], dkeys[:r], pts, mv_out, stream), r, 8)
+    res["ptmatvec_r12_unhoisted_rot_per_s"] = rate(unhoisted, r, 8)
+    del pts, pts_q, mv_out, tmp
     # the plain Rotate replayed from hipGraphs (one per pool entry)
     graphs = []
     for j in range(args.pool):
@@ -178,7 +197,8 @@ def extras(args, ctx, hks, synth, cts, ksks, outs, gal, key_mods, n, plain_value
     log(f"[bench] hrotate r=64 {res['hrotate_r64_ks_per_s']:.0f} ks/s; batch 32 shared key "
         f"{res['batch32_shared_key_ks_per_s']:.0f}, distinct keys {res['batch32_distinct_keys_ks_per_s']:.0f}, "
         f"distinct seeded keys {res['batch32_seeded_keys_ks_per_s']:.0f}; seeded Rotate "
-        f"{res['rotate_seeded_ks_per_s']:.0f}; "
+        f"{res['rotate_seeded_ks_per_s']:.0f}; PtMatVecMult r=12 {res['ptmatvec_r12_rot_per_s']:.0f} rot/s "
+        f"(unhoisted {res['ptmatvec_r12_unhoisted_rot_per_s']:.0f}); "
         f"graph-replayed Rotate {res['graph_rotate_ks_per_s']:.0f}")
     del dkeys, dcts, douts
     torch.cuda.empty_cache()

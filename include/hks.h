@@ -168,8 +168,20 @@ int hks_hrotate(hks_ctx *ctx, const uint64_t *ct, uint32_t level, uint32_t r,
                 const uint32_t *galois, const uint64_t *const *ksk, uint64_t *const *ct_out,
                 void *stream);
 
+/* PtMatVecMult with the ModDown hoisted (Sec. 5.2, Algorithm
+ * "PtMatVecMult"): ct_out = sum_i M_i * Rotate_{galois[i]}(ct) computed as one
+ * ModUp of a, per i the automorphed extended digits through KSKInnerProd
+ * with ksk[i], multiplied by M_i together with P * b_rot over Q_level U P and
+ * summed, then a single ModDown.  pt[i] is M_i over the extended basis,
+ * [level + K][N] evaluation form (residues mod q_0..q_{level-1},
+ * p_0..p_{K-1}; not multiplied by P).  galois, ksk, pt are HOST arrays of
+ * r <= 64 entries (device pointers).  The result carries the product's
+ * scale (no Rescale). */
+int hks_ptmatvec(hks_ctx *ctx, const uint64_t *ct, uint32_t level, uint32_t r, const uint32_t *galois,
+                 const uint64_t *const *ksk, const uint64_t *const *pt, uint64_t *ct_out, void *stream);
+
 /* Rotate of n_ct independent ciphertexts at one level (same semantics and
- * bits as n_ct calls of hks_rotate; the hoisting / batching of Sec. 4).  ct,
+ * bits as n_ct calls of hks_rotate; batching as in Sec. 2.4 and 5.2).  ct,
  * galois, ksk, ct_out are HOST arrays of n_ct entries; galois elements and
  * keys may differ per ciphertext.  Up to max_batch ciphertexts share every
  * launch of a step; the blocks of one key tile run on one XCD, so a key
@@ -180,7 +192,7 @@ int hks_batch_rotate(hks_ctx *ctx, uint32_t n_ct, const uint64_t *const *ct, uin
                      void *stream);
 
 /* ---------------------------------------------------------------- seeded keys
- * Key compression (Sec. 6): a seeded switching key stores only its rows b_j,
+ * Key compression (Sec. 5.3): a seeded switching key stores only its rows b_j,
  * ksk_b [dnum][L+K][N]; the uniform rows a_j are regenerated on the device
  * from a 64-bit seed.  Entry (j, kappa, i) of a_j, for key limb kappa and
  * slot i, is the low 96 bits c0 + c1 2^32 + c2 2^64 of Philox4x32-10 (Salmon

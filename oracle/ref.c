@@ -597,7 +597,7 @@ void oref_lift_signed(const int64_t *v, uint64_t *out, uint32_t log_n, const uin
 }
 
 /* ---------------------------------------------------------------------------
- * Seeded switching keys (the paper's key compression, Sec. 6: the uniform
+ * Seeded switching keys (the paper's key compression, Sec. 5.3: the uniform
  * row a_j of a switching key is regenerated from a short seed instead of
  * being stored).  The generator is Philox4x32-10 (Salmon, Moraes, Dror and
  * Shaw, "Parallel Random Numbers: As Easy as 1, 2, 3", SC 2011), written
@@ -653,9 +653,8 @@ void oref_expand_key_a(const oref_params *pr, uint64_t seed, uint64_t *a) {
 }
 
 /* ---------------------------------------------------------------------------
- * PtMatVecMult with the ModDown hoisted out of the rotation loop (the
- * paper's Algorithm "PtMatVecMult", Sec. "Hoisting the ModDown in
- * PtMatVecMult"): sum_i M_i * Rotate_{g_i}(x) with one ModDown.
+ * PtMatVecMult with the ModDown hoisted out of the rotation loop (Sec. 5.2,
+ * Algorithm "PtMatVecMult"): sum_i M_i * Rotate_{g_i}(x) with one ModDown.
  *   ModUp of a_x once; for each i: automorph the extended digits by g_i,
  *   KSKInnerProd with ksk_i -> (u, v) over Q_level U P; b_rot = automorph of
  *   b_x; PModUp(b_rot) = P * b_rot on the q limbs, 0 on the P limbs;

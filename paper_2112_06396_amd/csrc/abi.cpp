@@ -532,6 +532,33 @@ int hks_batch_rotate(hks_ctx *h, uint32_t n_ct, const uint64_t *const *ct, uint3
     GUARD_END
 }
 
+int hks_ptmatvec(hks_ctx *h, const uint64_t *ct, uint32_t level, uint32_t r, const uint32_t *galois,
+                 const uint64_t *const *ksk, const uint64_t *const *pt, uint64_t *ct_out, void *stream) {
+    GUARD_BEGIN
+    if (!h || !ct || !galois || !ksk || !pt || !ct_out || !aligned(ct) || !aligned(ct_out) || level < 1 ||
+        level > h->c.L || r == 0 || r > (uint32_t)MAXROT || ct == ct_out)
+        return HKS_EINVAL;
+    Ctx &c = h->c;
+    for (uint32_t i = 0; i < r; ++i)
+        if (!valid_galois(c, galois[i]) || !ksk[i] || !pt[i] || !aligned(ksk[i]) || !aligned(pt[i]))
+            return HKS_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t pl = (size_t)level * c.n;
+    const uint32_t one = 1;
+    int rc = do_modup_new(c, &ct, &one, 1, level, c.ws_ext, 0, s, false);
+    if (!rc) rc = do_modup_own(c, ct, level, 1, c.ws_ext, s);
+    if (rc) return rc;
+    HKS_TRY(launch_ksk_matvec(c, c.ws_ext, level, r, galois, ksk, pt, ct + pl, c.ws_uv, c.ws_p, s));
+    BatchIo epi{};
+    for (uint32_t p = 0; p < 2; ++p) {
+        epi.uq[p] = c.ws_uv + p * pl;
+        epi.out[p] = ct_out + p * pl;
+        epi.add_galois[p] = 1;
+    }
+    return do_moddown_tail(c, level, 2, epi, s);
+    GUARD_END
+}
+
 int hks_expand_key_a(hks_ctx *h, uint64_t seed, uint64_t *a, void *stream) {
     GUARD_BEGIN
     if (!h || !a || !aligned(a)) return HKS_EINVAL;

@@ -15,6 +15,7 @@ namespace hks {
 constexpr int MAXL = 160;  // limbs per launch descriptor
 constexpr int MAXB = 32;   // batch entries (polynomials) per launch
 constexpr int MAXCT = 16;  // ciphertexts per batched key-switch step (two polynomials each)
+constexpr int MAXROT = 64; // rotations of one PtMatVecMult launch
 
 // A list of limbs for one launch.  Limb i is read at in_base + in_off[i]*N
 // (+ blockIdx.y * in_bstride for batches), written at out_base + out_off[i]*N,
@@ -90,6 +91,7 @@ struct Ctx {
     std::vector<size_t> conv_modup_off;  // [L+1]
     uint64_t *conv_moddown = nullptr;  // [L][K]: [P/p_k]_{q_i} (row i), split 25/25
     Shoup *pinv = nullptr;             // [L]: P^-1 mod q_i
+    Shoup *pmod = nullptr;             // [L]: P mod q_i
     Shoup *rs_qinv = nullptr;          // [L+1][L]: q_{l-1}^-1 mod q_i
     uint64_t *rs_h = nullptr;          // [L+1][L]: ((q_{l-1}-1)/2) mod q_i
     LimbMap *dummy = nullptr;
@@ -191,6 +193,12 @@ struct KskBatch {
 hipError_t launch_ksk_rows(const Ctx &c, const KskBatch &kb, uint32_t nb, const uint64_t *ext, size_t ext_bstride,
                            bool rowpass, size_t dstride, uint32_t all_direct, uint32_t level, uint64_t *uq,
                            size_t uq_bstride, uint64_t *pc, size_t pc_bstride, hipStream_t s);
+// PtMatVecMult sums over Q_level U P (ModUp'd digits of a in ext, evaluation
+// form, [beta][level+K][N]): q limbs into uq [2][level][N], P limbs after
+// ModDown's inverse row pass into pc [2][K][N].  r <= MAXROT.
+hipError_t launch_ksk_matvec(const Ctx &c, const uint64_t *ext, uint32_t level, uint32_t r, const uint32_t *galois,
+                             const uint64_t *const *ksk, const uint64_t *const *pt, const uint64_t *b, uint64_t *uq,
+                             uint64_t *pc, hipStream_t s);
 // The rows a_j of the seeded key `seed`: a [dnum][L+K][N].
 hipError_t launch_expand_key_a(const Ctx &c, uint64_t seed, uint64_t *a, hipStream_t s);
 // Eval-domain automorph (gather) of limbs; or coefficient-domain map with negation.

@@ -685,4 +685,141 @@ hipError_t launch_ksk_rows(const Ctx &c, const KskBatch &kb, uint32_t nb, const 
                    : launch_ksk_rows_t<false, 8, false>(a, c.n2, grid, s);
 }
 
+// ------------------------------------------------------------------ PtMatVecMult with one ModDown
+
+struct MatvecArgs {
+    const uint64_t *ext;  // [beta][E][N] extended digits of a_x, evaluation form
+    const uint64_t *ksk[MAXROT];
+    const uint64_t *pt[MAXROT];  // diagonals over Q_level U P, [level + K][N]
+    uint32_t galois[MAXROT];
+    const uint64_t *b;     // b_x, [level][N]
+    const Shoup *pmod;     // [P]_{q_i}
+    uint64_t *uq;          // [2][level][N] sums on the q limbs
+    uint64_t *pc;          // [2][K][N] sums on the P limbs after the inverse row pass
+    const Shoup *twi;
+    const ModC *mc;
+    uint32_t n, n1, n2, level, L, K, E, beta, r;
+};
+
+// One block = one limb t of Q_level U P and ROW_LINES rows, over all r
+// rotations (the paper's PtMatVecMult with the ModDown hoisted): for each i,
+// u, v = KSKInnerProd of the extended digits gathered through g_i with
+// ksk_i; then a_y += M_i u and b_y += M_i (v + [P]_t b_rot) where b_rot is b
+// gathered through g_i (q limbs only).  The sums stay in registers; q limbs
+// store them, P limbs run ModDown's inverse row pass first.
+template <int LOGS, int E>
+__global__ void __launch_bounds__((Tile<LOGS, ROW_LINES, false, E>::NT)) ksk_matvec_kernel(const MatvecArgs a) {
+    using TL = Tile<LOGS, ROW_LINES, false, E>;
+    using IOF = IoLayout<LOGS, true, E>;
+    using IOI = IoLayout<LOGS, false, E>;
+    static_assert(IOF::OUT_LO == 0 && IOF::OUT_LO == IOI::IN_LO && IOF::OUT_HI == IOI::IN_HI,
+                  "E consecutive slots per thread, the inverse row pass's input layout");
+    __shared__ uint64_t lds[TL::WORDS];
+    const uint32_t tiles = (1u << a.n1) / ROW_LINES;
+    const uint32_t tgt = blockIdx.x / tiles;
+    const uint32_t tile = blockIdx.x % tiles;
+    const uint32_t N = 1u << a.n;
+    const uint32_t mod = tgt < a.level ? tgt : a.L + (tgt - a.level);
+    const ModC mcv = a.mc[mod];
+    const uint64_t q = mcv.q;
+    const size_t KL = (size_t)a.L + a.K;
+    const bool is_p = tgt >= a.level;
+    int line, t;
+    thread_coords<LOGS, ROW_LINES, false, E>(threadIdx.x, line, t);
+    const uint32_t lg = tile * ROW_LINES + line;
+    const uint32_t slot0 = (lg << a.n2) + E * t;
+    const Shoup pm = is_p ? Shoup{} : a.pmod[tgt];
+
+    uint64_t ya[E], yb[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) ya[e] = yb[e] = 0;
+    for (uint32_t i = 0; i < a.r; ++i) {
+        const uint32_t g = a.galois[i];
+        uint64_t u[E], v[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) u[e] = v[e] = 0;
+        for (uint32_t jd = 0; jd < a.beta; ++jd) {
+            const uint64_t *src = a.ext + ((size_t)jd * a.E + tgt) * N;
+            const ulonglong2 *k0 =
+                reinterpret_cast<const ulonglong2 *>(a.ksk[i] + ((size_t)(2 * jd) * KL + mod) * N + slot0);
+            const ulonglong2 *k1 = k0 + KL * N / 2;
+#pragma unroll
+            for (int c = 0; c < E / 2; ++c) {
+                const ulonglong2 kv0 = k0[c], kv1 = k1[c];
+                const uint64_t x0 = src[aut_eval_src(slot0 + 2 * c, g, a.n)];
+                const uint64_t x1 = src[aut_eval_src(slot0 + 2 * c + 1, g, a.n)];
+                u[2 * c] = add_mod(u[2 * c], mul_mod(x0, kv0.x, q, mcv.mu, mcv.nq), q);
+                u[2 * c + 1] = add_mod(u[2 * c + 1], mul_mod(x1, kv0.y, q, mcv.mu, mcv.nq), q);
+                v[2 * c] = add_mod(v[2 * c], mul_mod(x0, kv1.x, q, mcv.mu, mcv.nq), q);
+                v[2 * c + 1] = add_mod(v[2 * c + 1], mul_mod(x1, kv1.y, q, mcv.mu, mcv.nq), q);
+            }
+        }
+        const ulonglong2 *mi = reinterpret_cast<const ulonglong2 *>(a.pt[i] + (size_t)tgt * N + slot0);
+        const uint64_t *brow = a.b + (size_t)tgt * N;
+#pragma unroll
+        for (int c = 0; c < E / 2; ++c) {
+            const ulonglong2 m = mi[c];
+            uint64_t v0 = v[2 * c], v1 = v[2 * c + 1];
+            if (!is_p) {
+                v0 = add_mod(v0, mul_shoup(brow[aut_eval_src(slot0 + 2 * c, g, a.n)], pm.w, pm.wp, q), q);
+                v1 = add_mod(v1, mul_shoup(brow[aut_eval_src(slot0 + 2 * c + 1, g, a.n)], pm.w, pm.wp, q), q);
+            }
+            ya[2 * c] = add_mod(ya[2 * c], mul_mod(m.x, u[2 * c], q, mcv.mu, mcv.nq), q);
+            ya[2 * c + 1] = add_mod(ya[2 * c + 1], mul_mod(m.y, u[2 * c + 1], q, mcv.mu, mcv.nq), q);
+            yb[2 * c] = add_mod(yb[2 * c], mul_mod(m.x, v0, q, mcv.mu, mcv.nq), q);
+            yb[2 * c + 1] = add_mod(yb[2 * c + 1], mul_mod(m.y, v1, q, mcv.mu, mcv.nq), q);
+        }
+    }
+    if (!is_p) {
+        gstore<LOGS, false, IOF::OUT_LO, IOF::OUT_HI, E>(ya, a.uq + (size_t)tgt * N, t, lg, a.n2);
+        gstore<LOGS, false, IOF::OUT_LO, IOF::OUT_HI, E>(yb, a.uq + ((size_t)a.level + tgt) * N, t, lg, a.n2);
+        return;
+    }
+    const uint32_t kp = tgt - a.level;
+    const TwRows twi{a.twi + (size_t)mod * N, lg, a.n1};
+    pass_regs<LOGS, ROW_LINES, false, false, false, E>(true, ya, lds, line, t, q, mcv.nq, twi, LastInv{});
+    gstore<LOGS, false, IOI::OUT_LO, IOI::OUT_HI, E>(ya, a.pc + (size_t)kp * N, t, lg, a.n2);
+    __syncthreads();
+    pass_regs<LOGS, ROW_LINES, false, false, false, E>(true, yb, lds, line, t, q, mcv.nq, twi, LastInv{});
+    gstore<LOGS, false, IOI::OUT_LO, IOI::OUT_HI, E>(yb, a.pc + ((size_t)a.K + kp) * N, t, lg, a.n2);
+}
+
+hipError_t launch_ksk_matvec(const Ctx &c, const uint64_t *ext, uint32_t level, uint32_t r, const uint32_t *galois,
+                             const uint64_t *const *ksk, const uint64_t *const *pt, const uint64_t *b, uint64_t *uq,
+                             uint64_t *pc, hipStream_t s) {
+    if (r == 0 || r > (uint32_t)MAXROT) return hipErrorInvalidValue;
+    MatvecArgs a{};
+    a.ext = ext;
+    for (uint32_t i = 0; i < r; ++i) {
+        a.ksk[i] = ksk[i];
+        a.pt[i] = pt[i];
+        a.galois[i] = galois[i];
+    }
+    a.b = b;
+    a.pmod = c.pmod;
+    a.uq = uq;
+    a.pc = pc;
+    a.twi = c.tw_inv;
+    a.mc = c.mc;
+    a.n = c.log_n;
+    a.n1 = c.n1;
+    a.n2 = c.n2;
+    a.level = level;
+    a.L = c.L;
+    a.K = c.K;
+    a.E = level + c.K;
+    a.beta = (level + c.alpha - 1) / c.alpha;
+    a.r = r;
+    ProfScope ps(c, HKS_K_KSK, s);
+    const dim3 grid(((1u << c.n1) / ROW_LINES) * a.E);
+    switch (c.n2) {
+        case 5: hipLaunchKernelGGL((ksk_matvec_kernel<5, 8>), grid, dim3(Tile<5, ROW_LINES, false, 8>::NT), 0, s, a); break;
+        case 6: hipLaunchKernelGGL((ksk_matvec_kernel<6, 8>), grid, dim3(Tile<6, ROW_LINES, false, 8>::NT), 0, s, a); break;
+        case 7: hipLaunchKernelGGL((ksk_matvec_kernel<7, 8>), grid, dim3(Tile<7, ROW_LINES, false, 8>::NT), 0, s, a); break;
+        case 8: hipLaunchKernelGGL((ksk_matvec_kernel<8, 8>), grid, dim3(Tile<8, ROW_LINES, false, 8>::NT), 0, s, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 }  // namespace hks

@@ -158,7 +158,7 @@ int build_tables(Ctx &c) {
     // ModDown by P = prod p_k.
     std::vector<LastInv> limd(K);
     std::vector<uint64_t> convd((size_t)K * L);
-    std::vector<Shoup> pinv(L);
+    std::vector<Shoup> pinv(L), pmod(L);
     for (uint32_t k = 0; k < K; ++k) {
         uint64_t pk = c.mods[L + k], prod = 1;
         for (uint32_t kk = 0; kk < K; ++kk)
@@ -175,6 +175,7 @@ int build_tables(Ctx &c) {
         uint64_t qi = c.mods[i], P = 1;
         for (uint32_t k = 0; k < K; ++k) P = h_mulmod(P, c.mods[L + k] % qi, qi);
         pinv[i] = h_shoup(h_invmod(P, qi), qi);
+        pmod[i] = h_shoup(P, qi);
     }
 
     // Rescale at level l: divide by q_{l-1}, h = (q_{l-1} - 1) / 2.
@@ -199,6 +200,7 @@ int build_tables(Ctx &c) {
     if ((rc = upload(&c.conv_modup, convu))) return rc;
     if ((rc = upload(&c.conv_moddown, convd))) return rc;
     if ((rc = upload(&c.pinv, pinv))) return rc;
+    if ((rc = upload(&c.pmod, pmod))) return rc;
     if ((rc = upload(&c.rs_qinv, rsq))) return rc;
     if ((rc = upload(&c.rs_h, rsh))) return rc;
     return HKS_OK;
@@ -206,14 +208,14 @@ int build_tables(Ctx &c) {
 
 void free_tables(Ctx &c) {
     void *ptrs[] = {c.tw_fwd, c.tw_inv, c.mc, c.li_plain, c.li_modup, c.li_moddown, c.conv_modup,
-                    c.conv_moddown, c.pinv, c.rs_qinv, c.rs_h, c.ws};
+                    c.conv_moddown, c.pinv, c.pmod, c.rs_qinv, c.rs_h, c.ws};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     c.tw_fwd = c.tw_inv = nullptr;
     c.mc = nullptr;
     c.li_plain = c.li_modup = c.li_moddown = nullptr;
     c.conv_modup = c.conv_moddown = nullptr;
-    c.pinv = c.rs_qinv = nullptr;
+    c.pinv = c.pmod = c.rs_qinv = nullptr;
     c.rs_h = nullptr;
     c.ws = nullptr;
 }

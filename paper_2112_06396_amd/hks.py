@@ -43,7 +43,7 @@ EXPORTS = (
     "hks_create", "hks_destroy", "hks_query", "hks_ntt", "hks_intt", "hks_automorph",
     "hks_modup", "hks_ksk_inner", "hks_moddown", "hks_keyswitch", "hks_rotate", "hks_hrotate",
     "hks_batch_rotate", "hks_rescale", "hks_ptmult", "hks_mult_relin", "hks_batch_mult_relin", "hks_add",
-    "hks_expand_key_a", "hks_rotate_seeded", "hks_batch_rotate_seeded", "hks_prof_enable",
+    "hks_expand_key_a", "hks_rotate_seeded", "hks_batch_rotate_seeded", "hks_ptmatvec", "hks_prof_enable",
     "hks_prof_read",
 )
 
@@ -122,6 +122,8 @@ def lib():
                                             ctypes.POINTER(_vp), _i32, ctypes.POINTER(_vp), _vp]),
             "hks_add": (_i32, [_vp, _vp, _vp, _u32, _u32, _vp, _vp]),
             "hks_expand_key_a": (_i32, [_vp, ctypes.c_uint64, _vp, _vp]),
+            "hks_ptmatvec": (_i32, [_vp, _vp, _u32, _u32, ctypes.POINTER(_u32), ctypes.POINTER(_vp),
+                                    ctypes.POINTER(_vp), _vp, _vp]),
             "hks_rotate_seeded": (_i32, [_vp, _vp, _u32, _u32, ctypes.c_uint64, _vp, _vp, _vp]),
             "hks_batch_rotate_seeded": (_i32, [_vp, _u32, ctypes.POINTER(_vp), _u32, ctypes.POINTER(_u32), u64p,
                                                ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp]),
@@ -321,6 +323,17 @@ def hks_batch_mult_relin(ctx, ct1s, ct2s, level: int, rlks, rescale: bool, outs,
     o = (_vp * n)(*[_ptr(x) for x in outs])
     _check("hks_batch_mult_relin", lib().hks_batch_mult_relin(ctx.handle, n, a, b, level, k, 1 if rescale else 0, o,
                                                               _stream(stream)))
+
+
+def hks_ptmatvec(ctx, ct, level: int, galois, ksks, pts, ct_out, stream=None):
+    r = len(galois)
+    if len(ksks) != r or len(pts) != r:
+        raise ValueError("galois, ksks and pts must have the same length")
+    ga = (_u32 * r)(*[int(g) for g in galois])
+    ka = (_vp * r)(*[_ptr(k) for k in ksks])
+    pa = (_vp * r)(*[_ptr(p) for p in pts])
+    _check("hks_ptmatvec", lib().hks_ptmatvec(ctx.handle, _ptr(ct), level, r, ga, ka, pa, _ptr(ct_out),
+                                              _stream(stream)))
 
 
 def hks_expand_key_a(ctx, seed: int, a, stream=None):

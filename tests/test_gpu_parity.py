@@ -614,3 +614,26 @@ def test_batch_rotate_seeded_equals_oracle(name, max_batch):
     for i in range(n_ct):
         full = np.stack([O.expand_key_a(pr, seeds[i]), b_rows[i]], axis=1)
         assert np.array_equal(host(outs[i]), O.rotate(pr, cts[i], level, gals[i], full)), i
+
+
+# ------------------------------------------------------------------ PtMatVecMult with one ModDown
+
+
+@pytest.mark.parametrize("name,ks", [("n10", (1, 2, -5)), ("cfg1", (1, 3)), ("n13", (2, 7, 9, -3, 11)),
+                                     ("cfg2", tuple(range(1, 13)))])
+def test_ptmatvec_equals_oracle(name, ks):
+    """sum_i M_i * Rotate_i(ct) with the ModDown hoisted (one fused launch over
+    all rotations, one ModDown) equals the oracle's algorithm bit for bit,
+    at the top level and one with a short last digit."""
+    pr, ctx = _get(name)
+    hks = H()
+    gals = [hks.hks_galois_for_rotation(k, pr.log_n) for k in ks]
+    ksks = [_rand_ksk(pr, 800 + i) for i in range(len(ks))]
+    dk = [dev(k) for k in ksks]
+    for level in sorted({pr.L, pr.alpha + 1}):
+        g = synth.rng(810 + level)
+        ct = _rand_ct(pr, level, 811 + level)
+        pts = [synth.uniform_residues(g, pr.ext_mods(level), pr.n) for _ in ks]
+        out = hks.empty((2, level, pr.n))
+        hks.hks_ptmatvec(ctx, dev(ct), level, gals, dk, [dev(p) for p in pts], out)
+        assert np.array_equal(host(out), O.ptmatvec(pr, ct, level, gals, ksks, pts)), level
