@@ -218,6 +218,20 @@ def extras(args, ctx, hks, synth, cts, ksks, outs, gal, key_mods, n, plain_value
     res["trace_ks_per_s_graph"] = rate(lambda i: gr.replay(), plan.key_switches, 3)
     res["trace"] = {"key_switches": plan.key_switches, "rotation_keys": len(plan.rotations), "levels": "35->9",
                     "ops": len(plan.ops)}
+    del gr
+    # the same trace with each linear stage as one PtMatVecMult (ModDown hoisted)
+    hplan = trace.bootstrap_plan(35, hoisted=True)
+    hdiag = {d: synth.device_residues(pq, (), n, 100 + i) for i, d in enumerate(hplan.diagonals)}
+    hext = trace.ext_diagonals(hplan, hdiag, 35)
+    hbufs = trace.TraceBuffers(hplan, n)
+    hbufs.view("x0", 35).copy_(bufs.view("x0", 35))
+    res["trace_hoisted_ks_per_s_eager"] = rate(
+        lambda i: trace.run_plan(tctx, hplan, hbufs, hdiag, tkeys, rlk, diag_ext=hext), hplan.key_switches, 3)
+    gr = trace.capture(tctx, hplan, hbufs, hdiag, tkeys, rlk, diag_ext=hext)
+    res["trace_hoisted_ks_per_s_graph"] = rate(lambda i: gr.replay(), hplan.key_switches, 3)
+    log(f"[bench] hoisted trace: eager {res['trace_hoisted_ks_per_s_eager']:.0f} ks/s, "
+        f"graph {res['trace_hoisted_ks_per_s_graph']:.0f} ks/s")
+    del hdiag, hext, hbufs
     log(f"[bench] trace ({plan.key_switches} key-switches, L 35->9): eager {res['trace_ks_per_s_eager']:.0f} ks/s, "
         f"graph {res['trace_ks_per_s_graph']:.0f} ks/s")
     del gr, bufs, diag, tkeys, rlk

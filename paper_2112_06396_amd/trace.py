@@ -33,14 +33,17 @@ class Plan:
     out_level: int = 0
 
 
-def bootstrap_plan(top: int, counts=(12, 12, 16), strides=(1, 32, 1024), evalmod_levels: int = 20) -> Plan:
+def bootstrap_plan(top: int, counts=(12, 12, 16), strides=(1, 32, 1024), evalmod_levels: int = 20,
+                   hoisted: bool = False) -> Plan:
     """Ops (kind, ...) over ciphertext buffers named by strings:
       ("hrotate", src, level, [k...], [dst...])
       ("ptmult", src, diag, level, dst)
       ("add", a, b, level, dst)
+      ("ptmatvec", src, level, [k...], [diag...], dst)   sum_i M_i Rotate_k_i(src), one ModDown
       ("rescale", src, level, dst)        -> level - 1
       ("mult", a, b, level, dst)          -> level - 1 (relinearized, rescaled)
-    """
+    With `hoisted`, each linear stage is one ptmatvec (Sec. 5.2) instead of
+    an HRotate followed by PtMult and Add per rotation."""
     p = Plan(top=top)
     level, x = top, "x0"
     p.buffers.add(x)
@@ -51,20 +54,24 @@ def bootstrap_plan(top: int, counts=(12, 12, 16), strides=(1, 32, 1024), evalmod
         for si, (cnt, stride) in enumerate(zip(counts, strides)):
             ks = [sign * stride * (i + 1) for i in range(cnt)]
             rs = [f"r{i}" for i in range(cnt)]
-            p.ops.append(("hrotate", x, level, ks, rs))
+            ds = [f"{stage_id}{si}_{i}" for i in range(cnt)]
+            p.diagonals.extend(ds)
             p.key_switches += cnt
             for k in ks:
                 if k not in p.rotations:
                     p.rotations.append(k)
-            for i in range(cnt):
-                d = f"{stage_id}{si}_{i}"
-                p.diagonals.append(d)
-                p.ops.append(("ptmult", rs[i], d, level, "acc" if i == 0 else "t"))
-                if i:
-                    p.ops.append(("add", "acc", "t", level, "acc"))
+            if hoisted:
+                p.ops.append(("ptmatvec", x, level, ks, ds, "acc"))
+            else:
+                p.ops.append(("hrotate", x, level, ks, rs))
+                for i in range(cnt):
+                    p.ops.append(("ptmult", rs[i], ds[i], level, "acc" if i == 0 else "t"))
+                    if i:
+                        p.ops.append(("add", "acc", "t", level, "acc"))
+                p.buffers.update(rs + ["t"])
             y = next(nxt)
             p.ops.append(("rescale", "acc", level, y))
-            p.buffers.update(rs + ["acc", "t", y])
+            p.buffers.update(["acc", y])
             x, level = y, level - 1
 
     linear_stage(+1, "c")
@@ -94,14 +101,36 @@ class TraceBuffers:
         return self.ct[name][: 2 * level * self.n].view(2, level, self.n)
 
 
-def run_plan(ctx, plan: Plan, bufs: TraceBuffers, diag, keys, rlk, stream=None):
+def ext_diagonals(plan: Plan, diag, L: int) -> dict:
+    """For the ptmatvec ops: (diagonal, level) -> the diagonal over
+    Q_level U P, [level + K][N] contiguous, from diag[name] given over all
+    L + K primes (q_0..q_{L-1}, p_0..p_{K-1})."""
+    import torch
+    out = {}
+    for op in plan.ops:
+        if op[0] == "ptmatvec":
+            _, _, level, _, ds, _ = op
+            for d in ds:
+                t = diag[d]
+                out[(d, level)] = torch.cat([t[:level], t[L:]]).contiguous()
+    return out
+
+
+def run_plan(ctx, plan: Plan, bufs: TraceBuffers, diag, keys, rlk, stream=None, diag_ext=None):
     """Issue every op of the plan on `stream` (default: torch's current
     stream, which is the capture stream under torch.cuda.graph).  diag maps
-    a diagonal name to a [>= level][N] device tensor, keys maps a rotation
-    index to its switching key, rlk is the relinearization key."""
+    a diagonal name to a [>= level][N] device tensor (over all L + K primes
+    for a hoisted plan, with diag_ext from ext_diagonals), keys maps a
+    rotation index to its switching key, rlk is the relinearization key."""
     n = bufs.n
     for op in plan.ops:
         kind = op[0]
+        if kind == "ptmatvec":
+            _, src, level, ks, ds, dst = op
+            gals = [hks.hks_galois_for_rotation(k, ctx.log_n) for k in ks]
+            hks.hks_ptmatvec(ctx, bufs.view(src, level), level, gals, [keys[k] for k in ks],
+                             [diag_ext[(d, level)] for d in ds], bufs.view(dst, level), stream)
+            continue
         if kind == "hrotate":
             _, src, level, ks, dsts = op
             gals = [hks.hks_galois_for_rotation(k, ctx.log_n) for k in ks]
@@ -125,11 +154,11 @@ def run_plan(ctx, plan: Plan, bufs: TraceBuffers, diag, keys, rlk, stream=None):
     return bufs.view(plan.out, plan.out_level)
 
 
-def capture(ctx, plan: Plan, bufs: TraceBuffers, diag, keys, rlk) -> torch.cuda.CUDAGraph:
+def capture(ctx, plan: Plan, bufs: TraceBuffers, diag, keys, rlk, diag_ext=None) -> torch.cuda.CUDAGraph:
     """The whole plan as one hipGraph (replay with g.replay() on the current
     stream).  The library allocates nothing and sets no memory inside calls,
     so every node is a kernel launch."""
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g):
-        run_plan(ctx, plan, bufs, diag, keys, rlk)
+        run_plan(ctx, plan, bufs, diag, keys, rlk, diag_ext=diag_ext)
     return g

@@ -418,6 +418,11 @@ def _oracle_plan(pr, plan, x0, diag, keys, rlk):
         elif kind == "ptmult":
             _, src, d, level, dst = op
             bufs[dst] = O.ptmult(pr, bufs[src], diag[d][:level], level, False)
+        elif kind == "ptmatvec":
+            _, src, level, ks, ds, dst = op
+            gals = [pow(5, -k, 2 * pr.n) for k in ks]
+            pts = [np.concatenate([diag[d][:level], diag[d][pr.L:]]) for d in ds]
+            bufs[dst] = O.ptmatvec(pr, bufs[src], level, gals, [keys[k] for k in ks], pts)
         elif kind == "add":
             _, a, b, level, dst = op
             bufs[dst] = np.stack([O.add_vec(bufs[a][i], bufs[b][i], pr.log_n, pr.q[:level]) for i in range(2)])
@@ -463,6 +468,38 @@ def test_trace_eager_and_graph_replays_match_oracle():
                 t.zero_()
         hks.hks_rotate(ctx, other, pr.L, hks.hks_galois_for_rotation(3, pr.log_n), dkeys[plan.rotations[0]],
                        other_out)
+        torch.cuda.synchronize()
+        gr.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(host(bufs.view(plan.out, plan.out_level)), ref), rep
+
+
+def test_hoisted_trace_eager_and_graph_match_oracle():
+    """The same small trace with every linear stage as one PtMatVecMult with
+    the ModDown hoisted (Sec. 5.2): eager and two graph replays equal the
+    oracle's run of the same plan."""
+    from paper_2112_06396_amd import trace
+    pr, ctx = _get((12, 10, 4, 3), 4)
+    plan = trace.bootstrap_plan(pr.L, counts=(2, 2, 3), strides=(1, 4, 16), evalmod_levels=3, hoisted=True)
+    g = synth.rng(210)
+    x0 = _rand_ct(pr, pr.L, 211)
+    diag = {d: synth.uniform_residues(g, pr.key_mods(), pr.n) for d in plan.diagonals}
+    keys = {k: _rand_ksk(pr, 330 + i) for i, k in enumerate(plan.rotations)}
+    rlk = _rand_ksk(pr, 329)
+    ref = _oracle_plan(pr, plan, x0, diag, keys, rlk)
+    bufs = trace.TraceBuffers(plan, pr.n)
+    bufs.view("x0", pr.L).copy_(dev(x0))
+    ddiag = {d: dev(v) for d, v in diag.items()}
+    dext = trace.ext_diagonals(plan, ddiag, pr.L)
+    dkeys = {k: dev(v) for k, v in keys.items()}
+    drlk = dev(rlk)
+    out = trace.run_plan(ctx, plan, bufs, ddiag, dkeys, drlk, diag_ext=dext)
+    assert np.array_equal(host(out), ref)
+    gr = trace.capture(ctx, plan, bufs, ddiag, dkeys, drlk, diag_ext=dext)
+    for rep in range(2):
+        for name, t in bufs.ct.items():
+            if name != "x0":
+                t.zero_()
         torch.cuda.synchronize()
         gr.replay()
         torch.cuda.synchronize()
