@@ -537,7 +537,9 @@ ksk_rows_kernel(const KskRowArgs a) {
         x = blockIdx.x / a.nb;
     }
     const uint32_t tiles = (1u << a.n1) / ROW_LINES;
-    const uint32_t tgt = x / tiles;
+    // special-prime limbs first: their blocks also run ModDown's inverse row
+    // passes, so they go out in the first wave of blocks rather than the tail
+    const uint32_t tgt = (x / tiles + a.level) % a.E;
     const uint32_t tile = x % tiles;
     const uint32_t N = 1u << a.n;
     const uint64_t *ext = a.ext + b * a.ext_bstride;
@@ -716,7 +718,7 @@ __global__ void __launch_bounds__((Tile<LOGS, ROW_LINES, false, E>::NT)) ksk_mat
                   "E consecutive slots per thread, the inverse row pass's input layout");
     __shared__ uint64_t lds[TL::WORDS];
     const uint32_t tiles = (1u << a.n1) / ROW_LINES;
-    const uint32_t tgt = blockIdx.x / tiles;
+    const uint32_t tgt = (blockIdx.x / tiles + a.level) % a.E;  // special-prime limbs first
     const uint32_t tile = blockIdx.x % tiles;
     const uint32_t N = 1u << a.n;
     const uint32_t mod = tgt < a.level ? tgt : a.L + (tgt - a.level);
