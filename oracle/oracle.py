@@ -77,6 +77,7 @@ def lib():
             "oref_expand_key_a": (None, [P, u64, _u64p]),
             "oref_ptmatvec": (i32, [P, _u64p, u32, u32, ctypes.POINTER(u32), ctypes.POINTER(_u64p),
                                     ctypes.POINTER(_u64p), _u64p]),
+            "oref_new_mult": (i32, [P, _u64p, _u64p, u32, _u64p, _u64p]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -245,6 +246,15 @@ def ptmatvec(pr: Params, ct: np.ndarray, level: int, gs, ksks, pts) -> np.ndarra
     ka = (_u64p * r)(*[_p(k) for k in ksks])
     pa = (_u64p * r)(*[_p(p) for p in pts])
     _call("oref_ptmatvec", pr, _p(ct), level, r, ga, ka, pa, _p(out))
+    return out
+
+
+def new_mult(pr: Params, ct1, ct2, level: int, rlk) -> np.ndarray:
+    """Mult with the key-switch ModDown and Rescale merged into one ModDown by
+    P q_(level-1) (NewMult); output [2][level - 1][N]."""
+    ct1, ct2, rlk = _u64(ct1), _u64(ct2), _u64(rlk)
+    out = np.zeros((2, level - 1, pr.n), dtype=np.uint64)
+    _call("oref_new_mult", pr, _p(ct1), _p(ct2), level, _p(rlk), _p(out))
     return out
 
 

@@ -712,3 +712,95 @@ int oref_ptmatvec(const oref_params *pr, const uint64_t *ct, uint32_t level, uin
     free(ext);
     return rc;
 }
+
+/* ---------------------------------------------------------------------------
+ * NewMult (Sec. 5.1, Algorithm "NewMult"): Mult with its two ModDowns (the
+ * key-switch's division by P and Rescale's division by q_(level-1)) merged.
+ * The tensor terms b3, c3 are lifted with PModUp (times P on the q limbs, 0
+ * on the P limbs) and added to the KSKInnerProd outputs before one ModDown
+ * that divides by S = P q_(level-1): the special limbs are p_0..p_(K-1) and
+ * q_(level-1), y_s = iNTT(x_s) [(S/s)^-1]_s, z_i = NTT(sum_s y_s [S/s]_(q_i)),
+ * out_i = (x_i - z_i) [S^-1]_(q_i) for i < level - 1.  As for ModDown by P,
+ * the conversion is uncorrected (no rounding offset).  Output at level - 1.
+ * ------------------------------------------------------------------------- */
+static void moddown_s(const oref_params *pr, const uint64_t *x, uint32_t level, uint64_t *y) {
+    size_t n = (size_t)1 << pr->log_n;
+    uint32_t K = pr->K, ns = K + 1, lo = level - 1;
+    uint64_t *sm = (uint64_t *)malloc(sizeof(uint64_t) * ns);  /* special moduli */
+    for (uint32_t k = 0; k < K; k++) sm[k] = pr->p[k];
+    sm[K] = pr->q[lo];
+    uint64_t *ys = (uint64_t *)malloc(sizeof(uint64_t) * n * ns);
+    memcpy(ys, x + (size_t)level * n, sizeof(uint64_t) * n * K);     /* P limbs */
+    memcpy(ys + (size_t)K * n, x + (size_t)lo * n, sizeof(uint64_t) * n);  /* q_(level-1) */
+    for (uint32_t k = 0; k < ns; k++) {
+        uint64_t m = sm[k], prod = 1;
+        intt_limb(ys + (size_t)k * n, pr->log_n, m);
+        for (uint32_t kk = 0; kk < ns; kk++) if (kk != k) prod = mulmod(prod, sm[kk] % m, m);
+        uint64_t inv = invmod(prod, m);
+        for (size_t c = 0; c < n; c++) ys[k * n + c] = mulmod(ys[k * n + c], inv, m);
+    }
+    uint64_t *z = (uint64_t *)malloc(sizeof(uint64_t) * n);
+    for (uint32_t i = 0; i < lo; i++) {
+        uint64_t qi = pr->q[i], smod = 1;
+        uint64_t cst[64];
+        for (uint32_t k = 0; k < ns; k++) {
+            uint64_t prod = 1;
+            for (uint32_t kk = 0; kk < ns; kk++) if (kk != k) prod = mulmod(prod, sm[kk] % qi, qi);
+            cst[k] = prod;
+            smod = mulmod(smod, sm[k] % qi, qi);
+        }
+        uint64_t sinv = invmod(smod, qi);
+        for (size_t c = 0; c < n; c++) {
+            u128 acc = 0;
+            for (uint32_t k = 0; k < ns; k++) acc += (u128)ys[k * n + c] * cst[k];
+            z[c] = (uint64_t)(acc % qi);
+        }
+        ntt_limb(z, pr->log_n, qi);
+        for (size_t c = 0; c < n; c++) y[i * n + c] = mulmod(submod(x[i * n + c], z[c], qi), sinv, qi);
+    }
+    free(z);
+    free(ys);
+    free(sm);
+}
+
+int oref_new_mult(const oref_params *pr, const uint64_t *ct1, const uint64_t *ct2, uint32_t level,
+                  const uint64_t *rlk, uint64_t *out) {
+    if (check(pr, level) || level < 2 || pr->K + 1 > 64) return -1;
+    size_t n = (size_t)1 << pr->log_n;
+    size_t pl = (size_t)level * n;
+    uint32_t next = level + pr->K, beta = beta_of(pr, level);
+    if (beta > pr->dnum) return -1;
+    uint64_t *a3 = (uint64_t *)malloc(sizeof(uint64_t) * pl);
+    uint64_t *bc = (uint64_t *)malloc(sizeof(uint64_t) * pl * 2);
+    uint64_t *ext = (uint64_t *)malloc(sizeof(uint64_t) * n * next * beta);
+    uint64_t *hat = (uint64_t *)malloc(sizeof(uint64_t) * n * next * 2);
+    for (uint32_t i = 0; i < level; i++) {
+        uint64_t q = pr->q[i];
+        for (size_t c = 0; c < n; c++) {
+            size_t o = i * n + c;
+            uint64_t a1 = ct1[o], b1 = ct1[pl + o], a2 = ct2[o], b2 = ct2[pl + o];
+            a3[o] = mulmod(a1, a2, q);
+            bc[o] = addmod(mulmod(a1, b2, q), mulmod(a2, b1, q), q);
+            bc[pl + o] = mulmod(b1, b2, q);
+        }
+    }
+    int rc = oref_modup(pr, a3, level, ext);
+    if (!rc) rc = oref_ksk_inner(pr, ext, level, rlk, hat);
+    if (!rc) {
+        /* PModUp(b3), PModUp(c3) added on the q limbs */
+        for (uint32_t row = 0; row < 2; row++)
+            for (uint32_t i = 0; i < level; i++) {
+                uint64_t q = pr->q[i], pmod = 1;
+                for (uint32_t k = 0; k < pr->K; k++) pmod = mulmod(pmod, pr->p[k] % q, q);
+                uint64_t *h = hat + ((size_t)row * next + i) * n;
+                for (size_t c = 0; c < n; c++) h[c] = addmod(h[c], mulmod(pmod, bc[row * pl + i * n + c], q), q);
+            }
+        moddown_s(pr, hat, level, out);
+        moddown_s(pr, hat + (size_t)next * n, level, out + (size_t)(level - 1) * n);
+    }
+    free(hat);
+    free(ext);
+    free(bc);
+    free(a3);
+    return rc;
+}

@@ -460,3 +460,42 @@ def test_ptmatvec_decrypts_to_sum_of_rotated_products(cfg):
     dec_bad = O.decrypt_coef(pr, s, O.ptmatvec(pr, ct, level, gals, keys, bad), level)
     assert O.centered_small(O.sub_vec(dec_bad, O.lift_signed(want, pr.log_n, mods), pr.log_n, mods), mods,
                             bound) is None
+
+
+# ------------------------------------------------------------------ NewMult (ModDown merged with Rescale)
+
+
+def _crt_centered(res, mods):
+    M = B.prod(mods)
+    out = []
+    for c in range(res.shape[1]):
+        x = B.crt([int(res[i, c]) for i in range(len(mods))], mods)
+        out.append(x - M if x > M // 2 else x)
+    return out
+
+
+def test_new_mult_matches_mult_then_division_by_q_last():
+    """NewMult divides by P q_(level-1) in one ModDown; decrypted, it equals
+    Mult's decryption divided by q_(level-1) up to the merged ModDown's error
+    (below (K+1)(h_s+1) for the uncorrected conversion) plus rounding."""
+    pr, g, s = _setup(8, 5, 2, 3, 4242)
+    level = 5
+    rlk = O.relin_key(pr, s, g)
+    m1 = synth.small_uniform(g, pr.n, 1 << 36)
+    m2 = synth.small_uniform(g, pr.n, 1 << 36)
+    c1 = O.encrypt(pr, s, m1, level, g)
+    c2 = O.encrypt(pr, s, m2, level, g)
+    plain = O.mult_relin(pr, c1, c2, level, rlk, False)
+    newm = O.new_mult(pr, c1, c2, level, rlk)
+    assert newm.shape == (2, level - 1, pr.n)
+    D = _crt_centered(O.decrypt_coef(pr, s, plain, level), [int(q) for q in pr.q[:level]])
+    E = _crt_centered(O.decrypt_coef(pr, s, newm, level - 1), [int(q) for q in pr.q[: level - 1]])
+    ql = int(pr.q[level - 1])
+    hs = int(np.count_nonzero(s))
+    bound = (pr.K + 1) * (hs + 1) + O.ks_noise_bound(pr, level, s) // ql + 2
+    assert max(abs(e - d / ql) for e, d in zip(E, D)) <= bound
+    assert max(abs(d) for d in D) > (1 << 70)  # the product is large: the division is exercised
+    # and it equals Mult + Rescale (Algorithm 2) to within both errors
+    R = _crt_centered(O.decrypt_coef(pr, s, O.rescale(pr, plain, level), level - 1),
+                      [int(q) for q in pr.q[: level - 1]])
+    assert max(abs(e - r) for e, r in zip(E, R)) <= bound + pr.K * (hs + 1) + 2
