@@ -236,6 +236,19 @@ int hks_batch_mult_relin(hks_ctx *ctx, uint32_t n, const uint64_t *const *ct1, c
                          uint32_t level, const uint64_t *const *rlk, int rescale, uint64_t *const *ct_out,
                          void *stream);
 
+/* NewMult (Sec. 5.1): Mult with rescale = 1 where the key-switch ModDown
+ * and the Rescale are one ModDown by S = P q_{level-1}.  The KSKInnerProd
+ * kernel adds P b3 and P c3 to (u, v) on the q limbs (b3, c3 as in
+ * hks_mult_relin), the q_{level-1} limb joins the K special limbs, and the
+ * ModDown basis-converts those K+1 limbs, so the output ct_out
+ * [2][level-1][N] is floor((P (b3, c3) + (u, v)) / S) with the uncorrected
+ * conversion's small error.  Its bits differ from hks_mult_relin(..., 1, ...)
+ * by a few units (the two roundings become one); the difference decrypts
+ * within the scheme's error.  level >= 2; ct_out must not alias ct1 or ct2.
+ * HKS_EUNSUPPORTED when K + 1 > 16. */
+int hks_new_mult(hks_ctx *ctx, const uint64_t *ct1, const uint64_t *ct2, uint32_t level, const uint64_t *rlk,
+                 uint64_t *ct_out, void *stream);
+
 /* Add (Table "CKKS FHE API"): out = x + y limb-wise for n_poly (1..3)
  * polynomials of level limbs each, [n_poly][level][N]; out may be x or y
  * (elementwise, in place allowed). */

@@ -115,25 +115,47 @@ int do_modup_own(Ctx &c, const uint64_t *a, uint32_t level, uint32_t galois, uin
     return HKS_OK;
 }
 
-// ModDown of np polynomials whose P limbs went through the inverse row pass
-// into ws_p (polynomial p at ws_p + p*K*N): inverse column pass scaled by
-// N^-1 [(P/p_k)^-1]_{p_k}; NewLimb into the q limbs (ws_z + p*L*N); forward
-// column pass; row pass + (u - z) P^-1 (+ add), with u, the output, the
-// addend and its automorph per polynomial in `epi`.
-int do_moddown_tail(Ctx &c, uint32_t level, uint32_t np, BatchIo epi, hipStream_t s) {
+// The special limbs a ModDown divides by: the K primes of P, or for NewMult at
+// level l (divide by S = P q_(l-1)) also q_(l-1), stored after them.
+struct ModDownSpec {
+    uint32_t ns;          // special limbs per polynomial
+    uint32_t extra_mod;   // modulus index of the (K+1)-th special limb
+    const LastInv *li;    // [ns] folded scales (S/s)^-1 mod s
+    const uint64_t *conv; // [targets][ns] of [S/s]_{q_i}, split 25/25
+    const Shoup *sinv;    // [targets] S^-1 mod q_i
+};
+
+ModDownSpec spec_by_p(const Ctx &c) { return ModDownSpec{c.K, 0, c.li_moddown, c.conv_moddown, c.pinv}; }
+
+ModDownSpec spec_newmult(const Ctx &c, uint32_t level) {
+    return ModDownSpec{c.K + 1, level - 1, c.li_nm + (size_t)level * (c.K + 1), c.conv_nm + c.conv_nm_off[level],
+                       c.sinv_nm + (size_t)level * c.L};
+}
+
+// ModDown of np polynomials whose special limbs went through the inverse row
+// pass into ws_p (polynomial p at ws_p + p*ns*N): inverse column pass scaled
+// by N^-1 [(S/s)^-1]_s; NewLimb into the `level` output q limbs (ws_z +
+// p*L*N); forward column pass; row pass + (u - z) S^-1 (+ add), with u, the
+// output, the addend and its automorph per polynomial in `epi`.
+int do_moddown_tail(Ctx &c, uint32_t level, uint32_t np, BatchIo epi, hipStream_t s, const ModDownSpec &sp) {
     const uint32_t N = c.n, K = c.K, L = c.L;
-    const size_t pst = (size_t)K * N, zst = (size_t)L * N;
+    const size_t pst = (size_t)sp.ns * N, zst = (size_t)L * N;
     Lists pl, ql;
     for (uint32_t k = 0; k < K; ++k) pl.add(k, k, L + k, k);
+    if (sp.ns > K) pl.add(K, K, sp.extra_mod, K);
     for (uint32_t i = 0; i < level; ++i) ql.add(i, i, i, i);
     const BatchIo pio = strided_io(c.ws_p, pst, c.ws_p, pst, np);
-    HKS_TRY(pl.run([&](const LimbMap &m) { return launch_ntt_inv_cols(c, m, pio, c.li_moddown, np, s); }));
-    HKS_TRY(launch_conv_moddown(c, c.ws_p, level, c.ws_z, np, pst, zst, s));
+    HKS_TRY(pl.run([&](const LimbMap &m) { return launch_ntt_inv_cols(c, m, pio, sp.li, np, s); }));
+    HKS_TRY(launch_conv_moddown(c, c.ws_p, level, c.ws_z, np, pst, zst, sp.conv, sp.ns, s));
     const BatchIo zio = strided_io(c.ws_z, zst, c.ws_z, zst, np);
     HKS_TRY(ql.run([&](const LimbMap &m) { return launch_ntt_fwd_cols(c, m, zio, np, s); }));
     for (uint32_t p = 0; p < np; ++p) epi.in[p] = c.ws_z + p * zst;
-    HKS_TRY(ql.run([&](const LimbMap &m) { return launch_rows_mdepi(c, m, epi, np, s); }));
+    HKS_TRY(ql.run([&](const LimbMap &m) { return launch_rows_mdepi(c, m, epi, np, sp.sinv, s); }));
     return HKS_OK;
+}
+
+int do_moddown_tail(Ctx &c, uint32_t level, uint32_t np, BatchIo epi, hipStream_t s) {
+    return do_moddown_tail(c, level, np, epi, s, spec_by_p(c));
 }
 
 // One key-switch of a batch: d (level limbs, gathered through galois) with
@@ -147,6 +169,7 @@ struct KsJob {
     const uint64_t *add0, *add1;
     uint64_t seed = 0;
     bool seeded = false;
+    const uint64_t *newmult_bc = nullptr;  // NewMult: b3, c3 ([2][level][N]); out at level - 1
 };
 
 // KeySwitch of nb <= min(batch_cap, MAXCT) jobs in shared launches (9 per
@@ -158,27 +181,33 @@ int do_keyswitch_step(Ctx &c, const KsJob *jobs, uint32_t nb, uint32_t level, hi
     uint32_t g[MAXCT];
     KskBatch kb{};
     BatchIo epi{};
+    // one kind per step (the entry points never mix them)
+    const bool nm = jobs[0].newmult_bc != nullptr;
+    const uint32_t out_level = nm ? level - 1 : level;
     for (uint32_t b = 0; b < nb; ++b) {
         d[b] = jobs[b].d;
         g[b] = jobs[b].galois;
         kb.direct[b] = jobs[b].d;
         kb.ksk[b] = jobs[b].ksk;
+        kb.addp[b] = jobs[b].newmult_bc;
         kb.seed[b] = jobs[b].seed;
         kb.galois[b] = jobs[b].galois;
-        kb.seeded = jobs[b].seeded ? 1u : 0u;  // one kind per step (the entry points never mix them)
+        kb.seeded = jobs[b].seeded ? 1u : 0u;
+        kb.newmult = nm ? 1u : 0u;
         for (uint32_t poly = 0; poly < 2; ++poly) {
             const uint32_t p = 2 * b + poly;
             epi.uq[p] = c.ws_uv + b * c.st_uv() + poly * pl;
-            epi.out[p] = jobs[b].out + poly * pl;
+            epi.out[p] = jobs[b].out + poly * (size_t)out_level * c.n;
             epi.add[p] = poly ? jobs[b].add1 : jobs[b].add0;
             epi.add_galois[p] = jobs[b].galois;
         }
     }
     int rc = do_modup_new(c, d, g, nb, level, c.ws_ext, c.st_ext(), s, true);
     if (rc) return rc;
+    const ModDownSpec sp = nm ? spec_newmult(c, level) : spec_by_p(c);
     HKS_TRY(launch_ksk_rows(c, kb, nb, c.ws_ext, c.st_ext(), true, 0, 0, level, c.ws_uv, c.st_uv(), c.ws_p,
-                            c.st_p(), s));
-    return do_moddown_tail(c, level, 2 * nb, epi, s);
+                            (size_t)2 * sp.ns * c.n, s));
+    return do_moddown_tail(c, out_level, 2 * nb, epi, s, sp);
 }
 
 int do_keyswitch_jobs(Ctx &c, const KsJob *jobs, uint32_t n, uint32_t level, hipStream_t s) {
@@ -505,7 +534,7 @@ int hks_hrotate(hks_ctx *h, const uint64_t *ct, uint32_t level, uint32_t r, cons
             }
         }
         HKS_TRY(launch_ksk_rows(c, kb, nb, c.ws_ext, 0, false, (size_t)E * N, 1, level, c.ws_uv, c.st_uv(), c.ws_p,
-                                c.st_p(), s));
+                                (size_t)2 * c.K * N, s));
         rc = do_moddown_tail(c, level, 2 * nb, epi, s);
         if (rc) return rc;
     }
@@ -644,6 +673,38 @@ int do_mult_relin(Ctx &c, uint32_t n, const uint64_t *const *ct1, const uint64_t
         }
     }
     return HKS_OK;
+}
+
+// NewMult (Sec. 5.1) of n pairs at one level in steps of batch_cap: tensor
+// products into the workspace slots, then one batched key-switch whose
+// kernel adds P b3 / P c3 and whose ModDown divides by P q_(level-1).
+int do_new_mult(Ctx &c, uint32_t n, const uint64_t *const *ct1, const uint64_t *const *ct2, uint32_t level,
+                const uint64_t *const *rlk, uint64_t *const *out, hipStream_t s) {
+    const uint32_t step = std::min<uint32_t>(c.batch_cap, MAXCT);
+    for (uint32_t i0 = 0; i0 < n; i0 += step) {
+        const uint32_t nb = std::min(step, n - i0);
+        KsJob jobs[MAXCT];
+        for (uint32_t b = 0; b < nb; ++b) {
+            uint64_t *t = c.ws_t + b * c.st_t();
+            HKS_TRY(launch_tensor(c, ct1[i0 + b], ct2[i0 + b], t, level, s));
+            jobs[b] = KsJob{t, 1, rlk[i0 + b], out[i0 + b], nullptr, nullptr};
+            jobs[b].newmult_bc = t + (size_t)level * c.n;
+        }
+        int rc = do_keyswitch_step(c, jobs, nb, level, s);
+        if (rc) return rc;
+    }
+    return HKS_OK;
+}
+
+int hks_new_mult(hks_ctx *h, const uint64_t *ct1, const uint64_t *ct2, uint32_t level, const uint64_t *rlk,
+                 uint64_t *ct_out, void *stream) {
+    GUARD_BEGIN
+    if (!h || !ct1 || !ct2 || !rlk || !ct_out || !aligned(ct1) || !aligned(ct2) || !aligned(rlk) ||
+        !aligned(ct_out) || level < 2 || level > h->c.L || ct_out == ct1 || ct_out == ct2)
+        return HKS_EINVAL;
+    if (h->c.K + 1 > 16) return HKS_EUNSUPPORTED;
+    return do_new_mult(h->c, 1, &ct1, &ct2, level, &rlk, &ct_out, (hipStream_t)stream);
+    GUARD_END
 }
 
 int hks_mult_relin(hks_ctx *h, const uint64_t *ct1, const uint64_t *ct2, uint32_t level, const uint64_t *rlk,

@@ -90,6 +90,11 @@ struct Ctx {
     uint64_t *conv_modup = nullptr;  // per level: [beta][l+K][alpha] of [Qt_j/q_i]_t (row j*E+t), split 25/25
     std::vector<size_t> conv_modup_off;  // [L+1]
     uint64_t *conv_moddown = nullptr;  // [L][K]: [P/p_k]_{q_i} (row i), split 25/25
+    // ModDown by S = P q_(l-1) (NewMult at level l): special limbs p_0..p_(K-1), q_(l-1)
+    LastInv *li_nm = nullptr;          // [L+1][K+1]: scale (S/s)^-1 mod s
+    uint64_t *conv_nm = nullptr;       // per level: [l-1][K+1] of [S/s]_{q_i}, split 25/25
+    std::vector<size_t> conv_nm_off;   // [L+1]
+    Shoup *sinv_nm = nullptr;          // [L+1][L]: S^-1 mod q_i
     Shoup *pinv = nullptr;             // [L]: P^-1 mod q_i
     Shoup *pmod = nullptr;             // [L]: P mod q_i
     Shoup *rs_qinv = nullptr;          // [L+1][L]: q_{l-1}^-1 mod q_i
@@ -113,7 +118,7 @@ struct Ctx {
     size_t st_y() const { return (size_t)L * n; }
     size_t st_ext() const { return (size_t)dnum * M * n; }
     size_t st_uv() const { return (size_t)2 * M * n; }
-    size_t st_p() const { return (size_t)2 * K * n; }
+    size_t st_p() const { return (size_t)2 * (K + 1) * n; }
     size_t st_z() const { return (size_t)2 * L * n; }
     size_t st_rot() const { return (size_t)2 * L * n; }
     size_t st_t() const { return (size_t)3 * L * n; }
@@ -164,16 +169,19 @@ hipError_t launch_ntt_inv_cols(const Ctx &c, const LimbMap &m, const BatchIo &io
                                uint32_t batch, hipStream_t s);
 // Forward row pass of the ModDown correction z (io.in) followed by
 // out = (u - z) * P^-1 (+ io.add gathered through io.add_galois).
-hipError_t launch_rows_mdepi(const Ctx &c, const LimbMap &m, const BatchIo &io, uint32_t batch, hipStream_t s);
+hipError_t launch_rows_mdepi(const Ctx &c, const LimbMap &m, const BatchIo &io, uint32_t batch, const Shoup *pinv,
+                             hipStream_t s);
 // NewLimb of every digit of the coefficient-form y [level][N] into the other
 // limbs of Q_level U P: ext[j][t] (coefficient form, canonical) for t outside
 // digit j; `batch` polynomials at strides y_bstride / ext_bstride.
 hipError_t launch_conv_modup(const Ctx &c, const uint64_t *y, uint32_t level, uint64_t *ext, uint32_t batch,
                              size_t y_bstride, size_t ext_bstride, hipStream_t s);
-// NewLimb of ModDown: the K coefficient-form P limbs p [K][N] (scaled by
-// [(P/p_k)^-1]) into the level q limbs z [level][N], for `batch` polynomials.
-hipError_t launch_conv_moddown(const Ctx &c, const uint64_t *p, uint32_t level, uint64_t *z, uint32_t batch,
-                               size_t p_bstride, size_t z_bstride, hipStream_t s);
+// NewLimb of ModDown: the ns coefficient-form special limbs p [ns][N] (scaled
+// by [(S/s)^-1]) into the nt q limbs z [nt][N] with constants table [nt][ns]
+// of [S/s]_{q_i}, for `batch` polynomials.
+hipError_t launch_conv_moddown(const Ctx &c, const uint64_t *p, uint32_t nt, uint64_t *z, uint32_t batch,
+                               size_t p_bstride, size_t z_bstride, const uint64_t *table, uint32_t ns,
+                               hipStream_t s);
 // KSKInnerProd of `nb` ciphertexts per target limb and row tile (+ ModDown's
 // inverse row pass for the P limbs).  Entry b: converted limb t of digit j
 // at ext + b*ext_bstride + (j*E + t)*N, after the forward column pass only
@@ -183,16 +191,22 @@ hipError_t launch_conv_moddown(const Ctx &c, const uint64_t *p, uint32_t level, 
 // ([2][level][N]), P limbs to pc + b*pc_bstride ([2][K][N]).
 // With `seeded`, ksk[b] holds only the rows b_j ([dnum][L+K][N]) and the
 // rows a_j are regenerated from seed[b] (Philox4x32-10, see seeded_key_a).
+// With `newmult` (NewMult): P b3 and P c3 (b3 at addp[b], c3 at addp[b] +
+// level N) are added to u and v on the q limbs, and q_(level-1) joins the
+// special limbs (inverse row pass, stored after the P limbs).
 struct KskBatch {
     const uint64_t *direct[MAXCT];
     const uint64_t *ksk[MAXCT];
+    const uint64_t *addp[MAXCT];
     uint64_t seed[MAXCT];
     uint32_t galois[MAXCT];
     uint32_t seeded;
+    uint32_t newmult;
 };
 hipError_t launch_ksk_rows(const Ctx &c, const KskBatch &kb, uint32_t nb, const uint64_t *ext, size_t ext_bstride,
                            bool rowpass, size_t dstride, uint32_t all_direct, uint32_t level, uint64_t *uq,
                            size_t uq_bstride, uint64_t *pc, size_t pc_bstride, hipStream_t s);
+// (the special limbs of one polynomial in pc: K, or K + 1 with newmult)
 // PtMatVecMult sums over Q_level U P (ModUp'd digits of a in ext, evaluation
 // form, [beta][level+K][N]): q limbs into uq [2][level][N], P limbs after
 // ModDown's inverse row pass into pc [2][K][N].  r <= MAXROT.

@@ -140,23 +140,24 @@ hipError_t launch_conv_modup(const Ctx &c, const uint64_t *y, uint32_t level, ui
     return launch_conv_t<true>(a, c.alpha, dim3((c.n + 255) / 256, beta, batch), s);
 }
 
-hipError_t launch_conv_moddown(const Ctx &c, const uint64_t *p, uint32_t level, uint64_t *z, uint32_t batch,
-                               size_t p_bstride, size_t z_bstride, hipStream_t s) {
+hipError_t launch_conv_moddown(const Ctx &c, const uint64_t *p, uint32_t nt, uint64_t *z, uint32_t batch,
+                               size_t p_bstride, size_t z_bstride, const uint64_t *table, uint32_t ns,
+                               hipStream_t s) {
     if (batch == 0) return hipSuccess;
     ConvArgs a{};
     a.in = p;
     a.out = z;
-    a.conv = c.conv_moddown;
+    a.conv = table;
     a.mc = c.mc;
     a.in_bstride = p_bstride;
     a.out_bstride = z_bstride;
     a.n = c.log_n;
-    a.level = level;
+    a.level = nt;  // targets q_0..q_{nt-1}
     a.L = c.L;
-    a.K = c.K;
+    a.K = ns;      // sources: the ns special limbs
     a.alpha = c.alpha;
     ProfScope ps(c, HKS_K_CONV, s);
-    return launch_conv_t<false>(a, c.K, dim3((c.n + 255) / 256, 1, batch), s);
+    return launch_conv_t<false>(a, ns, dim3((c.n + 255) / 256, 1, batch), s);
 }
 
 // ------------------------------------------------------------------ seeded key rows

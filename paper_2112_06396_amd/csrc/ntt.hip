@@ -483,8 +483,11 @@ hipError_t launch_ntt_inv_cols(const Ctx &c, const LimbMap &m, const BatchIo &io
     return dispatch_pass<true, false, IO_PLAIN>(a, c.n1, m.count, batch, s);
 }
 
-hipError_t launch_rows_mdepi(const Ctx &c, const LimbMap &m, const BatchIo &io, uint32_t batch, hipStream_t s) {
-    return dispatch_pass<false, true, IO_MDEPI>(base_args(c, m, io, true), c.n2, m.count, batch, s);
+hipError_t launch_rows_mdepi(const Ctx &c, const LimbMap &m, const BatchIo &io, uint32_t batch, const Shoup *pinv,
+                             hipStream_t s) {
+    NttArgs a = base_args(c, m, io, true);
+    a.pinv = pinv;
+    return dispatch_pass<false, true, IO_MDEPI>(a, c.n2, m.count, batch, s);
 }
 
 // ------------------------------------------------------------------ KSKInnerProd (+ ModUp's last pass, + ModDown's first)
@@ -501,8 +504,9 @@ struct KskRowArgs {
     uint64_t *pc;            // [2][K][N] P limbs after the inverse row pass
     const Shoup *twf, *twi;
     const ModC *mc;
+    const Shoup *pmod;  // NewMult: [P]_{q_i}
     size_t dstride, ext_bstride, uq_bstride, pc_bstride;
-    uint32_t n, n1, n2, level, L, K, E, alpha, beta, all_direct, nb, xcd_group;
+    uint32_t n, n1, n2, level, L, K, E, alpha, beta, all_direct, nb, xcd_group, pck;
 };
 
 // One block = one target limb t of Q_level U P and ROW_LINES rows, in the
@@ -515,7 +519,7 @@ struct KskRowArgs {
 // ModDown's inverse row pass on both in registers before storing (the
 // forward pass ends in the layout the inverse pass starts from).
 // (at least two waves per SIMD: the register budget stays within 256)
-template <int LOGS, bool ROWPASS, int E, bool SEEDED>
+template <int LOGS, bool ROWPASS, int E, bool SEEDED, bool NM>
 __global__ void __launch_bounds__((Tile<LOGS, ROW_LINES, false, E>::NT)) __attribute__((amdgpu_waves_per_eu(E == 8 ? KSK_E8_WAVES : 2)))
 ksk_rows_kernel(const KskRowArgs a) {
     using TL = Tile<LOGS, ROW_LINES, false, E>;
@@ -554,8 +558,9 @@ ksk_rows_kernel(const KskRowArgs a) {
     const uint64_t q = mcv.q;
     const size_t KL = (size_t)a.L + a.K;
     const uint32_t own = (tgt < a.level) ? tgt / a.alpha : 0xffffffffu;
-    const bool is_p = tgt >= a.level;
-    const uint32_t kp = tgt - a.level;
+    // special limbs: the P limbs, and with NM also q_(level-1) (stored after them)
+    const bool is_p = tgt >= a.level || (NM && tgt == a.level - 1);
+    const uint32_t kp = tgt >= a.level ? tgt - a.level : a.K;
     int line, t;
     thread_coords<LOGS, ROW_LINES, false, E>(threadIdx.x, line, t);
     const uint32_t lg = tile * ROW_LINES + line;
@@ -612,28 +617,41 @@ ksk_rows_kernel(const KskRowArgs a) {
             v[2 * c + 1] = add_mod(v[2 * c + 1], mul_mod(xv[2 * c + 1], kv1.y, q, mcv.mu, mcv.nq), q);
         }
     }
+    if constexpr (NM) {
+        // NewMult: u += P b3, v += P c3 on the q limbs (PModUp)
+        if (tgt < a.level) {
+            const Shoup pm = a.pmod[tgt];
+            const uint64_t *b3 = a.kb.addp[b] + (size_t)tgt * N + (lg << a.n2) + E * t;
+            const uint64_t *c3 = b3 + (size_t)a.level * N;
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                u[e] = add_mod(u[e], mul_shoup(b3[e], pm.w, pm.wp, q), q);
+                v[e] = add_mod(v[e], mul_shoup(c3[e], pm.w, pm.wp, q), q);
+            }
+        }
+    }
     if (!is_p) {
         gstore<LOGS, false, IOF::OUT_LO, IOF::OUT_HI, E>(u, uq + (size_t)tgt * N, t, lg, a.n2);
         gstore<LOGS, false, IOF::OUT_LO, IOF::OUT_HI, E>(v, uq + ((size_t)a.level + tgt) * N, t, lg, a.n2);
         return;
     }
-    // special-prime limb: inverse row pass (first pass of ModDown's iNTT) of u and v
+    // special limb: inverse row pass (first pass of ModDown's iNTT) of u and v
     const TwRows twi{a.twi + (size_t)mod * N, lg, a.n1};
     if (lds_used) __syncthreads();
     pass_regs<LOGS, ROW_LINES, false, false, false, E>(true, u, lds, line, t, q, mcv.nq, twi, LastInv{});
     gstore<LOGS, false, IOI::OUT_LO, IOI::OUT_HI, E>(u, pc + (size_t)kp * N, t, lg, a.n2);
     __syncthreads();
     pass_regs<LOGS, ROW_LINES, false, false, false, E>(true, v, lds, line, t, q, mcv.nq, twi, LastInv{});
-    gstore<LOGS, false, IOI::OUT_LO, IOI::OUT_HI, E>(v, pc + ((size_t)a.K + kp) * N, t, lg, a.n2);
+    gstore<LOGS, false, IOI::OUT_LO, IOI::OUT_HI, E>(v, pc + ((size_t)a.pck + kp) * N, t, lg, a.n2);
 }
 
-template <bool ROWPASS, int E, bool SEEDED>
+template <bool ROWPASS, int E, bool SEEDED, bool NM = false>
 static hipError_t launch_ksk_rows_t(const KskRowArgs &a, uint32_t n2, dim3 grid, hipStream_t s) {
     switch (n2) {
-        case 5: hipLaunchKernelGGL((ksk_rows_kernel<5, ROWPASS, E, SEEDED>), grid, dim3(Tile<5, ROW_LINES, false, E>::NT), 0, s, a); break;
-        case 6: hipLaunchKernelGGL((ksk_rows_kernel<6, ROWPASS, E, SEEDED>), grid, dim3(Tile<6, ROW_LINES, false, E>::NT), 0, s, a); break;
-        case 7: hipLaunchKernelGGL((ksk_rows_kernel<7, ROWPASS, E, SEEDED>), grid, dim3(Tile<7, ROW_LINES, false, E>::NT), 0, s, a); break;
-        case 8: hipLaunchKernelGGL((ksk_rows_kernel<8, ROWPASS, E, SEEDED>), grid, dim3(Tile<8, ROW_LINES, false, E>::NT), 0, s, a); break;
+        case 5: hipLaunchKernelGGL((ksk_rows_kernel<5, ROWPASS, E, SEEDED, NM>), grid, dim3(Tile<5, ROW_LINES, false, E>::NT), 0, s, a); break;
+        case 6: hipLaunchKernelGGL((ksk_rows_kernel<6, ROWPASS, E, SEEDED, NM>), grid, dim3(Tile<6, ROW_LINES, false, E>::NT), 0, s, a); break;
+        case 7: hipLaunchKernelGGL((ksk_rows_kernel<7, ROWPASS, E, SEEDED, NM>), grid, dim3(Tile<7, ROW_LINES, false, E>::NT), 0, s, a); break;
+        case 8: hipLaunchKernelGGL((ksk_rows_kernel<8, ROWPASS, E, SEEDED, NM>), grid, dim3(Tile<8, ROW_LINES, false, E>::NT), 0, s, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -667,6 +685,8 @@ hipError_t launch_ksk_rows(const Ctx &c, const KskBatch &kb, uint32_t nb, const 
     a.alpha = c.alpha;
     a.beta = (level + c.alpha - 1) / c.alpha;
     a.nb = nb;
+    a.pmod = c.pmod;
+    a.pck = kb.newmult ? c.K + 1 : c.K;
     const uint32_t xs = ((1u << c.n1) / ROW_LINES) * a.E;
     a.xcd_group = (nb > 1 && xs % 8 == 0) ? 1u : 0u;
     ProfScope ps(c, HKS_K_KSK, s);
@@ -675,6 +695,10 @@ hipError_t launch_ksk_rows(const Ctx &c, const KskBatch &kb, uint32_t nb, const 
     // already holds many waves at 16
     const uint64_t thr16 = (uint64_t)ROW_LINES * (1u << c.n2) / 16;  // threads per block at 16
     const uint64_t waves16 = (uint64_t)xs * nb * ((thr16 + 63) / 64);
+    if (kb.newmult) {  // NewMult: a relinearization key, the converted limbs after the column pass
+        if (!rowpass || kb.seeded) return hipErrorInvalidValue;
+        return launch_ksk_rows_t<true, 8, false, true>(a, c.n2, grid, s);
+    }
     // a seeded key's rows a_j are generated in the kernel: always 8 elements
     // per thread there (the generator's registers on top of 16 would spill)
     if (kb.seeded)

@@ -178,6 +178,42 @@ int build_tables(Ctx &c) {
         pmod[i] = h_shoup(P, qi);
     }
 
+    // ModDown by S = P q_{l-1} at level l (NewMult): special limbs s_0..s_{K-1} =
+    // p_0..p_{K-1}, s_K = q_{l-1}; targets q_0..q_{l-2}.
+    std::vector<LastInv> linm((size_t)(L + 1) * (K + 1));
+    std::vector<Shoup> sinm((size_t)(L + 1) * L);
+    std::vector<uint64_t> convnm;
+    c.conv_nm_off.assign(L + 1, 0);
+    for (uint32_t l = 2; l <= L; ++l) {
+        std::vector<uint64_t> sm(K + 1);
+        std::vector<uint32_t> sidx(K + 1);
+        for (uint32_t k = 0; k < K; ++k) {
+            sm[k] = c.mods[L + k];
+            sidx[k] = L + k;
+        }
+        sm[K] = c.mods[l - 1];
+        sidx[K] = l - 1;
+        for (uint32_t k = 0; k <= K; ++k) {
+            uint64_t prod = 1;
+            for (uint32_t kk = 0; kk <= K; ++kk)
+                if (kk != k) prod = h_mulmod(prod, sm[kk] % sm[k], sm[k]);
+            linm[(size_t)l * (K + 1) + k] = make_last(sm[k], ninv[sidx[k]], h_invmod(prod, sm[k]), w0inv[sidx[k]]);
+        }
+        c.conv_nm_off[l] = convnm.size();
+        for (uint32_t i = 0; i + 1 < l; ++i) {
+            const uint64_t qi = c.mods[i];
+            uint64_t all = 1;
+            for (uint32_t k = 0; k <= K; ++k) {
+                uint64_t v = 1;
+                for (uint32_t kk = 0; kk <= K; ++kk)
+                    if (kk != k) v = h_mulmod(v, sm[kk] % qi, qi);
+                convnm.push_back(split25(v));
+                all = h_mulmod(all, sm[k] % qi, qi);
+            }
+            sinm[(size_t)l * L + i] = h_shoup(h_invmod(all, qi), qi);
+        }
+    }
+
     // Rescale at level l: divide by q_{l-1}, h = (q_{l-1} - 1) / 2.
     std::vector<Shoup> rsq((size_t)(L + 1) * L);
     std::vector<uint64_t> rsh((size_t)(L + 1) * L, 0);
@@ -201,6 +237,9 @@ int build_tables(Ctx &c) {
     if ((rc = upload(&c.conv_moddown, convd))) return rc;
     if ((rc = upload(&c.pinv, pinv))) return rc;
     if ((rc = upload(&c.pmod, pmod))) return rc;
+    if ((rc = upload(&c.li_nm, linm))) return rc;
+    if ((rc = upload(&c.conv_nm, convnm))) return rc;
+    if ((rc = upload(&c.sinv_nm, sinm))) return rc;
     if ((rc = upload(&c.rs_qinv, rsq))) return rc;
     if ((rc = upload(&c.rs_h, rsh))) return rc;
     return HKS_OK;
@@ -208,7 +247,8 @@ int build_tables(Ctx &c) {
 
 void free_tables(Ctx &c) {
     void *ptrs[] = {c.tw_fwd, c.tw_inv, c.mc, c.li_plain, c.li_modup, c.li_moddown, c.conv_modup,
-                    c.conv_moddown, c.pinv, c.pmod, c.rs_qinv, c.rs_h, c.ws};
+                    c.conv_moddown, c.pinv, c.pmod, c.rs_qinv, c.rs_h, c.ws,
+                    c.li_nm, c.conv_nm, c.sinv_nm};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     c.tw_fwd = c.tw_inv = nullptr;
@@ -216,6 +256,9 @@ void free_tables(Ctx &c) {
     c.li_plain = c.li_modup = c.li_moddown = nullptr;
     c.conv_modup = c.conv_moddown = nullptr;
     c.pinv = c.pmod = c.rs_qinv = nullptr;
+    c.li_nm = nullptr;
+    c.conv_nm = nullptr;
+    c.sinv_nm = nullptr;
     c.rs_h = nullptr;
     c.ws = nullptr;
 }

@@ -42,7 +42,8 @@ EXPORTS = (
     "hks_gen_primes", "hks_galois_for_rotation", "hks_galois_conjugate", "hks_strerror",
     "hks_create", "hks_destroy", "hks_query", "hks_ntt", "hks_intt", "hks_automorph",
     "hks_modup", "hks_ksk_inner", "hks_moddown", "hks_keyswitch", "hks_rotate", "hks_hrotate",
-    "hks_batch_rotate", "hks_rescale", "hks_ptmult", "hks_mult_relin", "hks_batch_mult_relin", "hks_add",
+    "hks_batch_rotate", "hks_rescale", "hks_ptmult", "hks_mult_relin", "hks_batch_mult_relin", "hks_new_mult",
+    "hks_add",
     "hks_expand_key_a", "hks_rotate_seeded", "hks_batch_rotate_seeded", "hks_ptmatvec", "hks_prof_enable",
     "hks_prof_read",
 )
@@ -120,6 +121,7 @@ def lib():
             "hks_mult_relin": (_i32, [_vp, _vp, _vp, _u32, _vp, _i32, _vp, _vp]),
             "hks_batch_mult_relin": (_i32, [_vp, _u32, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _u32,
                                             ctypes.POINTER(_vp), _i32, ctypes.POINTER(_vp), _vp]),
+            "hks_new_mult": (_i32, [_vp, _vp, _vp, _u32, _vp, _vp, _vp]),
             "hks_add": (_i32, [_vp, _vp, _vp, _u32, _u32, _vp, _vp]),
             "hks_expand_key_a": (_i32, [_vp, ctypes.c_uint64, _vp, _vp]),
             "hks_ptmatvec": (_i32, [_vp, _vp, _u32, _u32, ctypes.POINTER(_u32), ctypes.POINTER(_vp),
@@ -356,6 +358,11 @@ def hks_batch_rotate_seeded(ctx, cts, level: int, galois, seeds, ksk_bs, outs, s
     oa = (_vp * n)(*[_ptr(o) for o in outs])
     _check("hks_batch_rotate_seeded", lib().hks_batch_rotate_seeded(ctx.handle, n, ca, level, ga, sa, ka, oa,
                                                                     _stream(stream)))
+
+
+def hks_new_mult(ctx, ct1, ct2, level: int, rlk, ct_out, stream=None):
+    _check("hks_new_mult", lib().hks_new_mult(ctx.handle, _ptr(ct1), _ptr(ct2), level, _ptr(rlk), _ptr(ct_out),
+                                              _stream(stream)))
 
 
 def hks_add(ctx, x, y, level: int, n_poly: int, out, stream=None):

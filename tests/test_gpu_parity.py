@@ -674,3 +674,39 @@ def test_ptmatvec_equals_oracle(name, ks):
         out = hks.empty((2, level, pr.n))
         hks.hks_ptmatvec(ctx, dev(ct), level, gals, dk, [dev(p) for p in pts], out)
         assert np.array_equal(host(out), O.ptmatvec(pr, ct, level, gals, ksks, pts)), level
+
+
+# ------------------------------------------------------------------ NewMult (key-switch ModDown merged with Rescale)
+
+
+@pytest.mark.parametrize("name", ["n10", "n11", "cfg1", "n13", "cfg2", (16, 35, 12, 3)])
+def test_new_mult_equals_oracle(name):
+    """NewMult (ModDown by P q_(level-1) inside the key-switch) equals the
+    oracle's, at the top level, at a level whose last digit is short and at
+    level 2 (one output limb); a plain Mult on the same context afterwards
+    is unaffected by the workspace the NewMult used."""
+    pr, ctx = _get(name)
+    hks = H()
+    rlk = _rand_ksk(pr, 900)
+    drlk = dev(rlk)
+    for level in sorted({pr.L, pr.alpha + 1, 2}, reverse=True):
+        c1, c2 = _rand_ct(pr, level, 901 + level), _rand_ct(pr, level, 951 + level)
+        out = hks.empty((2, level - 1, pr.n))
+        hks.hks_new_mult(ctx, dev(c1), dev(c2), level, drlk, out)
+        assert np.array_equal(host(out), O.new_mult(pr, c1, c2, level, rlk)), level
+    level = pr.L
+    c1, c2 = _rand_ct(pr, level, 990), _rand_ct(pr, level, 991)
+    o = hks.empty((2, level - 1, pr.n))
+    hks.hks_mult_relin(ctx, dev(c1), dev(c2), level, drlk, True, o)
+    assert np.array_equal(host(o), O.mult_relin(pr, c1, c2, level, rlk, True))
+
+
+def test_new_mult_rejects_level_one_and_aliasing():
+    pr, ctx = _get("n10")
+    hks = H()
+    c1, c2 = dev(_rand_ct(pr, 2, 1)), dev(_rand_ct(pr, 2, 2))
+    rlk = dev(_rand_ksk(pr, 3))
+    for args in ((c1, c2, 1, rlk, hks.empty((2, 1, pr.n))), (c1, c2, 2, rlk, c1), (c1, c2, 2, rlk, c2)):
+        with pytest.raises(hks.HksError) as e:
+            hks.hks_new_mult(ctx, *args)
+        assert e.value.status == hks.HKS_EINVAL
