@@ -184,6 +184,17 @@ def extras(args, ctx, hks, synth, cts, ksks, outs, gal, key_mods, n, plain_value
         lambda i: hks.hks_ptmatvec(ctx, cts[i % args.pool], LEVEL, gals[:r], dkeys[:r], pts, mv_out, stream), r, 8)
     res["ptmatvec_r12_unhoisted_rot_per_s"] = rate(unhoisted, r, 8)
     del pts, pts_q, mv_out, tmp
+    # Mult + relinearization + Rescale vs NewMult (the key-switch ModDown and Rescale merged)
+    mrlk = dkeys[0]
+    mout = [hks.empty((2, LEVEL - 1, n)) for _ in range(2)]
+    res["mult_rescale_per_s"] = rate(
+        lambda i: hks.hks_mult_relin(ctx, dcts[i % 32], dcts[(i + 1) % 32], LEVEL, mrlk, True, mout[i % 2], stream),
+        1, max(50, args.steps))
+    res["new_mult_per_s"] = rate(
+        lambda i: hks.hks_new_mult(ctx, dcts[i % 32], dcts[(i + 1) % 32], LEVEL, mrlk, mout[i % 2], stream),
+        1, max(50, args.steps))
+    log(f"[bench] Mult+Rescale {res['mult_rescale_per_s']:.0f}/s, NewMult {res['new_mult_per_s']:.0f}/s")
+    del mout
     # the plain Rotate replayed from hipGraphs (one per pool entry)
     graphs = []
     for j in range(args.pool):
@@ -219,8 +230,9 @@ def extras(args, ctx, hks, synth, cts, ksks, outs, gal, key_mods, n, plain_value
     res["trace"] = {"key_switches": plan.key_switches, "rotation_keys": len(plan.rotations), "levels": "35->9",
                     "ops": len(plan.ops)}
     del gr
-    # the same trace with each linear stage as one PtMatVecMult (ModDown hoisted)
-    hplan = trace.bootstrap_plan(35, hoisted=True)
+    # the same trace with each linear stage as one PtMatVecMult (ModDown hoisted) and the
+    # EvalMod products as NewMult (one ModDown by P q_(l-1))
+    hplan = trace.bootstrap_plan(35, hoisted=True, new_mult=True)
     hdiag = {d: synth.device_residues(pq, (), n, 100 + i) for i, d in enumerate(hplan.diagonals)}
     hext = trace.ext_diagonals(hplan, hdiag, 35)
     hbufs = trace.TraceBuffers(hplan, n)

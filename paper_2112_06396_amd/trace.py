@@ -8,7 +8,7 @@ polynomial evaluation (Sec. 3: CoeffToSlot, EvalMod, SlotToCoeff):
     every rotation by a plaintext diagonal (Algorithm 1 without Rescale),
     summing, then one Rescale; one level per stage;
   - EvalMod-like: per level, two Mult + relinearization + Rescale
-    (Algorithm 2), x' = x y and y' = x x;
+    (Algorithm 2), or two NewMult (Sec. 5.1), x' = x y and y' = x x;
   - SlotToCoeff: the CoeffToSlot stages again with negated indices.
 Levels fall by one per stage or EvalMod level, so the limb count is uneven
 along the trace.  The plan is plain data; `run_plan` issues it through the
@@ -34,7 +34,7 @@ class Plan:
 
 
 def bootstrap_plan(top: int, counts=(12, 12, 16), strides=(1, 32, 1024), evalmod_levels: int = 20,
-                   hoisted: bool = False) -> Plan:
+                   hoisted: bool = False, new_mult: bool = False) -> Plan:
     """Ops (kind, ...) over ciphertext buffers named by strings:
       ("hrotate", src, level, [k...], [dst...])
       ("ptmult", src, diag, level, dst)
@@ -42,8 +42,10 @@ def bootstrap_plan(top: int, counts=(12, 12, 16), strides=(1, 32, 1024), evalmod
       ("ptmatvec", src, level, [k...], [diag...], dst)   sum_i M_i Rotate_k_i(src), one ModDown
       ("rescale", src, level, dst)        -> level - 1
       ("mult", a, b, level, dst)          -> level - 1 (relinearized, rescaled)
+      ("newmult", a, b, level, dst)       -> level - 1 (Sec. 5.1, one ModDown by P q_(level-1))
     With `hoisted`, each linear stage is one ptmatvec (Sec. 5.2) instead of
-    an HRotate followed by PtMult and Add per rotation."""
+    an HRotate followed by PtMult and Add per rotation; with `new_mult`, the
+    EvalMod products are NewMult instead of Mult + Rescale."""
     p = Plan(top=top)
     level, x = top, "x0"
     p.buffers.add(x)
@@ -78,8 +80,9 @@ def bootstrap_plan(top: int, counts=(12, 12, 16), strides=(1, 32, 1024), evalmod
     y = x
     for _ in range(evalmod_levels):
         a, b = next(nxt), next(nxt)
-        p.ops.append(("mult", x, y, level, a))
-        p.ops.append(("mult", x, x, level, b))
+        mult = "newmult" if new_mult else "mult"
+        p.ops.append((mult, x, y, level, a))
+        p.ops.append((mult, x, x, level, b))
         p.key_switches += 2
         p.buffers.update([a, b])
         x, y, level = a, b, level - 1
@@ -149,6 +152,10 @@ def run_plan(ctx, plan: Plan, bufs: TraceBuffers, diag, keys, rlk, stream=None, 
             _, a, b, level, dst = op
             hks.hks_mult_relin(ctx, bufs.view(a, level), bufs.view(b, level), level, rlk, True,
                                bufs.view(dst, level - 1), stream)
+        elif kind == "newmult":
+            _, a, b, level, dst = op
+            hks.hks_new_mult(ctx, bufs.view(a, level), bufs.view(b, level), level, rlk, bufs.view(dst, level - 1),
+                             stream)
         else:
             raise ValueError(f"unknown op {kind}")
     return bufs.view(plan.out, plan.out_level)

@@ -432,6 +432,9 @@ def _oracle_plan(pr, plan, x0, diag, keys, rlk):
         elif kind == "mult":
             _, a, b, level, dst = op
             bufs[dst] = O.mult_relin(pr, bufs[a], bufs[b], level, rlk, True)
+        elif kind == "newmult":
+            _, a, b, level, dst = op
+            bufs[dst] = O.new_mult(pr, bufs[a], bufs[b], level, rlk)
     return bufs[plan.out]
 
 
@@ -476,11 +479,13 @@ def test_trace_eager_and_graph_replays_match_oracle():
 
 def test_hoisted_trace_eager_and_graph_match_oracle():
     """The same small trace with every linear stage as one PtMatVecMult with
-    the ModDown hoisted (Sec. 5.2): eager and two graph replays equal the
-    oracle's run of the same plan."""
+    the ModDown hoisted (Sec. 5.2) and the EvalMod products as NewMult
+    (Sec. 5.1): eager and two graph replays equal the oracle's run of the
+    same plan."""
     from paper_2112_06396_amd import trace
     pr, ctx = _get((12, 10, 4, 3), 4)
-    plan = trace.bootstrap_plan(pr.L, counts=(2, 2, 3), strides=(1, 4, 16), evalmod_levels=3, hoisted=True)
+    plan = trace.bootstrap_plan(pr.L, counts=(2, 2, 3), strides=(1, 4, 16), evalmod_levels=3, hoisted=True,
+                                new_mult=True)
     g = synth.rng(210)
     x0 = _rand_ct(pr, pr.L, 211)
     diag = {d: synth.uniform_residues(g, pr.key_mods(), pr.n) for d in plan.diagonals}
