@@ -236,14 +236,16 @@ def hrotate(pr: Params, ct: np.ndarray, level: int, gs, ksks) -> list:
 
 def ptmatvec(pr: Params, ct: np.ndarray, level: int, gs, ksks, pts) -> np.ndarray:
     """sum_i M_i * Rotate_{g_i}(ct) with one ModDown (hoisted PtMatVecMult);
-    pts[i] is M_i over Q_level U P, [level + K][N] evaluation form."""
+    pts[i] is M_i over Q_level U P, [level + K][N] evaluation form.  A key of
+    None (with g_i = 1) is the diagonal without rotation: PModUp of ct
+    itself, no key switch."""
     ct = _u64(ct)
-    ksks = [_u64(k) for k in ksks]
+    ksks = [None if k is None else _u64(k) for k in ksks]
     pts = [_u64(p) for p in pts]
     r = len(gs)
     out = np.zeros((2, level, pr.n), dtype=np.uint64)
     ga = (ctypes.c_uint32 * r)(*[int(g) for g in gs])
-    ka = (_u64p * r)(*[_p(k) for k in ksks])
+    ka = (_u64p * r)(*[_u64p() if k is None else _p(k) for k in ksks])
     pa = (_u64p * r)(*[_p(p) for p in pts])
     _call("oref_ptmatvec", pr, _p(ct), level, r, ga, ka, pa, _p(out))
     return out

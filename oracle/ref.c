@@ -663,7 +663,10 @@ void oref_expand_key_a(const oref_params *pr, uint64_t seed, uint64_t *a) {
  * pts[i] is the diagonal M_i given over the extended basis ([level + K][N],
  * evaluation form, residues mod q_0..q_{level-1}, p_0..p_{K-1}): the
  * plaintext itself, not multiplied by P (a factor P on it would survive the
- * single ModDown).
+ * single ModDown).  ksks[i] == NULL with g_i = 1 is the diagonal without a
+ * rotation (offset 0 of a factored DFT matrix): its (u, v) is PModUp of the
+ * input, (P a, P b) on the q limbs, with no key switch; since ModDown is
+ * exact on multiples of P, that term alone gives M_0 * (a, b).
  * ------------------------------------------------------------------------- */
 int oref_ptmatvec(const oref_params *pr, const uint64_t *ct, uint32_t level, uint32_t r, const uint32_t *gs,
                   const uint64_t *const *ksks, const uint64_t *const *pts, uint64_t *out) {
@@ -682,11 +685,25 @@ int oref_ptmatvec(const oref_params *pr, const uint64_t *ct, uint32_t level, uin
     int rc = oref_modup(pr, ct, level, ext);
     for (uint32_t i = 0; !rc && i < r; i++) {
         if ((gs[i] & 1) == 0) { rc = -1; break; }
-        for (uint32_t j = 0; j < beta; j++)
-            oref_automorph(ext + (size_t)j * next * n, erot + (size_t)j * next * n, pr->log_n,
-                           emods, next, gs[i], 1);
-        rc = oref_ksk_inner(pr, erot, level, ksks[i], hat);
-        if (rc) break;
+        if (ksks[i] == NULL) {
+            /* the diagonal without rotation: (u, v) = (PModUp(a), 0), no key
+               switch (P a on the q limbs, 0 on the P limbs) */
+            if (gs[i] != 1) { rc = -1; break; }
+            for (uint32_t t = 0; t < next; t++) {
+                uint64_t m = emods[t], pmod = 1;
+                for (uint32_t k = 0; k < pr->K; k++) pmod = mulmod(pmod, pr->p[k] % m, m);
+                for (size_t c = 0; c < n; c++) {
+                    hat[t * n + c] = t < level ? mulmod(pmod, ct[t * n + c], m) : 0;
+                    hat[((size_t)next + t) * n + c] = 0;
+                }
+            }
+        } else {
+            for (uint32_t j = 0; j < beta; j++)
+                oref_automorph(ext + (size_t)j * next * n, erot + (size_t)j * next * n, pr->log_n,
+                               emods, next, gs[i], 1);
+            rc = oref_ksk_inner(pr, erot, level, ksks[i], hat);
+            if (rc) break;
+        }
         oref_automorph(ct + pl, brot, pr->log_n, pr->q, level, gs[i], 1);
         for (uint32_t t = 0; t < next; t++) {
             uint64_t m = emods[t];
