@@ -175,8 +175,10 @@ int hks_hrotate(hks_ctx *ctx, const uint64_t *ct, uint32_t level, uint32_t r,
  * summed, then a single ModDown.  pt[i] is M_i over the extended basis,
  * [level + K][N] evaluation form (residues mod q_0..q_{level-1},
  * p_0..p_{K-1}; not multiplied by P).  galois, ksk, pt are HOST arrays of
- * r <= 64 entries (device pointers).  The result carries the product's
- * scale (no Rescale). */
+ * r <= 64 entries (device pointers).  ksk[i] = NULL with galois[i] = 1 is
+ * the diagonal without rotation (offset 0 of a factored DFT matrix, Sec. 3):
+ * its term is M_i * (P a, P b), no key switch.  The result carries the
+ * product's scale (no Rescale). */
 int hks_ptmatvec(hks_ctx *ctx, const uint64_t *ct, uint32_t level, uint32_t r, const uint32_t *galois,
                  const uint64_t *const *ksk, const uint64_t *const *pt, uint64_t *ct_out, void *stream);
 
@@ -248,6 +250,22 @@ int hks_batch_mult_relin(hks_ctx *ctx, uint32_t n, const uint64_t *const *ct1, c
  * HKS_EUNSUPPORTED when K + 1 > 16. */
 int hks_new_mult(hks_ctx *ctx, const uint64_t *ct1, const uint64_t *ct2, uint32_t level, const uint64_t *rlk,
                  uint64_t *ct_out, void *stream);
+
+/* Encode (the CKKS canonical embedding, Sec. 2.1; the plaintexts of the
+ * factored DFT's diagonals in bootstrapping, Sec. 3).  slots: DEVICE array of
+ * N/2 complex values as interleaved fp64 (re, im), 16-byte aligned; slot j is
+ * the plaintext's value at zeta^(5^j mod 2N), zeta = exp(i pi / N).  With
+ * w = V^H z / (N/2) (V[j, k] = zeta^(5^j k)), the plaintext's coefficients
+ * are m_k = round(scale Re w_k), m_(k+N/2) = round(scale Im w_k) (round half
+ * to even, fp64), reduced mod q_0..q_{level-1} and, if with_p != 0, also
+ * p_0..p_{K-1}; pt_out [level (+K)][N] evaluation form.  Requires
+ * scale * |w_k| < 2^62 (larger values give undefined residues).  The
+ * transform runs in fp64 butterflies on the device; its rounding can differ
+ * from another fp64 evaluation order by one unit where scale * w_k lies
+ * within the rounding error of a half-integer.  Uses the context's
+ * workspace (stream-ordered like every call). */
+int hks_encode(hks_ctx *ctx, const double *slots, double scale, uint32_t level, int with_p, uint64_t *pt_out,
+               void *stream);
 
 /* Add (Table "CKKS FHE API"): out = x + y limb-wise for n_poly (1..3)
  * polynomials of level limbs each, [n_poly][level][N]; out may be x or y

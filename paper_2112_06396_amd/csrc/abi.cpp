@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -568,16 +569,23 @@ int hks_ptmatvec(hks_ctx *h, const uint64_t *ct, uint32_t level, uint32_t r, con
         level > h->c.L || r == 0 || r > (uint32_t)MAXROT || ct == ct_out)
         return HKS_EINVAL;
     Ctx &c = h->c;
-    for (uint32_t i = 0; i < r; ++i)
-        if (!valid_galois(c, galois[i]) || !ksk[i] || !pt[i] || !aligned(ksk[i]) || !aligned(pt[i]))
+    bool keyed = false;
+    for (uint32_t i = 0; i < r; ++i) {
+        // no key: the diagonal without rotation (galois 1)
+        if (!valid_galois(c, galois[i]) || !pt[i] || !aligned(pt[i]) || (ksk[i] && !aligned(ksk[i])) ||
+            (!ksk[i] && galois[i] != 1))
             return HKS_EINVAL;
+        keyed = keyed || ksk[i];
+    }
     hipStream_t s = (hipStream_t)stream;
     const size_t pl = (size_t)level * c.n;
     const uint32_t one = 1;
-    int rc = do_modup_new(c, &ct, &one, 1, level, c.ws_ext, 0, s, false);
-    if (!rc) rc = do_modup_own(c, ct, level, 1, c.ws_ext, s);
-    if (rc) return rc;
-    HKS_TRY(launch_ksk_matvec(c, c.ws_ext, level, r, galois, ksk, pt, ct + pl, c.ws_uv, c.ws_p, s));
+    if (keyed) {
+        int rc = do_modup_new(c, &ct, &one, 1, level, c.ws_ext, 0, s, false);
+        if (!rc) rc = do_modup_own(c, ct, level, 1, c.ws_ext, s);
+        if (rc) return rc;
+    }
+    HKS_TRY(launch_ksk_matvec(c, c.ws_ext, level, r, galois, ksk, pt, ct, ct + pl, c.ws_uv, c.ws_p, s));
     BatchIo epi{};
     for (uint32_t p = 0; p < 2; ++p) {
         epi.uq[p] = c.ws_uv + p * pl;
@@ -585,6 +593,31 @@ int hks_ptmatvec(hks_ctx *h, const uint64_t *ct, uint32_t level, uint32_t r, con
         epi.add_galois[p] = 1;
     }
     return do_moddown_tail(c, level, 2, epi, s);
+    GUARD_END
+}
+
+int hks_encode(hks_ctx *h, const double *slots, double scale, uint32_t level, int with_p, uint64_t *pt_out,
+               void *stream) {
+    GUARD_BEGIN
+    if (!h || !slots || !pt_out || ((uintptr_t)slots & 15) || !aligned(pt_out) || level < 1 || level > h->c.L ||
+        !(scale > 0.0) || !std::isfinite(scale))
+        return HKS_EINVAL;
+    Ctx &c = h->c;
+    hipStream_t s = (hipStream_t)stream;
+    const uint32_t nl = level + (with_p ? c.K : 0);
+    // the slots' transform runs in place in the tensor-product slot (N/2
+    // complex values = N words)
+    Cplx *x = reinterpret_cast<Cplx *>(c.ws_t);
+    HKS_TRY(hipMemcpyAsync(x, slots, sizeof(Cplx) * (c.n / 2), hipMemcpyDeviceToDevice, s));
+    HKS_TRY(launch_enc_fft(c, x, s));
+    Lists ls;
+    for (uint32_t i = 0; i < nl; ++i) {
+        const uint32_t mod = i < level ? i : c.L + (i - level);
+        ls.add(i, i, mod, mod);
+    }
+    HKS_TRY(ls.run([&](const LimbMap &m) { return launch_enc_round(c, x, scale, m, pt_out, s); }));
+    const BatchIo io = strided_io(pt_out, 0, pt_out, 0, 1);
+    return hip_status(ls.run([&](const LimbMap &m) { return launch_ntt_fwd(c, m, io, 1, s); }));
     GUARD_END
 }
 

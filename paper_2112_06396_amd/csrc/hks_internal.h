@@ -68,6 +68,10 @@ struct Shoup {
     uint64_t w, wp;
 };
 
+struct Cplx {
+    double re, im;
+};
+
 // Folded last inverse-NTT stage: multiply the sum by c and the difference by
 // c * W^-1 (W the stage-0 twiddle), c = N^-1 * scale.
 struct LastInv {
@@ -99,6 +103,8 @@ struct Ctx {
     Shoup *pmod = nullptr;             // [L]: P mod q_i
     Shoup *rs_qinv = nullptr;          // [L+1][L]: q_{l-1}^-1 mod q_i
     uint64_t *rs_h = nullptr;          // [L+1][L]: ((q_{l-1}-1)/2) mod q_i
+    uint32_t *enc_rotg = nullptr;      // [N/2]: 5^j mod 2N (the slots' rotation group)
+    Cplx *enc_roots = nullptr;         // [2N]: exp(2 pi i t / 2N)
     LimbMap *dummy = nullptr;
 
     // workspace (device), sized for the top level and the batch capacity:
@@ -209,10 +215,12 @@ hipError_t launch_ksk_rows(const Ctx &c, const KskBatch &kb, uint32_t nb, const 
 // (the special limbs of one polynomial in pc: K, or K + 1 with newmult)
 // PtMatVecMult sums over Q_level U P (ModUp'd digits of a in ext, evaluation
 // form, [beta][level+K][N]): q limbs into uq [2][level][N], P limbs after
-// ModDown's inverse row pass into pc [2][K][N].  r <= MAXROT.
+// ModDown's inverse row pass into pc [2][K][N].  r <= MAXROT.  ksk[i] ==
+// nullptr (with galois[i] == 1) is the diagonal without rotation, read from
+// the input's a (ax) and b.
 hipError_t launch_ksk_matvec(const Ctx &c, const uint64_t *ext, uint32_t level, uint32_t r, const uint32_t *galois,
-                             const uint64_t *const *ksk, const uint64_t *const *pt, const uint64_t *b, uint64_t *uq,
-                             uint64_t *pc, hipStream_t s);
+                             const uint64_t *const *ksk, const uint64_t *const *pt, const uint64_t *ax,
+                             const uint64_t *b, uint64_t *uq, uint64_t *pc, hipStream_t s);
 // The rows a_j of the seeded key `seed`: a [dnum][L+K][N].
 hipError_t launch_expand_key_a(const Ctx &c, uint64_t seed, uint64_t *a, hipStream_t s);
 // Eval-domain automorph (gather) of limbs; or coefficient-domain map with negation.
@@ -226,6 +234,13 @@ hipError_t launch_ksk(const Ctx &c, const uint64_t *ext, uint32_t level, uint32_
 // Elementwise: out[l] = x[l] * y[l] mod q_l (pt mult) for n_poly polys of level limbs.
 hipError_t launch_mulpt(const Ctx &c, const uint64_t *ct, const uint64_t *pt, uint64_t *out,
                         uint32_t level, uint32_t n_poly, hipStream_t s);
+// Encoding, in two steps: x (N/2 complex) <- V^H x, bit-reversed (in place);
+// then coefficients m = round(scale * (Re w, Im w)), w = V^H x / (N/2),
+// reduced mod the limbs of m (out_off = limb of out, coefficient form,
+// natural order).
+hipError_t launch_enc_fft(const Ctx &c, Cplx *x, hipStream_t s);
+hipError_t launch_enc_round(const Ctx &c, const Cplx *x, double scale, const LimbMap &m, uint64_t *out,
+                            hipStream_t s);
 // Tensor: (a1 a2, a1 b2 + a2 b1, b1 b2).
 hipError_t launch_tensor(const Ctx &c, const uint64_t *ct1, const uint64_t *ct2, uint64_t *out3,
                          uint32_t level, hipStream_t s);

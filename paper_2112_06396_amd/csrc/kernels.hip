@@ -297,6 +297,70 @@ hipError_t launch_ksk(const Ctx &c, const uint64_t *ext, uint32_t level, uint32_
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ encoding
+
+// One radix-2 stage of V^H, the conjugate transpose of the special DFT
+// V[j, k] = zeta^(g_j k) (zeta = exp(i pi / N), g_j = 5^j mod 2N) that maps a
+// plaintext's coefficient pairs w_k = m_k + i m_(k+N/2) to its slots.
+// V = S_(N/2) ... S_2 R (R the bit reversal, S_m the butterflies of block
+// size m with twiddles exp(2 pi i (5^j mod 4m) / 4m)), so V^H = R S_2^H ...
+// S_(N/2)^H: this kernel applies S_m^H, taking (x_r, x_(r+m/2)) to
+// (x_r + x_(r+m/2), conj(w) (x_r - x_(r+m/2))) for r = b m + j, j < m/2.
+__global__ void __launch_bounds__(256) enc_stage_kernel(Cplx *x, const uint32_t *rotg, const Cplx *roots,
+                                                        uint32_t ns, uint32_t m) {
+    const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid >= ns / 2) return;
+    const uint32_t h = m / 2, b = tid / h, j = tid % h, r = b * m + j;
+    // exp(2 pi i (5^j mod 4m) / 4m) is root (5^j mod 4m) (2N / 4m) of order 2N
+    const Cplx w = roots[(rotg[j] % (4 * m)) * (ns / m)];
+    const Cplx u = x[r], v = x[r + h];
+    const double dr = u.re - v.re, di = u.im - v.im;
+    x[r] = Cplx{u.re + v.re, u.im + v.im};
+    x[r + h] = Cplx{w.re * dr + w.im * di, w.re * di - w.im * dr};
+}
+
+// The plaintext's coefficients from V^H x (bit-reversed in x): w_k =
+// x[brev(k)] sc with sc = scale / (N/2); m_k = round(Re w_k) and m_(k+N/2) =
+// round(Im w_k) (half to even), each reduced mod every limb of the map.
+__global__ void __launch_bounds__(256) enc_round_kernel(const Cplx *x, double sc, uint32_t log_ns, const ModC *mc,
+                                                        const LimbMap m, uint64_t *out, uint32_t n) {
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t ns = 1u << log_ns;
+    if (k >= ns) return;
+    const Cplx v = x[log_ns ? __brev(k) >> (32 - log_ns) : 0];
+    const int64_t c[2] = {(int64_t)rint(v.re * sc), (int64_t)rint(v.im * sc)};
+    for (uint32_t i = 0; i < m.count; ++i) {
+        const uint64_t q = mc[m.mod[i]].q;
+        uint64_t *row = out + (size_t)m.out_off[i] * n;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const uint64_t a = c[h] < 0 ? (uint64_t)0 - (uint64_t)c[h] : (uint64_t)c[h];
+            uint64_t r = a % q;
+            if (c[h] < 0 && r) r = q - r;
+            row[k + h * ns] = r;
+        }
+    }
+}
+
+hipError_t launch_enc_fft(const Ctx &c, Cplx *x, hipStream_t s) {
+    const uint32_t ns = c.n / 2;
+    if (ns < 2) return hipErrorInvalidValue;
+    ProfScope ps(c, HKS_K_ELEMENTWISE, s);
+    for (uint32_t mm = ns; mm >= 2; mm /= 2)
+        hipLaunchKernelGGL(enc_stage_kernel, dim3((ns / 2 + 255) / 256), dim3(256), 0, s, x, c.enc_rotg,
+                           c.enc_roots, ns, mm);
+    return hipGetLastError();
+}
+
+hipError_t launch_enc_round(const Ctx &c, const Cplx *x, double scale, const LimbMap &m, uint64_t *out,
+                            hipStream_t s) {
+    const uint32_t ns = c.n / 2;
+    ProfScope ps(c, HKS_K_ELEMENTWISE, s);
+    hipLaunchKernelGGL(enc_round_kernel, dim3((ns + 255) / 256), dim3(256), 0, s, x, scale / ns, c.log_n - 1, c.mc,
+                       m, out, c.n);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ elementwise
 
 struct EwArgs {

@@ -715,7 +715,8 @@ hipError_t launch_ksk_rows(const Ctx &c, const KskBatch &kb, uint32_t nb, const 
 
 struct MatvecArgs {
     const uint64_t *ext;  // [beta][E][N] extended digits of a_x, evaluation form
-    const uint64_t *ksk[MAXROT];
+    const uint64_t *ax;   // a_x, [level][N] (the diagonal without rotation)
+    const uint64_t *ksk[MAXROT];  // nullptr: the diagonal without rotation (g = 1)
     const uint64_t *pt[MAXROT];  // diagonals over Q_level U P, [level + K][N]
     uint32_t galois[MAXROT];
     const uint64_t *b;     // b_x, [level][N]
@@ -731,7 +732,9 @@ struct MatvecArgs {
 // rotations (the paper's PtMatVecMult with the ModDown hoisted): for each i,
 // u, v = KSKInnerProd of the extended digits gathered through g_i with
 // ksk_i; then a_y += M_i u and b_y += M_i (v + [P]_t b_rot) where b_rot is b
-// gathered through g_i (q limbs only).  The sums stay in registers; q limbs
+// gathered through g_i (q limbs only).  A term without a key is the diagonal
+// of offset 0: (u, v) = ([P]_t a_x, 0) on the q limbs, 0 on the P limbs
+// (PModUp of the input, no key switch).  The sums stay in registers; q limbs
 // store them, P limbs run ModDown's inverse row pass first.
 template <int LOGS, int E>
 __global__ void __launch_bounds__((Tile<LOGS, ROW_LINES, false, E>::NT)) ksk_matvec_kernel(const MatvecArgs a) {
@@ -764,7 +767,18 @@ __global__ void __launch_bounds__((Tile<LOGS, ROW_LINES, false, E>::NT)) ksk_mat
         uint64_t u[E], v[E];
 #pragma unroll
         for (int e = 0; e < E; ++e) u[e] = v[e] = 0;
-        for (uint32_t jd = 0; jd < a.beta; ++jd) {
+        if (!a.ksk[i]) {
+            if (!is_p) {
+                const ulonglong2 *ar = reinterpret_cast<const ulonglong2 *>(a.ax + (size_t)tgt * N + slot0);
+#pragma unroll
+                for (int c = 0; c < E / 2; ++c) {
+                    const ulonglong2 x = ar[c];
+                    u[2 * c] = mul_shoup(x.x, pm.w, pm.wp, q);
+                    u[2 * c + 1] = mul_shoup(x.y, pm.w, pm.wp, q);
+                }
+            }
+        }
+        for (uint32_t jd = 0; a.ksk[i] && jd < a.beta; ++jd) {
             const uint64_t *src = a.ext + ((size_t)jd * a.E + tgt) * N;
             const ulonglong2 *k0 =
                 reinterpret_cast<const ulonglong2 *>(a.ksk[i] + ((size_t)(2 * jd) * KL + mod) * N + slot0);
@@ -811,11 +825,12 @@ __global__ void __launch_bounds__((Tile<LOGS, ROW_LINES, false, E>::NT)) ksk_mat
 }
 
 hipError_t launch_ksk_matvec(const Ctx &c, const uint64_t *ext, uint32_t level, uint32_t r, const uint32_t *galois,
-                             const uint64_t *const *ksk, const uint64_t *const *pt, const uint64_t *b, uint64_t *uq,
-                             uint64_t *pc, hipStream_t s) {
+                             const uint64_t *const *ksk, const uint64_t *const *pt, const uint64_t *ax,
+                             const uint64_t *b, uint64_t *uq, uint64_t *pc, hipStream_t s) {
     if (r == 0 || r > (uint32_t)MAXROT) return hipErrorInvalidValue;
     MatvecArgs a{};
     a.ext = ext;
+    a.ax = ax;
     for (uint32_t i = 0; i < r; ++i) {
         a.ksk[i] = ksk[i];
         a.pt[i] = pt[i];

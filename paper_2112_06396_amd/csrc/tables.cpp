@@ -226,7 +226,21 @@ int build_tables(Ctx &c) {
         }
     }
 
+    // Encoding: the rotation group g_j = 5^j mod 2N (j < N/2) and the 2N-th
+    // roots of unity exp(2 pi i t / 2N), rounded from long double.
+    const uint32_t ns = c.n / 2, m2 = 2 * c.n;
+    std::vector<uint32_t> rotg(ns);
+    for (uint32_t j = 0, x = 1; j < ns; ++j, x = (uint32_t)((uint64_t)x * 5 % m2)) rotg[j] = x;
+    std::vector<Cplx> roots(m2);
+    const long double two_pi = 6.283185307179586476925286766559005768L;
+    for (uint32_t t = 0; t < m2; ++t) {
+        const long double a = two_pi * (long double)t / (long double)m2;
+        roots[t] = Cplx{(double)cosl(a), (double)sinl(a)};
+    }
+
     int rc;
+    if ((rc = upload(&c.enc_rotg, rotg))) return rc;
+    if ((rc = upload(&c.enc_roots, roots))) return rc;
     if ((rc = upload(&c.tw_fwd, twf))) return rc;
     if ((rc = upload(&c.tw_inv, twi))) return rc;
     if ((rc = upload(&c.mc, mc))) return rc;
@@ -248,7 +262,7 @@ int build_tables(Ctx &c) {
 void free_tables(Ctx &c) {
     void *ptrs[] = {c.tw_fwd, c.tw_inv, c.mc, c.li_plain, c.li_modup, c.li_moddown, c.conv_modup,
                     c.conv_moddown, c.pinv, c.pmod, c.rs_qinv, c.rs_h, c.ws,
-                    c.li_nm, c.conv_nm, c.sinv_nm};
+                    c.li_nm, c.conv_nm, c.sinv_nm, c.enc_rotg, c.enc_roots};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     c.tw_fwd = c.tw_inv = nullptr;
@@ -260,6 +274,8 @@ void free_tables(Ctx &c) {
     c.conv_nm = nullptr;
     c.sinv_nm = nullptr;
     c.rs_h = nullptr;
+    c.enc_rotg = nullptr;
+    c.enc_roots = nullptr;
     c.ws = nullptr;
 }
 

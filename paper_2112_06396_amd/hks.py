@@ -43,7 +43,7 @@ EXPORTS = (
     "hks_create", "hks_destroy", "hks_query", "hks_ntt", "hks_intt", "hks_automorph",
     "hks_modup", "hks_ksk_inner", "hks_moddown", "hks_keyswitch", "hks_rotate", "hks_hrotate",
     "hks_batch_rotate", "hks_rescale", "hks_ptmult", "hks_mult_relin", "hks_batch_mult_relin", "hks_new_mult",
-    "hks_add",
+    "hks_encode", "hks_add",
     "hks_expand_key_a", "hks_rotate_seeded", "hks_batch_rotate_seeded", "hks_ptmatvec", "hks_prof_enable",
     "hks_prof_read",
 )
@@ -122,6 +122,7 @@ def lib():
             "hks_batch_mult_relin": (_i32, [_vp, _u32, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _u32,
                                             ctypes.POINTER(_vp), _i32, ctypes.POINTER(_vp), _vp]),
             "hks_new_mult": (_i32, [_vp, _vp, _vp, _u32, _vp, _vp, _vp]),
+            "hks_encode": (_i32, [_vp, _vp, ctypes.c_double, _u32, _i32, _vp, _vp]),
             "hks_add": (_i32, [_vp, _vp, _vp, _u32, _u32, _vp, _vp]),
             "hks_expand_key_a": (_i32, [_vp, ctypes.c_uint64, _vp, _vp]),
             "hks_ptmatvec": (_i32, [_vp, _vp, _u32, _u32, ctypes.POINTER(_u32), ctypes.POINTER(_vp),
@@ -328,11 +329,12 @@ def hks_batch_mult_relin(ctx, ct1s, ct2s, level: int, rlks, rescale: bool, outs,
 
 
 def hks_ptmatvec(ctx, ct, level: int, galois, ksks, pts, ct_out, stream=None):
+    """ksks[i] = None (with galois[i] = 1): the diagonal without rotation."""
     r = len(galois)
     if len(ksks) != r or len(pts) != r:
         raise ValueError("galois, ksks and pts must have the same length")
     ga = (_u32 * r)(*[int(g) for g in galois])
-    ka = (_vp * r)(*[_ptr(k) for k in ksks])
+    ka = (_vp * r)(*[_vp() if k is None else _ptr(k) for k in ksks])
     pa = (_vp * r)(*[_ptr(p) for p in pts])
     _check("hks_ptmatvec", lib().hks_ptmatvec(ctx.handle, _ptr(ct), level, r, ga, ka, pa, _ptr(ct_out),
                                               _stream(stream)))
@@ -363,6 +365,18 @@ def hks_batch_rotate_seeded(ctx, cts, level: int, galois, seeds, ksk_bs, outs, s
 def hks_new_mult(ctx, ct1, ct2, level: int, rlk, ct_out, stream=None):
     _check("hks_new_mult", lib().hks_new_mult(ctx.handle, _ptr(ct1), _ptr(ct2), level, _ptr(rlk), _ptr(ct_out),
                                               _stream(stream)))
+
+
+def hks_encode(ctx, slots, scale: float, level: int, with_p: bool, pt_out, stream=None):
+    """slots: complex128 (or float64 [.., 2]) device tensor of N/2 values."""
+    if slots.dtype == torch.complex128:
+        slots = torch.view_as_real(slots)
+    if slots.dtype != torch.float64 or not slots.is_cuda or not slots.is_contiguous():
+        raise ValueError("slots must be a contiguous complex128/float64 device tensor")
+    if slots.numel() != ctx.n:
+        raise ValueError("expected N/2 complex slots")
+    _check("hks_encode", lib().hks_encode(ctx.handle, ctypes.c_void_p(slots.data_ptr()), float(scale), level,
+                                          1 if with_p else 0, _ptr(pt_out), _stream(stream)))
 
 
 def hks_add(ctx, x, y, level: int, n_poly: int, out, stream=None):

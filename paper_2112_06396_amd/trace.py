@@ -33,8 +33,34 @@ class Plan:
     out_level: int = 0
 
 
+def dft_offsets(log_slots: int, iters: int, inverse: bool) -> list:
+    """Rotation offsets of the factored homomorphic DFT over n = 2^log_slots
+    slots, per PtMatVecMult in application order (Sec. 3).  The DFT is a
+    product of log_slots radix-2 stages whose butterflies pair slots m/2
+    apart (m = 2, 4, ..., n; SlotToCoeff applies them upward, CoeffToSlot the
+    inverses downward); `iters` groups of consecutive stages, balanced with
+    the larger groups last, are multiplied out.  A group whose stages pair
+    slots h_1, ..., h_r apart has non-zero diagonals exactly at the offsets
+    sum_t e_t h_t mod n, e_t in {-1, 0, 1}; offset d is the rotation right by
+    d, offset 0 the diagonal without rotation."""
+    n = 1 << log_slots
+    base, extra = divmod(log_slots, iters)
+    sizes = [base] * (iters - extra) + [base + 1] * extra
+    halves = [1 << s for s in range(log_slots)]  # m/2 for m = 2 .. n
+    if inverse:
+        halves = halves[::-1]
+    out, pos = [], 0
+    for r in sizes:
+        offs = {0}
+        for h in halves[pos:pos + r]:
+            offs = {(o + e * h) % n for o in offs for e in (-1, 0, 1)}
+        out.append(sorted(offs))
+        pos += r
+    return out
+
+
 def bootstrap_plan(top: int, counts=(12, 12, 16), strides=(1, 32, 1024), evalmod_levels: int = 20,
-                   hoisted: bool = False, new_mult: bool = False) -> Plan:
+                   hoisted: bool = False, new_mult: bool = False, dft=None) -> Plan:
     """Ops (kind, ...) over ciphertext buffers named by strings:
       ("hrotate", src, level, [k...], [dst...])
       ("ptmult", src, diag, level, dst)
@@ -45,38 +71,51 @@ def bootstrap_plan(top: int, counts=(12, 12, 16), strides=(1, 32, 1024), evalmod
       ("newmult", a, b, level, dst)       -> level - 1 (Sec. 5.1, one ModDown by P q_(level-1))
     With `hoisted`, each linear stage is one ptmatvec (Sec. 5.2) instead of
     an HRotate followed by PtMult and Add per rotation; with `new_mult`, the
-    EvalMod products are NewMult instead of Mult + Rescale."""
+    EvalMod products are NewMult instead of Mult + Rescale.  With
+    dft = (log_slots, iters), the linear stages have the factored DFT's
+    rotation offsets (dft_offsets: CoeffToSlot, then SlotToCoeff) instead of
+    `counts` x `strides`; offset 0 is a diagonal without rotation (a PtMult
+    of the input, no key)."""
     p = Plan(top=top)
     level, x = top, "x0"
     p.buffers.add(x)
     nxt = iter(f"s{i}" for i in range(10 ** 6))
 
-    def linear_stage(sign, stage_id):
+    if dft is not None:
+        groups_c = dft_offsets(dft[0], dft[1], True)
+        groups_s = dft_offsets(dft[0], dft[1], False)
+    else:
+        groups_c = [[stride * (i + 1) for i in range(cnt)] for cnt, stride in zip(counts, strides)]
+        groups_s = [[-k for k in ks] for ks in groups_c]
+
+    def linear_stage(groups, stage_id):
         nonlocal level, x
-        for si, (cnt, stride) in enumerate(zip(counts, strides)):
-            ks = [sign * stride * (i + 1) for i in range(cnt)]
-            rs = [f"r{i}" for i in range(cnt)]
+        for si, ks in enumerate(groups):
+            cnt = len(ks)
+            rot = [k for k in ks if k != 0]
+            rs = {k: f"r{i}" for i, k in enumerate(rot)}
             ds = [f"{stage_id}{si}_{i}" for i in range(cnt)]
             p.diagonals.extend(ds)
-            p.key_switches += cnt
-            for k in ks:
+            p.key_switches += len(rot)
+            for k in rot:
                 if k not in p.rotations:
                     p.rotations.append(k)
             if hoisted:
-                p.ops.append(("ptmatvec", x, level, ks, ds, "acc"))
+                p.ops.append(("ptmatvec", x, level, list(ks), ds, "acc"))
             else:
-                p.ops.append(("hrotate", x, level, ks, rs))
-                for i in range(cnt):
-                    p.ops.append(("ptmult", rs[i], ds[i], level, "acc" if i == 0 else "t"))
+                if rot:
+                    p.ops.append(("hrotate", x, level, rot, [rs[k] for k in rot]))
+                for i, k in enumerate(ks):
+                    p.ops.append(("ptmult", rs[k] if k else x, ds[i], level, "acc" if i == 0 else "t"))
                     if i:
                         p.ops.append(("add", "acc", "t", level, "acc"))
-                p.buffers.update(rs + ["t"])
+                p.buffers.update(list(rs.values()) + ["t"])
             y = next(nxt)
             p.ops.append(("rescale", "acc", level, y))
             p.buffers.update(["acc", y])
             x, level = y, level - 1
 
-    linear_stage(+1, "c")
+    linear_stage(groups_c, "c")
     y = x
     for _ in range(evalmod_levels):
         a, b = next(nxt), next(nxt)
@@ -86,7 +125,7 @@ def bootstrap_plan(top: int, counts=(12, 12, 16), strides=(1, 32, 1024), evalmod
         p.key_switches += 2
         p.buffers.update([a, b])
         x, y, level = a, b, level - 1
-    linear_stage(-1, "s")
+    linear_stage(groups_s, "s")
     p.out, p.out_level = x, level
     return p
 
@@ -130,8 +169,8 @@ def run_plan(ctx, plan: Plan, bufs: TraceBuffers, diag, keys, rlk, stream=None, 
         kind = op[0]
         if kind == "ptmatvec":
             _, src, level, ks, ds, dst = op
-            gals = [hks.hks_galois_for_rotation(k, ctx.log_n) for k in ks]
-            hks.hks_ptmatvec(ctx, bufs.view(src, level), level, gals, [keys[k] for k in ks],
+            gals = [hks.hks_galois_for_rotation(k, ctx.log_n) if k else 1 for k in ks]
+            hks.hks_ptmatvec(ctx, bufs.view(src, level), level, gals, [keys[k] if k else None for k in ks],
                              [diag_ext[(d, level)] for d in ds], bufs.view(dst, level), stream)
             continue
         if kind == "hrotate":

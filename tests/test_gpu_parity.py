@@ -420,9 +420,9 @@ def _oracle_plan(pr, plan, x0, diag, keys, rlk):
             bufs[dst] = O.ptmult(pr, bufs[src], diag[d][:level], level, False)
         elif kind == "ptmatvec":
             _, src, level, ks, ds, dst = op
-            gals = [pow(5, -k, 2 * pr.n) for k in ks]
+            gals = [pow(5, -k, 2 * pr.n) if k else 1 for k in ks]
             pts = [np.concatenate([diag[d][:level], diag[d][pr.L:]]) for d in ds]
-            bufs[dst] = O.ptmatvec(pr, bufs[src], level, gals, [keys[k] for k in ks], pts)
+            bufs[dst] = O.ptmatvec(pr, bufs[src], level, gals, [keys[k] if k else None for k in ks], pts)
         elif kind == "add":
             _, a, b, level, dst = op
             bufs[dst] = np.stack([O.add_vec(bufs[a][i], bufs[b][i], pr.log_n, pr.q[:level]) for i in range(2)])
