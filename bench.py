@@ -246,7 +246,42 @@ def extras(args, ctx, hks, synth, cts, ksks, outs, gal, key_mods, n, plain_value
     del hdiag, hext, hbufs
     log(f"[bench] trace ({plan.key_switches} key-switches, L 35->9): eager {res['trace_ks_per_s_eager']:.0f} ks/s, "
         f"graph {res['trace_ks_per_s_graph']:.0f} ks/s")
-    del gr, bufs, diag, tkeys, rlk
+    del gr, bufs, diag, tkeys
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    # the trace with the factored DFT's own rotation offsets (2^15 slots, fftIter = 3: CoeffToSlot
+    # 32/63/63 diagonals, SlotToCoeff 63/63/32, 155 rotation keys resident), diagonals encoded on the
+    # device from random slot vectors; hoisted PtMatVecMult + NewMult vs HRotate + PtMult + Mult
+    dplan = trace.bootstrap_plan(35, hoisted=True, new_mult=True, dft=(LOG_N - 1, 3))
+    dkeys = {k: synth.device_residues(pq, (3, 2), n, 4000 + i) for i, k in enumerate(dplan.rotations)}
+    gz = torch.Generator(device="cuda")
+    gz.manual_seed(12)
+    ddiag = {}
+    for d in dplan.diagonals:
+        zs = torch.rand((n // 2, 2), generator=gz, dtype=torch.float64, device="cuda") * 2 - 1
+        ddiag[d] = hks.empty((len(pq), n))
+        hks.hks_encode(tctx, zs, 2.0 ** 40, 35, True, ddiag[d])
+    dext = trace.ext_diagonals(dplan, ddiag, 35)
+    dbufs = trace.TraceBuffers(dplan, n)
+    dbufs.view("x0", 35).copy_(synth.device_residues(pq[:35], (2,), n, 13))
+    torch.cuda.synchronize()
+    log(f"[bench] DFT trace: {len(dkeys)} rotation keys, {len(ddiag)} encoded diagonals resident")
+    res["dft_trace_ks_per_s_eager"] = rate(
+        lambda i: trace.run_plan(tctx, dplan, dbufs, {}, dkeys, rlk, diag_ext=dext), dplan.key_switches, 3)
+    gr = trace.capture(tctx, dplan, dbufs, {}, dkeys, rlk, diag_ext=dext)
+    res["dft_trace_ks_per_s_graph"] = rate(lambda i: gr.replay(), dplan.key_switches, 3)
+    del gr, dext, dbufs
+    uplan = trace.bootstrap_plan(35, dft=(LOG_N - 1, 3))
+    ubufs = trace.TraceBuffers(uplan, n)
+    ubufs.view("x0", 35).copy_(synth.device_residues(pq[:35], (2,), n, 13))
+    res["dft_trace_unhoisted_ks_per_s_eager"] = rate(
+        lambda i: trace.run_plan(tctx, uplan, ubufs, ddiag, dkeys, rlk), uplan.key_switches, 2)
+    res["dft_trace"] = {"key_switches": dplan.key_switches, "rotation_keys": len(dplan.rotations),
+                        "diagonals": [len(op[3]) for op in dplan.ops if op[0] == "ptmatvec"], "levels": "35->9"}
+    log(f"[bench] DFT trace ({dplan.key_switches} key-switches): hoisted + NewMult eager "
+        f"{res['dft_trace_ks_per_s_eager']:.0f} ks/s, graph {res['dft_trace_ks_per_s_graph']:.0f}; "
+        f"HRotate + PtMult + Mult {res['dft_trace_unhoisted_ks_per_s_eager']:.0f}")
+    del ubufs, ddiag, dkeys, rlk
     torch.cuda.synchronize()
     tctx.close()
     torch.cuda.empty_cache()
