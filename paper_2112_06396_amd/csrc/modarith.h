@@ -68,6 +68,7 @@ __device__ __forceinline__ uint64_t reduce64(uint64_t x, uint64_t q, uint64_t mu
 struct Acc128 {
     uint64_t lo, hi;
     __device__ __forceinline__ Acc128() : lo(0), hi(0) {}
+    __device__ __forceinline__ explicit Acc128(uint64_t v) : lo(v), hi(0) {}
     __device__ __forceinline__ void mac(uint64_t a, uint64_t b) {
         u128 p = (u128)a * b;
         uint64_t plo = (uint64_t)p, phi = (uint64_t)(p >> 64);

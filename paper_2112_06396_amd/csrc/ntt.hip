@@ -565,11 +565,24 @@ ksk_rows_kernel(const KskRowArgs a) {
     thread_coords<LOGS, ROW_LINES, false, E>(threadIdx.x, line, t);
     const uint32_t lg = tile * ROW_LINES + line;
 
+    // KSKInnerProd sums: with LAZY (8 elements per thread, where the
+    // registers allow) the digits' 128-bit products are added without
+    // reduction (each < 2^106: row-pass outputs < 2^56 times key words
+    // < 2^50) and reduced once, folding every 16 digits to stay below 2^111
+    constexpr bool LAZY = E == 8;
     uint64_t u[E], v[E];
+    Acc128 ua[LAZY ? E : 1], va[LAZY ? E : 1];
 #pragma unroll
     for (int e = 0; e < E; ++e) u[e] = v[e] = 0;
     bool lds_used = false;
     for (uint32_t jd = 0; jd < a.beta; ++jd) {
+        if (LAZY && jd && (jd & 15) == 0) {
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                ua[LAZY ? e : 0] = Acc128(reduce128(ua[LAZY ? e : 0].hi, ua[LAZY ? e : 0].lo, q, mcv.mu, mcv.nq));
+                va[LAZY ? e : 0] = Acc128(reduce128(va[LAZY ? e : 0].hi, va[LAZY ? e : 0].lo, q, mcv.mu, mcv.nq));
+            }
+        }
         const bool dir = a.all_direct || jd == own;
         uint64_t xv[E];
         if (dir) {
@@ -611,10 +624,24 @@ ksk_rows_kernel(const KskRowArgs a) {
                 kv0 = k0[c];
             }
             const ulonglong2 kv1 = k1[c];
-            u[2 * c] = add_mod(u[2 * c], mul_mod(xv[2 * c], kv0.x, q, mcv.mu, mcv.nq), q);
-            u[2 * c + 1] = add_mod(u[2 * c + 1], mul_mod(xv[2 * c + 1], kv0.y, q, mcv.mu, mcv.nq), q);
-            v[2 * c] = add_mod(v[2 * c], mul_mod(xv[2 * c], kv1.x, q, mcv.mu, mcv.nq), q);
-            v[2 * c + 1] = add_mod(v[2 * c + 1], mul_mod(xv[2 * c + 1], kv1.y, q, mcv.mu, mcv.nq), q);
+            if constexpr (LAZY) {
+                ua[2 * c].mac(xv[2 * c], kv0.x);
+                ua[2 * c + 1].mac(xv[2 * c + 1], kv0.y);
+                va[2 * c].mac(xv[2 * c], kv1.x);
+                va[2 * c + 1].mac(xv[2 * c + 1], kv1.y);
+            } else {
+                u[2 * c] = add_mod(u[2 * c], mul_mod(xv[2 * c], kv0.x, q, mcv.mu, mcv.nq), q);
+                u[2 * c + 1] = add_mod(u[2 * c + 1], mul_mod(xv[2 * c + 1], kv0.y, q, mcv.mu, mcv.nq), q);
+                v[2 * c] = add_mod(v[2 * c], mul_mod(xv[2 * c], kv1.x, q, mcv.mu, mcv.nq), q);
+                v[2 * c + 1] = add_mod(v[2 * c + 1], mul_mod(xv[2 * c + 1], kv1.y, q, mcv.mu, mcv.nq), q);
+            }
+        }
+    }
+    if constexpr (LAZY) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            u[e] = reduce128(ua[LAZY ? e : 0].hi, ua[LAZY ? e : 0].lo, q, mcv.mu, mcv.nq);
+            v[e] = reduce128(va[LAZY ? e : 0].hi, va[LAZY ? e : 0].lo, q, mcv.mu, mcv.nq);
         }
     }
     if constexpr (NM) {
