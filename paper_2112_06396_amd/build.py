@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhks.so")
-SOURCES = ["ntt.hip", "kernels.hip", "tables.cpp", "abi.cpp"]
+SOURCES = ["ntt.hip", "kernels.hip", "tables.cpp", "abi.cpp", "ks32.hip", "ctx32.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

@@ -792,6 +792,10 @@ __global__ void __launch_bounds__((Tile<LOGS, ROW_LINES, false, E>::NT)) ksk_mat
     for (uint32_t i = 0; i < a.r; ++i) {
         const uint32_t g = a.galois[i];
         uint64_t u[E], v[E];
+        // the digits' products (canonical times canonical, < 2^100) summed in
+        // 128 bits and reduced once per rotation (beta < 2^11 keeps the sum
+        // below Barrett's 2^111 bound)
+        Acc128 ua[E], va[E];
 #pragma unroll
         for (int e = 0; e < E; ++e) u[e] = v[e] = 0;
         if (!a.ksk[i]) {
@@ -815,10 +819,17 @@ __global__ void __launch_bounds__((Tile<LOGS, ROW_LINES, false, E>::NT)) ksk_mat
                 const ulonglong2 kv0 = k0[c], kv1 = k1[c];
                 const uint64_t x0 = src[aut_eval_src(slot0 + 2 * c, g, a.n)];
                 const uint64_t x1 = src[aut_eval_src(slot0 + 2 * c + 1, g, a.n)];
-                u[2 * c] = add_mod(u[2 * c], mul_mod(x0, kv0.x, q, mcv.mu, mcv.nq), q);
-                u[2 * c + 1] = add_mod(u[2 * c + 1], mul_mod(x1, kv0.y, q, mcv.mu, mcv.nq), q);
-                v[2 * c] = add_mod(v[2 * c], mul_mod(x0, kv1.x, q, mcv.mu, mcv.nq), q);
-                v[2 * c + 1] = add_mod(v[2 * c + 1], mul_mod(x1, kv1.y, q, mcv.mu, mcv.nq), q);
+                ua[2 * c].mac(x0, kv0.x);
+                ua[2 * c + 1].mac(x1, kv0.y);
+                va[2 * c].mac(x0, kv1.x);
+                va[2 * c + 1].mac(x1, kv1.y);
+            }
+        }
+        if (a.ksk[i]) {
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                u[e] = reduce128(ua[e].hi, ua[e].lo, q, mcv.mu, mcv.nq);
+                v[e] = reduce128(va[e].hi, va[e].lo, q, mcv.mu, mcv.nq);
             }
         }
         const ulonglong2 *mi = reinterpret_cast<const ulonglong2 *>(a.pt[i] + (size_t)tgt * N + slot0);

@@ -48,6 +48,9 @@ EXPORTS = (
     "hks_prof_read",
 )
 
+# every symbol declared in include/hks32.h (the 32-bit-word key-switch)
+EXPORTS32 = ("hks32_create", "hks32_destroy", "hks32_ntt", "hks32_intt", "hks32_rotate")
+
 HKS_K_NTT_FWD_COLS = 0
 HKS_K_NTT_FWD_ROWS = 1
 HKS_K_NTT_INV_ROWS = 2
@@ -80,6 +83,17 @@ class _Params(ctypes.Structure):
         ("q", ctypes.POINTER(ctypes.c_uint64)),
         ("p", ctypes.POINTER(ctypes.c_uint64)),
         ("max_batch", ctypes.c_uint32),
+    ]
+
+
+class _Params32(ctypes.Structure):
+    _fields_ = [
+        ("log_n", ctypes.c_uint32),
+        ("L", ctypes.c_uint32),
+        ("K", ctypes.c_uint32),
+        ("dnum", ctypes.c_uint32),
+        ("q", ctypes.POINTER(ctypes.c_uint32)),
+        ("p", ctypes.POINTER(ctypes.c_uint32)),
     ]
 
 
@@ -130,6 +144,11 @@ def lib():
             "hks_rotate_seeded": (_i32, [_vp, _vp, _u32, _u32, ctypes.c_uint64, _vp, _vp, _vp]),
             "hks_batch_rotate_seeded": (_i32, [_vp, _u32, ctypes.POINTER(_vp), _u32, ctypes.POINTER(_u32), u64p,
                                                ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp]),
+            "hks32_create": (_i32, [ctypes.POINTER(_Params32), _i32, ctypes.POINTER(_vp)]),
+            "hks32_destroy": (None, [_vp]),
+            "hks32_ntt": (_i32, [_vp, _vp, _u32, _u32, _vp]),
+            "hks32_intt": (_i32, [_vp, _vp, _u32, _u32, _vp]),
+            "hks32_rotate": (_i32, [_vp, _vp, _u32, _u32, _vp, _vp, _vp]),
             "hks_prof_enable": (_i32, [_vp, _u32]),
             "hks_prof_read": (_i32, [_vp, _i32, ctypes.POINTER(ctypes.c_double), u64p]),
         }
@@ -401,6 +420,79 @@ def hks_prof_read(ctx, kernel_class: int):
 
 
 # ---------------------------------------------------------------- tensor helpers
+
+class Context32:
+    """Owns an hks32_ctx: the key-switch in 32-bit words (primes below 2^30)."""
+
+    def __init__(self, log_n: int, q, p, dnum: int, device: int = 0):
+        self.q = [int(v) for v in q]
+        self.p = [int(v) for v in p]
+        self.log_n, self.L, self.K, self.dnum = int(log_n), len(self.q), len(self.p), int(dnum)
+        qa = (ctypes.c_uint32 * self.L)(*self.q)
+        pa = (ctypes.c_uint32 * self.K)(*self.p)
+        prm = _Params32(self.log_n, self.L, self.K, self.dnum, qa, pa)
+        h = ctypes.c_void_p()
+        _check("hks32_create", lib().hks32_create(ctypes.byref(prm), int(device), ctypes.byref(h)))
+        self._h = h
+        self.n = 1 << self.log_n
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise RuntimeError("context destroyed")
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            lib().hks32_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _ptr32(t: torch.Tensor):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch tensor")
+    if t.dtype not in (torch.int32, torch.uint32):
+        raise TypeError(f"expected 32-bit integer tensor, got {t.dtype}")
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("tensor must be a contiguous GPU tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def hks32_ntt(ctx, x, first_mod: int, n_limbs: int, stream=None):
+    _check("hks32_ntt", lib().hks32_ntt(ctx.handle, _ptr32(x), first_mod, n_limbs, _stream(stream)))
+
+
+def hks32_intt(ctx, x, first_mod: int, n_limbs: int, stream=None):
+    _check("hks32_intt", lib().hks32_intt(ctx.handle, _ptr32(x), first_mod, n_limbs, _stream(stream)))
+
+
+def hks32_rotate(ctx, ct, level: int, galois: int, ksk, ct_out, stream=None):
+    _check("hks32_rotate", lib().hks32_rotate(ctx.handle, _ptr32(ct), level, galois, _ptr32(ksk), _ptr32(ct_out),
+                                              _stream(stream)))
+
+
+def to_device32(a, device="cuda") -> torch.Tensor:
+    """numpy array of residues below 2^32 -> contiguous int32 GPU tensor (bit copy)."""
+    import numpy as np
+    a = np.ascontiguousarray(np.asarray(a).astype(np.uint32))
+    return torch.from_numpy(a.view(np.int32)).to(device)
+
+
+def to_host32(t: torch.Tensor):
+    """32-bit GPU tensor -> numpy uint64 array of the same residues."""
+    import numpy as np
+    return t.view(torch.int32).cpu().numpy().view(np.uint32).astype(np.uint64)
+
+
+def empty32(shape, device="cuda") -> torch.Tensor:
+    return torch.empty(shape, dtype=torch.int32, device=device)
+
 
 def to_device(a, device="cuda") -> torch.Tensor:
     """numpy uint64 array -> contiguous torch.uint64 tensor on the GPU (bit copy)."""

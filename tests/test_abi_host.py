@@ -21,10 +21,10 @@ def hks():
     return H
 
 
-def _declared():
-    src = open(os.path.join(ROOT, "include", "hks.h")).read()
+def _declared(header="hks.h", prefix="hks_"):
+    src = open(os.path.join(ROOT, "include", header)).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(hks_[a-z0-9_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(" + prefix + r"[a-z0-9_]+)\s*\(", src)))
 
 
 def test_every_declared_symbol_is_exported(hks):
@@ -34,6 +34,11 @@ def test_every_declared_symbol_is_exported(hks):
     for name in declared:
         assert hasattr(lib, name), name
     assert sorted(hks.EXPORTS) == declared
+    declared32 = _declared("hks32.h", "hks32_")
+    assert len(declared32) == 5
+    for name in declared32:
+        assert hasattr(lib, name), name
+    assert sorted(hks.EXPORTS32) == declared32
 
 
 def test_gen_primes_matches_oracle_rule(hks):
@@ -92,3 +97,32 @@ def test_calls_reject_null_context(hks):
     out = ctypes.c_uint64()
     assert lib.hks_query(None, hks.HKS_Q_N, 0, ctypes.byref(out)) == hks.HKS_EINVAL
     lib.hks_destroy(None)
+
+
+def _create32(hks, log_n, q, p, dnum):
+    qa = (ctypes.c_uint32 * len(q))(*q)
+    pa = (ctypes.c_uint32 * len(p))(*p)
+    prm = hks._Params32(log_n, len(q), len(p), dnum, qa, pa)
+    h = ctypes.c_void_p()
+    return hks.lib().hks32_create(ctypes.byref(prm), 0, ctypes.byref(h))
+
+
+def test_create32_rejects_invalid_parameters(hks):
+    """The 32-bit-word context: primes must lie in (2^20, 2^30), be 1 mod 2N,
+    prime and distinct; K >= alpha; dnum in [1, L]."""
+    primes = hks.hks_gen_primes(30, 17, 12)
+    assert all(v < (1 << 30) for v in primes)
+    q, p = primes[:6], primes[6:9]
+    EINVAL = hks.HKS_EINVAL
+    assert _create32(hks, 9, q, p, 3) == EINVAL
+    assert _create32(hks, 12, q, p[:1], 3) == EINVAL              # K < alpha
+    assert _create32(hks, 12, q, p, 0) == EINVAL
+    assert _create32(hks, 12, q[:5] + [q[0]], p, 3) == EINVAL     # repeated
+    assert _create32(hks, 12, q[:5] + [q[5] + 2], p, 3) == EINVAL
+    big = hks.hks_gen_primes(31, 17, 1)                           # 2^30 < q < 2^31: 4q overflows a word
+    assert _create32(hks, 12, q[:5] + [v & 0xFFFFFFFF for v in big], p, 3) == EINVAL
+    lib = hks.lib()
+    assert lib.hks32_create(None, 0, ctypes.byref(ctypes.c_void_p())) == EINVAL
+    assert lib.hks32_rotate(None, None, 1, 5, None, None, None) == EINVAL
+    assert lib.hks32_ntt(None, None, 0, 1, None) == EINVAL
+    lib.hks32_destroy(None)

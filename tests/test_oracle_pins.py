@@ -288,6 +288,29 @@ def test_rotate_decrypts_to_automorphed_message(cfg):
     assert bound < int(mods[0]) // 1024
 
 
+@pytest.mark.parametrize("cfg", [(10, 8, 3, 3, 8), (11, 9, 4, 3, 5)])
+def test_rotate_decrypts_with_30_bit_primes(cfg):
+    """The oracle's key switch is written for any prime below 2^62: with
+    30-bit primes (the 32-bit-word variant, Sec. 5.4) a Rotate still
+    decrypts to the automorphed message within the noise bound."""
+    log_n, L, K, dnum, level = cfg
+    pr = O.make_params(log_n, L, K, dnum, bits=30)
+    assert all(int(q) < (1 << 30) for q in list(pr.q) + list(pr.p))
+    g = synth.rng(4300 + level)
+    s = synth.ternary(g, pr.n)
+    gal = pow(5, -3, 2 * pr.n)
+    ksk = O.rotation_key(pr, s, gal, g)
+    ct = O.encrypt(pr, s, synth.small_uniform(g, pr.n, 1 << 20), level, g)
+    out = O.rotate(pr, ct, level, gal, ksk)
+    mods = pr.q[:level]
+    diff = O.sub_vec(O.decrypt_coef(pr, s, out, level),
+                     O.automorph(O.decrypt_coef(pr, s, ct, level), pr.log_n, mods, gal, eval_domain=False),
+                     pr.log_n, mods)
+    bound = O.ks_noise_bound(pr, level, s)
+    assert O.centered_small(diff, mods, bound) is not None
+    assert bound < int(mods[0]) // 64
+
+
 def test_rotate_with_wrong_key_fails_decryption():
     pr, g, s = _setup(10, 6, 2, 3, 55)
     gal = pow(5, -1, 2 * pr.n)
