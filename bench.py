@@ -285,8 +285,54 @@ def extras(args, ctx, hks, synth, cts, ksks, outs, gal, key_mods, n, plain_value
     torch.cuda.synchronize()
     tctx.close()
     torch.cuda.empty_cache()
+    res["w32"] = w32_extra(args, hks, synth, torch.cuda.current_stream())
     res["serving"] = serving_extra(args, hks, synth)
     return res
+
+
+def w32_extra(args, hks, synth, stream):
+    """The same Rotate in 32-bit words (Sec. 5.4): N = 2^16, 30-bit primes,
+    L = 40, K = 14, dnum = 3 (log2 QP = 1620 bits against 1600 for the 50-bit
+    L = 24, K = 8), level 40, a pool of (ciphertext, key) pairs as for the
+    main line."""
+    import torch
+    L32, K32 = 40, 14
+    pq = hks.hks_gen_primes(30, LOG_N + 1, L32 + K32)
+    c32 = hks.Context32(LOG_N, pq[:L32], pq[L32:], DNUM)
+    n = 1 << LOG_N
+
+    def d32(mods, lead, seed):
+        return synth.device_residues(mods, lead, n, seed).view(torch.int64).to(torch.int32)
+
+    cts = [d32(pq[:L32], (2,), 9100 + i) for i in range(args.pool)]
+    keys = [d32(pq, (DNUM, 2), 9200 + i) for i in range(args.pool)]
+    outs = [hks.empty32((2, L32, n)) for _ in range(args.pool)]
+    gal = hks.hks_galois_for_rotation(1, LOG_N)
+
+    def step(i):
+        j = i % args.pool
+        hks.hks32_rotate(c32, cts[j], L32, gal, keys[j], outs[j], stream)
+
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for i in range(args.steps):
+        step(i)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    key_bytes = keys[0].numel() * 4
+    compulsory = key_bytes + 2 * cts[0].numel() * 4
+    del cts, keys, outs
+    torch.cuda.synchronize()
+    c32.close()
+    torch.cuda.empty_cache()
+    log(f"[bench] 32-bit words (L=40, K=14, 30-bit primes): {ms * 1e3:.1f} us/step, {1e3 / ms:.0f} ks/s")
+    return {"rotate_ks_per_s": 1e3 / ms, "us_per_step": ms * 1e3, "key_mib": key_bytes / 2 ** 20,
+            "hbm_compulsory_bytes_per_step": compulsory,
+            "config": {"log_n": LOG_N, "L": L32, "K": K32, "dnum": DNUM, "level": L32, "prime_bits": 30}}
 
 
 def serving_extra(args, hks, synth):
@@ -356,6 +402,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--w32-only", action="store_true",
+                    help="time only the 32-bit-word Rotate (for profiling) and print its figures")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one plain copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -372,6 +420,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.init()
+    if args.w32_only:
+        print(json.dumps(w32_extra(args, hks, synth, torch.cuda.current_stream())), flush=True)
+        return
     pq = hks.hks_gen_primes(50, LOG_N + 1, L + K)
     q, p = pq[:L], pq[L:]
     ctx = hks.Context(LOG_N, q, p, DNUM, max_batch=args.batch)

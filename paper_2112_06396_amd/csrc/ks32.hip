@@ -178,6 +178,40 @@ __device__ __forceinline__ void coords32(int tid, int &line, int &t) {
     }
 }
 
+// Load / store a thread's E32 elements of line lg in layout [LO, HI); a row
+// pass in a [0, b) layout owns E32 consecutive words: four 16-byte accesses.
+template <bool COLS, int LO, int HI>
+__device__ __forceinline__ void load32(uint32_t (&x)[E32], const uint32_t *__restrict__ src, int t, uint32_t lg,
+                                       uint32_t n2) {
+    if (!COLS && LO == 0) {
+        const uint4 *p = reinterpret_cast<const uint4 *>(src + (lg << n2) + E32 * t);
+#pragma unroll
+        for (int c = 0; c < E32 / 4; ++c) {
+            const uint4 v = p[c];
+            x[4 * c] = v.x;
+            x[4 * c + 1] = v.y;
+            x[4 * c + 2] = v.z;
+            x[4 * c + 3] = v.w;
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < E32; ++e) x[e] = src[jdx32<COLS>(lg, k32<LO, HI>(t, e), n2)];
+    }
+}
+
+template <bool COLS, int LO, int HI>
+__device__ __forceinline__ void store32(const uint32_t (&x)[E32], uint32_t *__restrict__ dst, int t, uint32_t lg,
+                                        uint32_t n2) {
+    if (!COLS && LO == 0) {
+        uint4 *p = reinterpret_cast<uint4 *>(dst + (lg << n2) + E32 * t);
+#pragma unroll
+        for (int c = 0; c < E32 / 4; ++c) p[c] = make_uint4(x[4 * c], x[4 * c + 1], x[4 * c + 2], x[4 * c + 3]);
+    } else {
+#pragma unroll
+        for (int e = 0; e < E32; ++e) dst[jdx32<COLS>(lg, k32<LO, HI>(t, e), n2)] = x[e];
+    }
+}
+
 // ------------------------------------------------------------------ NTT passes
 
 enum { P32_PLAIN = 0, P32_GATHER = 1, P32_REDUCE = 2, P32_EPI = 3 };
@@ -217,11 +251,19 @@ __global__ void __launch_bounds__((Tile32<LOGS, LINES, COLS>::NT)) pass32_kernel
     coords32<LOGS, LINES, COLS>(threadIdx.x, line, t);
     const uint32_t lg = tile * LINES + line;
 
+    // ModDown epilogue operand u, issued before the pass input
+    uint32_t uv[E32];
+    if (IO == P32_EPI)
+        load32<COLS, OUT_LO, OUT_HI>(uv, a.uq + y * a.uq_ys + (size_t)a.m.cidx[li] * N, t, lg, a.n2);
     uint32_t x[E32];
+    if (IO == P32_GATHER) {
 #pragma unroll
-    for (int e = 0; e < E32; ++e) {
-        const uint32_t j = jdx32<COLS>(lg, k32<IN_LO, IN_HI>(t, e), a.n2);
-        x[e] = src[(IO == P32_GATHER && a.galois != 1) ? aut_eval_src(j, a.galois, a.n) : j];
+        for (int e = 0; e < E32; ++e) {
+            const uint32_t j = jdx32<COLS>(lg, k32<IN_LO, IN_HI>(t, e), a.n2);
+            x[e] = src[a.galois != 1 ? aut_eval_src(j, a.galois, a.n) : j];
+        }
+    } else {
+        load32<COLS, IN_LO, IN_HI>(x, src, t, lg, a.n2);
     }
     const Last32 fold = (!FWD && COLS) ? a.fold[a.m.cidx[li]] : Last32{};
     if constexpr (COLS)
@@ -231,14 +273,13 @@ __global__ void __launch_bounds__((Tile32<LOGS, LINES, COLS>::NT)) pass32_kernel
 
     if (IO == P32_EPI) {
         const uint32_t ui = a.m.cidx[li];
-        const uint32_t *u = a.uq + y * a.uq_ys + (size_t)ui * N;
         const uint32_t *bb = (y == 1 && a.b) ? a.b + (size_t)ui * N : nullptr;
         const Shoup32 pi = a.pinv[ui];
 #pragma unroll
         for (int e = 0; e < E32; ++e) {
             const uint32_t j = jdx32<COLS>(lg, k32<OUT_LO, OUT_HI>(t, e), a.n2);
             const uint32_t z = csub32(csub32(x[e], 2 * q), q);
-            uint32_t r = csub32(shoup32(u[j] + q - z, pi.w, pi.wp, q), q);
+            uint32_t r = csub32(shoup32(uv[e] + q - z, pi.w, pi.wp, q), q);
             if (bb) r = csub32(r + bb[a.galois != 1 ? aut_eval_src(j, a.galois, a.n) : j], q);
             x[e] = r;
         }
@@ -249,8 +290,7 @@ __global__ void __launch_bounds__((Tile32<LOGS, LINES, COLS>::NT)) pass32_kernel
 #pragma unroll
         for (int e = 0; e < E32; ++e) x[e] = csub32(x[e], q);  // canonical coefficients
     }
-#pragma unroll
-    for (int e = 0; e < E32; ++e) dst[jdx32<COLS>(lg, k32<OUT_LO, OUT_HI>(t, e), a.n2)] = x[e];
+    store32<COLS, OUT_LO, OUT_HI>(x, dst, t, lg, a.n2);
 }
 
 template <bool COLS, bool FWD, int IO>
@@ -468,8 +508,7 @@ __global__ void __launch_bounds__((Tile32<LOGS, ROW32, false>::NT)) ksk32_kernel
             }
         } else {
             const uint32_t *src = a.ext + ((size_t)jd * a.E + tgt) * N;
-#pragma unroll
-            for (int e = 0; e < E32; ++e) xv[e] = src[jdx32<false>(lg, k32<P::HL, P::HH>(t, e), a.n2)];
+            load32<false, P::HL, P::HH>(xv, src, t, lg, a.n2);
             if (lds_used) __syncthreads();
             pass32<LOGS, ROW32, false, true>(xv, lds, line, t, q, Tw32Rows{a.twf + (size_t)mod * N, lg, a.n1},
                                              Last32{});
