@@ -18,20 +18,23 @@
 //               mu = floor(2^64 / q) and two conditional subtractions reduce.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "device_util.h"
 #include "ks32.h"
 
 namespace hks {
 namespace w32 {
 
-constexpr int E32 = 16;        // elements per thread
+constexpr int E32 = 16;        // elements per thread of the NTT passes
+constexpr int EK32 = 16;       // elements per thread of the key-switch kernel (8 measured slower)
 constexpr int COL32 = 32;      // columns per column tile (128-byte segments)
 constexpr int ROW32 = 8;       // rows per row tile
 
-template <int LOGS, int LINES, bool COLS>
+template <int LOGS, int LINES, bool COLS, int E = E32>
 struct Tile32 {
     static constexpr int S = 1 << LOGS;
-    static constexpr int T = S / E32;
+    static constexpr int T = S / E;
     static constexpr int NT = LINES * T;
     static constexpr int ROWP = S + S / 32;
     static constexpr int COLP = LINES + 1;
@@ -41,21 +44,27 @@ struct Tile32 {
     }
 };
 
-// Phases of four stages over the LOGS bits of the in-line index k: the
-// forward pass runs [LOGS-4, LOGS) then [0, LOGS-4) (LOGS <= 8), the inverse
-// the reverse.
-template <int LOGS>
+// Phases of R = log2(E) stages over the LOGS bits of the in-line index k:
+// P0 = [LOGS-R, LOGS), P1 = [max(LOGS-2R, 0), LOGS-R), P2 = [0, LOGS-2R)
+// when LOGS > 2R.  The forward pass runs P0, P1 (, P2); the inverse the
+// reverse.  HL/HH is the high phase P0, LL/LH the lowest (P2, or P1).
+template <int LOGS, int E = E32>
 struct Ph32 {
-    static_assert(LOGS > 4 && LOGS <= 8, "two phases of up to four stages");
-    static constexpr int HL = LOGS - 4, HH = LOGS, LL = 0, LH = LOGS - 4;
+    static constexpr int R = E == 16 ? 4 : 3;
+    static_assert(E == 8 || E == 16, "8 or 16 elements per thread");
+    static_assert(LOGS > R && LOGS <= 3 * R, "two or three phases");
+    static constexpr bool THREE = LOGS > 2 * R;
+    static constexpr int HL = LOGS - R, HH = LOGS;
+    static constexpr int ML = THREE ? LOGS - 2 * R : 0, MH = LOGS - R;  // P1
+    static constexpr int LL = 0, LH = THREE ? LOGS - 2 * R : LOGS - R;
 };
 
 // element e of thread t in the layout of phase [LO, HI) (see the 64-bit
 // kernels: the thread holds all values of bits [LO, HI) for E >> (HI-LO)
 // values of the other bits)
-template <int LO, int HI>
+template <int LO, int HI, int E = E32>
 __device__ __forceinline__ int k32(int t, int e) {
-    constexpr int B = HI - LO, G = E32 >> B;
+    constexpr int B = HI - LO, G = E >> B;
     const int v = e & ((1 << B) - 1), g = e >> B;
     const int r = t * G + g;
     return ((r >> LO) << HI) | (v << LO) | (r & ((1 << LO) - 1));
@@ -91,9 +100,9 @@ struct Tw32Rows {
     }
 };
 
-template <int LOGS, bool FWD, bool FOLD, int LO, int HI, typename TW>
-__device__ __forceinline__ void phase32(uint32_t (&x)[E32], int t, uint32_t q, const TW &tws, const Last32 &fold) {
-    constexpr int B = HI - LO, H = E32 / 2;
+template <int LOGS, bool FWD, bool FOLD, int LO, int HI, int E, typename TW>
+__device__ __forceinline__ void phase32(uint32_t (&x)[E], int t, uint32_t q, const TW &tws, const Last32 &fold) {
+    constexpr int B = HI - LO, H = E / 2;
     const uint32_t q2 = 2 * q;
 #pragma unroll
     for (int st = 0; st < B; ++st) {
@@ -104,13 +113,13 @@ __device__ __forceinline__ void phase32(uint32_t (&x)[E32], int t, uint32_t q, c
         Shoup32 wc[H];
 #pragma unroll
         for (int key = 0; key < H; ++key) {
-            if (key < (E32 >> (vb + 1)) && !fold_stage) {
-                const uint32_t k = (uint32_t)k32<LO, HI>(t, key << (vb + 1));
+            if (key < (E >> (vb + 1)) && !fold_stage) {
+                const uint32_t k = (uint32_t)k32<LO, HI, E>(t, key << (vb + 1));
                 wc[key] = tws(ls, k >> (bit + 1));
             }
         }
 #pragma unroll
-        for (int e = 0; e < E32; ++e) {
+        for (int e = 0; e < E; ++e) {
             if ((e >> vb) & 1) continue;
             const int e2 = e + (1 << vb);
             const Shoup32 w = wc[(e >> (vb + 1)) & (H - 1)];
@@ -133,60 +142,74 @@ __device__ __forceinline__ void phase32(uint32_t (&x)[E32], int t, uint32_t q, c
     }
 }
 
-template <int LOGS, int LINES, bool COLS, int LO, int HI>
-__device__ __forceinline__ void put32(uint32_t *lds, const uint32_t (&x)[E32], int line, int t) {
+template <int LOGS, int LINES, bool COLS, int LO, int HI, int E>
+__device__ __forceinline__ void put32(uint32_t *lds, const uint32_t (&x)[E], int line, int t) {
 #pragma unroll
-    for (int e = 0; e < E32; ++e) lds[Tile32<LOGS, LINES, COLS>::idx(line, k32<LO, HI>(t, e))] = x[e];
+    for (int e = 0; e < E; ++e) lds[Tile32<LOGS, LINES, COLS, E>::idx(line, k32<LO, HI, E>(t, e))] = x[e];
 }
-template <int LOGS, int LINES, bool COLS, int LO, int HI>
-__device__ __forceinline__ void get32(const uint32_t *lds, uint32_t (&x)[E32], int line, int t) {
+template <int LOGS, int LINES, bool COLS, int LO, int HI, int E>
+__device__ __forceinline__ void get32(const uint32_t *lds, uint32_t (&x)[E], int line, int t) {
 #pragma unroll
-    for (int e = 0; e < E32; ++e) x[e] = lds[Tile32<LOGS, LINES, COLS>::idx(line, k32<LO, HI>(t, e))];
+    for (int e = 0; e < E; ++e) x[e] = lds[Tile32<LOGS, LINES, COLS, E>::idx(line, k32<LO, HI, E>(t, e))];
 }
 
 // A whole pass in registers: forward enters in [HL, HH) and leaves in
 // [LL, LH); inverse the other way round.  The caller synchronizes before the
 // LDS tile is written again.
-template <int LOGS, int LINES, bool COLS, bool FWD, typename TW>
-__device__ __forceinline__ void pass32(uint32_t (&x)[E32], uint32_t *lds, int line, int t, uint32_t q, const TW &tws,
+template <int LOGS, int LINES, bool COLS, bool FWD, int E, typename TW>
+__device__ __forceinline__ void pass32(uint32_t (&x)[E], uint32_t *lds, int line, int t, uint32_t q, const TW &tws,
                                        const Last32 &fold) {
-    using P = Ph32<LOGS>;
+    using P = Ph32<LOGS, E>;
     constexpr bool FOLD = !FWD && COLS;
     if (FWD) {
-        phase32<LOGS, true, false, P::HL, P::HH>(x, t, q, tws, fold);
-        put32<LOGS, LINES, COLS, P::HL, P::HH>(lds, x, line, t);
+        phase32<LOGS, true, false, P::HL, P::HH, E>(x, t, q, tws, fold);
+        put32<LOGS, LINES, COLS, P::HL, P::HH, E>(lds, x, line, t);
         __syncthreads();
-        get32<LOGS, LINES, COLS, P::LL, P::LH>(lds, x, line, t);
-        phase32<LOGS, true, false, P::LL, P::LH>(x, t, q, tws, fold);
+        get32<LOGS, LINES, COLS, P::ML, P::MH, E>(lds, x, line, t);
+        phase32<LOGS, true, false, P::ML, P::MH, E>(x, t, q, tws, fold);
+        if constexpr (P::THREE) {
+            __syncthreads();
+            put32<LOGS, LINES, COLS, P::ML, P::MH, E>(lds, x, line, t);
+            __syncthreads();
+            get32<LOGS, LINES, COLS, P::LL, P::LH, E>(lds, x, line, t);
+            phase32<LOGS, true, false, P::LL, P::LH, E>(x, t, q, tws, fold);
+        }
     } else {
-        phase32<LOGS, false, FOLD, P::LL, P::LH>(x, t, q, tws, fold);
-        put32<LOGS, LINES, COLS, P::LL, P::LH>(lds, x, line, t);
+        if constexpr (P::THREE) {
+            phase32<LOGS, false, FOLD, P::LL, P::LH, E>(x, t, q, tws, fold);
+            put32<LOGS, LINES, COLS, P::LL, P::LH, E>(lds, x, line, t);
+            __syncthreads();
+            get32<LOGS, LINES, COLS, P::ML, P::MH, E>(lds, x, line, t);
+            __syncthreads();
+        }
+        phase32<LOGS, false, FOLD, P::ML, P::MH, E>(x, t, q, tws, fold);
+        put32<LOGS, LINES, COLS, P::ML, P::MH, E>(lds, x, line, t);
         __syncthreads();
-        get32<LOGS, LINES, COLS, P::HL, P::HH>(lds, x, line, t);
-        phase32<LOGS, false, FOLD, P::HL, P::HH>(x, t, q, tws, fold);
+        get32<LOGS, LINES, COLS, P::HL, P::HH, E>(lds, x, line, t);
+        phase32<LOGS, false, FOLD, P::HL, P::HH, E>(x, t, q, tws, fold);
     }
 }
 
-template <int LOGS, int LINES, bool COLS>
+template <int LOGS, int LINES, bool COLS, int E = E32>
 __device__ __forceinline__ void coords32(int tid, int &line, int &t) {
     if (COLS) {
         line = tid % LINES;
         t = tid / LINES;
     } else {
-        t = tid % Tile32<LOGS, LINES, COLS>::T;
-        line = tid / Tile32<LOGS, LINES, COLS>::T;
+        t = tid % Tile32<LOGS, LINES, COLS, E>::T;
+        line = tid / Tile32<LOGS, LINES, COLS, E>::T;
     }
 }
 
 // Load / store a thread's E32 elements of line lg in layout [LO, HI); a row
 // pass in a [0, b) layout owns E32 consecutive words: four 16-byte accesses.
-template <bool COLS, int LO, int HI>
-__device__ __forceinline__ void load32(uint32_t (&x)[E32], const uint32_t *__restrict__ src, int t, uint32_t lg,
+template <bool COLS, int LO, int HI, int E = E32>
+__device__ __forceinline__ void load32(uint32_t (&x)[E], const uint32_t *__restrict__ src, int t, uint32_t lg,
                                        uint32_t n2) {
     if (!COLS && LO == 0) {
-        const uint4 *p = reinterpret_cast<const uint4 *>(src + (lg << n2) + E32 * t);
+        const uint4 *p = reinterpret_cast<const uint4 *>(src + (lg << n2) + E * t);
 #pragma unroll
-        for (int c = 0; c < E32 / 4; ++c) {
+        for (int c = 0; c < E / 4; ++c) {
             const uint4 v = p[c];
             x[4 * c] = v.x;
             x[4 * c + 1] = v.y;
@@ -195,20 +218,20 @@ __device__ __forceinline__ void load32(uint32_t (&x)[E32], const uint32_t *__res
         }
     } else {
 #pragma unroll
-        for (int e = 0; e < E32; ++e) x[e] = src[jdx32<COLS>(lg, k32<LO, HI>(t, e), n2)];
+        for (int e = 0; e < E; ++e) x[e] = src[jdx32<COLS>(lg, k32<LO, HI, E>(t, e), n2)];
     }
 }
 
-template <bool COLS, int LO, int HI>
-__device__ __forceinline__ void store32(const uint32_t (&x)[E32], uint32_t *__restrict__ dst, int t, uint32_t lg,
+template <bool COLS, int LO, int HI, int E = E32>
+__device__ __forceinline__ void store32(const uint32_t (&x)[E], uint32_t *__restrict__ dst, int t, uint32_t lg,
                                         uint32_t n2) {
     if (!COLS && LO == 0) {
-        uint4 *p = reinterpret_cast<uint4 *>(dst + (lg << n2) + E32 * t);
+        uint4 *p = reinterpret_cast<uint4 *>(dst + (lg << n2) + E * t);
 #pragma unroll
-        for (int c = 0; c < E32 / 4; ++c) p[c] = make_uint4(x[4 * c], x[4 * c + 1], x[4 * c + 2], x[4 * c + 3]);
+        for (int c = 0; c < E / 4; ++c) p[c] = make_uint4(x[4 * c], x[4 * c + 1], x[4 * c + 2], x[4 * c + 3]);
     } else {
 #pragma unroll
-        for (int e = 0; e < E32; ++e) dst[jdx32<COLS>(lg, k32<LO, HI>(t, e), n2)] = x[e];
+        for (int e = 0; e < E; ++e) dst[jdx32<COLS>(lg, k32<LO, HI, E>(t, e), n2)] = x[e];
     }
 }
 
@@ -383,11 +406,14 @@ struct Conv32Args {
     uint32_t *out;
     const uint32_t *conv;
     const Mod32 *mc;
-    uint32_t n, level, L, K, alpha;
+    uint32_t n, level, L, K, alpha, tgroups;
 };
 
-// One thread = one coefficient: its source residues are loaded once and every
-// target limb is produced from them (64-bit exact sums, one reduction).
+// One thread = one coefficient and one group of target limbs: its source
+// residues are loaded once and the group's targets are produced from them
+// (64-bit exact sums, one reduction).  blockIdx.z picks the group (targets
+// [z T, (z+1) T) of the nt, T = ceil(nt / tgroups)), so that a launch has
+// several blocks per CU; the groups re-read the sources from L2.
 //   MODUP:   digit j = blockIdx.y, sources y[j alpha ..), targets t of
 //            Q_level U P outside the digit -> out[(j E + t) N], row j E + t;
 //   ModDown: polynomial p = blockIdx.y, sources the K P limbs at in + p K N,
@@ -420,7 +446,9 @@ __global__ void __launch_bounds__(256) conv32_kernel(const Conv32Args a) {
     for (int i = 0; i < MAXS; ++i) y[i] = (i < (int)ns) ? src[(size_t)i * N] : 0;
     __syncthreads();
     uint32_t *dst = MODUP ? a.out + c : a.out + (size_t)j * a.L * N + c;
-    for (uint32_t tt = 0; tt < nt; ++tt) {
+    const uint32_t per = (nt + a.tgroups - 1) / a.tgroups;
+    const uint32_t t0 = blockIdx.z * per, t1 = min(nt, t0 + per);
+    for (uint32_t tt = t0; tt < t1; ++tt) {
         if (MODUP && tt >= lo && tt < lo + ns) continue;
         const uint32_t *kr = kc + tt * MAXS;
         uint64_t acc = 0;
@@ -438,16 +466,21 @@ static hipError_t launch_conv32_t(const Conv32Args &a, uint32_t ns, dim3 grid, h
     return hipGetLastError();
 }
 
+// target groups per launch: about 8 targets per thread, at least one group
+static uint32_t conv_groups(uint32_t nt) { return std::max<uint32_t>(1, nt / 8); }
+
 hipError_t launch32_conv_modup(const Ctx32 &c, const uint32_t *y, uint32_t level, uint32_t *ext, hipStream_t s) {
-    Conv32Args a{y, ext, c.conv_modup + c.conv_modup_off[level], c.mc, c.log_n, level, c.L, c.K, c.alpha};
     if (level + c.K > 256) return hipErrorInvalidValue;
+    const uint32_t g = conv_groups(level + c.K);
+    Conv32Args a{y, ext, c.conv_modup + c.conv_modup_off[level], c.mc, c.log_n, level, c.L, c.K, c.alpha, g};
     const uint32_t beta = (level + c.alpha - 1) / c.alpha;
-    return launch_conv32_t<true>(a, c.alpha, dim3((c.n + 255) / 256, beta), s);
+    return launch_conv32_t<true>(a, c.alpha, dim3((c.n + 255) / 256, beta, g), s);
 }
 
 hipError_t launch32_conv_moddown(const Ctx32 &c, const uint32_t *pc, uint32_t level, uint32_t *z, hipStream_t s) {
-    Conv32Args a{pc, z, c.conv_moddown, c.mc, c.log_n, level, c.L, c.K, c.alpha};
-    return launch_conv32_t<false>(a, c.K, dim3((c.n + 255) / 256, 2), s);
+    const uint32_t g = conv_groups(level);
+    Conv32Args a{pc, z, c.conv_moddown, c.mc, c.log_n, level, c.L, c.K, c.alpha, g};
+    return launch_conv32_t<false>(a, c.K, dim3((c.n + 255) / 256, 2, g), s);
 }
 
 // ------------------------------------------------------------------ KSKInnerProd
@@ -467,10 +500,10 @@ struct Ksk32Args {
 // own limb gathered from a through the automorphism), reduced to [0, q),
 // times the key rows, summed exactly in 64 bits (folded every 16 digits).
 // q limbs store u, v; P limbs run ModDown's inverse row pass first.
-template <int LOGS>
-__global__ void __launch_bounds__((Tile32<LOGS, ROW32, false>::NT)) ksk32_kernel(const Ksk32Args a) {
-    using TL = Tile32<LOGS, ROW32, false>;
-    using P = Ph32<LOGS>;
+template <int LOGS, int E>
+__global__ void __launch_bounds__((Tile32<LOGS, ROW32, false, E>::NT)) ksk32_kernel(const Ksk32Args a) {
+    using TL = Tile32<LOGS, ROW32, false, E>;
+    using P = Ph32<LOGS, E>;
     __shared__ uint32_t lds[TL::WORDS];
     const uint32_t tiles = (1u << a.n1) / ROW32;
     const uint32_t tgt = (blockIdx.x / tiles + a.level) % a.E;
@@ -482,44 +515,44 @@ __global__ void __launch_bounds__((Tile32<LOGS, ROW32, false>::NT)) ksk32_kernel
     const size_t KL = (size_t)a.L + a.K;
     const uint32_t own = tgt < a.level ? tgt / a.alpha : 0xffffffffu;
     int line, t;
-    coords32<LOGS, ROW32, false>(threadIdx.x, line, t);
+    coords32<LOGS, ROW32, false, E>(threadIdx.x, line, t);
     const uint32_t lg = tile * ROW32 + line;
-    const uint32_t slot0 = (lg << a.n2) + E32 * t;  // forward output layout: E32 consecutive slots
+    const uint32_t slot0 = (lg << a.n2) + E * t;  // forward output layout: E consecutive slots
 
-    uint64_t ua[E32], va[E32];
+    uint64_t ua[E], va[E];
 #pragma unroll
-    for (int e = 0; e < E32; ++e) ua[e] = va[e] = 0;
+    for (int e = 0; e < E; ++e) ua[e] = va[e] = 0;
     bool lds_used = false;
     for (uint32_t jd = 0; jd < a.beta; ++jd) {
         if (jd && (jd & 15) == 0) {
 #pragma unroll
-            for (int e = 0; e < E32; ++e) {
+            for (int e = 0; e < E; ++e) {
                 ua[e] = reduce64_32(ua[e], mc);
                 va[e] = reduce64_32(va[e], mc);
             }
         }
-        uint32_t xv[E32];
+        uint32_t xv[E];
         if (jd == own) {
             const uint32_t *src = a.a + (size_t)tgt * N;
 #pragma unroll
-            for (int e = 0; e < E32; ++e) {
+            for (int e = 0; e < E; ++e) {
                 const uint32_t j = slot0 + e;
                 xv[e] = src[a.galois != 1 ? aut_eval_src(j, a.galois, a.n) : j];
             }
         } else {
             const uint32_t *src = a.ext + ((size_t)jd * a.E + tgt) * N;
-            load32<false, P::HL, P::HH>(xv, src, t, lg, a.n2);
+            load32<false, P::HL, P::HH, E>(xv, src, t, lg, a.n2);
             if (lds_used) __syncthreads();
             pass32<LOGS, ROW32, false, true>(xv, lds, line, t, q, Tw32Rows{a.twf + (size_t)mod * N, lg, a.n1},
                                              Last32{});
             lds_used = true;
 #pragma unroll
-            for (int e = 0; e < E32; ++e) xv[e] = csub32(csub32(xv[e], 2 * q), q);
+            for (int e = 0; e < E; ++e) xv[e] = csub32(csub32(xv[e], 2 * q), q);
         }
         const uint4 *k0 = reinterpret_cast<const uint4 *>(a.ksk + ((size_t)(2 * jd) * KL + mod) * N + slot0);
         const uint4 *k1 = reinterpret_cast<const uint4 *>(a.ksk + ((size_t)(2 * jd + 1) * KL + mod) * N + slot0);
 #pragma unroll
-        for (int c4 = 0; c4 < E32 / 4; ++c4) {
+        for (int c4 = 0; c4 < E / 4; ++c4) {
             const uint4 p0 = k0[c4], p1 = k1[c4];
             const uint32_t kv0[4] = {p0.x, p0.y, p0.z, p0.w}, kv1[4] = {p1.x, p1.y, p1.z, p1.w};
 #pragma unroll
@@ -529,9 +562,9 @@ __global__ void __launch_bounds__((Tile32<LOGS, ROW32, false>::NT)) ksk32_kernel
             }
         }
     }
-    uint32_t u[E32], v[E32];
+    uint32_t u[E], v[E];
 #pragma unroll
-    for (int e = 0; e < E32; ++e) {
+    for (int e = 0; e < E; ++e) {
         u[e] = reduce64_32(ua[e], mc);
         v[e] = reduce64_32(va[e], mc);
     }
@@ -539,7 +572,7 @@ __global__ void __launch_bounds__((Tile32<LOGS, ROW32, false>::NT)) ksk32_kernel
         uint4 *du = reinterpret_cast<uint4 *>(a.uq + (size_t)tgt * N + slot0);
         uint4 *dv = reinterpret_cast<uint4 *>(a.uq + ((size_t)a.level + tgt) * N + slot0);
 #pragma unroll
-        for (int c4 = 0; c4 < E32 / 4; ++c4) {
+        for (int c4 = 0; c4 < E / 4; ++c4) {
             du[c4] = make_uint4(u[4 * c4], u[4 * c4 + 1], u[4 * c4 + 2], u[4 * c4 + 3]);
             dv[c4] = make_uint4(v[4 * c4], v[4 * c4 + 1], v[4 * c4 + 2], v[4 * c4 + 3]);
         }
@@ -550,12 +583,12 @@ __global__ void __launch_bounds__((Tile32<LOGS, ROW32, false>::NT)) ksk32_kernel
     if (lds_used) __syncthreads();
     pass32<LOGS, ROW32, false, false>(u, lds, line, t, q, twi, Last32{});
 #pragma unroll
-    for (int e = 0; e < E32; ++e) a.pc[(size_t)kp * N + jdx32<false>(lg, k32<P::HL, P::HH>(t, e), a.n2)] = u[e];
+    for (int e = 0; e < E; ++e) a.pc[(size_t)kp * N + jdx32<false>(lg, k32<P::HL, P::HH, E>(t, e), a.n2)] = u[e];
     __syncthreads();
     pass32<LOGS, ROW32, false, false>(v, lds, line, t, q, twi, Last32{});
 #pragma unroll
-    for (int e = 0; e < E32; ++e)
-        a.pc[((size_t)a.K + kp) * N + jdx32<false>(lg, k32<P::HL, P::HH>(t, e), a.n2)] = v[e];
+    for (int e = 0; e < E; ++e)
+        a.pc[((size_t)a.K + kp) * N + jdx32<false>(lg, k32<P::HL, P::HH, E>(t, e), a.n2)] = v[e];
 }
 
 hipError_t launch32_ksk(const Ctx32 &c, const uint32_t *ext, const uint32_t *a, uint32_t galois, uint32_t level,
@@ -582,11 +615,12 @@ hipError_t launch32_ksk(const Ctx32 &c, const uint32_t *ext, const uint32_t *a, 
     const uint32_t lines = 1u << c.n1;
     if (lines % ROW32) return hipErrorInvalidValue;
     const dim3 grid(k.E * (lines / ROW32));
+    constexpr int E = EK32;
     switch (c.n2) {
-        case 5: hipLaunchKernelGGL((ksk32_kernel<5>), grid, dim3(Tile32<5, ROW32, false>::NT), 0, s, k); break;
-        case 6: hipLaunchKernelGGL((ksk32_kernel<6>), grid, dim3(Tile32<6, ROW32, false>::NT), 0, s, k); break;
-        case 7: hipLaunchKernelGGL((ksk32_kernel<7>), grid, dim3(Tile32<7, ROW32, false>::NT), 0, s, k); break;
-        case 8: hipLaunchKernelGGL((ksk32_kernel<8>), grid, dim3(Tile32<8, ROW32, false>::NT), 0, s, k); break;
+        case 5: hipLaunchKernelGGL((ksk32_kernel<5, E>), grid, dim3(Tile32<5, ROW32, false, E>::NT), 0, s, k); break;
+        case 6: hipLaunchKernelGGL((ksk32_kernel<6, E>), grid, dim3(Tile32<6, ROW32, false, E>::NT), 0, s, k); break;
+        case 7: hipLaunchKernelGGL((ksk32_kernel<7, E>), grid, dim3(Tile32<7, ROW32, false, E>::NT), 0, s, k); break;
+        case 8: hipLaunchKernelGGL((ksk32_kernel<8, E>), grid, dim3(Tile32<8, ROW32, false, E>::NT), 0, s, k); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
