@@ -5,6 +5,8 @@
 // kernels live in ntt.hip.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "device_util.h"
 #include "hks_internal.h"
 #include "modarith.h"
@@ -55,17 +57,20 @@ struct ConvArgs {
     const uint64_t *conv;  // split constants
     const ModC *mc;
     size_t in_bstride, out_bstride;
-    uint32_t n, level, L, K, alpha;
+    uint32_t n, level, L, K, alpha, tgroups;
 };
 
 // Fast basis conversion (NewLimb, Algorithm "ModUp"; also ModDown's step).
 // One thread = one coefficient of one digit: its n_src source residues are
 // loaded once (split into 25-bit halves) and every target limb of the digit
 // is produced from them (the alpha limbs stay on chip for all new limbs).
-//   MODUP:   digit j = blockIdx.y, sources y[j*alpha .. +n_src), targets t of
-//            Q_level U P outside the digit, out[j*E + t], constants row j*E+t;
+//   MODUP:   digit j = blockIdx.y / tgroups, sources y[j*alpha .. +n_src),
+//            targets t of Q_level U P outside the digit, out[j*E + t],
+//            constants row j*E+t;
 //   ModDown: sources the K P limbs, targets the level q limbs, out[t],
 //            constants row t.
+// blockIdx.y % tgroups picks a group of consecutive targets (more blocks for
+// a small launch; the groups re-read the sources from L2).
 template <bool MODUP, int MAXS>
 __global__ void __launch_bounds__(256) conv_kernel(const ConvArgs a) {
     constexpr int MAXT = 80;  // targets of one digit: level + K <= 64
@@ -73,7 +78,7 @@ __global__ void __launch_bounds__(256) conv_kernel(const ConvArgs a) {
     __shared__ ModC mt[MAXT];
     const uint32_t N = 1u << a.n;
     const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
-    const uint32_t j = blockIdx.y, b = blockIdx.z;
+    const uint32_t j = blockIdx.y / a.tgroups, grp = blockIdx.y % a.tgroups, b = blockIdx.z;
     const uint32_t lo = MODUP ? j * a.alpha : 0;
     const uint32_t ns = MODUP ? min(a.alpha, a.level - lo) : a.K;
     const uint32_t E = a.level + a.K;
@@ -98,8 +103,10 @@ __global__ void __launch_bounds__(256) conv_kernel(const ConvArgs a) {
     }
     __syncthreads();
     uint64_t *dst = a.out + b * a.out_bstride + c;
+    const uint32_t per = (nt + a.tgroups - 1) / a.tgroups;
+    const uint32_t t1 = min(nt, (grp + 1) * per);
 #pragma unroll 2
-    for (uint32_t t = 0; t < nt; ++t) {
+    for (uint32_t t = grp * per; t < t1; ++t) {
         if (MODUP && t >= lo && t < lo + ns) continue;
         const ModC m = mt[t];
         const uint64_t *kr = kc + t * MAXS;
@@ -109,6 +116,10 @@ __global__ void __launch_bounds__(256) conv_kernel(const ConvArgs a) {
         dst[(size_t)(MODUP ? j * E + t : t) * N] = acc.reduce(m.q, m.mu, m.nq);
     }
 }
+
+// Target groups of a launch: about 8 targets per thread when the launch is a
+// single step of one or two ciphertexts (a thin grid), else one group.
+static uint32_t conv_groups(uint32_t nt, uint32_t batch) { return batch <= 2 ? std::max<uint32_t>(1, nt / 8) : 1; }
 
 template <bool MODUP>
 static hipError_t launch_conv_t(const ConvArgs &a, uint32_t ns_max, dim3 grid, hipStream_t s) {
@@ -136,8 +147,9 @@ hipError_t launch_conv_modup(const Ctx &c, const uint64_t *y, uint32_t level, ui
     a.K = c.K;
     a.alpha = c.alpha;
     const uint32_t beta = (level + c.alpha - 1) / c.alpha;
+    a.tgroups = conv_groups(level + c.K, batch);
     ProfScope ps(c, HKS_K_CONV, s);
-    return launch_conv_t<true>(a, c.alpha, dim3((c.n + 255) / 256, beta, batch), s);
+    return launch_conv_t<true>(a, c.alpha, dim3((c.n + 255) / 256, beta * a.tgroups, batch), s);
 }
 
 hipError_t launch_conv_moddown(const Ctx &c, const uint64_t *p, uint32_t nt, uint64_t *z, uint32_t batch,
@@ -156,8 +168,9 @@ hipError_t launch_conv_moddown(const Ctx &c, const uint64_t *p, uint32_t nt, uin
     a.L = c.L;
     a.K = ns;      // sources: the ns special limbs
     a.alpha = c.alpha;
+    a.tgroups = conv_groups(nt, batch);
     ProfScope ps(c, HKS_K_CONV, s);
-    return launch_conv_t<false>(a, ns, dim3((c.n + 255) / 256, 1, batch), s);
+    return launch_conv_t<false>(a, ns, dim3((c.n + 255) / 256, a.tgroups, batch), s);
 }
 
 // ------------------------------------------------------------------ seeded key rows
