@@ -56,6 +56,7 @@ extern "C" {
 #define HKS_ENOMEM (-2)       /* device or host allocation failed */
 #define HKS_EHIP (-3)         /* a HIP runtime call or kernel launch failed */
 #define HKS_EUNSUPPORTED (-4) /* valid request outside what this build supports */
+#define HKS_ERANGE (-5)       /* an input residue is not below its modulus (checks on) */
 
 /* hks_query keys */
 #define HKS_Q_N 1              /* ring degree N */
@@ -272,6 +273,36 @@ int hks_encode(hks_ctx *ctx, const double *slots, double scale, uint32_t level, 
  * (elementwise, in place allowed). */
 int hks_add(hks_ctx *ctx, const uint64_t *x, const uint64_t *y, uint32_t level, uint32_t n_poly,
             uint64_t *out, void *stream);
+
+/* ---------------------------------------------------------------- input checks */
+
+/* Canonical-range checks.  With on != 0 every call that reads residues
+ * first checks on the device that each input word (ciphertexts,
+ * plaintexts, keys, NTT operands, over the limbs the call reads) is below
+ * its modulus, and returns HKS_ERANGE without enqueuing its work when one is
+ * not.  The check copies its verdict to the host and synchronizes the
+ * stream, so it is a debugging aid: a call with checks on returns
+ * HKS_EUNSUPPORTED on a capturing stream.  Off by default; the environment
+ * variable HKS_DEBUG_CHECK_CANONICAL (non-empty, not "0") turns it on for
+ * contexts created afterwards. */
+int hks_set_check(hks_ctx *ctx, int on);
+
+/* ---------------------------------------------------------------- graphs */
+
+/* Call sequences recorded once and replayed as one HIP graph (a
+ * bootstrapping-shaped trace of many key-switches, Sec. 3).  The library's
+ * calls allocate nothing and set no memory, so every node of such a graph
+ * is a kernel launch (or the encoder's device copy).  hks_graph_begin
+ * starts capturing `stream` (a created stream, not the legacy default one;
+ * capture mode: this thread only); the calls that follow on that stream are
+ * recorded, not run; hks_graph_end stops the capture and instantiates the
+ * graph; hks_graph_launch replays it on `stream`.  The recorded calls read
+ * and write the same device buffers at every replay. */
+typedef struct hks_graph hks_graph;
+int hks_graph_begin(void *stream);
+int hks_graph_end(void *stream, hks_graph **out);
+int hks_graph_launch(hks_graph *graph, void *stream);
+void hks_graph_destroy(hks_graph *graph);
 
 /* ---------------------------------------------------------------- kernel timing */
 

@@ -15,6 +15,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -68,6 +69,48 @@ struct Lists {
 };
 
 uint32_t beta_of(const Ctx &c, uint32_t level) { return (level + c.alpha - 1) / c.alpha; }
+
+// Canonical-range checks of call inputs (hks_set_check): `reps` copies of
+// `limbs` limbs whose moduli are first_mod, first_mod + 1, ...
+struct Chk {
+    const uint64_t *p;
+    uint32_t reps, limbs, first_mod;
+};
+Chk ct_chk(const uint64_t *p, uint32_t n_poly, uint32_t level) { return Chk{p, n_poly, level, 0}; }
+Chk key_chk(const Ctx &c, const uint64_t *p) { return Chk{p, 2 * c.dnum, c.M, 0}; }
+Chk keyb_chk(const Ctx &c, const uint64_t *p) { return Chk{p, c.dnum, c.M, 0}; }
+// one polynomial over Q_level U P ([level + K][N])
+void ext_chk(const Ctx &c, std::vector<Chk> &v, const uint64_t *p, uint32_t level) {
+    v.push_back(Chk{p, 1, level, 0});
+    v.push_back(Chk{p + (size_t)level * c.n, 1, c.K, c.L});
+}
+
+// With the context's checks on: HKS_ERANGE when a word of the items is not
+// below its modulus (nothing else is enqueued then).  The check reads the
+// result back and synchronizes the stream, so it refuses a capturing stream.
+int check_inputs(Ctx &c, hipStream_t s, const std::vector<Chk> &items) {
+    if (!c.check) return HKS_OK;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess) return HKS_EHIP;
+    if (cs != hipStreamCaptureStatusNone) return HKS_EUNSUPPORTED;
+    if (launch_clear_flag(c.chk_flag, s) != hipSuccess) return HKS_EHIP;
+    for (const Chk &k : items)
+        if (k.p && launch_check(c, k.p, k.reps, k.limbs, k.first_mod, c.chk_flag, s) != hipSuccess) return HKS_EHIP;
+    uint32_t flag = 0;
+    if (hipMemcpyAsync(&flag, c.chk_flag, sizeof(flag), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return HKS_EHIP;
+    return flag ? HKS_ERANGE : HKS_OK;
+}
+
+// (the item list is only built when checks are on)
+#define HKS_CHECKED(ctx, stream, ...)                                                          \
+    do {                                                                                       \
+        if ((ctx).check) {                                                                     \
+            const int _rc = check_inputs(ctx, (hipStream_t)(stream), std::vector<Chk>{__VA_ARGS__}); \
+            if (_rc) return _rc;                                                               \
+        }                                                                                      \
+    } while (0)
 
 // ModUp of the converted limbs (Algorithm "ModUp") of nb polynomials at
 // once; entry b uses workspace slot b:
@@ -244,6 +287,7 @@ const char *status_text(int s) {
         case HKS_ENOMEM: return "out of memory";
         case HKS_EHIP: return "HIP runtime error";
         case HKS_EUNSUPPORTED: return "unsupported";
+        case HKS_ERANGE: return "input residue not below its modulus";
         default: return "unknown status";
     }
 }
@@ -325,6 +369,11 @@ int hks_create(const hks_params *p, int device, hks_ctx **out) {
     c.n2 = p->log_n - c.n1;
     c.mods = mods;
     int rc = build_tables(c);
+    if (rc == HKS_OK && hipMalloc((void **)&c.chk_flag, 256) != hipSuccess) {
+        c.chk_flag = nullptr;
+        rc = HKS_ENOMEM;
+    }
+    if (const char *env = std::getenv("HKS_DEBUG_CHECK_CANONICAL")) c.check = env[0] && std::strcmp(env, "0") != 0;
     if (rc == HKS_OK) {
         const size_t N = c.n, L = c.L, cap = c.batch_cap;
         size_t words[] = {cap * c.st_y(), cap * c.st_ext(), cap * c.st_uv(), cap * c.st_p(), cap * c.st_z(),
@@ -395,6 +444,7 @@ int hks_ntt(hks_ctx *h, uint64_t *x, uint32_t first_mod, uint32_t n_limbs, void 
     GUARD_BEGIN
     if (!h || !x || !aligned(x) || n_limbs == 0 || first_mod + n_limbs > h->c.M) return HKS_EINVAL;
     Ctx &c = h->c;
+    HKS_CHECKED(c, stream, Chk{x, 1, n_limbs, first_mod});
     Lists ls;
     for (uint32_t i = 0; i < n_limbs; ++i) ls.add(i, i, first_mod + i, first_mod + i);
     const BatchIo io = strided_io(x, 0, x, 0, 1);
@@ -406,6 +456,7 @@ int hks_intt(hks_ctx *h, uint64_t *x, uint32_t first_mod, uint32_t n_limbs, void
     GUARD_BEGIN
     if (!h || !x || !aligned(x) || n_limbs == 0 || first_mod + n_limbs > h->c.M) return HKS_EINVAL;
     Ctx &c = h->c;
+    HKS_CHECKED(c, stream, Chk{x, 1, n_limbs, first_mod});
     Lists ls;
     for (uint32_t i = 0; i < n_limbs; ++i) ls.add(i, i, first_mod + i, first_mod + i);
     const BatchIo io = strided_io(x, 0, x, 0, 1);
@@ -424,6 +475,7 @@ int hks_automorph(hks_ctx *h, const uint64_t *x, uint64_t *y, uint32_t first_mod
     const uint64_t *xe = x + (size_t)n_limbs * c.n;
     const uint64_t *ye = y + (size_t)n_limbs * c.n;
     if (x < ye && y < xe) return HKS_EINVAL;
+    HKS_CHECKED(c, stream, Chk{x, 1, n_limbs, first_mod});
     Lists ls;
     for (uint32_t i = 0; i < n_limbs; ++i) ls.add(i, i, first_mod + i, 0);
     return hip_status(ls.run([&](const LimbMap &m) {
@@ -436,6 +488,7 @@ int hks_modup(hks_ctx *h, const uint64_t *a, uint32_t level, uint64_t *ext, void
     GUARD_BEGIN
     if (!h || !a || !ext || !aligned(a) || !aligned(ext) || level < 1 || level > h->c.L) return HKS_EINVAL;
     hipStream_t s = (hipStream_t)stream;
+    HKS_CHECKED(h->c, s, ct_chk(a, 1, level));
     const uint32_t one = 1;
     int rc = do_modup_new(h->c, &a, &one, 1, level, ext, 0, s, false);
     return rc ? rc : do_modup_own(h->c, a, level, 1, ext, s);
@@ -449,6 +502,12 @@ int hks_ksk_inner(hks_ctx *h, const uint64_t *ext, uint32_t level, const uint64_
         level > h->c.L)
         return HKS_EINVAL;
     Ctx &c = h->c;
+    if (c.check) {
+        std::vector<Chk> v{key_chk(c, ksk)};
+        for (uint32_t j = 0; j < beta_of(c, level); ++j) ext_chk(c, v, ext + (size_t)j * (level + c.K) * c.n, level);
+        const int rc = check_inputs(c, (hipStream_t)stream, v);
+        if (rc) return rc;
+    }
     return hip_status(launch_ksk(c, ext, level, beta_of(c, level), ksk, uv, 1, 1, 0, 0, (hipStream_t)stream));
     GUARD_END
 }
@@ -458,6 +517,12 @@ int hks_moddown(hks_ctx *h, const uint64_t *x, uint32_t level, uint64_t *y, void
     if (!h || !x || !y || !aligned(x) || !aligned(y) || level < 1 || level > h->c.L) return HKS_EINVAL;
     Ctx &c = h->c;
     hipStream_t s = (hipStream_t)stream;
+    if (c.check) {
+        std::vector<Chk> v;
+        ext_chk(c, v, x, level);
+        const int rc = check_inputs(c, s, v);
+        if (rc) return rc;
+    }
     // P limbs: inverse row pass into ws_p (the column pass runs in the tail)
     Lists pl;
     for (uint32_t k = 0; k < c.K; ++k) pl.add(level + k, k, c.L + k, k);
@@ -477,6 +542,7 @@ int hks_keyswitch(hks_ctx *h, const uint64_t *d, uint32_t level, const uint64_t 
     if (!h || !d || !ksk || !uv || !aligned(d) || !aligned(ksk) || !aligned(uv) || level < 1 ||
         level > h->c.L)
         return HKS_EINVAL;
+    HKS_CHECKED(h->c, stream, ct_chk(d, 1, level), key_chk(h->c, ksk));
     const KsJob job{d, 1, ksk, uv, nullptr, nullptr};
     return do_keyswitch_jobs(h->c, &job, 1, level, (hipStream_t)stream);
     GUARD_END
@@ -490,6 +556,7 @@ int hks_rotate(hks_ctx *h, const uint64_t *ct, uint32_t level, uint32_t galois, 
         return HKS_EINVAL;
     Ctx &c = h->c;
     if (!valid_galois(c, galois)) return HKS_EINVAL;
+    HKS_CHECKED(c, stream, ct_chk(ct, 2, level), key_chk(c, ksk));
     // (u, v + b_rot): the ModDown epilogue adds b (poly 1 of ct) gathered
     // through the automorph to v
     const KsJob job{ct, galois, ksk, ct_out, nullptr, ct + (size_t)level * c.n};
@@ -508,6 +575,12 @@ int hks_hrotate(hks_ctx *h, const uint64_t *ct, uint32_t level, uint32_t r, cons
             ct_out[i] == ct)
             return HKS_EINVAL;
     hipStream_t s = (hipStream_t)stream;
+    if (c.check) {
+        std::vector<Chk> v{ct_chk(ct, 2, level)};
+        for (uint32_t i = 0; i < r; ++i) v.push_back(key_chk(c, ksk[i]));
+        const int rc = check_inputs(c, s, v);
+        if (rc) return rc;
+    }
     const uint32_t N = c.n, E = level + c.K;
     const size_t pl = (size_t)level * N;
     const uint32_t one = 1;
@@ -558,6 +631,15 @@ int hks_batch_rotate(hks_ctx *h, uint32_t n_ct, const uint64_t *const *ct, uint3
             if (ct_out[i] == ct[j] || (j != i && ct_out[i] == ct_out[j])) return HKS_EINVAL;
         jobs[i] = KsJob{ct[i], galois[i], ksk[i], ct_out[i], nullptr, ct[i] + (size_t)level * c.n};
     }
+    if (c.check) {
+        std::vector<Chk> v;
+        for (uint32_t i = 0; i < n_ct; ++i) {
+            v.push_back(ct_chk(ct[i], 2, level));
+            v.push_back(key_chk(c, ksk[i]));
+        }
+        const int rc = check_inputs(c, (hipStream_t)stream, v);
+        if (rc) return rc;
+    }
     return do_keyswitch_jobs(c, jobs.data(), n_ct, level, (hipStream_t)stream);
     GUARD_END
 }
@@ -578,6 +660,15 @@ int hks_ptmatvec(hks_ctx *h, const uint64_t *ct, uint32_t level, uint32_t r, con
         keyed = keyed || ksk[i];
     }
     hipStream_t s = (hipStream_t)stream;
+    if (c.check) {
+        std::vector<Chk> v{ct_chk(ct, 2, level)};
+        for (uint32_t i = 0; i < r; ++i) {
+            if (ksk[i]) v.push_back(key_chk(c, ksk[i]));
+            ext_chk(c, v, pt[i], level);
+        }
+        const int rc = check_inputs(c, s, v);
+        if (rc) return rc;
+    }
     const size_t pl = (size_t)level * c.n;
     const uint32_t one = 1;
     if (keyed) {
@@ -644,6 +735,15 @@ int hks_batch_rotate_seeded(hks_ctx *h, uint32_t n_ct, const uint64_t *const *ct
             if (ct_out[i] == ct[j] || (j != i && ct_out[i] == ct_out[j])) return HKS_EINVAL;
         jobs[i] = KsJob{ct[i], galois[i], ksk_b[i], ct_out[i], nullptr, ct[i] + (size_t)level * c.n, seeds[i], true};
     }
+    if (c.check) {
+        std::vector<Chk> v;
+        for (uint32_t i = 0; i < n_ct; ++i) {
+            v.push_back(ct_chk(ct[i], 2, level));
+            v.push_back(keyb_chk(c, ksk_b[i]));
+        }
+        const int rc = check_inputs(c, (hipStream_t)stream, v);
+        if (rc) return rc;
+    }
     return do_keyswitch_jobs(c, jobs.data(), n_ct, level, (hipStream_t)stream);
     GUARD_END
 }
@@ -656,6 +756,7 @@ int hks_rotate_seeded(hks_ctx *h, const uint64_t *ct, uint32_t level, uint32_t g
         return HKS_EINVAL;
     Ctx &c = h->c;
     if (!valid_galois(c, galois)) return HKS_EINVAL;
+    HKS_CHECKED(c, stream, ct_chk(ct, 2, level), keyb_chk(c, ksk_b));
     const KsJob job{ct, galois, ksk_b, ct_out, nullptr, ct + (size_t)level * c.n, seed, true};
     return do_keyswitch_jobs(c, &job, 1, level, (hipStream_t)stream);
     GUARD_END
@@ -665,6 +766,7 @@ int hks_rescale(hks_ctx *h, const uint64_t *ct, uint32_t level, uint64_t *ct_out
     GUARD_BEGIN
     if (!h || !ct || !ct_out || !aligned(ct) || !aligned(ct_out) || level < 2 || level > h->c.L || ct == ct_out)
         return HKS_EINVAL;
+    HKS_CHECKED(h->c, stream, ct_chk(ct, 2, level));
     return do_rescale(h->c, ct, level, ct_out, (hipStream_t)stream);
     GUARD_END
 }
@@ -677,6 +779,7 @@ int hks_ptmult(hks_ctx *h, const uint64_t *ct, const uint64_t *pt, uint32_t leve
         return HKS_EINVAL;
     Ctx &c = h->c;
     hipStream_t s = (hipStream_t)stream;
+    HKS_CHECKED(c, s, ct_chk(ct, 2, level), ct_chk(pt, 1, level));
     if (!rescale) return hip_status(launch_mulpt(c, ct, pt, ct_out, level, 2, s));
     HKS_TRY(launch_mulpt(c, ct, pt, c.ws_rot, level, 2, s));
     return do_rescale(c, c.ws_rot, level, ct_out, s);
@@ -736,6 +839,7 @@ int hks_new_mult(hks_ctx *h, const uint64_t *ct1, const uint64_t *ct2, uint32_t 
         !aligned(ct_out) || level < 2 || level > h->c.L || ct_out == ct1 || ct_out == ct2)
         return HKS_EINVAL;
     if (h->c.K + 1 > 16) return HKS_EUNSUPPORTED;
+    HKS_CHECKED(h->c, stream, ct_chk(ct1, 2, level), ct_chk(ct2, 2, level), key_chk(h->c, rlk));
     return do_new_mult(h->c, 1, &ct1, &ct2, level, &rlk, &ct_out, (hipStream_t)stream);
     GUARD_END
 }
@@ -746,6 +850,7 @@ int hks_mult_relin(hks_ctx *h, const uint64_t *ct1, const uint64_t *ct2, uint32_
     if (!h || !ct1 || !ct2 || !rlk || !ct_out || !aligned(ct1) || !aligned(ct2) || !aligned(rlk) ||
         !aligned(ct_out) || level < 1 || level > h->c.L || (rescale && level < 2))
         return HKS_EINVAL;
+    HKS_CHECKED(h->c, stream, ct_chk(ct1, 2, level), ct_chk(ct2, 2, level), key_chk(h->c, rlk));
     return do_mult_relin(h->c, 1, &ct1, &ct2, level, &rlk, rescale, &ct_out, (hipStream_t)stream);
     GUARD_END
 }
@@ -763,6 +868,16 @@ int hks_batch_mult_relin(hks_ctx *h, uint32_t n, const uint64_t *const *ct1, con
         for (uint32_t j = 0; j < n; ++j)
             if (ct_out[i] == ct1[j] || ct_out[i] == ct2[j] || (j != i && ct_out[i] == ct_out[j])) return HKS_EINVAL;
     }
+    if (h->c.check) {
+        std::vector<Chk> v;
+        for (uint32_t i = 0; i < n; ++i) {
+            v.push_back(ct_chk(ct1[i], 2, level));
+            v.push_back(ct_chk(ct2[i], 2, level));
+            v.push_back(key_chk(h->c, rlk[i]));
+        }
+        const int rc = check_inputs(h->c, (hipStream_t)stream, v);
+        if (rc) return rc;
+    }
     return do_mult_relin(h->c, n, ct1, ct2, level, rlk, rescale, ct_out, (hipStream_t)stream);
     GUARD_END
 }
@@ -773,7 +888,60 @@ int hks_add(hks_ctx *h, const uint64_t *x, const uint64_t *y, uint32_t level, ui
     if (!h || !x || !y || !out || !aligned(x) || !aligned(y) || !aligned(out) || level < 1 || level > h->c.L ||
         n_poly < 1 || n_poly > 3)
         return HKS_EINVAL;
+    HKS_CHECKED(h->c, stream, ct_chk(x, n_poly, level), ct_chk(y, n_poly, level));
     return hip_status(launch_add(h->c, x, y, out, n_poly * level, level, (hipStream_t)stream));
+    GUARD_END
+}
+
+struct hks_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+int hks_graph_begin(void *stream) {
+    GUARD_BEGIN
+    if (!stream) return HKS_EINVAL;  // the legacy default stream cannot be captured
+    return hip_status(hipStreamBeginCapture((hipStream_t)stream, hipStreamCaptureModeThreadLocal));
+    GUARD_END
+}
+
+int hks_graph_end(void *stream, hks_graph **out) {
+    GUARD_BEGIN
+    if (!stream || !out) return HKS_EINVAL;
+    hipGraph_t g = nullptr;
+    if (hipStreamEndCapture((hipStream_t)stream, &g) != hipSuccess || !g) return HKS_EHIP;
+    hipGraphExec_t e = nullptr;
+    if (hipGraphInstantiate(&e, g, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return HKS_EHIP;
+    }
+    hks_graph *h = new hks_graph();
+    h->graph = g;
+    h->exec = e;
+    *out = h;
+    return HKS_OK;
+    GUARD_END
+}
+
+int hks_graph_launch(hks_graph *g, void *stream) {
+    GUARD_BEGIN
+    if (!g || !g->exec) return HKS_EINVAL;
+    return hip_status(hipGraphLaunch(g->exec, (hipStream_t)stream));
+    GUARD_END
+}
+
+void hks_graph_destroy(hks_graph *g) {
+    if (!g) return;
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
+}
+
+int hks_set_check(hks_ctx *h, int on) {
+    GUARD_BEGIN
+    if (!h) return HKS_EINVAL;
+    h->c.check = on != 0;
+    return HKS_OK;
     GUARD_END
 }
 

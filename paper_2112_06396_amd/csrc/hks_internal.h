@@ -130,6 +130,9 @@ struct Ctx {
     size_t st_t() const { return (size_t)3 * L * n; }
 
     // kernel timing (hks_prof_*): event pairs per kernel class
+    // canonical-range checks of call inputs (hks_set_check)
+    bool check = false;
+    uint32_t *chk_flag = nullptr;  // device word set by check_kernel
     mutable uint32_t prof_mask = 0;
     mutable std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev[HKS_K_COUNT];
     mutable std::vector<hipEvent_t> prof_pool;
@@ -221,6 +224,11 @@ hipError_t launch_ksk_rows(const Ctx &c, const KskBatch &kb, uint32_t nb, const 
 hipError_t launch_ksk_matvec(const Ctx &c, const uint64_t *ext, uint32_t level, uint32_t r, const uint32_t *galois,
                              const uint64_t *const *ksk, const uint64_t *const *pt, const uint64_t *ax,
                              const uint64_t *b, uint64_t *uq, uint64_t *pc, hipStream_t s);
+// Canonical-range check: sets *flag when a word of p, read as reps copies of
+// `limbs` limbs with moduli first_mod.., is not below its modulus.
+hipError_t launch_check(const Ctx &c, const uint64_t *p, uint32_t reps, uint32_t limbs, uint32_t first_mod,
+                        uint32_t *flag, hipStream_t s);
+hipError_t launch_clear_flag(uint32_t *flag, hipStream_t s);
 // The rows a_j of the seeded key `seed`: a [dnum][L+K][N].
 hipError_t launch_expand_key_a(const Ctx &c, uint64_t seed, uint64_t *a, hipStream_t s);
 // Eval-domain automorph (gather) of limbs; or coefficient-domain map with negation.

@@ -173,6 +173,30 @@ hipError_t launch_conv_moddown(const Ctx &c, const uint64_t *p, uint32_t nt, uin
     return launch_conv_t<false>(a, ns, dim3((c.n + 255) / 256, a.tgroups, batch), s);
 }
 
+// ------------------------------------------------------------------ input checks
+
+__global__ void __launch_bounds__(256) check_kernel(const uint64_t *p, uint32_t limbs, uint32_t first_mod,
+                                                    const ModC *mc, uint32_t n, uint32_t *flag) {
+    const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x, limb = blockIdx.y, rep = blockIdx.z;
+    if (c >= n) return;
+    if (p[((size_t)rep * limbs + limb) * n + c] >= mc[first_mod + limb].q) *flag = 1u;
+}
+
+__global__ void clear_flag_kernel(uint32_t *flag) { *flag = 0u; }
+
+hipError_t launch_check(const Ctx &c, const uint64_t *p, uint32_t reps, uint32_t limbs, uint32_t first_mod,
+                        uint32_t *flag, hipStream_t s) {
+    if (reps == 0 || limbs == 0) return hipSuccess;
+    hipLaunchKernelGGL(check_kernel, dim3((c.n + 255) / 256, limbs, reps), dim3(256), 0, s, p, limbs, first_mod,
+                       c.mc, c.n, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_clear_flag(uint32_t *flag, hipStream_t s) {
+    hipLaunchKernelGGL(clear_flag_kernel, dim3(1), dim3(1), 0, s, flag);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ seeded key rows
 
 // a[j][kappa][i] for the seeded key `seed`: grid (N/256, L+K, dnum).

@@ -262,7 +262,7 @@ int build_tables(Ctx &c) {
 void free_tables(Ctx &c) {
     void *ptrs[] = {c.tw_fwd, c.tw_inv, c.mc, c.li_plain, c.li_modup, c.li_moddown, c.conv_modup,
                     c.conv_moddown, c.pinv, c.pmod, c.rs_qinv, c.rs_h, c.ws,
-                    c.li_nm, c.conv_nm, c.sinv_nm, c.enc_rotg, c.enc_roots};
+                    c.li_nm, c.conv_nm, c.sinv_nm, c.enc_rotg, c.enc_roots, c.chk_flag};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     c.tw_fwd = c.tw_inv = nullptr;
@@ -276,6 +276,7 @@ void free_tables(Ctx &c) {
     c.rs_h = nullptr;
     c.enc_rotg = nullptr;
     c.enc_roots = nullptr;
+    c.chk_flag = nullptr;
     c.ws = nullptr;
 }
 

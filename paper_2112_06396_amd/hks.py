@@ -25,6 +25,7 @@ HKS_EINVAL = -1
 HKS_ENOMEM = -2
 HKS_EHIP = -3
 HKS_EUNSUPPORTED = -4
+HKS_ERANGE = -5
 
 HKS_Q_N = 1
 HKS_Q_ALPHA = 2
@@ -44,7 +45,8 @@ EXPORTS = (
     "hks_modup", "hks_ksk_inner", "hks_moddown", "hks_keyswitch", "hks_rotate", "hks_hrotate",
     "hks_batch_rotate", "hks_rescale", "hks_ptmult", "hks_mult_relin", "hks_batch_mult_relin", "hks_new_mult",
     "hks_encode", "hks_add",
-    "hks_expand_key_a", "hks_rotate_seeded", "hks_batch_rotate_seeded", "hks_ptmatvec", "hks_prof_enable",
+    "hks_expand_key_a", "hks_rotate_seeded", "hks_batch_rotate_seeded", "hks_ptmatvec", "hks_set_check",
+    "hks_graph_begin", "hks_graph_end", "hks_graph_launch", "hks_graph_destroy", "hks_prof_enable",
     "hks_prof_read",
 )
 
@@ -144,6 +146,11 @@ def lib():
             "hks_rotate_seeded": (_i32, [_vp, _vp, _u32, _u32, ctypes.c_uint64, _vp, _vp, _vp]),
             "hks_batch_rotate_seeded": (_i32, [_vp, _u32, ctypes.POINTER(_vp), _u32, ctypes.POINTER(_u32), u64p,
                                                ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp]),
+            "hks_set_check": (_i32, [_vp, _i32]),
+            "hks_graph_begin": (_i32, [_vp]),
+            "hks_graph_end": (_i32, [_vp, ctypes.POINTER(_vp)]),
+            "hks_graph_launch": (_i32, [_vp, _vp]),
+            "hks_graph_destroy": (None, [_vp]),
             "hks32_create": (_i32, [ctypes.POINTER(_Params32), _i32, ctypes.POINTER(_vp)]),
             "hks32_destroy": (None, [_vp]),
             "hks32_ntt": (_i32, [_vp, _vp, _u32, _u32, _vp]),
@@ -396,6 +403,41 @@ def hks_encode(ctx, slots, scale: float, level: int, with_p: bool, pt_out, strea
         raise ValueError("expected N/2 complex slots")
     _check("hks_encode", lib().hks_encode(ctx.handle, ctypes.c_void_p(slots.data_ptr()), float(scale), level,
                                           1 if with_p else 0, _ptr(pt_out), _stream(stream)))
+
+
+def hks_set_check(ctx, on: bool):
+    _check("hks_set_check", lib().hks_set_check(ctx.handle, 1 if on else 0))
+
+
+class Graph:
+    """A call sequence recorded on a stream and replayed as one HIP graph."""
+
+    def __init__(self, handle):
+        self._h = handle
+
+    def launch(self, stream):
+        _check("hks_graph_launch", lib().hks_graph_launch(self._h, _stream(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            lib().hks_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def hks_graph_begin(stream):
+    _check("hks_graph_begin", lib().hks_graph_begin(_stream(stream)))
+
+
+def hks_graph_end(stream) -> Graph:
+    h = ctypes.c_void_p()
+    _check("hks_graph_end", lib().hks_graph_end(_stream(stream), ctypes.byref(h)))
+    return Graph(h)
 
 
 def hks_add(ctx, x, y, level: int, n_poly: int, out, stream=None):

@@ -715,3 +715,86 @@ def test_new_mult_rejects_level_one_and_aliasing():
         with pytest.raises(hks.HksError) as e:
             hks.hks_new_mult(ctx, *args)
         assert e.value.status == hks.HKS_EINVAL
+
+
+# ------------------------------------------------------------------ input checks and C-ABI graphs
+
+
+def test_canonical_checks_reject_out_of_range_inputs():
+    """With checks on, a ciphertext word equal to its modulus, or a key word
+    above it, makes the call return HKS_ERANGE before any work; canonical
+    inputs give the same bits as with checks off; checks off accept (and do
+    not look at) the bad input."""
+    pr, ctx = _get("n10")
+    hks = H()
+    level = pr.L
+    ct = _rand_ct(pr, level, 1200)
+    ksk = _rand_ksk(pr, 1201)
+    g = hks.hks_galois_for_rotation(1, pr.log_n)
+    out = hks.empty((2, level, pr.n))
+    try:
+        hks.hks_set_check(ctx, True)
+        hks.hks_rotate(ctx, dev(ct), level, g, dev(ksk), out)
+        assert np.array_equal(host(out), O.rotate(pr, ct, level, g, ksk))
+        bad = ct.copy()
+        bad[1, level - 1, 77] = pr.q[level - 1]
+        with pytest.raises(hks.HksError) as e:
+            hks.hks_rotate(ctx, dev(bad), level, g, dev(ksk), out)
+        assert e.value.status == hks.HKS_ERANGE
+        badk = ksk.copy()
+        badk[pr.dnum - 1, 0, pr.L + pr.K - 1, 5] = np.uint64((1 << 63) + 3)
+        with pytest.raises(hks.HksError) as e:
+            hks.hks_rotate(ctx, dev(ct), level, g, dev(badk), out)
+        assert e.value.status == hks.HKS_ERANGE
+        x = synth.uniform_residues(synth.rng(1202), pr.q[:2], pr.n)
+        x[1, 3] = pr.q[1] + 1
+        with pytest.raises(hks.HksError) as e:
+            hks.hks_ntt(ctx, dev(x), 0, 2)
+        assert e.value.status == hks.HKS_ERANGE
+    finally:
+        hks.hks_set_check(ctx, False)
+    hks.hks_rotate(ctx, dev(bad), level, g, dev(ksk), out)  # unchecked: runs
+    torch.cuda.synchronize()
+
+
+def test_c_abi_graph_replays_equal_eager():
+    """hks_graph_begin/end/launch: a Rotate and a hoisted rotation recorded
+    on a stream and replayed three times, with eager calls and buffer
+    clearing in between, give the eager results every time; checks on
+    refuse a capturing stream."""
+    pr, ctx = _get("cfg1", 4)
+    hks = H()
+    level = pr.L
+    ct = dev(_rand_ct(pr, level, 1300))
+    keys = [dev(_rand_ksk(pr, 1301 + i)) for i in range(3)]
+    gals = [hks.hks_galois_for_rotation(k, pr.log_n) for k in (1, 2, -3)]
+    o1 = hks.empty((2, level, pr.n))
+    oh = [hks.empty((2, level, pr.n)) for _ in range(3)]
+    hks.hks_rotate(ctx, ct, level, gals[0], keys[0], o1)
+    hks.hks_hrotate(ctx, ct, level, gals, keys, oh)
+    ref1, refh = host(o1).copy(), [host(t).copy() for t in oh]
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    hks.hks_graph_begin(s)
+    try:
+        hks.hks_set_check(ctx, True)
+        with pytest.raises(hks.HksError) as e:
+            hks.hks_rotate(ctx, ct, level, gals[0], keys[0], o1, s)
+        assert e.value.status == hks.HKS_EUNSUPPORTED
+    finally:
+        hks.hks_set_check(ctx, False)
+    hks.hks_rotate(ctx, ct, level, gals[0], keys[0], o1, s)
+    hks.hks_hrotate(ctx, ct, level, gals, keys, oh, s)
+    graph = hks.hks_graph_end(s)
+    other = hks.empty((2, level, pr.n))
+    for rep in range(3):
+        for t in [o1] + oh:
+            t.zero_()
+        hks.hks_rotate(ctx, ct, level, gals[1], keys[1], other)
+        torch.cuda.synchronize()
+        graph.launch(s)
+        s.synchronize()
+        assert np.array_equal(host(o1), ref1), rep
+        for i in range(3):
+            assert np.array_equal(host(oh[i]), refh[i]), (rep, i)
+    graph.close()
