@@ -521,6 +521,25 @@ def main():
     # compulsory HBM bytes of one Rotate: a, b, key (digits < beta, limbs [0,level) U P), output
     key_bytes = beta * 2 * (LEVEL + K) * n * 8
     comp_bytes = 2 * LEVEL * n * 8 + key_bytes + 2 * LEVEL * n * 8
+    # the whole key-switch against both rooflines: max(bytes / HBM, modmul / ALU)
+    step_mm = sum(kernel_work(c_, n, LEVEL, K, alpha, beta)[0] for c_ in range(len(hks.HKS_K_NAMES)))
+    whole = {"modmul_per_step": step_mm, "Tmodmul_per_s": step_mm / (ms_per_step / 1e3) / 1e12,
+             "alu_frac": step_mm / (ms_per_step / 1e3) / MODMUL_PEAK,
+             "hbm_frac": comp_bytes / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS}
+    # a plain device copy of 1 GiB as the measured bandwidth reference
+    src_ = torch.empty(1 << 27, dtype=torch.int64, device="cuda")
+    dst_ = torch.empty_like(src_)
+    dst_.copy_(src_)
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record()
+    for _ in range(5):
+        dst_.copy_(src_)
+    c1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 5 * 2 * src_.numel() * 8 / (c0.elapsed_time(c1) / 1e3) / 1e9
+    del src_, dst_
+    if roof["unit"] == "GB/s":
+        roof["frac_of_measured_copy"] = roof["achieved"] / copy_gbs
     result = {
         "metric": METRIC,
         "value": value,
@@ -542,7 +561,11 @@ def main():
         "hbm_compulsory_bytes_per_step": comp_bytes,
         "hbm_algorithmic_GBps": comp_bytes / (ms_per_step / 1e3) / 1e9,
         "roofline": roof,
+        "whole_keyswitch": whole,
+        "measured_copy_GBps": copy_gbs,
         "kernel_breakdown_us": {k_: v["ms_per_step"] * 1e3 for k_, v in breakdown.items()},
+        "env": {"numpy": np.__version__, "torch": torch.__version__, "hip": torch.version.hip,
+                "arch": torch.cuda.get_device_properties(0).gcnArchName, "nproc": os.cpu_count()},
     }
 
     if not args.no_extras:
