@@ -492,7 +492,6 @@ hipError_t launch_rows_mdepi(const Ctx &c, const LimbMap &m, const BatchIo &io, 
 
 // ------------------------------------------------------------------ KSKInnerProd (+ ModUp's last pass, + ModDown's first)
 
-constexpr uint64_t KSK_WAVES_FOR_E16 = 6 * 1024;
 #ifndef KSK_E8_WAVES
 #define KSK_E8_WAVES 2
 #endif
@@ -718,22 +717,17 @@ hipError_t launch_ksk_rows(const Ctx &c, const KskBatch &kb, uint32_t nb, const 
     a.xcd_group = (nb > 1 && xs % 8 == 0) ? 1u : 0u;
     ProfScope ps(c, HKS_K_KSK, s);
     const dim3 grid(xs * nb);
-    // elements per thread as for the pass kernels: 8 unless the launch
-    // already holds many waves at 16
-    const uint64_t thr16 = (uint64_t)ROW_LINES * (1u << c.n2) / 16;  // threads per block at 16
-    const uint64_t waves16 = (uint64_t)xs * nb * ((thr16 + 63) / 64);
+    // 8 elements per thread for every launch: the 128-bit lazy sums fit in
+    // the registers only there, and measured faster than 16 also for
+    // batched and hoisted launches
     if (kb.newmult) {  // NewMult: a relinearization key, the converted limbs after the column pass
         if (!rowpass || kb.seeded) return hipErrorInvalidValue;
         return launch_ksk_rows_t<true, 8, false, true>(a, c.n2, grid, s);
     }
-    // a seeded key's rows a_j are generated in the kernel: always 8 elements
-    // per thread there (the generator's registers on top of 16 would spill)
+    // a seeded key's rows a_j are generated in the kernel
     if (kb.seeded)
         return rowpass ? launch_ksk_rows_t<true, 8, true>(a, c.n2, grid, s)
                        : launch_ksk_rows_t<false, 8, true>(a, c.n2, grid, s);
-    if (waves16 >= KSK_WAVES_FOR_E16)
-        return rowpass ? launch_ksk_rows_t<true, 16, false>(a, c.n2, grid, s)
-                       : launch_ksk_rows_t<false, 16, false>(a, c.n2, grid, s);
     return rowpass ? launch_ksk_rows_t<true, 8, false>(a, c.n2, grid, s)
                    : launch_ksk_rows_t<false, 8, false>(a, c.n2, grid, s);
 }
