@@ -298,6 +298,8 @@ struct NttArgs {
     const LastInv *li;    // folded last inverse stage, indexed by cidx
     const Shoup *pinv;    // IO_MDEPI: P^-1 mod q_i
     uint32_t n, n1, n2;
+    uint32_t nb;          // batch entries in blockIdx.x (xcd_batch) or blockIdx.y
+    uint32_t xcd_batch;   // the entries of one (limb, tile) on one XCD, one after another
     LimbMap m;
     BatchIo io;
 };
@@ -311,9 +313,20 @@ __global__ void __launch_bounds__((Tile<LOGS, LINES, COLS, E>::NT)) ntt_pass_ker
     __shared__ uint64_t lds[TL::WORDS];
     const uint32_t lines_per_limb = 1u << (COLS ? a.n2 : a.n1);
     const uint32_t tiles = lines_per_limb / LINES;
-    const uint32_t li = blockIdx.x / tiles;
-    const uint32_t tile = blockIdx.x % tiles;
-    const uint32_t b = blockIdx.y;
+    // xcd_batch: block ids are dealt round-robin over the 8 XCDs, so the nb
+    // entries of one (limb, tile) get ids equal modulo 8 and consecutive in
+    // dispatch order: the second entry finds the tile's twiddles in L2
+    uint32_t bx, b;
+    if (a.xcd_batch) {
+        const uint32_t rest = blockIdx.x >> 3;
+        b = rest % a.nb;
+        bx = ((rest / a.nb) << 3) | (blockIdx.x & 7u);
+    } else {
+        bx = blockIdx.x;
+        b = blockIdx.y;
+    }
+    const uint32_t li = bx / tiles;
+    const uint32_t tile = bx % tiles;
     const uint32_t N = 1u << a.n;
     const uint32_t mod = a.m.mod[li];
     const ModC mcv = a.mc[mod];
@@ -388,8 +401,14 @@ static hipError_t launch_pass_t(const NttArgs &a, uint32_t count, uint32_t batch
     ProfScope ps(*a.ctx, FWD ? (COLS ? HKS_K_NTT_FWD_COLS : HKS_K_NTT_FWD_ROWS)
                              : (COLS ? HKS_K_NTT_INV_COLS : HKS_K_NTT_INV_ROWS), s);
     const uint32_t lines_per_limb = 1u << (COLS ? a.n2 : a.n1);
-    dim3 grid(count * (lines_per_limb / LINES), batch);
-    hipLaunchKernelGGL((ntt_pass_kernel<LOGS, LINES, COLS, FWD, IO, E>), grid, dim3(TL::NT), 0, s, a);
+    const uint32_t xs = count * (lines_per_limb / LINES);
+    NttArgs ab = a;
+    ab.nb = batch;
+    // row passes read a twiddle table as large as the limb: share it across
+    // the batch through L2 (column-pass twiddles are few and always cached)
+    ab.xcd_batch = (!COLS && batch > 1 && xs % 8 == 0) ? 1u : 0u;
+    const dim3 grid = ab.xcd_batch ? dim3(xs * batch, 1) : dim3(xs, batch);
+    hipLaunchKernelGGL((ntt_pass_kernel<LOGS, LINES, COLS, FWD, IO, E>), grid, dim3(TL::NT), 0, s, ab);
     return hipGetLastError();
 }
 
