@@ -218,3 +218,41 @@ def test_dft_plan_eager_and_graph_match_oracle():
         gr.replay()
         torch.cuda.synchronize()
         assert np.array_equal(host(bufs.view(plan.out, plan.out_level)), ref), rep
+
+
+def test_full_size_dft_trace_graph_equals_eager():
+    """The bootstrapping-shaped plan with the factored DFT's offsets at
+    N = 2^16, L = 35 -> 9, K = 12, dnum = 3 (2^15 slots, three iterations:
+    155 rotation keys, 350 key-switches, diagonals encoded on the device):
+    one captured hipGraph replayed twice equals the eager run."""
+    from paper_2112_06396_amd import hks, trace
+    pq = hks.hks_gen_primes(50, 17, 47)
+    ctx = hks.Context(16, pq[:35], pq[35:], 3, max_batch=16)
+    try:
+        n = ctx.n
+        plan = trace.bootstrap_plan(35, hoisted=True, new_mult=True, dft=(15, 3))
+        assert plan.key_switches == 350 and len(plan.rotations) == 155
+        keys = {k: synth.device_residues(pq, (3, 2), n, 3000 + i) for i, k in enumerate(plan.rotations)}
+        rlk = synth.device_residues(pq, (3, 2), n, 2999)
+        gz = torch.Generator(device="cuda")
+        gz.manual_seed(5)
+        diag = {}
+        for d in plan.diagonals:
+            zs = torch.rand((n // 2, 2), generator=gz, dtype=torch.float64, device="cuda") * 2 - 1
+            diag[d] = hks.empty((len(pq), n))
+            hks.hks_encode(ctx, zs, 2.0 ** 40, 35, True, diag[d])
+        ext = trace.ext_diagonals(plan, diag, 35)
+        bufs = trace.TraceBuffers(plan, n)
+        bufs.view("x0", 35).copy_(synth.device_residues(pq[:35], (2,), n, 3))
+        eager = trace.run_plan(ctx, plan, bufs, {}, keys, rlk, diag_ext=ext).clone()
+        gr = trace.capture(ctx, plan, bufs, {}, keys, rlk, diag_ext=ext)
+        for rep in range(2):
+            bufs.view(plan.out, plan.out_level).zero_()
+            torch.cuda.synchronize()
+            gr.replay()
+            torch.cuda.synchronize()
+            assert torch.equal(bufs.view(plan.out, plan.out_level).view(torch.int64), eager.view(torch.int64)), rep
+        del gr
+    finally:
+        torch.cuda.synchronize()
+        ctx.close()
