@@ -402,6 +402,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--serving-only", action="store_true",
+                    help="run only the serving figures (with the --serving-* sizes) and print them")
     ap.add_argument("--w32-only", action="store_true",
                     help="time only the 32-bit-word Rotate (for profiling) and print its figures")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -422,6 +424,9 @@ def main():
     torch.cuda.init()
     if args.w32_only:
         print(json.dumps(w32_extra(args, hks, synth, torch.cuda.current_stream())), flush=True)
+        return
+    if args.serving_only:
+        print(json.dumps(serving_extra(args, hks, synth)), flush=True)
         return
     pq = hks.hks_gen_primes(50, LOG_N + 1, L + K)
     q, p = pq[:L], pq[L:]
