@@ -156,6 +156,45 @@ def extras(args, ctx, hks, synth, cts, ksks, outs, gal, key_mods, n, plain_value
         lambda i: hks.hks_batch_rotate(ctx, dcts, LEVEL, gals[:32], dkeys[32 * (i % 2):32 * (i % 2) + 32],
                                        douts[:32], stream), 32, 8)
     res["batch_vs_plain"] = res["batch32_shared_key_ks_per_s"] / plain_value
+
+    # the key-switch kernel's achieved HBM rate in the batched and hoisted
+    # forms (separate pass with the library's per-launch events):
+    # algorithmic bytes of the launches / their summed durations
+    kcls = hks.HKS_K_NAMES.index("ksk")
+    alpha, beta = ctx.alpha, ctx.beta(LEVEL)
+
+    def ksk_rate(fn, reps, bytes_of):
+        fn(0)
+        torch.cuda.synchronize()
+        hks.hks_prof_enable(ctx, 1 << kcls)
+        for i in range(reps):
+            fn(i + 1)
+        torch.cuda.synchronize()
+        ms, cnt = hks.hks_prof_read(ctx, kcls)
+        hks.hks_prof_enable(ctx, 0)
+        gbs = bytes_of(reps, cnt) / (ms / 1e3) / 1e9
+        return {"achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+                "avg_launch_us": ms * 1e3 / cnt, "launches": cnt / reps}
+
+    E = LEVEL + K
+    per_rot = kernel_work(kcls, n, LEVEL, K, alpha, beta)[1]  # key, digits, own limbs, u/v, P limbs
+    # HRotate: the beta digits of E limbs (converted + own) are shared by the
+    # rotations of a launch and count once per launch
+    shared = beta * E * n * 8
+    forms = {
+        "batch32_distinct_keys": ksk_rate(
+            lambda i: hks.hks_batch_rotate(ctx, dcts, LEVEL, gals[:32], dkeys[32 * (i % 2):32 * (i % 2) + 32],
+                                           douts[:32], stream), 4, lambda reps, cnt: reps * 32 * per_rot),
+        "hrotate_r64": ksk_rate(
+            lambda i: hks.hks_hrotate(ctx, cts[i % args.pool], LEVEL, gals, dkeys, douts, stream), 4,
+            lambda reps, cnt: reps * nk * (per_rot - shared) + cnt * shared),
+    }
+    forms["batch32_distinct_keys"]["algorithmic_bytes_per_rotation"] = per_rot
+    forms["hrotate_r64"]["algorithmic_bytes_per_rotation"] = per_rot - shared
+    forms["hrotate_r64"]["shared_bytes_per_launch"] = shared
+    res["ksk_roofline_batched"] = forms
+    log(f"[bench] ksk kernel HBM rate: batch 32 distinct keys "
+        f"{forms['batch32_distinct_keys']['achieved']:.0f} GB/s, hrotate r=64 {forms['hrotate_r64']['achieved']:.0f} GB/s")
     # seeded keys (rows a_j regenerated on chip, half the key bytes)
     b_rows = [k[:, 1].contiguous() for k in dkeys[:32]]
     res["rotate_seeded_ks_per_s"] = rate(
@@ -294,7 +333,7 @@ def w32_extra(args, hks, synth, stream):
     """The same Rotate in 32-bit words (Sec. 5.4): N = 2^16, 30-bit primes,
     L = 40, K = 14, dnum = 3 (log2 QP = 1620 bits against 1600 for the 50-bit
     L = 24, K = 8), level 40, a pool of (ciphertext, key) pairs as for the
-    main line."""
+    main line; and HRotate over 64 distinct keys as for the 64-bit extra."""
     import torch
     L32, K32 = 40, 14
     pq = hks.hks_gen_primes(30, LOG_N + 1, L32 + K32)
@@ -325,13 +364,28 @@ def w32_extra(args, hks, synth, stream):
     ms = e0.elapsed_time(e1) / args.steps
     key_bytes = keys[0].numel() * 4
     compulsory = key_bytes + 2 * cts[0].numel() * 4
-    del cts, keys, outs
+    del keys, outs
+    # hoisted rotations (Algorithm 4): one ModUp shared by 64 rotations with distinct keys
+    nk, reps = 64, 4
+    hkeys = [d32(pq, (DNUM, 2), 9300 + i) for i in range(nk)]
+    houts = [hks.empty32((2, L32, n)) for _ in range(nk)]
+    hgals = [hks.hks_galois_for_rotation(k + 1, LOG_N) for k in range(nk)]
+    hks.hks32_hrotate(c32, cts[0], L32, hgals, hkeys, houts, stream)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for i in range(reps):
+        hks.hks32_hrotate(c32, cts[(i + 1) % args.pool], L32, hgals, hkeys, houts, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    hrot = reps * nk / (e0.elapsed_time(e1) / 1e3)
+    del cts, hkeys, houts
     torch.cuda.synchronize()
     c32.close()
     torch.cuda.empty_cache()
-    log(f"[bench] 32-bit words (L=40, K=14, 30-bit primes): {ms * 1e3:.1f} us/step, {1e3 / ms:.0f} ks/s")
-    return {"rotate_ks_per_s": 1e3 / ms, "us_per_step": ms * 1e3, "key_mib": key_bytes / 2 ** 20,
-            "hbm_compulsory_bytes_per_step": compulsory,
+    log(f"[bench] 32-bit words (L=40, K=14, 30-bit primes): {ms * 1e3:.1f} us/step, {1e3 / ms:.0f} ks/s; "
+        f"hrotate r=64 {hrot:.0f} ks/s")
+    return {"rotate_ks_per_s": 1e3 / ms, "us_per_step": ms * 1e3, "hrotate_r64_ks_per_s": hrot,
+            "key_mib": key_bytes / 2 ** 20, "hbm_compulsory_bytes_per_step": compulsory,
             "config": {"log_n": LOG_N, "L": L32, "K": K32, "dnum": DNUM, "level": L32, "prime_bits": 30}}
 
 

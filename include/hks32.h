@@ -3,12 +3,12 @@
  * at the price of more limbs for the same log2(QP)).
  *
  * The operations are those of include/hks.h (ModUp, KSKInnerProd, ModDown,
- * Rotate = Algorithm 3), in the same layouts with uint32_t words: a
- * polynomial at level l is [l][N] limb-major canonical residues in the
- * bit-reversed evaluation order of the 64-bit library; a ciphertext is
- * [2][l][N] (a, b); a switching key [dnum][2][L+K][N].  Primes satisfy
- * 2^20 < q < 2^30 and q = 1 mod 2N, so that values up to 4q fit in a word
- * and products of two residues fit in 64 bits.  Status codes, the Galois
+ * Rotate = Algorithm 3, HRotate = Algorithm 4), in the same layouts with
+ * uint32_t words: a polynomial at level l is [l][N] limb-major canonical
+ * residues in the bit-reversed evaluation order of the 64-bit library; a
+ * ciphertext is [2][l][N] (a, b); a switching key [dnum][2][L+K][N].  Primes
+ * satisfy 2^20 < q < 2^30 and q = 1 mod 2N, so that values up to 4q fit in
+ * a word and products of two residues fit in 64 bits.  Status codes, the Galois
  * element helpers and the stream convention are those of include/hks.h.
  * The decomposition, the uncorrected fast basis conversion, the floor-style
  * ModDown and the automorphism are the same as in the 64-bit library, so
@@ -54,6 +54,18 @@ int hks32_intt(hks32_ctx *ctx, uint32_t *x, uint32_t first_mod, uint32_t n_limbs
  * aligned; ct_out must not alias ct.  galois odd, below 2N. */
 int hks32_rotate(hks32_ctx *ctx, const uint32_t *ct, uint32_t level, uint32_t galois, const uint32_t *ksk,
                  uint32_t *ct_out, void *stream);
+
+/* HRotate (Algorithm 4): one ModUp of a (no automorphism; the extended
+ * digits taken fully into evaluation form), then for each i < r the
+ * KSKInnerProd with ksk[i] over the digits automorphed by galois[i], ModDown
+ * of u and v, and ct_out[i] = (u, v + automorph(b, galois[i])).  galois, ksk
+ * and ct_out are HOST arrays of r entries (ksk[i], ct_out[i] device
+ * pointers, 16-byte aligned, ct_out[i] not aliasing ct).  Same residues as
+ * hks_hrotate of include/hks.h for the same primes; they differ from r calls
+ * of hks32_rotate, since the automorphism follows the uncorrected basis
+ * conversion.  HKS_EINVAL for r = 0 or any invalid entry (nothing runs). */
+int hks32_hrotate(hks32_ctx *ctx, const uint32_t *ct, uint32_t level, uint32_t r, const uint32_t *galois,
+                  const uint32_t *const *ksk, uint32_t *const *ct_out, void *stream);
 
 #ifdef __cplusplus
 }

@@ -191,6 +191,76 @@ Map32 consecutive(uint32_t first_mod, uint32_t n) {
         return HKS_EINVAL;                 \
     }
 
+namespace {
+
+bool valid_galois32(const Ctx32 &c, uint32_t g) { return (g & 1) != 0 && g < 2 * c.n; }
+
+// ModUp of automorph(a, galois) at `level` into ws_ext: inverse NTT (rows
+// gathered through the automorphism, columns with (Qt_j / q_i)^-1 folded),
+// NewLimb, forward column pass of the new limbs, and their row pass too when
+// `full` (the digits then stay in evaluation form for several automorphisms).
+hipError_t modup32(const Ctx32 &c, const uint32_t *a, uint32_t level, uint32_t galois, bool full, hipStream_t s) {
+    const uint32_t A = c.alpha, K = c.K, E = level + K, beta = (level + A - 1) / A;
+    Map32 inv = consecutive(0, level);
+    for (uint32_t i = 0; i < level; ++i) inv.cidx[i] = (uint16_t)(level * c.L + i);
+    hipError_t e = launch32_inv_rows(c, inv, a, c.ws_y, galois, s);
+    if (e == hipSuccess) e = launch32_inv_cols(c, inv, c.ws_y, c.ws_y, c.li_modup, s);
+    if (e == hipSuccess) e = launch32_conv_modup(c, c.ws_y, level, c.ws_ext, s);
+    Map32 nl{};
+    auto flush = [&]() {
+        hipError_t f = launch32_fwd_cols(c, nl, c.ws_ext, c.ws_ext, s);
+        if (f == hipSuccess && full) f = launch32_fwd_rows(c, nl, c.ws_ext, c.ws_ext, s);
+        nl.count = 0;
+        return f;
+    };
+    for (uint32_t j = 0; j < beta && e == hipSuccess; ++j) {
+        const uint32_t lo = j * A, hi = std::min((j + 1) * A, level);
+        for (uint32_t t = 0; t < E && e == hipSuccess; ++t) {
+            if (t >= lo && t < hi) continue;
+            if (nl.count == MAXL32) e = flush();
+            const uint32_t i = nl.count++;
+            nl.in_off[i] = nl.out_off[i] = (uint16_t)(j * E + t);
+            nl.mod[i] = (uint8_t)(t < level ? t : c.L + (t - level));
+            nl.cidx[i] = 0;
+        }
+    }
+    if (e == hipSuccess && nl.count) e = flush();
+    return e;
+}
+
+// ModDown of u and v (ws_uv's q limbs, ws_p's P limbs after their inverse
+// row pass) into ct_out: inverse column pass of the P limbs with
+// N^-1 (P / p_k)^-1, NewLimb, forward NTT + (u - z) P^-1, plus b gathered
+// through galois on v.
+hipError_t moddown32(const Ctx32 &c, uint32_t level, const uint32_t *b, uint32_t galois, uint32_t *ct_out,
+                     hipStream_t s) {
+    const uint32_t K = c.K;
+    Map32 pm{};
+    pm.count = 2 * K;
+    for (uint32_t i = 0; i < 2 * K; ++i) {
+        pm.in_off[i] = pm.out_off[i] = (uint16_t)i;
+        pm.mod[i] = (uint8_t)(c.L + i % K);
+        pm.cidx[i] = (uint16_t)(i % K);
+    }
+    hipError_t e = launch32_inv_cols(c, pm, c.ws_p, c.ws_p, c.li_moddown, s);
+    if (e == hipSuccess) e = launch32_conv_moddown(c, c.ws_p, level, c.ws_z, s);
+    if (e == hipSuccess) {
+        Map32 zm{};
+        for (uint32_t p = 0; p < 2; ++p)
+            for (uint32_t i = 0; i < level; ++i) {
+                const uint32_t k = zm.count++;
+                zm.in_off[k] = zm.out_off[k] = (uint16_t)(p * c.L + i);
+                zm.mod[k] = (uint8_t)i;
+                zm.cidx[k] = (uint16_t)i;
+            }
+        e = launch32_fwd_cols(c, zm, c.ws_z, c.ws_z, s);
+    }
+    if (e == hipSuccess) e = launch32_rows_epi(c, level, c.ws_z, c.ws_uv, b, galois, ct_out, s);
+    return e;
+}
+
+}  // namespace
+
 extern "C" {
 
 int hks32_create(const hks32_params *p, int device, hks32_ctx **out) {
@@ -289,68 +359,36 @@ int hks32_rotate(hks32_ctx *h, const uint32_t *ct, uint32_t level, uint32_t galo
                  uint32_t *ct_out, void *stream) {
     GUARD32_BEGIN
     if (!h || !ct || !ksk || !ct_out || !al16(ct) || !al16(ksk) || !al16(ct_out) || ct == ct_out || level < 1 ||
-        level > h->c.L || (galois & 1) == 0 || galois >= 2 * h->c.n)
+        level > h->c.L || !valid_galois32(h->c, galois))
         return HKS_EINVAL;
     const Ctx32 &c = h->c;
     hipStream_t s = (hipStream_t)stream;
-    const uint32_t N = c.n, A = c.alpha, K = c.K, E = level + K, beta = (level + A - 1) / A;
-    // ModUp of automorph(a): inverse NTT (rows gathered through the
-    // automorphism, columns with (Qt_j / q_i)^-1 folded), NewLimb, forward
-    // column pass of the new limbs
-    Map32 inv = consecutive(0, level);
-    for (uint32_t i = 0; i < level; ++i) inv.cidx[i] = (uint16_t)(level * c.L + i);
-    hipError_t e = launch32_inv_rows(c, inv, ct, c.ws_y, galois, s);
-    if (e == hipSuccess) e = launch32_inv_cols(c, inv, c.ws_y, c.ws_y, c.li_modup, s);
-    if (e == hipSuccess) e = launch32_conv_modup(c, c.ws_y, level, c.ws_ext, s);
-    if (e == hipSuccess) {
-        Map32 nl{};
-        for (uint32_t j = 0; j < beta; ++j) {
-            const uint32_t lo = j * A, hi = std::min((j + 1) * A, level);
-            for (uint32_t t = 0; t < E; ++t) {
-                if (t >= lo && t < hi) continue;
-                if (nl.count == MAXL32) {
-                    e = launch32_fwd_cols(c, nl, c.ws_ext, c.ws_ext, s);
-                    if (e != hipSuccess) break;
-                    nl.count = 0;
-                }
-                const uint32_t i = nl.count++;
-                nl.in_off[i] = nl.out_off[i] = (uint16_t)(j * E + t);
-                nl.mod[i] = (uint8_t)(t < level ? t : c.L + (t - level));
-                nl.cidx[i] = 0;
-            }
-            if (e != hipSuccess) break;
-        }
-        if (e == hipSuccess) e = launch32_fwd_cols(c, nl, c.ws_ext, c.ws_ext, s);
-    }
+    hipError_t e = modup32(c, ct, level, galois, false, s);
     // KSKInnerProd (+ the new limbs' row pass, + ModDown's P-limb inverse rows)
-    if (e == hipSuccess) e = launch32_ksk(c, c.ws_ext, ct, galois, level, ksk, c.ws_uv, c.ws_p, s);
-    // ModDown of u and v: inverse column pass of the P limbs with
-    // N^-1 (P / p_k)^-1, NewLimb, forward NTT + (u - z) P^-1 (+ b_rot on v)
-    if (e == hipSuccess) {
-        Map32 pm{};
-        pm.count = 2 * K;
-        for (uint32_t i = 0; i < 2 * K; ++i) {
-            pm.in_off[i] = pm.out_off[i] = (uint16_t)i;
-            pm.mod[i] = (uint8_t)(c.L + i % K);
-            pm.cidx[i] = (uint16_t)(i % K);
-        }
-        e = launch32_inv_cols(c, pm, c.ws_p, c.ws_p, c.li_moddown, s);
+    if (e == hipSuccess) e = launch32_ksk(c, c.ws_ext, false, ct, galois, level, ksk, c.ws_uv, c.ws_p, s);
+    if (e == hipSuccess) e = moddown32(c, level, ct + (size_t)level * c.n, galois, ct_out, s);
+    return st32(e);
+    GUARD32_END
+}
+
+int hks32_hrotate(hks32_ctx *h, const uint32_t *ct, uint32_t level, uint32_t r, const uint32_t *galois,
+                  const uint32_t *const *ksk, uint32_t *const *ct_out, void *stream) {
+    GUARD32_BEGIN
+    if (!h || !ct || !galois || !ksk || !ct_out || !al16(ct) || level < 1 || level > h->c.L || r == 0)
+        return HKS_EINVAL;
+    const Ctx32 &c = h->c;
+    for (uint32_t i = 0; i < r; ++i)
+        if (!valid_galois32(c, galois[i]) || !ksk[i] || !ct_out[i] || !al16(ksk[i]) || !al16(ct_out[i]) ||
+            ct_out[i] == ct)
+            return HKS_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    // one ModUp of a, new limbs fully transformed; then per rotation the
+    // KSKInnerProd gathers every digit limb through its automorphism
+    hipError_t e = modup32(c, ct, level, 1, true, s);
+    for (uint32_t i = 0; i < r && e == hipSuccess; ++i) {
+        e = launch32_ksk(c, c.ws_ext, true, ct, galois[i], level, ksk[i], c.ws_uv, c.ws_p, s);
+        if (e == hipSuccess) e = moddown32(c, level, ct + (size_t)level * c.n, galois[i], ct_out[i], s);
     }
-    if (e == hipSuccess) e = launch32_conv_moddown(c, c.ws_p, level, c.ws_z, s);
-    if (e == hipSuccess) {
-        Map32 zm{};
-        zm.count = 0;
-        for (uint32_t p = 0; p < 2; ++p)
-            for (uint32_t i = 0; i < level; ++i) {
-                const uint32_t k = zm.count++;
-                zm.in_off[k] = zm.out_off[k] = (uint16_t)(p * c.L + i);
-                zm.mod[k] = (uint8_t)i;
-                zm.cidx[k] = (uint16_t)i;
-            }
-        e = launch32_fwd_cols(c, zm, c.ws_z, c.ws_z, s);
-    }
-    if (e == hipSuccess)
-        e = launch32_rows_epi(c, level, c.ws_z, c.ws_uv, ct + (size_t)level * N, galois, ct_out, s);
     return st32(e);
     GUARD32_END
 }

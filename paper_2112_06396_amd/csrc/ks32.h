@@ -80,9 +80,10 @@ hipError_t launch32_conv_modup(const Ctx32 &c, const uint32_t *y, uint32_t level
 hipError_t launch32_conv_moddown(const Ctx32 &c, const uint32_t *pc, uint32_t level, uint32_t *z, hipStream_t s);
 // Forward row pass of ext's new limbs + KSKInnerProd (own limbs gathered from
 // `a` through galois) + inverse row pass of the P limbs: uq [2][level][N],
-// pc [2][K][N].
-hipError_t launch32_ksk(const Ctx32 &c, const uint32_t *ext, const uint32_t *a, uint32_t galois, uint32_t level,
-                        const uint32_t *ksk, uint32_t *uq, uint32_t *pc, hipStream_t s);
+// pc [2][K][N].  With `direct`, ext's new limbs are in evaluation form
+// already and are gathered through galois as well (no row pass).
+hipError_t launch32_ksk(const Ctx32 &c, const uint32_t *ext, bool direct, const uint32_t *a, uint32_t galois,
+                        uint32_t level, const uint32_t *ksk, uint32_t *uq, uint32_t *pc, hipStream_t s);
 // ModDown's last step on the forward row pass of z: out[p] = (u[p] - z[p])
 // P^-1 (+ b gathered through galois for p = 1), p < 2.
 hipError_t launch32_rows_epi(const Ctx32 &c, uint32_t level, const uint32_t *z, const uint32_t *uq,

@@ -493,12 +493,15 @@ struct Ksk32Args {
     const Shoup32 *twf, *twi;
     const Mod32 *mc;
     uint32_t galois, n, n1, n2, level, L, K, E, alpha, beta;
+    uint32_t direct;  // ext holds the new limbs fully transformed: gather them too
 };
 
 // One block = one limb t of Q_level U P and ROW32 rows (the special-prime
 // limbs first): for each digit, the limb's forward row pass (or the digit's
 // own limb gathered from a through the automorphism), reduced to [0, q),
 // times the key rows, summed exactly in 64 bits (folded every 16 digits).
+// With `direct` (hoisted rotations) the new limbs are already in evaluation
+// form and are gathered through the automorphism like the own limbs.
 // q limbs store u, v; P limbs run ModDown's inverse row pass first.
 template <int LOGS, int E>
 __global__ void __launch_bounds__((Tile32<LOGS, ROW32, false, E>::NT)) ksk32_kernel(const Ksk32Args a) {
@@ -532,8 +535,8 @@ __global__ void __launch_bounds__((Tile32<LOGS, ROW32, false, E>::NT)) ksk32_ker
             }
         }
         uint32_t xv[E];
-        if (jd == own) {
-            const uint32_t *src = a.a + (size_t)tgt * N;
+        if (jd == own || a.direct) {
+            const uint32_t *src = jd == own ? a.a + (size_t)tgt * N : a.ext + ((size_t)jd * a.E + tgt) * N;
 #pragma unroll
             for (int e = 0; e < E; ++e) {
                 const uint32_t j = slot0 + e;
@@ -591,10 +594,11 @@ __global__ void __launch_bounds__((Tile32<LOGS, ROW32, false, E>::NT)) ksk32_ker
         a.pc[((size_t)a.K + kp) * N + jdx32<false>(lg, k32<P::HL, P::HH, E>(t, e), a.n2)] = v[e];
 }
 
-hipError_t launch32_ksk(const Ctx32 &c, const uint32_t *ext, const uint32_t *a, uint32_t galois, uint32_t level,
-                        const uint32_t *ksk, uint32_t *uq, uint32_t *pc, hipStream_t s) {
+hipError_t launch32_ksk(const Ctx32 &c, const uint32_t *ext, bool direct, const uint32_t *a, uint32_t galois,
+                        uint32_t level, const uint32_t *ksk, uint32_t *uq, uint32_t *pc, hipStream_t s) {
     Ksk32Args k{};
     k.ext = ext;
+    k.direct = direct ? 1 : 0;
     k.a = a;
     k.ksk = ksk;
     k.uq = uq;

@@ -51,7 +51,7 @@ EXPORTS = (
 )
 
 # every symbol declared in include/hks32.h (the 32-bit-word key-switch)
-EXPORTS32 = ("hks32_create", "hks32_destroy", "hks32_ntt", "hks32_intt", "hks32_rotate")
+EXPORTS32 = ("hks32_create", "hks32_destroy", "hks32_ntt", "hks32_intt", "hks32_rotate", "hks32_hrotate")
 
 HKS_K_NTT_FWD_COLS = 0
 HKS_K_NTT_FWD_ROWS = 1
@@ -156,6 +156,8 @@ def lib():
             "hks32_ntt": (_i32, [_vp, _vp, _u32, _u32, _vp]),
             "hks32_intt": (_i32, [_vp, _vp, _u32, _u32, _vp]),
             "hks32_rotate": (_i32, [_vp, _vp, _u32, _u32, _vp, _vp, _vp]),
+            "hks32_hrotate": (_i32, [_vp, _vp, _u32, _u32, ctypes.POINTER(_u32), ctypes.POINTER(_vp),
+                                     ctypes.POINTER(_vp), _vp]),
             "hks_prof_enable": (_i32, [_vp, _u32]),
             "hks_prof_read": (_i32, [_vp, _i32, ctypes.POINTER(ctypes.c_double), u64p]),
         }
@@ -517,6 +519,16 @@ def hks32_intt(ctx, x, first_mod: int, n_limbs: int, stream=None):
 def hks32_rotate(ctx, ct, level: int, galois: int, ksk, ct_out, stream=None):
     _check("hks32_rotate", lib().hks32_rotate(ctx.handle, _ptr32(ct), level, galois, _ptr32(ksk), _ptr32(ct_out),
                                               _stream(stream)))
+
+
+def hks32_hrotate(ctx, ct, level: int, galois, ksks, outs, stream=None):
+    r = len(galois)
+    if len(ksks) != r or len(outs) != r:
+        raise ValueError("galois, ksks and outs must have the same length")
+    ga = (_u32 * r)(*[int(g) for g in galois])
+    ka = (_vp * r)(*[_ptr32(k) for k in ksks])
+    oa = (_vp * r)(*[_ptr32(o) for o in outs])
+    _check("hks32_hrotate", lib().hks32_hrotate(ctx.handle, _ptr32(ct), level, r, ga, ka, oa, _stream(stream)))
 
 
 def to_device32(a, device="cuda") -> torch.Tensor:

@@ -35,7 +35,7 @@ def test_every_declared_symbol_is_exported(hks):
         assert hasattr(lib, name), name
     assert sorted(hks.EXPORTS) == declared
     declared32 = _declared("hks32.h", "hks32_")
-    assert len(declared32) == 5
+    assert len(declared32) == 6
     for name in declared32:
         assert hasattr(lib, name), name
     assert sorted(hks.EXPORTS32) == declared32

@@ -1,5 +1,5 @@
 """Parity of the 32-bit-word key-switch (include/hks32.h) with the oracle
-run on the same 30-bit primes: NTT / iNTT and Rotate, bit for bit, at small
+run on the same 30-bit primes: NTT / iNTT, Rotate and HRotate, bit for bit, at small
 sizes (several tiles, short last digit, level 1) and at N = 2^16 with the
 log2(QP) of the 50-bit benchmark (L = 40, K = 14, dnum = 3)."""
 import numpy as np
@@ -94,6 +94,38 @@ def test_rotate_equals_oracle(name):
             out = hks.empty32((2, level, pr.n))
             hks.hks32_rotate(ctx, hks.to_device32(ct), level, gal, dk, out)
             assert np.array_equal(host(out), O.rotate(pr, ct, level, gal, ksk)), (level, k)
+
+
+@pytest.mark.parametrize("name", list(CFGS))
+def test_hrotate_equals_oracle(name):
+    """HRotate (one ModUp, r KSKInnerProds over the automorphed digits) equals
+    the oracle's Algorithm 4 with the same 30-bit primes, bit for bit."""
+    pr, ctx = _get(name)
+    hks = H()
+    ks = (1, -5, 3) if name != "full" else (1, 7)
+    gals = [hks.hks_galois_for_rotation(k, pr.log_n) for k in ks]
+    ksks = [_ksk(pr, 850 + i) for i in range(len(ks))]
+    dks = [hks.to_device32(k) for k in ksks]
+    levels = [pr.L, 1] if name != "full" else [pr.L]
+    for level in levels:
+        ct = _ct(pr, level, 860 + level)
+        outs = [hks.empty32((2, level, pr.n)) for _ in ks]
+        hks.hks32_hrotate(ctx, hks.to_device32(ct), level, gals, dks, outs)
+        want = O.hrotate(pr, ct, level, gals, ksks)
+        for k, o, w in zip(ks, outs, want):
+            assert np.array_equal(host(o), w), (level, k)
+
+
+def test_hrotate_rejects_bad_arguments():
+    pr, ctx = _get("n10")
+    hks = H()
+    ct = hks.to_device32(_ct(pr, 2, 870))
+    k = hks.to_device32(_ksk(pr, 871))
+    out = hks.empty32((2, 2, pr.n))
+    for level, gals, o in ((0, [5], out), (pr.L + 1, [5], out), (2, [5, 4], out), (2, [5], ct), (2, [], out)):
+        with pytest.raises(hks.HksError) as e:
+            hks.hks32_hrotate(ctx, ct, level, gals, [k] * len(gals), [o] * len(gals))
+        assert e.value.status == hks.HKS_EINVAL
 
 
 def test_rotate_valid_key_decrypts():

@@ -311,6 +311,25 @@ def test_rotate_decrypts_with_30_bit_primes(cfg):
     assert bound < int(mods[0]) // 64
 
 
+def test_hrotate_decrypts_with_30_bit_primes():
+    """HRotate (Algorithm 4) in the oracle with 30-bit primes: every output
+    decrypts to its automorphed message within the key-switch noise bound."""
+    pr = O.make_params(10, 8, 3, 3, bits=30)
+    level = 7
+    g = synth.rng(4350)
+    s = synth.ternary(g, pr.n)
+    gals = [pow(5, -k, 2 * pr.n) for k in (1, 6, -4)]
+    ksks = [O.rotation_key(pr, s, gal, g) for gal in gals]
+    ct = O.encrypt(pr, s, synth.small_uniform(g, pr.n, 1 << 20), level, g)
+    mods = pr.q[:level]
+    m_in = O.decrypt_coef(pr, s, ct, level)
+    bound = O.ks_noise_bound(pr, level, s)
+    for gal, out in zip(gals, O.hrotate(pr, ct, level, gals, ksks)):
+        diff = O.sub_vec(O.decrypt_coef(pr, s, out, level),
+                         O.automorph(m_in, pr.log_n, mods, gal, eval_domain=False), pr.log_n, mods)
+        assert O.centered_small(diff, mods, bound) is not None
+
+
 def test_rotate_with_wrong_key_fails_decryption():
     pr, g, s = _setup(10, 6, 2, 3, 55)
     gal = pow(5, -1, 2 * pr.n)
