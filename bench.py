@@ -14,6 +14,7 @@ stderr.
   python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
 import argparse
+import contextlib
 import hashlib
 import json
 import os
@@ -40,6 +41,31 @@ MODMUL_PEAK = VALU_PEAK_OPS / MULS_PER_MODMUL
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+# launch plans used per workload ("tuned": the package's cache of plans timed
+# on this architecture and shape; "default": the library's)
+PLANS_USED = {}
+USE_TUNED_PLANS = True
+
+
+@contextlib.contextmanager
+def tuned_plan(hks, ctx, workload: str):
+    """Inside the block, the context runs the cached tuned plan for
+    `workload` (e.g. "batch16_l24"), if the cache has one; the previous plan
+    is restored after."""
+    import torch
+    from paper_2112_06396_amd import tune
+    prev = hks.hks_get_plan(ctx)
+    entry = None
+    if USE_TUNED_PLANS:
+        arch = torch.cuda.get_device_properties(0).gcnArchName
+        entry = tune.apply_cached(ctx, tune.cache_key(arch, LOG_N, L, K, DNUM, workload))
+    PLANS_USED[workload] = "tuned" if entry else "default"
+    try:
+        yield
+    finally:
+        hks.hks_set_plan(ctx, prev)
 
 
 def kernel_work(cls: int, n: int, level: int, k: int, alpha: int, beta: int):
@@ -146,15 +172,17 @@ def extras(args, ctx, hks, synth, cts, ksks, outs, gal, key_mods, n, plain_value
     log(f"[bench] extras: {nk} keys, 32 ciphertexts resident")
 
     # hoisted rotations (Algorithm 4): one ModUp shared by 64 rotations with distinct keys
-    res["hrotate_r64_ks_per_s"] = rate(
-        lambda i: hks.hks_hrotate(ctx, cts[i % args.pool], LEVEL, gals, dkeys, douts, stream), nk, 4)
+    with tuned_plan(hks, ctx, f"hrotate{nk}_l{LEVEL}"):
+        res["hrotate_r64_ks_per_s"] = rate(
+            lambda i: hks.hks_hrotate(ctx, cts[i % args.pool], LEVEL, gals, dkeys, douts, stream), nk, 4)
     # 32 ciphertexts rotated once: one shared key (read once per step) / 32 distinct keys and indices
-    res["batch32_shared_key_ks_per_s"] = rate(
-        lambda i: hks.hks_batch_rotate(ctx, dcts, LEVEL, [gal] * 32, [dkeys[i % nk]] * 32, douts[:32], stream),
-        32, 8)
-    res["batch32_distinct_keys_ks_per_s"] = rate(
-        lambda i: hks.hks_batch_rotate(ctx, dcts, LEVEL, gals[:32], dkeys[32 * (i % 2):32 * (i % 2) + 32],
-                                       douts[:32], stream), 32, 8)
+    with tuned_plan(hks, ctx, f"batch{args.batch}_l{LEVEL}"):
+        res["batch32_shared_key_ks_per_s"] = rate(
+            lambda i: hks.hks_batch_rotate(ctx, dcts, LEVEL, [gal] * 32, [dkeys[i % nk]] * 32, douts[:32],
+                                           stream), 32, 8)
+        res["batch32_distinct_keys_ks_per_s"] = rate(
+            lambda i: hks.hks_batch_rotate(ctx, dcts, LEVEL, gals[:32], dkeys[32 * (i % 2):32 * (i % 2) + 32],
+                                           douts[:32], stream), 32, 8)
     res["batch_vs_plain"] = res["batch32_shared_key_ks_per_s"] / plain_value
 
     # the key-switch kernel's achieved HBM rate in the batched and hoisted
@@ -181,14 +209,15 @@ def extras(args, ctx, hks, synth, cts, ksks, outs, gal, key_mods, n, plain_value
     # HRotate: the beta digits of E limbs (converted + own) are shared by the
     # rotations of a launch and count once per launch
     shared = beta * E * n * 8
-    forms = {
-        "batch32_distinct_keys": ksk_rate(
+    forms = {}
+    with tuned_plan(hks, ctx, f"batch{args.batch}_l{LEVEL}"):
+        forms["batch32_distinct_keys"] = ksk_rate(
             lambda i: hks.hks_batch_rotate(ctx, dcts, LEVEL, gals[:32], dkeys[32 * (i % 2):32 * (i % 2) + 32],
-                                           douts[:32], stream), 4, lambda reps, cnt: reps * 32 * per_rot),
-        "hrotate_r64": ksk_rate(
+                                           douts[:32], stream), 4, lambda reps, cnt: reps * 32 * per_rot)
+    with tuned_plan(hks, ctx, f"hrotate{nk}_l{LEVEL}"):
+        forms["hrotate_r64"] = ksk_rate(
             lambda i: hks.hks_hrotate(ctx, cts[i % args.pool], LEVEL, gals, dkeys, douts, stream), 4,
-            lambda reps, cnt: reps * nk * (per_rot - shared) + cnt * shared),
-    }
+            lambda reps, cnt: reps * nk * (per_rot - shared) + cnt * shared)
     forms["batch32_distinct_keys"]["algorithmic_bytes_per_rotation"] = per_rot
     forms["hrotate_r64"]["algorithmic_bytes_per_rotation"] = per_rot - shared
     forms["hrotate_r64"]["shared_bytes_per_launch"] = shared
@@ -460,9 +489,13 @@ def main():
                     help="run only the serving figures (with the --serving-* sizes) and print them")
     ap.add_argument("--w32-only", action="store_true",
                     help="time only the 32-bit-word Rotate (for profiling) and print its figures")
+    ap.add_argument("--default-plans", action="store_true",
+                    help="run every figure with the library's default launch plan (no tuned plans)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one plain copy of this many MiB (counter calibration)")
     args = ap.parse_args()
+    global USE_TUNED_PLANS
+    USE_TUNED_PLANS = not args.default_plans
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the key-switching path here runs on a single MI355X "
@@ -489,6 +522,9 @@ def main():
     alpha = ctx.alpha
     beta = ctx.beta(LEVEL)
     key_mods = q + p
+    # the main line runs the plan tuned for the plain Rotate (if cached)
+    main_plan = contextlib.ExitStack()
+    main_plan.enter_context(tuned_plan(hks, ctx, f"rotate_l{LEVEL}"))
 
     log(f"[bench] building pool of {args.pool} (ciphertext, key) pairs")
     cts, ksks, outs = [], [], []
@@ -628,7 +664,10 @@ def main():
     }
 
     if not args.no_extras:
+        main_plan.close()
         result.update(extras(args, ctx, hks, synth, cts, ksks, outs, gal, key_mods, n, value, stream))
+    main_plan.close()
+    result["launch_plans"] = dict(PLANS_USED)
 
     if args.calib_copy_mib:
         nw = args.calib_copy_mib * (1 << 20) // 8

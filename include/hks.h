@@ -287,6 +287,42 @@ int hks_add(hks_ctx *ctx, const uint64_t *x, const uint64_t *y, uint32_t level, 
  * contexts created afterwards. */
 int hks_set_check(hks_ctx *ctx, int on);
 
+/* ---------------------------------------------------------------- launch plans */
+
+/* Launch-shape choices of a context: how a launch's work is laid over the
+ * chip (elements per thread, grouping of conversion targets, block order
+ * across the 8 XCDs).  No field changes a result: every plan computes the
+ * same residues.  hks_create sets the defaults given below; the tuner
+ * (paper_2112_06396_amd/tune.py) times candidate plans on a workload and
+ * keeps the fastest per device and shape. */
+typedef struct {
+    /* NTT passes, indexed by class HKS_K_NTT_FWD_COLS .. HKS_K_NTT_INV_COLS:
+     * a launch runs 16 elements per thread when it holds at least this many
+     * waves of 16-element threads, else 8 (one more LDS exchange, twice the
+     * waves).  0 = always 16, 0xFFFFFFFF = always 8.  Default 6144. */
+    uint32_t e16_min_waves[4];
+    /* NewLimb (ModUp and ModDown conversions): a launch of at most
+     * conv_group_max_batch ciphertexts splits its target limbs into groups of
+     * about conv_group_limbs (one block row per group); wider launches keep
+     * all targets in one group.  Defaults 8 and 2; conv_group_limbs 1..64,
+     * conv_group_max_batch any value (0: never split). */
+    uint32_t conv_group_limbs;
+    uint32_t conv_group_max_batch;
+    /* Batched launches: 1 deals the entries of one (limb, row tile) to one
+     * XCD one after another, so that what they share (row-pass twiddles,
+     * a key tile shared by a batch) is fetched into that XCD's L2 once;
+     * 0 orders blocks entry by entry.  Defaults 1 and 1. */
+    uint32_t row_xcd_order;  /* batched NTT row passes */
+    uint32_t ksk_xcd_order;  /* batched KSKInnerProd */
+} hks_plan;
+
+/* Copies the context's plan into *out. */
+int hks_get_plan(hks_ctx *ctx, hks_plan *out);
+/* Replaces the plan for the calls that follow (enqueued work keeps the plan
+ * it was launched with).  HKS_EINVAL, plan unchanged, if conv_group_limbs is
+ * 0 or above 64 or an order flag is above 1. */
+int hks_set_plan(hks_ctx *ctx, const hks_plan *plan);
+
 /* ---------------------------------------------------------------- graphs */
 
 /* Call sequences recorded once and replayed as one HIP graph (a

@@ -945,6 +945,24 @@ int hks_set_check(hks_ctx *h, int on) {
     GUARD_END
 }
 
+int hks_get_plan(hks_ctx *h, hks_plan *out) {
+    GUARD_BEGIN
+    if (!h || !out) return HKS_EINVAL;
+    *out = h->c.plan;
+    return HKS_OK;
+    GUARD_END
+}
+
+int hks_set_plan(hks_ctx *h, const hks_plan *p) {
+    GUARD_BEGIN
+    if (!h || !p || p->conv_group_limbs == 0 || p->conv_group_limbs > 64 || p->row_xcd_order > 1 ||
+        p->ksk_xcd_order > 1)
+        return HKS_EINVAL;
+    h->c.plan = *p;
+    return HKS_OK;
+    GUARD_END
+}
+
 int hks_prof_enable(hks_ctx *h, uint32_t mask) {
     GUARD_BEGIN
     if (!h) return HKS_EINVAL;

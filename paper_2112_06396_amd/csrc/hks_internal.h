@@ -78,8 +78,20 @@ struct LastInv {
     Shoup c, cw;
 };
 
+// The launch plan hks_create starts from (include/hks.h, hks_plan).
+inline hks_plan default_plan() {
+    hks_plan p{};
+    for (int i = 0; i < 4; ++i) p.e16_min_waves[i] = 6 * 1024;
+    p.conv_group_limbs = 8;
+    p.conv_group_max_batch = 2;
+    p.row_xcd_order = 1;
+    p.ksk_xcd_order = 1;
+    return p;
+}
+
 struct Ctx {
     int device = 0;
+    hks_plan plan = default_plan();
     uint32_t log_n = 0, n = 0, L = 0, K = 0, dnum = 0, alpha = 0, M = 0;
     uint32_t n1 = 0, n2 = 0;  // NTT split: N = 2^n1 * 2^n2 (columns of 2^n1, rows of 2^n2)
     std::vector<uint64_t> mods;  // [M]: q_0..q_{L-1}, p_0..p_{K-1}

@@ -117,9 +117,12 @@ __global__ void __launch_bounds__(256) conv_kernel(const ConvArgs a) {
     }
 }
 
-// Target groups of a launch: about 8 targets per thread when the launch is a
-// single step of one or two ciphertexts (a thin grid), else one group.
-static uint32_t conv_groups(uint32_t nt, uint32_t batch) { return batch <= 2 ? std::max<uint32_t>(1, nt / 8) : 1; }
+// Target groups of a launch: about conv_group_limbs targets per block row
+// when the launch is a single step of a few ciphertexts (a thin grid: by
+// default one or two ciphertexts, groups of 8), else one group.
+static uint32_t conv_groups(const Ctx &c, uint32_t nt, uint32_t batch) {
+    return batch <= c.plan.conv_group_max_batch ? std::max<uint32_t>(1, nt / c.plan.conv_group_limbs) : 1;
+}
 
 template <bool MODUP>
 static hipError_t launch_conv_t(const ConvArgs &a, uint32_t ns_max, dim3 grid, hipStream_t s) {
@@ -147,7 +150,7 @@ hipError_t launch_conv_modup(const Ctx &c, const uint64_t *y, uint32_t level, ui
     a.K = c.K;
     a.alpha = c.alpha;
     const uint32_t beta = (level + c.alpha - 1) / c.alpha;
-    a.tgroups = conv_groups(level + c.K, batch);
+    a.tgroups = conv_groups(c, level + c.K, batch);
     ProfScope ps(c, HKS_K_CONV, s);
     return launch_conv_t<true>(a, c.alpha, dim3((c.n + 255) / 256, beta * a.tgroups, batch), s);
 }
@@ -168,7 +171,7 @@ hipError_t launch_conv_moddown(const Ctx &c, const uint64_t *p, uint32_t nt, uin
     a.L = c.L;
     a.K = ns;      // sources: the ns special limbs
     a.alpha = c.alpha;
-    a.tgroups = conv_groups(nt, batch);
+    a.tgroups = conv_groups(c, nt, batch);
     ProfScope ps(c, HKS_K_CONV, s);
     return launch_conv_t<false>(a, ns, dim3((c.n + 255) / 256, a.tgroups, batch), s);
 }

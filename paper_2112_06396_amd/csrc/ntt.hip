@@ -406,17 +406,17 @@ static hipError_t launch_pass_t(const NttArgs &a, uint32_t count, uint32_t batch
     ab.nb = batch;
     // row passes read a twiddle table as large as the limb: share it across
     // the batch through L2 (column-pass twiddles are few and always cached)
-    ab.xcd_batch = (!COLS && batch > 1 && xs % 8 == 0) ? 1u : 0u;
+    ab.xcd_batch = (!COLS && batch > 1 && xs % 8 == 0 && a.ctx->plan.row_xcd_order) ? 1u : 0u;
     const dim3 grid = ab.xcd_batch ? dim3(xs * batch, 1) : dim3(xs, batch);
     hipLaunchKernelGGL((ntt_pass_kernel<LOGS, LINES, COLS, FWD, IO, E>), grid, dim3(TL::NT), 0, s, ab);
     return hipGetLastError();
 }
 
 // Elements per thread: 16 (radix-16 phases) when the launch has enough
-// waves to fill the chip several times over, else 8 (radix-8 phases, one
+// waves to fill the chip several times over (the plan's threshold for the
+// pass class, 6 waves per SIMD by default), else 8 (radix-8 phases, one
 // more LDS exchange, twice the waves with half the work each), so that a
 // small launch still hides its memory latency.
-constexpr uint32_t WAVES_FOR_E16 = 6 * 1024;
 
 template <bool COLS, bool FWD, int IO, int E>
 static hipError_t dispatch_pass_e(const NttArgs &a, int logs, uint32_t count, uint32_t batch, hipStream_t s) {
@@ -434,8 +434,10 @@ static hipError_t dispatch_pass(const NttArgs &a, int logs, uint32_t count, uint
     if (count == 0 || batch == 0) return hipSuccess;
     if (batch > (uint32_t)MAXB) return hipErrorInvalidValue;
     const uint64_t waves16 = (uint64_t)count * batch * ((1ull << a.n) / 16) / 64;
-    return waves16 >= WAVES_FOR_E16 ? dispatch_pass_e<COLS, FWD, IO, 16>(a, logs, count, batch, s)
-                                    : dispatch_pass_e<COLS, FWD, IO, 8>(a, logs, count, batch, s);
+    const int cls = FWD ? (COLS ? HKS_K_NTT_FWD_COLS : HKS_K_NTT_FWD_ROWS)
+                        : (COLS ? HKS_K_NTT_INV_COLS : HKS_K_NTT_INV_ROWS);
+    return waves16 >= a.ctx->plan.e16_min_waves[cls] ? dispatch_pass_e<COLS, FWD, IO, 16>(a, logs, count, batch, s)
+                                                     : dispatch_pass_e<COLS, FWD, IO, 8>(a, logs, count, batch, s);
 }
 
 static NttArgs base_args(const Ctx &c, const LimbMap &m, const BatchIo &io, bool fwd) {
@@ -733,7 +735,7 @@ hipError_t launch_ksk_rows(const Ctx &c, const KskBatch &kb, uint32_t nb, const 
     a.pmod = c.pmod;
     a.pck = kb.newmult ? c.K + 1 : c.K;
     const uint32_t xs = ((1u << c.n1) / ROW_LINES) * a.E;
-    a.xcd_group = (nb > 1 && xs % 8 == 0) ? 1u : 0u;
+    a.xcd_group = (nb > 1 && xs % 8 == 0 && c.plan.ksk_xcd_order) ? 1u : 0u;
     ProfScope ps(c, HKS_K_KSK, s);
     const dim3 grid(xs * nb);
     // 8 elements per thread for every launch: the 128-bit lazy sums fit in

@@ -46,6 +46,7 @@ EXPORTS = (
     "hks_batch_rotate", "hks_rescale", "hks_ptmult", "hks_mult_relin", "hks_batch_mult_relin", "hks_new_mult",
     "hks_encode", "hks_add",
     "hks_expand_key_a", "hks_rotate_seeded", "hks_batch_rotate_seeded", "hks_ptmatvec", "hks_set_check",
+    "hks_get_plan", "hks_set_plan",
     "hks_graph_begin", "hks_graph_end", "hks_graph_launch", "hks_graph_destroy", "hks_prof_enable",
     "hks_prof_read",
 )
@@ -86,6 +87,21 @@ class _Params(ctypes.Structure):
         ("p", ctypes.POINTER(ctypes.c_uint64)),
         ("max_batch", ctypes.c_uint32),
     ]
+
+
+class _Plan(ctypes.Structure):
+    _fields_ = [
+        ("e16_min_waves", ctypes.c_uint32 * 4),
+        ("conv_group_limbs", ctypes.c_uint32),
+        ("conv_group_max_batch", ctypes.c_uint32),
+        ("row_xcd_order", ctypes.c_uint32),
+        ("ksk_xcd_order", ctypes.c_uint32),
+    ]
+
+
+# hks_plan fields as a flat dict: e16_min_waves is split per NTT pass class
+PLAN_FIELDS = ("e16_fwd_cols", "e16_fwd_rows", "e16_inv_rows", "e16_inv_cols", "conv_group_limbs",
+               "conv_group_max_batch", "row_xcd_order", "ksk_xcd_order")
 
 
 class _Params32(ctypes.Structure):
@@ -147,6 +163,8 @@ def lib():
             "hks_batch_rotate_seeded": (_i32, [_vp, _u32, ctypes.POINTER(_vp), _u32, ctypes.POINTER(_u32), u64p,
                                                ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp]),
             "hks_set_check": (_i32, [_vp, _i32]),
+            "hks_get_plan": (_i32, [_vp, ctypes.POINTER(_Plan)]),
+            "hks_set_plan": (_i32, [_vp, ctypes.POINTER(_Plan)]),
             "hks_graph_begin": (_i32, [_vp]),
             "hks_graph_end": (_i32, [_vp, ctypes.POINTER(_vp)]),
             "hks_graph_launch": (_i32, [_vp, _vp]),
@@ -409,6 +427,30 @@ def hks_encode(ctx, slots, scale: float, level: int, with_p: bool, pt_out, strea
 
 def hks_set_check(ctx, on: bool):
     _check("hks_set_check", lib().hks_set_check(ctx.handle, 1 if on else 0))
+
+
+def hks_get_plan(ctx) -> dict:
+    """The context's launch plan as a flat dict (keys PLAN_FIELDS)."""
+    p = _Plan()
+    _check("hks_get_plan", lib().hks_get_plan(ctx.handle, ctypes.byref(p)))
+    vals = list(p.e16_min_waves) + [p.conv_group_limbs, p.conv_group_max_batch, p.row_xcd_order, p.ksk_xcd_order]
+    return dict(zip(PLAN_FIELDS, (int(v) for v in vals)))
+
+
+def hks_set_plan(ctx, plan: dict):
+    """Sets the launch plan from a flat dict (keys PLAN_FIELDS; missing keys
+    keep the context's current values)."""
+    cur = hks_get_plan(ctx)
+    unknown = set(plan) - set(PLAN_FIELDS)
+    if unknown:
+        raise ValueError(f"unknown plan fields {sorted(unknown)}")
+    cur.update({k: int(v) for k, v in plan.items()})
+    p = _Plan()
+    for i, k in enumerate(PLAN_FIELDS[:4]):
+        p.e16_min_waves[i] = cur[k]
+    p.conv_group_limbs, p.conv_group_max_batch = cur["conv_group_limbs"], cur["conv_group_max_batch"]
+    p.row_xcd_order, p.ksk_xcd_order = cur["row_xcd_order"], cur["ksk_xcd_order"]
+    _check("hks_set_plan", lib().hks_set_plan(ctx.handle, ctypes.byref(p)))
 
 
 class Graph:
