@@ -98,6 +98,27 @@ struct TwRows {
         return tw[(((1u << n1) + row) << ls) + m];
     }
 };
+// The row twiddles of `lines` consecutive rows from row0, staged in LDS: for
+// local stage ls the rows' entries ((2^n1 + r) << ls) + m form one
+// contiguous run of lines << ls entries, stored at lines (2^ls - 1).
+template <int LINES>
+struct TwRowsLds {
+    const Shoup *tw;  // LDS
+    uint32_t line;    // row - row0
+    __device__ __forceinline__ Shoup operator()(int ls, uint32_t m) const {
+        return tw[LINES * ((1u << ls) - 1) + (line << ls) + m];
+    }
+};
+template <int LOGS, int LINES>
+__device__ __forceinline__ void stage_row_twiddles(Shoup *lds_tw, const Shoup *__restrict__ tw, uint32_t row0,
+                                                   uint32_t n1) {
+#pragma unroll
+    for (int ls = 0; ls < LOGS; ++ls) {
+        const Shoup *src = tw + (((1u << n1) + row0) << ls);
+        Shoup *dst = lds_tw + LINES * ((1u << ls) - 1);
+        for (uint32_t i = threadIdx.x; i < (LINES << ls); i += blockDim.x) dst[i] = src[i];
+    }
+}
 // The butterflies of one phase on the thread's E registers (layout [LO, HI)).
 // Each stage loads E >> (vb+1) distinct twiddles.  With FOLD (the inverse
 // column pass) the global last inverse stage multiplies by the folded
@@ -547,6 +568,11 @@ ksk_rows_kernel(const KskRowArgs a) {
     using IOI = IoLayout<LOGS, false, E>;
     static_assert(IOF::OUT_LO == IOI::IN_LO && IOF::OUT_HI == IOI::IN_HI, "row-pass layouts must chain");
     __shared__ uint64_t lds[TL::WORDS];
+    // direct digits (hoisted rotations): the special limbs' inverse row-pass
+    // twiddles for the block's ROW_LINES rows (every stage), staged once for
+    // u's and v's passes (measured: HRotate +2%; with the forward row passes
+    // of ROWPASS the staging latency costs more than it saves)
+    __shared__ Shoup lds_tw[ROWPASS ? 1 : ROW_LINES * ((1 << LOGS) - 1)];
     // block -> (x = target limb and row tile, b = ciphertext).  With
     // xcd_group the nb blocks of one x get ids that are equal modulo 8, so
     // that they run on one XCD (ids are dealt round-robin over the 8 XCDs)
@@ -683,12 +709,22 @@ ksk_rows_kernel(const KskRowArgs a) {
         return;
     }
     // special limb: inverse row pass (first pass of ModDown's iNTT) of u and v
-    const TwRows twi{a.twi + (size_t)mod * N, lg, a.n1};
     if (lds_used) __syncthreads();
-    pass_regs<LOGS, ROW_LINES, false, false, false, E>(true, u, lds, line, t, q, mcv.nq, twi, LastInv{});
-    gstore<LOGS, false, IOI::OUT_LO, IOI::OUT_HI, E>(u, pc + (size_t)kp * N, t, lg, a.n2);
-    __syncthreads();
-    pass_regs<LOGS, ROW_LINES, false, false, false, E>(true, v, lds, line, t, q, mcv.nq, twi, LastInv{});
+    if constexpr (ROWPASS) {
+        const TwRows twi{a.twi + (size_t)mod * N, lg, a.n1};
+        pass_regs<LOGS, ROW_LINES, false, false, false, E>(true, u, lds, line, t, q, mcv.nq, twi, LastInv{});
+        gstore<LOGS, false, IOI::OUT_LO, IOI::OUT_HI, E>(u, pc + (size_t)kp * N, t, lg, a.n2);
+        __syncthreads();
+        pass_regs<LOGS, ROW_LINES, false, false, false, E>(true, v, lds, line, t, q, mcv.nq, twi, LastInv{});
+    } else {
+        const TwRowsLds<ROW_LINES> twl{lds_tw, (uint32_t)line};
+        stage_row_twiddles<LOGS, ROW_LINES>(lds_tw, a.twi + (size_t)mod * N, tile * ROW_LINES, a.n1);
+        __syncthreads();
+        pass_regs<LOGS, ROW_LINES, false, false, false, E>(true, u, lds, line, t, q, mcv.nq, twl, LastInv{});
+        gstore<LOGS, false, IOI::OUT_LO, IOI::OUT_HI, E>(u, pc + (size_t)kp * N, t, lg, a.n2);
+        __syncthreads();
+        pass_regs<LOGS, ROW_LINES, false, false, false, E>(true, v, lds, line, t, q, mcv.nq, twl, LastInv{});
+    }
     gstore<LOGS, false, IOI::OUT_LO, IOI::OUT_HI, E>(v, pc + ((size_t)a.pck + kp) * N, t, lg, a.n2);
 }
 
