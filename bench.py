@@ -52,15 +52,15 @@ USE_TUNED_PLANS = True
 @contextlib.contextmanager
 def tuned_plan(hks, ctx, workload: str):
     """Inside the block, the context runs the cached tuned plan for
-    `workload` (e.g. "batch16_l24"), if the cache has one; the previous plan
-    is restored after."""
+    `workload` (e.g. "batch16_l24") and the context's shape, if the cache has
+    one; the previous plan is restored after."""
     import torch
     from paper_2112_06396_amd import tune
     prev = hks.hks_get_plan(ctx)
     entry = None
     if USE_TUNED_PLANS:
         arch = torch.cuda.get_device_properties(0).gcnArchName
-        entry = tune.apply_cached(ctx, tune.cache_key(arch, LOG_N, L, K, DNUM, workload))
+        entry = tune.apply_cached(ctx, tune.cache_key(arch, ctx.log_n, ctx.L, ctx.K, ctx.dnum, workload))
     PLANS_USED[workload] = "tuned" if entry else "default"
     try:
         yield
@@ -291,9 +291,10 @@ def extras(args, ctx, hks, synth, cts, ksks, outs, gal, key_mods, n, plain_value
     diag = {d: synth.device_residues(pq[:35], (), n, 100 + i) for i, d in enumerate(plan.diagonals)}
     tkeys = {k: synth.device_residues(pq, (3, 2), n, 2000 + i) for i, k in enumerate(plan.rotations)}
     rlk = synth.device_residues(pq, (3, 2), n, 1999)
-    res["trace_ks_per_s_eager"] = rate(lambda i: trace.run_plan(tctx, plan, bufs, diag, tkeys, rlk),
-                                       plan.key_switches, 3)
-    gr = trace.capture(tctx, plan, bufs, diag, tkeys, rlk)
+    with tuned_plan(hks, tctx, "trace_l35"):
+        res["trace_ks_per_s_eager"] = rate(lambda i: trace.run_plan(tctx, plan, bufs, diag, tkeys, rlk),
+                                           plan.key_switches, 3)
+        gr = trace.capture(tctx, plan, bufs, diag, tkeys, rlk)
     res["trace_ks_per_s_graph"] = rate(lambda i: gr.replay(), plan.key_switches, 3)
     res["trace"] = {"key_switches": plan.key_switches, "rotation_keys": len(plan.rotations), "levels": "35->9",
                     "ops": len(plan.ops)}
@@ -305,9 +306,10 @@ def extras(args, ctx, hks, synth, cts, ksks, outs, gal, key_mods, n, plain_value
     hext = trace.ext_diagonals(hplan, hdiag, 35)
     hbufs = trace.TraceBuffers(hplan, n)
     hbufs.view("x0", 35).copy_(bufs.view("x0", 35))
-    res["trace_hoisted_ks_per_s_eager"] = rate(
-        lambda i: trace.run_plan(tctx, hplan, hbufs, hdiag, tkeys, rlk, diag_ext=hext), hplan.key_switches, 3)
-    gr = trace.capture(tctx, hplan, hbufs, hdiag, tkeys, rlk, diag_ext=hext)
+    with tuned_plan(hks, tctx, "hoisted_trace_l35"):
+        res["trace_hoisted_ks_per_s_eager"] = rate(
+            lambda i: trace.run_plan(tctx, hplan, hbufs, hdiag, tkeys, rlk, diag_ext=hext), hplan.key_switches, 3)
+        gr = trace.capture(tctx, hplan, hbufs, hdiag, tkeys, rlk, diag_ext=hext)
     res["trace_hoisted_ks_per_s_graph"] = rate(lambda i: gr.replay(), hplan.key_switches, 3)
     log(f"[bench] hoisted trace: eager {res['trace_hoisted_ks_per_s_eager']:.0f} ks/s, "
         f"graph {res['trace_hoisted_ks_per_s_graph']:.0f} ks/s")
@@ -334,9 +336,10 @@ def extras(args, ctx, hks, synth, cts, ksks, outs, gal, key_mods, n, plain_value
     dbufs.view("x0", 35).copy_(synth.device_residues(pq[:35], (2,), n, 13))
     torch.cuda.synchronize()
     log(f"[bench] DFT trace: {len(dkeys)} rotation keys, {len(ddiag)} encoded diagonals resident")
-    res["dft_trace_ks_per_s_eager"] = rate(
-        lambda i: trace.run_plan(tctx, dplan, dbufs, {}, dkeys, rlk, diag_ext=dext), dplan.key_switches, 3)
-    gr = trace.capture(tctx, dplan, dbufs, {}, dkeys, rlk, diag_ext=dext)
+    with tuned_plan(hks, tctx, "dft_trace_l35"):
+        res["dft_trace_ks_per_s_eager"] = rate(
+            lambda i: trace.run_plan(tctx, dplan, dbufs, {}, dkeys, rlk, diag_ext=dext), dplan.key_switches, 3)
+        gr = trace.capture(tctx, dplan, dbufs, {}, dkeys, rlk, diag_ext=dext)
     res["dft_trace_ks_per_s_graph"] = rate(lambda i: gr.replay(), dplan.key_switches, 3)
     del gr, dext, dbufs
     uplan = trace.bootstrap_plan(35, dft=(LOG_N - 1, 3))

@@ -22,6 +22,8 @@ plans tuned on MI355X (gfx950) for the shapes the benchmark runs:
     python -m paper_2112_06396_amd.tune --workload rotate
     python -m paper_2112_06396_amd.tune --workload batch --size 16
     python -m paper_2112_06396_amd.tune --workload hrotate --size 64
+    python -m paper_2112_06396_amd.tune --workload dft_trace --L 35 --K 12 --level 35
+    (likewise trace, hoisted_trace)
 """
 import argparse
 import json
@@ -165,7 +167,8 @@ def tune(ctx, run, outputs, stream, reps: int, rounds: int = 2, min_gain: float 
 
 def _workload(args, hks, synth, ctx, key_mods, n, stream):
     """The benchmark's shapes: plain Rotate, a batch of `size` ciphertexts
-    with distinct keys, HRotate over `size` rotations; synthetic residues."""
+    with distinct keys, HRotate over `size` rotations, and the
+    bootstrapping-shaped traces; synthetic residues."""
     level = args.level
     gals = [hks.hks_galois_for_rotation(k + 1, args.log_n) for k in range(max(args.size, 1))]
     if args.workload == "rotate":
@@ -196,12 +199,33 @@ def _workload(args, hks, synth, ctx, key_mods, n, stream):
         def run(i):
             hks.hks_hrotate(ctx, ct, level, gals[:r], keys, outs, stream)
         return run, (lambda: outs), max(3, 100 // r), f"hrotate{r}_l{level}"
+    if args.workload in ("trace", "hoisted_trace", "dft_trace"):
+        # bootstrapping-shaped traces (trace.bootstrap_plan) run eagerly from
+        # the top level: synthetic stages, the same with hoisted PtMatVecMult
+        # stages and NewMult, or the factored DFT's own offsets
+        from . import trace
+        kw = {"trace": {}, "hoisted_trace": {"hoisted": True, "new_mult": True},
+              "dft_trace": {"hoisted": True, "new_mult": True, "dft": (args.log_n - 1, 3)}}[args.workload]
+        plan = trace.bootstrap_plan(level, **kw)
+        bufs = trace.TraceBuffers(plan, n)
+        bufs.view("x0", level).copy_(synth.device_residues(key_mods[:level], (2,), n, 11))
+        keys = {k: synth.device_residues(key_mods, (args.dnum, 2), n, 2000 + i) for i, k in enumerate(plan.rotations)}
+        rlk = synth.device_residues(key_mods, (args.dnum, 2), n, 1999)
+        dmods = key_mods if kw else key_mods[:level]
+        diag = {d: synth.device_residues(dmods, (), n, 100 + i) for i, d in enumerate(plan.diagonals)}
+        ext = trace.ext_diagonals(plan, diag, args.L) if kw else None
+
+        def run(i):
+            trace.run_plan(ctx, plan, bufs, diag, keys, rlk, stream=stream, diag_ext=ext)
+        outs = [bufs.ct[name] for name in sorted(plan.buffers) if name != "x0"]
+        return run, (lambda: outs), 3, f"{args.workload}_l{level}"
     raise ValueError(args.workload)
 
 
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
-    ap.add_argument("--workload", choices=("rotate", "batch", "hrotate"), default="rotate")
+    ap.add_argument("--workload", choices=("rotate", "batch", "hrotate", "trace", "hoisted_trace", "dft_trace"),
+                    default="rotate")
     ap.add_argument("--size", type=int, default=16, help="ciphertexts (batch) or rotations (hrotate)")
     ap.add_argument("--log-n", type=int, default=16)
     ap.add_argument("--L", type=int, default=24)
