@@ -299,7 +299,8 @@ typedef struct {
     /* NTT passes, indexed by class HKS_K_NTT_FWD_COLS .. HKS_K_NTT_INV_COLS:
      * a launch runs 16 elements per thread when it holds at least this many
      * waves of 16-element threads, else 8 (one more LDS exchange, twice the
-     * waves).  0 = always 16, 0xFFFFFFFF = always 8.  Default 6144. */
+     * waves).  0 = always 16, 0xFFFFFFFF = always 8.  Defaults 6144, except
+     * 0xFFFFFFFF for the forward row pass. */
     uint32_t e16_min_waves[4];
     /* NewLimb (ModUp and ModDown conversions): a launch of at most
      * conv_group_max_batch ciphertexts splits its target limbs into groups of

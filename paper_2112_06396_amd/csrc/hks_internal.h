@@ -82,6 +82,9 @@ struct LastInv {
 inline hks_plan default_plan() {
     hks_plan p{};
     for (int i = 0; i < 4; ++i) p.e16_min_waves[i] = 6 * 1024;
+    // the forward row pass (ModDown's last pass with its epilogue) measured
+    // faster with 8 elements per thread at every batch size
+    p.e16_min_waves[HKS_K_NTT_FWD_ROWS] = 0xFFFFFFFFu;
     p.conv_group_limbs = 8;
     p.conv_group_max_batch = 2;
     p.row_xcd_order = 1;

@@ -435,9 +435,10 @@ static hipError_t launch_pass_t(const NttArgs &a, uint32_t count, uint32_t batch
 
 // Elements per thread: 16 (radix-16 phases) when the launch has enough
 // waves to fill the chip several times over (the plan's threshold for the
-// pass class, 6 waves per SIMD by default), else 8 (radix-8 phases, one
-// more LDS exchange, twice the waves with half the work each), so that a
-// small launch still hides its memory latency.
+// pass class: 6 waves per SIMD by default, never for the forward row pass
+// by default), else 8 (radix-8 phases, one more LDS exchange, twice the
+// waves with half the work each), so that a small launch still hides its
+// memory latency.
 
 template <bool COLS, bool FWD, int IO, int E>
 static hipError_t dispatch_pass_e(const NttArgs &a, int logs, uint32_t count, uint32_t batch, hipStream_t s) {

@@ -68,7 +68,7 @@ def test_plan_get_set_and_rejection():
     hks = H()
     pr, ctx = _get("n10")
     d = hks.hks_get_plan(ctx)
-    assert d == {"e16_fwd_cols": 6144, "e16_fwd_rows": 6144, "e16_inv_rows": 6144, "e16_inv_cols": 6144,
+    assert d == {"e16_fwd_cols": 6144, "e16_fwd_rows": A8, "e16_inv_rows": 6144, "e16_inv_cols": 6144,
                  "conv_group_limbs": 8, "conv_group_max_batch": 2, "row_xcd_order": 1, "ksk_xcd_order": 1}
     hks.hks_set_plan(ctx, PLANS["mixed"])
     assert hks.hks_get_plan(ctx) == PLANS["mixed"]

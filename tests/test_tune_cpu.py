@@ -20,7 +20,7 @@ def _cost(best):
 
 
 def _default():
-    return {"e16_fwd_cols": 6144, "e16_fwd_rows": 6144, "e16_inv_rows": 6144, "e16_inv_cols": 6144,
+    return {"e16_fwd_cols": 6144, "e16_fwd_rows": tune.ALWAYS8, "e16_inv_rows": 6144, "e16_inv_cols": 6144,
             "conv_group_limbs": 8, "conv_group_max_batch": 2, "row_xcd_order": 1, "ksk_xcd_order": 1}
 
 
