@@ -36,9 +36,10 @@ typedef struct {
 } hks32_params;
 
 /* Context: validates the primes (HKS_EINVAL otherwise), builds twiddle and
- * conversion tables on `device` and allocates the workspace of one
- * key-switch at the top level ([L] + [dnum][L+K] + [2][L] + [2][K] + [2][L]
- * limbs).  Calls on one context must not overlap. */
+ * conversion tables on `device` and allocates the workspace of a key-switch
+ * at the top level with ModDown slots for four (hoisted) rotations
+ * ([L] + [dnum][L+K] + 4 ([2][L] + [2][K] + [2][L]) limbs).  Calls on one
+ * context must not overlap. */
 int hks32_create(const hks32_params *params, int device, hks32_ctx **out);
 void hks32_destroy(hks32_ctx *ctx);
 
@@ -58,7 +59,8 @@ int hks32_rotate(hks32_ctx *ctx, const uint32_t *ct, uint32_t level, uint32_t ga
 /* HRotate (Algorithm 4): one ModUp of a (no automorphism; the extended
  * digits taken fully into evaluation form), then for each i < r the
  * KSKInnerProd with ksk[i] over the digits automorphed by galois[i], ModDown
- * of u and v, and ct_out[i] = (u, v + automorph(b, galois[i])).  galois, ksk
+ * of u and v (one sequence per four rotations), and
+ * ct_out[i] = (u, v + automorph(b, galois[i])).  galois, ksk
  * and ct_out are HOST arrays of r entries (ksk[i], ct_out[i] device
  * pointers, 16-byte aligned, ct_out[i] not aliasing ct).  Same residues as
  * hks_hrotate of include/hks.h for the same primes; they differ from r calls

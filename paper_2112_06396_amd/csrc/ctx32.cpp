@@ -228,34 +228,28 @@ hipError_t modup32(const Ctx32 &c, const uint32_t *a, uint32_t level, uint32_t g
     return e;
 }
 
-// ModDown of u and v (ws_uv's q limbs, ws_p's P limbs after their inverse
-// row pass) into ct_out: inverse column pass of the P limbs with
-// N^-1 (P / p_k)^-1, NewLimb, forward NTT + (u - z) P^-1, plus b gathered
-// through galois on v.
-hipError_t moddown32(const Ctx32 &c, uint32_t level, const uint32_t *b, uint32_t galois, uint32_t *ct_out,
-                     hipStream_t s) {
-    const uint32_t K = c.K;
+// ModDown of u and v for nrot <= HB32 key switches r (ws_uv's slot r, q
+// limbs; ws_p's slot r, P limbs after their inverse row pass) into
+// outs[r]: inverse column pass of the P limbs with N^-1 (P / p_k)^-1,
+// NewLimb, forward NTT + (u - z) P^-1, plus b gathered through gals[r] on v.
+hipError_t moddown32(const Ctx32 &c, uint32_t level, uint32_t nrot, const uint32_t *b, uint32_t *const *outs,
+                     const uint32_t *gals, hipStream_t s) {
+    const uint32_t K = c.K, ys = 2 * nrot;
+    const size_t N = c.n;
     Map32 pm{};
-    pm.count = 2 * K;
-    for (uint32_t i = 0; i < 2 * K; ++i) {
-        pm.in_off[i] = pm.out_off[i] = (uint16_t)i;
-        pm.mod[i] = (uint8_t)(c.L + i % K);
-        pm.cidx[i] = (uint16_t)(i % K);
+    pm.count = K;
+    for (uint32_t k = 0; k < K; ++k) {
+        pm.in_off[k] = pm.out_off[k] = (uint16_t)k;
+        pm.mod[k] = (uint8_t)(c.L + k);
+        pm.cidx[k] = (uint16_t)k;
     }
-    hipError_t e = launch32_inv_cols(c, pm, c.ws_p, c.ws_p, c.li_moddown, s);
-    if (e == hipSuccess) e = launch32_conv_moddown(c, c.ws_p, level, c.ws_z, s);
+    hipError_t e = launch32_inv_cols(c, pm, c.ws_p, c.ws_p, c.li_moddown, s, ys, K * N, K * N);
+    if (e == hipSuccess) e = launch32_conv_moddown(c, c.ws_p, level, ys, c.ws_z, s);
     if (e == hipSuccess) {
-        Map32 zm{};
-        for (uint32_t p = 0; p < 2; ++p)
-            for (uint32_t i = 0; i < level; ++i) {
-                const uint32_t k = zm.count++;
-                zm.in_off[k] = zm.out_off[k] = (uint16_t)(p * c.L + i);
-                zm.mod[k] = (uint8_t)i;
-                zm.cidx[k] = (uint16_t)i;
-            }
-        e = launch32_fwd_cols(c, zm, c.ws_z, c.ws_z, s);
+        const Map32 zm = consecutive(0, level);
+        e = launch32_fwd_cols(c, zm, c.ws_z, c.ws_z, s, ys, c.L * N, c.L * N);
     }
-    if (e == hipSuccess) e = launch32_rows_epi(c, level, c.ws_z, c.ws_uv, b, galois, ct_out, s);
+    if (e == hipSuccess) e = launch32_rows_epi(c, level, c.ws_z, c.ws_uv, b, nrot, outs, gals, s);
     return e;
 }
 
@@ -298,7 +292,8 @@ int hks32_create(const hks32_params *p, int device, hks32_ctx **out) {
     int rc = build_tables32(c);
     if (rc == HKS_OK) {
         const size_t N = c.n, L = c.L, K = c.K;
-        const size_t words[] = {L * N, (size_t)c.dnum * c.M * N, 2 * L * N, 2 * K * N, 2 * L * N};
+        const size_t words[] = {L * N, (size_t)c.dnum * c.M * N, HB32 * 2 * L * N, HB32 * 2 * K * N,
+                                HB32 * 2 * L * N};
         size_t total = 0;
         for (size_t w : words) total += w;
         if (hipMalloc((void **)&c.ws, total * sizeof(uint32_t)) != hipSuccess) {
@@ -366,7 +361,7 @@ int hks32_rotate(hks32_ctx *h, const uint32_t *ct, uint32_t level, uint32_t galo
     hipError_t e = modup32(c, ct, level, galois, false, s);
     // KSKInnerProd (+ the new limbs' row pass, + ModDown's P-limb inverse rows)
     if (e == hipSuccess) e = launch32_ksk(c, c.ws_ext, false, ct, galois, level, ksk, c.ws_uv, c.ws_p, s);
-    if (e == hipSuccess) e = moddown32(c, level, ct + (size_t)level * c.n, galois, ct_out, s);
+    if (e == hipSuccess) e = moddown32(c, level, 1, ct + (size_t)level * c.n, &ct_out, &galois, s);
     return st32(e);
     GUARD32_END
 }
@@ -383,11 +378,17 @@ int hks32_hrotate(hks32_ctx *h, const uint32_t *ct, uint32_t level, uint32_t r, 
             return HKS_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     // one ModUp of a, new limbs fully transformed; then per rotation the
-    // KSKInnerProd gathers every digit limb through its automorphism
+    // KSKInnerProd gathers every digit limb through its automorphism, into
+    // the rotation's slot of the workspace, and one ModDown sequence serves
+    // HB32 rotations
+    const size_t N = c.n;
     hipError_t e = modup32(c, ct, level, 1, true, s);
-    for (uint32_t i = 0; i < r && e == hipSuccess; ++i) {
-        e = launch32_ksk(c, c.ws_ext, true, ct, galois[i], level, ksk[i], c.ws_uv, c.ws_p, s);
-        if (e == hipSuccess) e = moddown32(c, level, ct + (size_t)level * c.n, galois[i], ct_out[i], s);
+    for (uint32_t i0 = 0; i0 < r && e == hipSuccess; i0 += HB32) {
+        const uint32_t nb = std::min(HB32, r - i0);
+        for (uint32_t b = 0; b < nb && e == hipSuccess; ++b)
+            e = launch32_ksk(c, c.ws_ext, true, ct, galois[i0 + b], level, ksk[i0 + b],
+                             c.ws_uv + (size_t)b * 2 * level * N, c.ws_p + (size_t)b * 2 * c.K * N, s);
+        if (e == hipSuccess) e = moddown32(c, level, nb, ct + (size_t)level * N, ct_out + i0, galois + i0, s);
     }
     return st32(e);
     GUARD32_END

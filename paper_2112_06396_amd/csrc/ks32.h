@@ -19,6 +19,7 @@ namespace w32 {
 
 constexpr uint32_t MAXL32 = 255;  // moduli per context (uint8 indices)
 constexpr uint32_t MAXS32 = 16;   // source limbs of one basis conversion
+constexpr uint32_t HB32 = 4;      // rotations of one ModDown step (HRotate)
 
 struct Shoup32 {
     uint32_t w, wp;  // wp = floor(w 2^32 / q)
@@ -57,37 +58,46 @@ struct Ctx32 {
     std::vector<size_t> conv_modup_off;  // [L+1]
     uint32_t *conv_moddown = nullptr;    // [L][K] of [P / p_k]_{q_i}
     Shoup32 *pinv = nullptr;             // [L]: P^-1 mod q_i
-    // workspace, allocated at create: sized for the top level
+    // workspace, allocated at create: sized for the top level and HB32
+    // rotations per ModDown step; the per-rotation slots of ws_uv are
+    // [2][level][N] at stride 2 level N, those of ws_p [2][K][N]
     uint32_t *ws = nullptr;
-    uint32_t *ws_y = nullptr;    // [L][N]        coefficient-form input limbs
-    uint32_t *ws_ext = nullptr;  // [dnum][L+K][N] extended digits
-    uint32_t *ws_uv = nullptr;   // [2][L][N]     KSKInnerProd on the q limbs
-    uint32_t *ws_p = nullptr;    // [2][K][N]     P limbs of u, v
-    uint32_t *ws_z = nullptr;    // [2][L][N]     ModDown corrections
+    uint32_t *ws_y = nullptr;    // [L][N]             coefficient-form input limbs
+    uint32_t *ws_ext = nullptr;  // [dnum][L+K][N]     extended digits
+    uint32_t *ws_uv = nullptr;   // [HB32][2][L][N]    KSKInnerProd on the q limbs
+    uint32_t *ws_p = nullptr;    // [HB32][2][K][N]    P limbs of u, v
+    uint32_t *ws_z = nullptr;    // [HB32][2][L][N]    ModDown corrections
 };
 
-// Launchers (ks32.hip).  All limbs of a launch share the batch-free layout
-// of their map; the pass launches take `fold` for the inverse column pass.
-hipError_t launch32_fwd_cols(const Ctx32 &c, const Map32 &m, const uint32_t *in, uint32_t *out, hipStream_t s);
+// Launchers (ks32.hip).  The limbs of a launch follow its map, repeated for
+// `ys` polynomials at strides in_ys / out_ys words; the inverse column pass
+// takes `fold`.
+hipError_t launch32_fwd_cols(const Ctx32 &c, const Map32 &m, const uint32_t *in, uint32_t *out, hipStream_t s,
+                             uint32_t ys = 1, size_t in_ys = 0, size_t out_ys = 0);
 hipError_t launch32_fwd_rows(const Ctx32 &c, const Map32 &m, const uint32_t *in, uint32_t *out, hipStream_t s);
 hipError_t launch32_inv_rows(const Ctx32 &c, const Map32 &m, const uint32_t *in, uint32_t *out, uint32_t galois,
                              hipStream_t s);
 hipError_t launch32_inv_cols(const Ctx32 &c, const Map32 &m, const uint32_t *in, uint32_t *out, const Last32 *fold,
-                             hipStream_t s);
+                             hipStream_t s, uint32_t ys = 1, size_t in_ys = 0, size_t out_ys = 0);
 // ModUp's NewLimb at `level`: ext[j][t] for t outside digit j, from y.
 hipError_t launch32_conv_modup(const Ctx32 &c, const uint32_t *y, uint32_t level, uint32_t *ext, hipStream_t s);
-// ModDown's NewLimb: z[p][i] (i < level) from the K P limbs pc[p][k], p < 2.
-hipError_t launch32_conv_moddown(const Ctx32 &c, const uint32_t *pc, uint32_t level, uint32_t *z, hipStream_t s);
+// ModDown's NewLimb: z[p][i] (i < level, z at stride L N) from the K P limbs
+// pc[p][k], p < polys.
+hipError_t launch32_conv_moddown(const Ctx32 &c, const uint32_t *pc, uint32_t level, uint32_t polys, uint32_t *z,
+                                 hipStream_t s);
 // Forward row pass of ext's new limbs + KSKInnerProd (own limbs gathered from
 // `a` through galois) + inverse row pass of the P limbs: uq [2][level][N],
 // pc [2][K][N].  With `direct`, ext's new limbs are in evaluation form
 // already and are gathered through galois as well (no row pass).
 hipError_t launch32_ksk(const Ctx32 &c, const uint32_t *ext, bool direct, const uint32_t *a, uint32_t galois,
                         uint32_t level, const uint32_t *ksk, uint32_t *uq, uint32_t *pc, hipStream_t s);
-// ModDown's last step on the forward row pass of z: out[p] = (u[p] - z[p])
-// P^-1 (+ b gathered through galois for p = 1), p < 2.
+// ModDown's last step on the forward row pass of z, for nrot <= HB32
+// ciphertexts r: polynomial p of r is y = 2 r + p, z at z + y L N, u at
+// uq + y level N; outs[r][p] = (u - z) P^-1, plus b gathered through
+// gals[r] for p = 1.
 hipError_t launch32_rows_epi(const Ctx32 &c, uint32_t level, const uint32_t *z, const uint32_t *uq,
-                             const uint32_t *b, uint32_t galois, uint32_t *out, hipStream_t s);
+                             const uint32_t *b, uint32_t nrot, uint32_t *const *outs, const uint32_t *gals,
+                             hipStream_t s);
 
 int build_tables32(Ctx32 &c);
 void free_tables32(Ctx32 &c);

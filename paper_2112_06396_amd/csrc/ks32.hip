@@ -249,8 +249,10 @@ struct Pass32Args {
     size_t in_ys, out_ys;   // per blockIdx.y (polynomial) strides in words
     const uint32_t *uq;     // P32_EPI: u at uq + y uq_ys + cidx N
     size_t uq_ys;
-    const uint32_t *b;      // P32_EPI: added to polynomial 1, gathered through galois
-    uint32_t galois;        // P32_GATHER / P32_EPI
+    const uint32_t *b;      // P32_EPI: added to polynomial 1, gathered through gal[y / 2]
+    uint32_t galois;        // P32_GATHER
+    uint32_t *outs[HB32];   // P32_EPI: polynomial y at outs[y / 2] + (y % 2) out_ys
+    uint32_t gal[HB32];
     uint32_t n, n1, n2;
     Map32 m;
 };
@@ -269,7 +271,8 @@ __global__ void __launch_bounds__((Tile32<LOGS, LINES, COLS>::NT)) pass32_kernel
     const Mod32 mc = a.mc[mod];
     const uint32_t q = mc.q;
     const uint32_t *src = a.in + y * a.in_ys + (size_t)a.m.in_off[li] * N;
-    uint32_t *dst = a.out + y * a.out_ys + (size_t)a.m.out_off[li] * N;
+    uint32_t *dst = (IO == P32_EPI ? a.outs[y >> 1] + (y & 1) * a.out_ys : a.out + y * a.out_ys) +
+                    (size_t)a.m.out_off[li] * N;
     int line, t;
     coords32<LOGS, LINES, COLS>(threadIdx.x, line, t);
     const uint32_t lg = tile * LINES + line;
@@ -296,14 +299,15 @@ __global__ void __launch_bounds__((Tile32<LOGS, LINES, COLS>::NT)) pass32_kernel
 
     if (IO == P32_EPI) {
         const uint32_t ui = a.m.cidx[li];
-        const uint32_t *bb = (y == 1 && a.b) ? a.b + (size_t)ui * N : nullptr;
+        const uint32_t *bb = ((y & 1) && a.b) ? a.b + (size_t)ui * N : nullptr;
+        const uint32_t g = a.gal[y >> 1];
         const Shoup32 pi = a.pinv[ui];
 #pragma unroll
         for (int e = 0; e < E32; ++e) {
             const uint32_t j = jdx32<COLS>(lg, k32<OUT_LO, OUT_HI>(t, e), a.n2);
             const uint32_t z = csub32(csub32(x[e], 2 * q), q);
             uint32_t r = csub32(shoup32(uv[e] + q - z, pi.w, pi.wp, q), q);
-            if (bb) r = csub32(r + bb[a.galois != 1 ? aut_eval_src(j, a.galois, a.n) : j], q);
+            if (bb) r = csub32(r + bb[g != 1 ? aut_eval_src(j, g, a.n) : j], q);
             x[e] = r;
         }
     } else if (FWD && IO == P32_REDUCE) {
@@ -355,8 +359,12 @@ static Pass32Args pass_args(const Ctx32 &c, const Map32 &m, const uint32_t *in, 
     return a;
 }
 
-hipError_t launch32_fwd_cols(const Ctx32 &c, const Map32 &m, const uint32_t *in, uint32_t *out, hipStream_t s) {
-    return launch_pass32<true, true, P32_PLAIN>(c, pass_args(c, m, in, out, true), 1, s);
+hipError_t launch32_fwd_cols(const Ctx32 &c, const Map32 &m, const uint32_t *in, uint32_t *out, hipStream_t s,
+                             uint32_t ys, size_t in_ys, size_t out_ys) {
+    Pass32Args a = pass_args(c, m, in, out, true);
+    a.in_ys = in_ys;
+    a.out_ys = out_ys;
+    return launch_pass32<true, true, P32_PLAIN>(c, a, ys, s);
 }
 
 hipError_t launch32_fwd_rows(const Ctx32 &c, const Map32 &m, const uint32_t *in, uint32_t *out, hipStream_t s) {
@@ -372,14 +380,18 @@ hipError_t launch32_inv_rows(const Ctx32 &c, const Map32 &m, const uint32_t *in,
 }
 
 hipError_t launch32_inv_cols(const Ctx32 &c, const Map32 &m, const uint32_t *in, uint32_t *out, const Last32 *fold,
-                             hipStream_t s) {
+                             hipStream_t s, uint32_t ys, size_t in_ys, size_t out_ys) {
     Pass32Args a = pass_args(c, m, in, out, false);
     a.fold = fold;
-    return launch_pass32<true, false, P32_PLAIN>(c, a, 1, s);
+    a.in_ys = in_ys;
+    a.out_ys = out_ys;
+    return launch_pass32<true, false, P32_PLAIN>(c, a, ys, s);
 }
 
 hipError_t launch32_rows_epi(const Ctx32 &c, uint32_t level, const uint32_t *z, const uint32_t *uq,
-                             const uint32_t *b, uint32_t galois, uint32_t *out, hipStream_t s) {
+                             const uint32_t *b, uint32_t nrot, uint32_t *const *outs, const uint32_t *gals,
+                             hipStream_t s) {
+    if (nrot == 0 || nrot > HB32) return hipErrorInvalidValue;
     Map32 m{};
     m.count = level;
     for (uint32_t i = 0; i < level; ++i) {
@@ -388,15 +400,18 @@ hipError_t launch32_rows_epi(const Ctx32 &c, uint32_t level, const uint32_t *z, 
         m.mod[i] = (uint8_t)i;
         m.cidx[i] = (uint16_t)i;
     }
-    Pass32Args a = pass_args(c, m, z, out, true);
+    Pass32Args a = pass_args(c, m, z, nullptr, true);
     const size_t pl = (size_t)level * c.n;
     a.in_ys = (size_t)c.L * c.n;
     a.out_ys = pl;
     a.uq = uq;
     a.uq_ys = pl;
     a.b = b;
-    a.galois = galois;
-    return launch_pass32<false, true, P32_EPI>(c, a, 2, s);
+    for (uint32_t r = 0; r < nrot; ++r) {
+        a.outs[r] = outs[r];
+        a.gal[r] = gals[r];
+    }
+    return launch_pass32<false, true, P32_EPI>(c, a, 2 * nrot, s);
 }
 
 // ------------------------------------------------------------------ NewLimb
@@ -477,10 +492,11 @@ hipError_t launch32_conv_modup(const Ctx32 &c, const uint32_t *y, uint32_t level
     return launch_conv32_t<true>(a, c.alpha, dim3((c.n + 255) / 256, beta, g), s);
 }
 
-hipError_t launch32_conv_moddown(const Ctx32 &c, const uint32_t *pc, uint32_t level, uint32_t *z, hipStream_t s) {
+hipError_t launch32_conv_moddown(const Ctx32 &c, const uint32_t *pc, uint32_t level, uint32_t polys, uint32_t *z,
+                                 hipStream_t s) {
     const uint32_t g = conv_groups(level);
     Conv32Args a{pc, z, c.conv_moddown, c.mc, c.log_n, level, c.L, c.K, c.alpha, g};
-    return launch_conv32_t<false>(a, c.K, dim3((c.n + 255) / 256, 2, g), s);
+    return launch_conv32_t<false>(a, c.K, dim3((c.n + 255) / 256, polys, g), s);
 }
 
 // ------------------------------------------------------------------ KSKInnerProd

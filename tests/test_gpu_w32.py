@@ -102,7 +102,8 @@ def test_hrotate_equals_oracle(name):
     the oracle's Algorithm 4 with the same 30-bit primes, bit for bit."""
     pr, ctx = _get(name)
     hks = H()
-    ks = (1, -5, 3) if name != "full" else (1, 7)
+    # six rotations: ModDown steps of four and two
+    ks = (1, -5, 3, 2, -1, 6) if name != "full" else (1, 7)
     gals = [hks.hks_galois_for_rotation(k, pr.log_n) for k in ks]
     ksks = [_ksk(pr, 850 + i) for i in range(len(ks))]
     dks = [hks.to_device32(k) for k in ksks]
