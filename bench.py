@@ -615,6 +615,8 @@ def main():
     roof["algorithmic_per_launch"] = {"modmul": per_launch_mm, "bytes": per_launch_bytes}
     tr = read_traffic(dom_name)
     roof["traffic"] = tr
+    # the counted bytes (L2 misses, Infinity Cache hits included) over the same duration
+    roof["traffic_GBps"] = tr / avg_launch_s / 1e9 if tr else None
 
     # compulsory HBM bytes of one Rotate: a, b, key (digits < beta, limbs [0,level) U P), output
     key_bytes = beta * 2 * (LEVEL + K) * n * 8
