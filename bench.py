@@ -183,7 +183,8 @@ def extras(args, ctx, hks, synth, cts, ksks, outs, gal, key_mods, n, plain_value
         res["batch32_distinct_keys_ks_per_s"] = rate(
             lambda i: hks.hks_batch_rotate(ctx, dcts, LEVEL, gals[:32], dkeys[32 * (i % 2):32 * (i % 2) + 32],
                                            douts[:32], stream), 32, 8)
-    res["batch_vs_plain"] = res["batch32_shared_key_ks_per_s"] / plain_value
+    if plain_value:
+        res["batch_vs_plain"] = res["batch32_shared_key_ks_per_s"] / plain_value
 
     # the key-switch kernel's achieved HBM rate in the batched and hoisted
     # forms (separate pass with the library's per-launch events):
@@ -224,6 +225,8 @@ def extras(args, ctx, hks, synth, cts, ksks, outs, gal, key_mods, n, plain_value
     res["ksk_roofline_batched"] = forms
     log(f"[bench] ksk kernel HBM rate: batch 32 distinct keys "
         f"{forms['batch32_distinct_keys']['achieved']:.0f} GB/s, hrotate r=64 {forms['hrotate_r64']['achieved']:.0f} GB/s")
+    if args.batched_only:
+        return res
     # seeded keys (rows a_j regenerated on chip, half the key bytes)
     b_rows = [k[:, 1].contiguous() for k in dkeys[:32]]
     res["rotate_seeded_ks_per_s"] = rate(
@@ -490,6 +493,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--serving-only", action="store_true",
                     help="run only the serving figures (with the --serving-* sizes) and print them")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="run only the hoisted and batched Rotate figures (for profiling) and print them")
     ap.add_argument("--w32-only", action="store_true",
                     help="time only the 32-bit-word Rotate (for profiling) and print its figures")
     ap.add_argument("--default-plans", action="store_true",
@@ -544,6 +549,10 @@ def main():
     log(f"[bench] pool resident: {pool_bytes / 2**30:.2f} GiB")
     gal = hks.hks_galois_for_rotation(1, LOG_N)
     stream = torch.cuda.current_stream()
+    if args.batched_only:
+        main_plan.close()
+        print(json.dumps(extras(args, ctx, hks, synth, cts, ksks, outs, gal, key_mods, n, None, stream)), flush=True)
+        return
 
     def step(i):
         j = i % args.pool
