@@ -428,10 +428,13 @@ def serving_extra(args, hks, synth):
     """Continuous batching vs one request at a time for Poisson arrivals of
     Rotate / Mult+relin requests from per-client keys at N in {2^15, 2^16},
     level uniform in [3, 35], L_max = 35, K = 12, dnum = 3, keys resident up
-    to a budget (LRU, re-upload from pinned host memory)."""
+    to a budget (LRU, re-upload from pinned host memory).  With
+    --serving-seeded-keys the keys are seeded (Sec. 5.3): only their rows
+    b_j are stored, uploaded and read, the rows a_j regenerated on chip."""
     import torch
     from paper_2112_06396_amd import serving
     n_clients, budget_gib, n_req = args.serving_clients, args.serving_budget_gib, args.serving_requests
+    seeds = {} if args.serving_seeded_keys else None
     params = {}
     for ln in (15, 16):
         pq = hks.hks_gen_primes(50, ln + 1, 47)
@@ -441,7 +444,10 @@ def serving_extra(args, hks, synth):
         ln = 15 if c % 2 == 0 else 16
         q, p, _ = params[ln]
         for j, kind in enumerate(("rot", "rlk")):
-            d = synth.device_residues(q + p, (3, 2), 1 << ln, 30000 + 2 * c + j)
+            lead = (3,) if seeds is not None else (3, 2)
+            d = synth.device_residues(q + p, lead, 1 << ln, 30000 + 2 * c + j)
+            if seeds is not None:
+                seeds[(c, kind, ln)] = 0x5EED0000 + 2 * c + j
             h = torch.empty(d.shape, dtype=torch.int64, pin_memory=True).view(torch.uint64)
             h.copy_(d)
             host_keys[(c, kind, ln)] = h
@@ -452,13 +458,15 @@ def serving_extra(args, hks, synth):
     key_bytes = sum(t.numel() * 8 for t in host_keys.values())
     ks = serving.KeyStore(host_keys, budget=budget_gib << 30)
     ex = serving.HksExecutor(params, lanes=args.serving_lanes, max_batch=args.batch, slots_per_n=64, keystore=ks,
-                             inputs=inputs)
+                             inputs=inputs, seeds=seeds)
     eng = serving.Engine(ex, lanes=args.serving_lanes, max_batch=args.batch)
-    log(f"[bench] serving: {n_clients} clients, {key_bytes / 2**30:.1f} GiB of keys, budget {budget_gib} GiB")
+    log(f"[bench] serving: {n_clients} clients, {key_bytes / 2**30:.1f} GiB of {'seeded ' if seeds else ''}keys, "
+        f"budget {budget_gib} GiB")
     # capacity of the plain loop: everything arrives at once, one request at a time
     sat = serving.poisson_requests(min(n_req, 2000), rate=1e9, n_clients=n_clients, seed=1)
     cap = eng.run(sat, one_at_a_time=True)["throughput_per_s"]
-    out = {"clients": n_clients, "key_gib": round(key_bytes / 2**30, 1), "key_budget_gib": budget_gib,
+    out = {"clients": n_clients, "key_format": "seeded (rows b_j)" if seeds else "full",
+           "key_gib": round(key_bytes / 2**30, 1), "key_budget_gib": budget_gib,
            "requests_per_run": n_req, "plain_capacity_per_s": cap, "runs": []}
     for f in (0.5, 0.8, 1.0, 1.2):
         row = {"load": f}
@@ -488,6 +496,8 @@ def main():
     ap.add_argument("--serving-budget-gib", type=int, default=8)
     ap.add_argument("--serving-requests", type=int, default=4000)
     ap.add_argument("--serving-lanes", type=int, default=2)
+    ap.add_argument("--serving-seeded-keys", action="store_true",
+                    help="serve with seeded keys (only the rows b_j stored and uploaded)")
     ap.add_argument("--cpu-sample", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")

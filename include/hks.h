@@ -217,6 +217,14 @@ int hks_batch_rotate_seeded(hks_ctx *ctx, uint32_t n_ct, const uint64_t *const *
                             const uint32_t *galois, const uint64_t *seeds, const uint64_t *const *ksk_b,
                             uint64_t *const *ct_out, void *stream);
 
+/* hks_batch_mult_relin with seeded relinearization keys: seeds and rlk_b are
+ * HOST arrays of n entries, rlk_b[i] the rows b_j [dnum][L+K][N] of seeded
+ * key seeds[i] (device).  Same bits as hks_batch_mult_relin with the full
+ * keys (hks_expand_key_a(seeds[i]), rlk_b[i]). */
+int hks_batch_mult_relin_seeded(hks_ctx *ctx, uint32_t n, const uint64_t *const *ct1, const uint64_t *const *ct2,
+                                uint32_t level, const uint64_t *seeds, const uint64_t *const *rlk_b, int rescale,
+                                uint64_t *const *ct_out, void *stream);
+
 /* Rescale = ModDown_{B,1} (Sec. 2.4, rounding to nearest): divide by
  * q_{level-1}.  ct [2][level][N] -> ct_out [2][level-1][N], level >= 2. */
 int hks_rescale(hks_ctx *ctx, const uint64_t *ct, uint32_t level, uint64_t *ct_out, void *stream);

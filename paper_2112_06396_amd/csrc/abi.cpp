@@ -789,8 +789,10 @@ int hks_ptmult(hks_ctx *h, const uint64_t *ct, const uint64_t *pt, uint32_t leve
 // Mult (Algorithm 2) of n pairs at one level in steps of batch_cap: per pair
 // the tensor product into its workspace slot, then one batched key-switch of
 // the a1 a2 terms with the (b3, c3) additions, then Rescale per pair.
+// (seeds non-null: rlk[i] holds only the rows b_j of seeded key seeds[i])
 int do_mult_relin(Ctx &c, uint32_t n, const uint64_t *const *ct1, const uint64_t *const *ct2, uint32_t level,
-                  const uint64_t *const *rlk, int rescale, uint64_t *const *out, hipStream_t s) {
+                  const uint64_t *const *rlk, int rescale, uint64_t *const *out, hipStream_t s,
+                  const uint64_t *seeds = nullptr) {
     const size_t pl = (size_t)level * c.n;
     const uint32_t step = std::min<uint32_t>(c.batch_cap, MAXCT);
     for (uint32_t i0 = 0; i0 < n; i0 += step) {
@@ -800,6 +802,10 @@ int do_mult_relin(Ctx &c, uint32_t n, const uint64_t *const *ct1, const uint64_t
             uint64_t *t = c.ws_t + b * c.st_t();
             HKS_TRY(launch_tensor(c, ct1[i0 + b], ct2[i0 + b], t, level, s));
             jobs[b] = KsJob{t, 1, rlk[i0 + b], rescale ? c.ws_rot + b * c.st_rot() : out[i0 + b], t + pl, t + 2 * pl};
+            if (seeds) {
+                jobs[b].seed = seeds[i0 + b];
+                jobs[b].seeded = true;
+            }
         }
         int rc = do_keyswitch_step(c, jobs, nb, level, s);
         if (rc) return rc;
@@ -879,6 +885,34 @@ int hks_batch_mult_relin(hks_ctx *h, uint32_t n, const uint64_t *const *ct1, con
         if (rc) return rc;
     }
     return do_mult_relin(h->c, n, ct1, ct2, level, rlk, rescale, ct_out, (hipStream_t)stream);
+    GUARD_END
+}
+
+int hks_batch_mult_relin_seeded(hks_ctx *h, uint32_t n, const uint64_t *const *ct1, const uint64_t *const *ct2,
+                                uint32_t level, const uint64_t *seeds, const uint64_t *const *rlk_b, int rescale,
+                                uint64_t *const *ct_out, void *stream) {
+    GUARD_BEGIN
+    if (!h || !ct1 || !ct2 || !seeds || !rlk_b || !ct_out || n == 0 || level < 1 || level > h->c.L ||
+        (rescale && level < 2))
+        return HKS_EINVAL;
+    for (uint32_t i = 0; i < n; ++i) {
+        if (!ct1[i] || !ct2[i] || !rlk_b[i] || !ct_out[i] || !aligned(ct1[i]) || !aligned(ct2[i]) ||
+            !aligned(rlk_b[i]) || !aligned(ct_out[i]))
+            return HKS_EINVAL;
+        for (uint32_t j = 0; j < n; ++j)
+            if (ct_out[i] == ct1[j] || ct_out[i] == ct2[j] || (j != i && ct_out[i] == ct_out[j])) return HKS_EINVAL;
+    }
+    if (h->c.check) {
+        std::vector<Chk> v;
+        for (uint32_t i = 0; i < n; ++i) {
+            v.push_back(ct_chk(ct1[i], 2, level));
+            v.push_back(ct_chk(ct2[i], 2, level));
+            v.push_back(keyb_chk(h->c, rlk_b[i]));
+        }
+        const int rc = check_inputs(h->c, (hipStream_t)stream, v);
+        if (rc) return rc;
+    }
+    return do_mult_relin(h->c, n, ct1, ct2, level, rlk_b, rescale, ct_out, (hipStream_t)stream, seeds);
     GUARD_END
 }
 

@@ -45,7 +45,8 @@ EXPORTS = (
     "hks_modup", "hks_ksk_inner", "hks_moddown", "hks_keyswitch", "hks_rotate", "hks_hrotate",
     "hks_batch_rotate", "hks_rescale", "hks_ptmult", "hks_mult_relin", "hks_batch_mult_relin", "hks_new_mult",
     "hks_encode", "hks_add",
-    "hks_expand_key_a", "hks_rotate_seeded", "hks_batch_rotate_seeded", "hks_ptmatvec", "hks_set_check",
+    "hks_expand_key_a", "hks_rotate_seeded", "hks_batch_rotate_seeded", "hks_batch_mult_relin_seeded",
+    "hks_ptmatvec", "hks_set_check",
     "hks_get_plan", "hks_set_plan",
     "hks_graph_begin", "hks_graph_end", "hks_graph_launch", "hks_graph_destroy", "hks_prof_enable",
     "hks_prof_read",
@@ -162,6 +163,8 @@ def lib():
             "hks_rotate_seeded": (_i32, [_vp, _vp, _u32, _u32, ctypes.c_uint64, _vp, _vp, _vp]),
             "hks_batch_rotate_seeded": (_i32, [_vp, _u32, ctypes.POINTER(_vp), _u32, ctypes.POINTER(_u32), u64p,
                                                ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp]),
+            "hks_batch_mult_relin_seeded": (_i32, [_vp, _u32, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _u32, u64p,
+                                                   ctypes.POINTER(_vp), _i32, ctypes.POINTER(_vp), _vp]),
             "hks_set_check": (_i32, [_vp, _i32]),
             "hks_get_plan": (_i32, [_vp, ctypes.POINTER(_Plan)]),
             "hks_set_plan": (_i32, [_vp, ctypes.POINTER(_Plan)]),
@@ -406,6 +409,19 @@ def hks_batch_rotate_seeded(ctx, cts, level: int, galois, seeds, ksk_bs, outs, s
     oa = (_vp * n)(*[_ptr(o) for o in outs])
     _check("hks_batch_rotate_seeded", lib().hks_batch_rotate_seeded(ctx.handle, n, ca, level, ga, sa, ka, oa,
                                                                     _stream(stream)))
+
+
+def hks_batch_mult_relin_seeded(ctx, ct1s, ct2s, level: int, seeds, rlk_bs, rescale: bool, outs, stream=None):
+    n = len(ct1s)
+    if len(ct2s) != n or len(seeds) != n or len(rlk_bs) != n or len(outs) != n:
+        raise ValueError("ct1s, ct2s, seeds, rlk_bs and outs must have the same length")
+    a1 = (_vp * n)(*[_ptr(c) for c in ct1s])
+    a2 = (_vp * n)(*[_ptr(c) for c in ct2s])
+    sa = (ctypes.c_uint64 * n)(*[int(x) for x in seeds])
+    ka = (_vp * n)(*[_ptr(k) for k in rlk_bs])
+    oa = (_vp * n)(*[_ptr(o) for o in outs])
+    _check("hks_batch_mult_relin_seeded", lib().hks_batch_mult_relin_seeded(ctx.handle, n, a1, a2, level, sa, ka,
+                                                                            1 if rescale else 0, oa, _stream(stream)))
 
 
 def hks_new_mult(ctx, ct1, ct2, level: int, rlk, ct_out, stream=None):

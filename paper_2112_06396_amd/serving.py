@@ -7,10 +7,11 @@ clients each holding its own rotation and relinearization keys.  The loop
     device memory of ciphertexts is a fixed pool of slots);
   - keeps per-client keys resident in HBM up to a byte budget, evicting the
     least recently used key that no in-flight step reads, and uploading
-    misses from pinned host copies on the step's stream;
+    misses from pinned host copies on the step's stream (full keys, or
+    seeded keys whose rows b_j alone are stored and moved);
   - forms a step from the queue: the oldest request's (N, level, op) group,
     up to max_batch requests of it in arrival order, issued as one batched
-    call (hks_batch_rotate / hks_batch_mult_relin);
+    call (hks_batch_rotate / hks_batch_mult_relin, or their seeded forms);
   - keeps up to `lanes` steps in flight, each lane with its own stream and
     contexts (workspaces), so steps of different groups overlap on the GPU;
   - records arrival, start and completion times; completion is when the
@@ -154,7 +155,10 @@ class HksExecutor:
     output slots [2][L][N] and of input ciphertexts per level; keys through
     a KeyStore."""
 
-    def __init__(self, params: dict, lanes: int, max_batch: int, slots_per_n: int, keystore, inputs):
+    def __init__(self, params: dict, lanes: int, max_batch: int, slots_per_n: int, keystore, inputs, seeds=None):
+        """seeds: key id -> seed when the key store holds seeded keys (only
+        their rows b_j; the rows a_j are regenerated in the key-switch kernel,
+        Sec. 5.3), else None (full keys)."""
         import torch
         from . import hks
         self.hks, self.torch = hks, torch
@@ -165,6 +169,7 @@ class HksExecutor:
         self.L = {n: len(q) for n, (q, p, d) in params.items()}
         self.out = {n: [hks.empty((2 * self.L[n] << n,)) for _ in range(slots_per_n)] for n in params}
         self.keys = keystore
+        self.seeds = seeds
         self.inputs = inputs      # (log_n, level) -> list of device ciphertexts [2][level][N]
 
     def slots(self, log_n):
@@ -187,18 +192,25 @@ class HksExecutor:
         r0 = batch[0]
         ctx = self.ctx[lane][r0.log_n]
         kind = "rot" if r0.op == "rotate" else "rlk"
-        keys = [self.keys.acquire((r.client, kind, r.log_n), s) for r in batch]
+        kids = [(r.client, kind, r.log_n) for r in batch]
+        keys = [self.keys.acquire(k, s) for k in kids]
         with torch.cuda.stream(s):
             outs = [self.out_view(r) for r in batch]
+            a, b = [self.in_ct(r) for r in batch], [self.in_ct(r, 1) for r in batch]
             if r0.op == "rotate":
                 gals = [hks.hks_galois_for_rotation(r.k, r.log_n) for r in batch]
-                hks.hks_batch_rotate(ctx, [self.in_ct(r) for r in batch], r0.level, gals, keys, outs, s)
+                if self.seeds is None:
+                    hks.hks_batch_rotate(ctx, a, r0.level, gals, keys, outs, s)
+                else:
+                    hks.hks_batch_rotate_seeded(ctx, a, r0.level, gals, [self.seeds[k] for k in kids], keys, outs, s)
+            elif self.seeds is None:
+                hks.hks_batch_mult_relin(ctx, a, b, r0.level, keys, True, outs, s)
             else:
-                hks.hks_batch_mult_relin(ctx, [self.in_ct(r) for r in batch], [self.in_ct(r, 1) for r in batch],
-                                         r0.level, keys, True, outs, s)
+                hks.hks_batch_mult_relin_seeded(ctx, a, b, r0.level, [self.seeds[k] for k in kids], keys, True,
+                                                outs, s)
             ev = torch.cuda.Event()
             ev.record(s)
-        self.keys.hold([(r.client, kind, r.log_n) for r in batch], ev)
+        self.keys.hold(kids, ev)
         return ev
 
     def done(self, ev):

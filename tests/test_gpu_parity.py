@@ -545,24 +545,33 @@ def test_full_trace_graph_equals_eager():
 # ------------------------------------------------------------------ serving loop
 
 
-def test_serving_results_same_alone_and_in_the_mix():
+@pytest.mark.parametrize("seeded", [False, True])
+def test_serving_results_same_alone_and_in_the_mix(seeded):
     """Requests of two ring degrees and mixed levels and ops, served with
     continuous batching on two lanes under a key budget that forces
     evictions, give exactly the bits of the same requests served one at a
-    time; a sample of them also equals the oracle (Algorithms 2 and 3)."""
+    time; a sample of them also equals the oracle (Algorithms 2 and 3).
+    With seeded keys the store holds and uploads only the rows b_j."""
     import copy
     from paper_2112_06396_amd import serving
     hks = H()
     prs = {12: O.make_params(12, 8, 3, 3), 13: O.make_params(13, 8, 3, 3)}
     n_clients = 6
     reqs = serving.poisson_requests(48, rate=2e5, n_clients=n_clients, log_ns=(12, 13), levels=(3, 8), seed=5)
-    host_np, host_keys = {}, {}
+    host_np, host_keys, seeds = {}, {}, ({} if seeded else None)
     for c in range(n_clients):
         ln = 12 if c % 2 == 0 else 13
         for j, kind in enumerate(("rot", "rlk")):
             k = _rand_ksk(prs[ln], 400 + 2 * c + j)
+            if seeded:
+                sd = 0x5E000 + 2 * c + j
+                seeds[(c, kind, ln)] = sd
+                k = np.stack([O.expand_key_a(prs[ln], sd), k[:, 1]], axis=1)
+                store = np.ascontiguousarray(k[:, 1])
+            else:
+                store = k
             host_np[(c, kind, ln)] = k
-            host_keys[(c, kind, ln)] = torch.from_numpy(k.view(np.int64)).view(torch.uint64).pin_memory()
+            host_keys[(c, kind, ln)] = torch.from_numpy(store.view(np.int64)).view(torch.uint64).pin_memory()
     inputs_np, inputs = {}, {}
     for ln, pr in prs.items():
         for level in range(3, 9):
@@ -571,7 +580,8 @@ def test_serving_results_same_alone_and_in_the_mix():
             inputs[(ln, level)] = [dev(c) for c in cts]
     params = {ln: (pr.q, pr.p, 3) for ln, pr in prs.items()}
     ks = serving.KeyStore(host_keys, budget=9 * max(t.numel() for t in host_keys.values()) * 8)
-    ex = serving.HksExecutor(params, lanes=2, max_batch=4, slots_per_n=len(reqs), keystore=ks, inputs=inputs)
+    ex = serving.HksExecutor(params, lanes=2, max_batch=4, slots_per_n=len(reqs), keystore=ks, inputs=inputs,
+                             seeds=seeds)
     try:
         eng = serving.Engine(ex, lanes=2, max_batch=4)
         alone_reqs = copy.deepcopy(reqs)
@@ -595,6 +605,26 @@ def test_serving_results_same_alone_and_in_the_mix():
             assert np.array_equal(mix[r.rid], ref), r
     finally:
         ex.close()
+
+
+@pytest.mark.parametrize("name,max_batch,n", [("cfg1", 4, 6), ("n13", 3, 4)])
+def test_batch_mult_relin_seeded_equals_oracle(name, max_batch, n):
+    """Mult + relinearization + Rescale with seeded keys (rows b_j only)
+    equals the oracle's with the full keys (expanded rows a_j, rows b_j), in
+    batched steps of max_batch."""
+    pr, ctx = _get(name, max_batch)
+    hks = H()
+    level = pr.L
+    seeds = [0x7E00 + i for i in range(n)]
+    b_rows = [_rand_ksk(pr, 730 + i)[:, 1].copy() for i in range(n)]
+    c1 = [_rand_ct(pr, level, 740 + i) for i in range(n)]
+    c2 = [_rand_ct(pr, level, 750 + i) for i in range(n)]
+    outs = [hks.empty((2, level - 1, pr.n)) for _ in range(n)]
+    hks.hks_batch_mult_relin_seeded(ctx, [dev(c) for c in c1], [dev(c) for c in c2], level, seeds,
+                                    [dev(b) for b in b_rows], True, outs)
+    for i in range(n):
+        full = np.stack([O.expand_key_a(pr, seeds[i]), b_rows[i]], axis=1)
+        assert np.array_equal(host(outs[i]), O.mult_relin(pr, c1[i], c2[i], level, full, True)), i
 
 
 @pytest.mark.parametrize("name,max_batch,n", [("cfg1", 4, 6), ("n13", 3, 4)])
