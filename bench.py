@@ -428,13 +428,13 @@ def serving_extra(args, hks, synth):
     """Continuous batching vs one request at a time for Poisson arrivals of
     Rotate / Mult+relin requests from per-client keys at N in {2^15, 2^16},
     level uniform in [3, 35], L_max = 35, K = 12, dnum = 3, keys resident up
-    to a budget (LRU, re-upload from pinned host memory).  With
-    --serving-seeded-keys the keys are seeded (Sec. 5.3): only their rows
-    b_j are stored, uploaded and read, the rows a_j regenerated on chip."""
+    to a budget (LRU, re-upload from pinned host memory).  The keys are
+    seeded (Sec. 5.3): only their rows b_j are stored, uploaded and read, the
+    rows a_j regenerated on chip (--serving-full-keys: full keys)."""
     import torch
     from paper_2112_06396_amd import serving
     n_clients, budget_gib, n_req = args.serving_clients, args.serving_budget_gib, args.serving_requests
-    seeds = {} if args.serving_seeded_keys else None
+    seeds = None if args.serving_full_keys else {}
     params = {}
     for ln in (15, 16):
         pq = hks.hks_gen_primes(50, ln + 1, 47)
@@ -492,12 +492,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--pool", type=int, default=8)
     ap.add_argument("--batch", type=int, default=16, help="ciphertexts per batched launch step (extras)")
-    ap.add_argument("--serving-clients", type=int, default=64)
-    ap.add_argument("--serving-budget-gib", type=int, default=8)
+    ap.add_argument("--serving-clients", type=int, default=256)
+    ap.add_argument("--serving-budget-gib", type=int, default=16)
     ap.add_argument("--serving-requests", type=int, default=4000)
     ap.add_argument("--serving-lanes", type=int, default=2)
-    ap.add_argument("--serving-seeded-keys", action="store_true",
-                    help="serve with seeded keys (only the rows b_j stored and uploaded)")
+    ap.add_argument("--serving-full-keys", action="store_true",
+                    help="serve with full keys instead of seeded ones (rows a_j and b_j stored and uploaded; "
+                         "256 clients then need 53 GiB of pinned host memory)")
     ap.add_argument("--cpu-sample", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
