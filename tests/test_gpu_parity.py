@@ -781,6 +781,13 @@ def test_canonical_checks_reject_out_of_range_inputs():
         with pytest.raises(hks.HksError) as e:
             hks.hks_ntt(ctx, dev(x), 0, 2)
         assert e.value.status == hks.HKS_ERANGE
+        # a seeded relinearization key's rows b_j, one word above its modulus
+        brow = ksk[:, 1].copy()
+        brow[0, pr.L, 9] = pr.p[0]
+        mo = hks.empty((2, level - 1, pr.n))
+        with pytest.raises(hks.HksError) as e:
+            hks.hks_batch_mult_relin_seeded(ctx, [dev(ct)], [dev(ct)], level, [7], [dev(brow)], True, [mo])
+        assert e.value.status == hks.HKS_ERANGE
     finally:
         hks.hks_set_check(ctx, False)
     hks.hks_rotate(ctx, dev(bad), level, g, dev(ksk), out)  # unchecked: runs
