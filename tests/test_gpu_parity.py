@@ -5,7 +5,8 @@ modular arithmetic; both sides reduce to canonical [0, q)).  Inputs are
 seeded synthetic residues from paper_2112_06396_amd.synth; valid keys and
 ciphertexts (for the decryption checks) come from the oracle's test-side
 key generation.  Shapes cover several NTT tiles and splits (log N = 10..16,
-odd sub-transform sizes), short last digits, level 1, and the full
+odd sub-transform sizes), short last digits, level 1, more special primes
+than a digit has limbs (K = 4 > alpha = 3 at N = 2^14), and the full
 N = 2^16, L = 24, K = 8, dnum = 3 key-switch and L = 35, K = 12.
 """
 import numpy as np
@@ -23,6 +24,7 @@ CFGS = {
     "n11": (11, 5, 3, 2),
     "cfg1": (12, 4, 2, 2),
     "n13": (13, 7, 3, 3),
+    "n14": (14, 9, 4, 3),
     "n15": (15, 6, 2, 3),
     "cfg2": (16, 24, 8, 3),
 }
@@ -152,7 +154,7 @@ def test_moddown(name):
 
 # ------------------------------------------------------------------ composite calls
 
-@pytest.mark.parametrize("name", ["n10", "n11", "cfg1", "n13", "n15", "cfg2"])
+@pytest.mark.parametrize("name", ["n10", "n11", "cfg1", "n13", "n14", "n15", "cfg2"])
 def test_keyswitch(name):
     pr, ctx = _get(name)
     hks = H()
@@ -165,7 +167,7 @@ def test_keyswitch(name):
         assert np.array_equal(host(uv), O.keyswitch(pr, d, level, ksk)), level
 
 
-@pytest.mark.parametrize("name", ["n10", "n11", "cfg1", "n13", "n15", "cfg2"])
+@pytest.mark.parametrize("name", ["n10", "n11", "cfg1", "n13", "n14", "n15", "cfg2"])
 def test_rotate(name):
     pr, ctx = _get(name)
     hks = H()
