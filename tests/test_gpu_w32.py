@@ -1,7 +1,8 @@
 """Parity of the 32-bit-word key-switch (include/hks32.h) with the oracle
-run on the same 30-bit primes: NTT / iNTT, Rotate and HRotate, bit for bit, at small
-sizes (several tiles, short last digit, level 1) and at N = 2^16 with the
-log2(QP) of the 50-bit benchmark (L = 40, K = 14, dnum = 3)."""
+run on the same 30-bit primes: NTT / iNTT, Rotate and HRotate, bit for
+bit, at small sizes (several tiles, short last digit, level 1, K above
+alpha) and at N = 2^16 with the log2(QP) of the 50-bit benchmark (L = 40,
+K = 14, dnum = 3)."""
 import numpy as np
 import pytest
 import torch
@@ -16,6 +17,7 @@ CFGS = {
     "n10": (10, 8, 3, 3),
     "n11": (11, 5, 2, 3),
     "n13": (13, 10, 4, 3),
+    "n15": (15, 9, 4, 3),   # K = 4 special primes above alpha = 3
     "full": (16, 40, 14, 3),
 }
 _CTX = {}
