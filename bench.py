@@ -646,6 +646,11 @@ def main():
     whole = {"modmul_per_step": step_mm, "Tmodmul_per_s": step_mm / (ms_per_step / 1e3) / 1e12,
              "alu_frac": step_mm / (ms_per_step / 1e3) / MODMUL_PEAK,
              "hbm_frac": comp_bytes / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS}
+    # the measured modular-product rate of the chip (lazy Shoup chains at full
+    # occupancy) as the second ALU reference
+    mm_rate = hks.hks_modmul_rate(ctx, 1024, stream)
+    whole["measured_Tmodmul_peak"] = mm_rate / 1e12
+    whole["alu_frac_of_measured"] = step_mm / (ms_per_step / 1e3) / mm_rate
     # a plain device copy of 1 GiB as the measured bandwidth reference
     src_ = torch.empty(1 << 27, dtype=torch.int64, device="cuda")
     dst_ = torch.empty_like(src_)

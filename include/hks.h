@@ -372,6 +372,15 @@ void hks_graph_destroy(hks_graph *graph);
 int hks_prof_enable(hks_ctx *ctx, uint32_t mask);
 int hks_prof_read(hks_ctx *ctx, int kernel_class, double *ms, uint64_t *launches);
 
+/* Measurement aid: the device's rate of modular products, as *per_s
+ * products per second.  One kernel at full occupancy runs 8 independent
+ * chains of the lazy Shoup product (x w mod q in [0, 2q) with a precomputed
+ * quotient: the NTT butterfly's multiply, Sec. 2.2) for `iters` rounds per
+ * thread, timed with HIP events on `stream`; the call waits for it.  It
+ * writes one word per thread into the context's workspace, so it must not
+ * overlap other calls on the context. */
+int hks_modmul_rate(hks_ctx *ctx, uint32_t iters, void *stream, double *per_s);
+
 #ifdef __cplusplus
 }
 #endif

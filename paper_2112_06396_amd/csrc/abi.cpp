@@ -1007,6 +1007,31 @@ int hks_prof_enable(hks_ctx *h, uint32_t mask) {
     GUARD_END
 }
 
+int hks_modmul_rate(hks_ctx *h, uint32_t iters, void *stream, double *per_s) {
+    GUARD_BEGIN
+    if (!h || !per_s || iters == 0) return HKS_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return HKS_EHIP;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return HKS_EHIP;
+    }
+    uint64_t products = 0;
+    float ms = 0.f;
+    hipError_t e = hipEventRecord(e0, s);
+    if (e == hipSuccess) e = launch_modmul_rate(h->c, iters, s, &products);
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return HKS_EHIP;
+    *per_s = ms > 0.f ? (double)products / (ms * 1e-3) : 0.0;
+    return HKS_OK;
+    GUARD_END
+}
+
 int hks_prof_read(hks_ctx *h, int kernel_class, double *ms, uint64_t *launches) {
     GUARD_BEGIN
     if (!h || !ms || !launches || kernel_class < 0 || kernel_class >= HKS_K_COUNT) return HKS_EINVAL;

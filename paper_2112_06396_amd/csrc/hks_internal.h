@@ -244,6 +244,8 @@ hipError_t launch_ksk_matvec(const Ctx &c, const uint64_t *ext, uint32_t level, 
 hipError_t launch_check(const Ctx &c, const uint64_t *p, uint32_t reps, uint32_t limbs, uint32_t first_mod,
                         uint32_t *flag, hipStream_t s);
 hipError_t launch_clear_flag(uint32_t *flag, hipStream_t s);
+// Independent lazy Shoup products into the workspace; *products = their count.
+hipError_t launch_modmul_rate(const Ctx &c, uint32_t iters, hipStream_t s, uint64_t *products);
 // The rows a_j of the seeded key `seed`: a [dnum][L+K][N].
 hipError_t launch_expand_key_a(const Ctx &c, uint64_t seed, uint64_t *a, hipStream_t s);
 // Eval-domain automorph (gather) of limbs; or coefficient-domain map with negation.

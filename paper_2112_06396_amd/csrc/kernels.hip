@@ -570,6 +570,42 @@ __global__ void __launch_bounds__(256) copy_kernel(const uint64_t *in, uint64_t 
     for (; i < words; i += stride) out[i] = in[i];
 }
 
+// Modular-multiply throughput (hks_modmul_rate): each thread runs MR_CHAINS
+// independent chains of the lazy Shoup product x <- x w mod q (values below
+// 2q, the NTT butterfly's multiply) for `iters` rounds and writes one word,
+// so that no product is dead code.
+constexpr int MR_CHAINS = 8;
+
+__global__ void __launch_bounds__(256) modmul_rate_kernel(uint64_t *out, uint64_t q, uint64_t nq, uint64_t w,
+                                                          uint64_t wp, uint32_t iters) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    uint64_t x[MR_CHAINS];
+#pragma unroll
+    for (int c = 0; c < MR_CHAINS; ++c) x[c] = (t * 2654435761u + 7919u * c) % q;
+    for (uint32_t i = 0; i < iters; ++i) {
+#pragma unroll
+        for (int c = 0; c < MR_CHAINS; ++c) x[c] = mul_shoup_lazy_nq(x[c], w, wp, nq);
+    }
+    uint64_t acc = 0;
+#pragma unroll
+    for (int c = 0; c < MR_CHAINS; ++c) acc += x[c];
+    out[t] = acc;
+}
+
+hipError_t launch_modmul_rate(const Ctx &c, uint32_t iters, hipStream_t s, uint64_t *products) {
+    // 32 blocks of 256 threads per CU of the 256, fewer if the workspace
+    // (one word per thread) is smaller
+    uint32_t blocks = 256 * 32;
+    const size_t words = c.ws_bytes / sizeof(uint64_t);
+    if ((size_t)blocks * 256 > words) blocks = (uint32_t)(words / 256);
+    if (blocks == 0) return hipErrorInvalidValue;
+    const uint64_t q = c.mods[0];
+    const uint64_t w = q - 12345, wp = (uint64_t)(((unsigned __int128)w << 64) / q);
+    hipLaunchKernelGGL(modmul_rate_kernel, dim3(blocks), dim3(256), 0, s, c.ws, q, 0 - q, w, wp, iters);
+    *products = (uint64_t)blocks * 256 * MR_CHAINS * iters;
+    return hipGetLastError();
+}
+
 hipError_t launch_copy(const uint64_t *in, uint64_t *out, size_t words, hipStream_t s) {
     if (!words) return hipSuccess;
     size_t blocks = (words + 255) / 256;

@@ -49,7 +49,7 @@ EXPORTS = (
     "hks_ptmatvec", "hks_set_check",
     "hks_get_plan", "hks_set_plan",
     "hks_graph_begin", "hks_graph_end", "hks_graph_launch", "hks_graph_destroy", "hks_prof_enable",
-    "hks_prof_read",
+    "hks_prof_read", "hks_modmul_rate",
 )
 
 # every symbol declared in include/hks32.h (the 32-bit-word key-switch)
@@ -181,6 +181,7 @@ def lib():
                                      ctypes.POINTER(_vp), _vp]),
             "hks_prof_enable": (_i32, [_vp, _u32]),
             "hks_prof_read": (_i32, [_vp, _i32, ctypes.POINTER(ctypes.c_double), u64p]),
+            "hks_modmul_rate": (_i32, [_vp, _u32, _vp, ctypes.POINTER(ctypes.c_double)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -519,6 +520,13 @@ def hks_prof_read(ctx, kernel_class: int):
     n = ctypes.c_uint64()
     _check("hks_prof_read", lib().hks_prof_read(ctx.handle, int(kernel_class), ctypes.byref(ms), ctypes.byref(n)))
     return float(ms.value), int(n.value)
+
+
+def hks_modmul_rate(ctx, iters: int = 1024, stream=None) -> float:
+    """Measured lazy Shoup products per second (uses the context's workspace)."""
+    r = ctypes.c_double()
+    _check("hks_modmul_rate", lib().hks_modmul_rate(ctx.handle, int(iters), _stream(stream), ctypes.byref(r)))
+    return float(r.value)
 
 
 # ---------------------------------------------------------------- tensor helpers

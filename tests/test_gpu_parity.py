@@ -796,6 +796,18 @@ def test_canonical_checks_reject_out_of_range_inputs():
     torch.cuda.synchronize()
 
 
+def test_modmul_rate_is_measured():
+    """The measurement aid returns a plausible products-per-second figure
+    (between 0.1 and 20 T/s on one device) and rejects zero rounds."""
+    pr, ctx = _get("cfg1")
+    hks = H()
+    r = hks.hks_modmul_rate(ctx, 64)
+    assert 1e11 < r < 2e13, r
+    with pytest.raises(hks.HksError) as e:
+        hks.hks_modmul_rate(ctx, 0)
+    assert e.value.status == hks.HKS_EINVAL
+
+
 def test_c_abi_graph_replays_equal_eager():
     """hks_graph_begin/end/launch: a Rotate and a hoisted rotation recorded
     on a stream and replayed three times, with eager calls and buffer
