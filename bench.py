@@ -499,7 +499,7 @@ def main():
     ap.add_argument("--serving-full-keys", action="store_true",
                     help="serve with full keys instead of seeded ones (rows a_j and b_j stored and uploaded; "
                          "256 clients then need 53 GiB of pinned host memory)")
-    ap.add_argument("--cpu-sample", type=int, default=4)
+    ap.add_argument("--cpu-sample", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--serving-only", action="store_true",
