@@ -15,7 +15,6 @@ stderr.
 """
 import argparse
 import contextlib
-import hashlib
 import json
 import os
 import re
@@ -24,6 +23,8 @@ import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+
+from paper_2112_06396_amd import build  # noqa: E402  (source hash of the kernel files; no GPU use)
 
 METRIC = "key-switch ops/s @N=2^16,L=24 (batched vs plain); achieved HBM GB/s; p99 ms"
 LOG_N, L, K, DNUM, LEVEL = 16, 24, 8, 3, 24
@@ -102,14 +103,6 @@ def kernel_work(cls: int, n: int, level: int, k: int, alpha: int, beta: int):
     return 0, 0
 
 
-def source_hash() -> str:
-    h = hashlib.sha256()
-    # the files that define the kernels and their launch shapes (host orchestration excluded)
-    for f in ("ntt.hip", "kernels.hip", "modarith.h", "device_util.h", "hks_internal.h"):
-        h.update(open(os.path.join(ROOT, "paper_2112_06396_amd", "csrc", f), "rb").read())
-    return h.hexdigest()[:16]
-
-
 def read_traffic(kernel_name: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
     was taken on the current kernel sources (else None)."""
@@ -119,7 +112,7 @@ def read_traffic(kernel_name: str):
     txt = open(path).read()
     m = re.search(r"source_hash:\s*([0-9a-f]+)", txt)
     t = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
-    if not m or not t or m.group(1) != source_hash():
+    if not m or not t or m.group(1) != build.source_hash():
         return None
     return float(t.group(1))
 

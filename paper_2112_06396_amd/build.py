@@ -1,9 +1,10 @@
 """Build libhks.so (HIP for gfx950) in-tree with hipcc.
 
 Every HIP translation unit is compiled with packed-FP32 instructions disabled
-(the library has no floating-point arithmetic; the flag keeps the compiler
-from forming packed FP32 ops anywhere).
+(the key-switch path has no floating-point arithmetic and the encoder's is
+fp64; the flag keeps the compiler from forming packed FP32 ops anywhere).
 """
+import hashlib
 import os
 import subprocess
 import sys
@@ -12,6 +13,17 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhks.so")
 SOURCES = ["ntt.hip", "kernels.hip", "tables.cpp", "abi.cpp", "ks32.hip", "ctx32.cpp"]
+# the files that define the 64-bit kernels and their launch shapes (host
+# orchestration excluded): counter summaries are valid for one hash of them
+KERNEL_SOURCES = ["ntt.hip", "kernels.hip", "modarith.h", "device_util.h", "hks_internal.h"]
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
