@@ -269,6 +269,27 @@ def extras(args, ctx, hks, synth, cts, ksks, outs, gal, key_mods, n, plain_value
     torch.cuda.synchronize()
     res["graph_rotate_ks_per_s"] = rate(lambda i: graphs[i % args.pool].replay(), 1, max(50, args.steps))
     del graphs
+    # the small configuration (N = 2^12, L = 4, K = 2, dnum = 2): latency-bound,
+    # a pool of 64 ciphertexts rotated one at a time, eager and from a hipGraph
+    sq = hks.hks_gen_primes(50, 13, 6)
+    sctx = hks.Context(12, sq[:4], sq[4:], 2)
+    scts = [synth.device_residues(sq[:4], (2,), 1 << 12, 60000 + i) for i in range(64)]
+    skey = synth.device_residues(sq, (2, 2), 1 << 12, 60100)
+    souts = [hks.empty((2, 4, 1 << 12)) for _ in range(64)]
+    sgal = hks.hks_galois_for_rotation(1, 12)
+    us_eager = 1e6 / rate(lambda i: hks.hks_rotate(sctx, scts[i % 64], 4, sgal, skey, souts[i % 64], stream), 1, 500)
+    sg = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(sg):
+        for j in range(64):
+            hks.hks_rotate(sctx, scts[j], 4, sgal, skey, souts[j])
+    torch.cuda.synchronize()
+    us_graph = 1e6 / rate(lambda i: sg.replay(), 64, 8)
+    res["small_rotate"] = {"config": {"log_n": 12, "L": 4, "K": 2, "dnum": 2}, "launches_per_rotate": 9,
+                           "us_per_rotate_eager": us_eager, "us_per_rotate_graph": us_graph}
+    del sg, scts, souts, skey
+    torch.cuda.synchronize()
+    sctx.close()
+    log(f"[bench] N=2^12 L=4 Rotate: {us_eager:.1f} us eager, {us_graph:.1f} us from a graph of 64")
     log(f"[bench] hrotate r=64 {res['hrotate_r64_ks_per_s']:.0f} ks/s; batch 32 shared key "
         f"{res['batch32_shared_key_ks_per_s']:.0f}, distinct keys {res['batch32_distinct_keys_ks_per_s']:.0f}, "
         f"distinct seeded keys {res['batch32_seeded_keys_ks_per_s']:.0f}; seeded Rotate "
