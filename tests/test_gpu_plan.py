@@ -157,3 +157,45 @@ def test_full_size_plans_equal_default():
     finally:
         torch.cuda.synchronize()
         ctx.close()
+
+
+def test_tuner_end_to_end_small():
+    """tune.tune on a small Rotate workload: times every candidate of two
+    fields, keeps a plan whose outputs equal the start plan's, and returns a
+    cache entry that apply_cached restores."""
+    import json
+    import os
+    import tempfile
+    hks = H()
+    pr, ctx = _get("n13")
+    level = pr.L
+    ct = hks.to_device(_ct(pr, level, 990))
+    key = hks.to_device(_ksk(pr, 991))
+    out = hks.empty((2, level, pr.n))
+    gal = hks.hks_galois_for_rotation(3, pr.log_n)
+    stream = torch.cuda.current_stream()
+    start = hks.hks_get_plan(ctx)
+
+    def run(i):
+        hks.hks_rotate(ctx, ct, level, gal, key, out, stream)
+
+    cands = {"conv_group_limbs": (4, 8, 16), "e16_fwd_cols": (0, A8)}
+    best, t_best, t_start, trace = tune.coordinate_descent(tune.event_measure(ctx, run, stream, 5), start,
+                                                           candidates=cands, rounds=1)
+    assert len(trace) == 1 + sum(len([v for v in vals if v != start[f]]) for f, vals in cands.items())
+    assert t_best <= t_start
+    hks.hks_set_plan(ctx, start)
+    entry = tune.tune(ctx, run, lambda: [out], stream, 5, rounds=1)
+    assert entry["outputs_equal"] and entry["us"] <= entry["default_us"] and set(entry["plan"]) == set(start)
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "plans.json")
+        tune.save_entry("k", entry, path)
+        hks.hks_set_plan(ctx, start)
+        assert tune.apply_cached(ctx, "k", path)["plan"] == entry["plan"]
+        assert hks.hks_get_plan(ctx) == entry["plan"]
+        assert tune.apply_cached(ctx, "missing", path) is None
+        with open(path) as f:
+            json.load(f)
+    hks.hks_set_plan(ctx, start)
+    torch.cuda.synchronize()
+    assert np.array_equal(host(out), O.rotate(pr, _ct(pr, level, 990), level, gal, _ksk(pr, 991)))
