@@ -218,6 +218,18 @@ def extras(args, ctx, hks, synth, cts, ksks, outs, gal, key_mods, n, plain_value
     res["ksk_roofline_batched"] = forms
     log(f"[bench] ksk kernel HBM rate: batch 32 distinct keys "
         f"{forms['batch32_distinct_keys']['achieved']:.0f} GB/s, hrotate r=64 {forms['hrotate_r64']['achieved']:.0f} GB/s")
+    # the key-streaming step alone (KSKInnerProd, hks_ksk_inner: digits already
+    # in evaluation form, 16 keys cycled): key, digits and u, v once each
+    exts = [synth.device_residues(key_mods[:LEVEL] + key_mods[L:], (beta,), n, 8000 + i) for i in range(4)]
+    uv_d = hks.empty((2, E, n))
+    ks_rate = rate(lambda i: hks.hks_ksk_inner(ctx, exts[i % 4], LEVEL, dkeys[i % 16], uv_d, stream), 1, 64)
+    ks_bytes = (beta * 2 * E + beta * E + 2 * E) * n * 8
+    res["ksk_inner_alone"] = {"us_per_call": 1e6 / ks_rate, "bytes_per_call": ks_bytes,
+                              "achieved": ks_rate * ks_bytes / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                              "frac": ks_rate * ks_bytes / 1e9 / HBM_PEAK_GBS}
+    del exts, uv_d
+    log(f"[bench] KSKInnerProd alone: {res['ksk_inner_alone']['achieved']:.0f} GB/s "
+        f"({100 * res['ksk_inner_alone']['frac']:.0f}% of 8 TB/s)")
     if args.batched_only:
         return res
     # seeded keys (rows a_j regenerated on chip, half the key bytes)
