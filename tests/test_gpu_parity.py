@@ -174,12 +174,13 @@ def test_rotate(name):
     ksk = _rand_ksk(pr, 60)
     dk = dev(ksk)
     for level in _levels(pr):
-        for k in (1, -3):
-            g = hks.hks_galois_for_rotation(k, pr.log_n)
+        # rotations by 1 and -3 and the conjugation (galois 2N - 1)
+        for g in (hks.hks_galois_for_rotation(1, pr.log_n), hks.hks_galois_for_rotation(-3, pr.log_n),
+                  hks.hks_galois_conjugate(pr.log_n)):
             ct = _rand_ct(pr, level, 61 + level)
             out = hks.empty((2, level, pr.n))
             hks.hks_rotate(ctx, dev(ct), level, g, dk, out)
-            assert np.array_equal(host(out), O.rotate(pr, ct, level, g, ksk)), (level, k)
+            assert np.array_equal(host(out), O.rotate(pr, ct, level, g, ksk)), (level, g)
 
 
 def test_rotate_config1_valid_key_decrypts():
@@ -231,11 +232,11 @@ def test_hrotate(name):
     pr, ctx = _get(name)
     hks = H()
     level = pr.L
-    ks = (1, 2, -5)
-    gals = [hks.hks_galois_for_rotation(k, pr.log_n) for k in ks]
-    ksks = [_rand_ksk(pr, 70 + i) for i in range(len(ks))]
+    # three rotations and the conjugation
+    gals = [hks.hks_galois_for_rotation(k, pr.log_n) for k in (1, 2, -5)] + [hks.hks_galois_conjugate(pr.log_n)]
+    ksks = [_rand_ksk(pr, 70 + i) for i in range(len(gals))]
     ct = _rand_ct(pr, level, 75)
-    outs = [hks.empty((2, level, pr.n)) for _ in ks]
+    outs = [hks.empty((2, level, pr.n)) for _ in gals]
     hks.hks_hrotate(ctx, dev(ct), level, gals, [dev(k) for k in ksks], outs)
     refs = O.hrotate(pr, ct, level, gals, ksks)
     for o, r in zip(outs, refs):
