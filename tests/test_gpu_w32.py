@@ -91,11 +91,11 @@ def test_rotate_equals_oracle(name):
         levels = [pr.L, 17]
     for level in levels:
         ct = _ct(pr, level, 820 + level)
-        for k in (1, -5):
-            gal = hks.hks_galois_for_rotation(k, pr.log_n)
+        for gal in (hks.hks_galois_for_rotation(1, pr.log_n), hks.hks_galois_for_rotation(-5, pr.log_n),
+                    hks.hks_galois_conjugate(pr.log_n)):
             out = hks.empty32((2, level, pr.n))
             hks.hks32_rotate(ctx, hks.to_device32(ct), level, gal, dk, out)
-            assert np.array_equal(host(out), O.rotate(pr, ct, level, gal, ksk)), (level, k)
+            assert np.array_equal(host(out), O.rotate(pr, ct, level, gal, ksk)), (level, gal)
 
 
 @pytest.mark.parametrize("name", list(CFGS))
