@@ -148,6 +148,22 @@ class Params:
         return ctypes.byref(cp), cp
 
 
+def c_alpha(pr: Params) -> int:
+    """alpha as the C oracle computes it (limbs per digit of Decomp)."""
+    ref, keep = pr.c()
+    a = int(lib().oref_alpha(ref))
+    del keep
+    return a
+
+
+def c_beta(pr: Params, level: int) -> int:
+    """beta at `level` limbs as the C oracle computes it (digits of Decomp)."""
+    ref, keep = pr.c()
+    b = int(lib().oref_beta(ref, int(level)))
+    del keep
+    return b
+
+
 def make_params(log_n: int, L: int, K: int, dnum: int, bits: int = 50, log_step: int = 17) -> Params:
     pr = gen_primes(bits, log_step, L + K)
     return Params(log_n, L, K, dnum, pr[:L].copy(), pr[L:].copy())

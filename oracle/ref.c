@@ -251,8 +251,13 @@ static uint64_t ext_mod(const oref_params *pr, uint32_t level, uint32_t t) {
 static uint32_t key_limb(const oref_params *pr, uint32_t level, uint32_t t) {
     return t < level ? t : pr->L + (t - level);
 }
+/* The conversions keep their per-target constants in fixed arrays of
+   OREF_MAX_SRC entries: at most that many limbs per digit (alpha), and at
+   most OREF_MAX_SRC - 1 special primes (NewMult divides by K + 1 limbs). */
+#define OREF_MAX_SRC 64
 static int check(const oref_params *pr, uint32_t level) {
     if (!pr || level < 1 || level > pr->L || pr->dnum < 1 || pr->K < 1) return -1;
+    if (pr->dnum > pr->L || alpha_of(pr) > OREF_MAX_SRC || pr->K + 1 > OREF_MAX_SRC) return -1;
     return 0;
 }
 
@@ -292,7 +297,7 @@ int oref_modup(const oref_params *pr, const uint64_t *a, uint32_t level, uint64_
             if (t >= lo && t < hi) { memcpy(dst, a + (size_t)t * n, sizeof(uint64_t) * n); continue; }
             uint64_t m = ext_mod(pr, level, t);
             /* constants [Qt/q_i]_t */
-            uint64_t cst[64];
+            uint64_t cst[OREF_MAX_SRC];
             for (uint32_t i = lo; i < hi; i++) {
                 uint64_t prod = 1;
                 for (uint32_t k = lo; k < hi; k++) if (k != i) prod = mulmod(prod, pr->q[k] % m, m);
@@ -367,7 +372,7 @@ int oref_moddown(const oref_params *pr, const uint64_t *x, uint32_t level, uint6
     uint64_t *z = (uint64_t *)malloc(sizeof(uint64_t) * n);
     for (uint32_t i = 0; i < level; i++) {
         uint64_t qi = pr->q[i];
-        uint64_t cst[64];
+        uint64_t cst[OREF_MAX_SRC];
         uint64_t pmod = 1;
         for (uint32_t k = 0; k < K; k++) {
             uint64_t prod = 1;
@@ -759,7 +764,7 @@ static void moddown_s(const oref_params *pr, const uint64_t *x, uint32_t level, 
     uint64_t *z = (uint64_t *)malloc(sizeof(uint64_t) * n);
     for (uint32_t i = 0; i < lo; i++) {
         uint64_t qi = pr->q[i], smod = 1;
-        uint64_t cst[64];
+        uint64_t cst[OREF_MAX_SRC];
         for (uint32_t k = 0; k < ns; k++) {
             uint64_t prod = 1;
             for (uint32_t kk = 0; kk < ns; kk++) if (kk != k) prod = mulmod(prod, sm[kk] % qi, qi);
@@ -782,7 +787,7 @@ static void moddown_s(const oref_params *pr, const uint64_t *x, uint32_t level, 
 
 int oref_new_mult(const oref_params *pr, const uint64_t *ct1, const uint64_t *ct2, uint32_t level,
                   const uint64_t *rlk, uint64_t *out) {
-    if (check(pr, level) || level < 2 || pr->K + 1 > 64) return -1;
+    if (check(pr, level) || level < 2) return -1;
     size_t n = (size_t)1 << pr->log_n;
     size_t pl = (size_t)level * n;
     uint32_t next = level + pr->K, beta = beta_of(pr, level);

@@ -170,8 +170,20 @@ def _coef(pr, x, mods):
     return O.intt(x, pr.log_n, mods)
 
 
+def _fractional_floor(ys, mods):
+    """floor(sum_i y_i / m_i) in exact rational arithmetic"""
+    from fractions import Fraction
+    return int(sum((Fraction(int(y), int(m)) for y, m in zip(ys, mods)), Fraction(0)) // 1)
+
+
 @pytest.mark.parametrize("level", [6, 5, 3, 1])
 def test_modup_is_basis_extension_without_correction(level):
+    """Table "CKKS Subroutines" (ModUp), reading 6: limb t of digit j's output
+    is exactly xhat mod t, xhat = sum_{i in I_j} [x_i (Qt/q_i)^-1]_{q_i} (Qt/q_i),
+    an integer below |I_j| Qt.  xhat is rebuilt here from the Chinese remainder
+    X of the digit's coefficients and checked against the overflow
+    characterization xhat = X + Qt floor(sum_i y_i / q_i), so every output word
+    is fixed, not a range."""
     pr = _pr(4, 6, 2, 3)  # alpha = 2
     g = synth.rng(100 + level)
     a = synth.uniform_residues(g, pr.q[:level], pr.n)
@@ -181,34 +193,48 @@ def test_modup_is_basis_extension_without_correction(level):
     xc = _coef(pr, a, pr.q[:level])
     for j in range(pr.beta(level)):
         lo, hi = j * pr.alpha, min((j + 1) * pr.alpha, level)
-        Qt = B.prod(pr.q[lo:hi])
+        qs = [int(q) for q in pr.q[lo:hi]]
+        Qt = B.prod(qs)
         ec = _coef(pr, ext[j], emods)
         for t in range(lo, hi):
             assert np.array_equal(ext[j, t], a[t])
         for c in range(pr.n):
-            X = B.crt([xc[i, c] for i in range(lo, hi)], pr.q[lo:hi])
-            ok = [u for u in range(hi - lo)
-                  if all(int(ec[t, c]) == (X + u * Qt) % int(emods[t])
-                         for t in range(level + pr.K) if not (lo <= t < hi))]
-            assert ok, (j, c)
+            X = B.crt([xc[i, c] for i in range(lo, hi)], qs)
+            ys = [X * pow(Qt // qi, -1, qi) % qi for qi in qs]
+            xhat = sum(y * (Qt // qi) for y, qi in zip(ys, qs))
+            assert xhat == X + Qt * _fractional_floor(ys, qs)
+            assert 0 <= xhat < (hi - lo) * Qt
+            for t in range(level + pr.K):
+                if not (lo <= t < hi):
+                    assert int(ec[t, c]) == xhat % int(emods[t]), (j, t, c)
 
 
-def test_moddown_floor_division_by_P():
-    pr = _pr(4, 4, 3, 2)
-    level = 4
-    g = synth.rng(77)
+@pytest.mark.parametrize("cfg", [(4, 4, 3, 2, 4), (4, 6, 2, 3, 3), (5, 5, 4, 5, 2)])
+def test_moddown_floor_division_by_P(cfg):
+    """Table "CKKS Subroutines" (ModDown), reading 7: the output is exactly
+    (U - Utilde) / P mod Q_level, with U the Chinese remainder of the input
+    over Q_level U P and Utilde = sum_k [U (P/p_k)^-1]_{p_k} (P/p_k), which
+    equals floor(U / P) - floor(sum_k y_k / p_k): every output word is fixed."""
+    log_n, L, K, dnum, level = cfg
+    pr = _pr(log_n, L, K, dnum)
+    g = synth.rng(77 + level)
     emods = pr.ext_mods(level)
     x = synth.uniform_residues(g, emods, pr.n)
     y = O.moddown(pr, x, level)
     xc = _coef(pr, x, emods)
     yc = _coef(pr, y, pr.q[:level])
-    P = B.prod(pr.p)
+    ps = [int(p) for p in pr.p]
+    P = B.prod(ps)
+    Q = B.prod(pr.q[:level])
     for c in range(pr.n):
         U = B.crt(xc[:, c], emods)
-        Y = B.crt(yc[:, c], pr.q[:level])
-        Q = B.prod(pr.q[:level])
-        errs = [e for e in range(pr.K) if (U // P - e) % Q == Y]
-        assert errs, c
+        ys = [U * pow(P // pk, -1, pk) % pk for pk in ps]
+        Ut = sum(yk * (P // pk) for yk, pk in zip(ys, ps))
+        assert (U - Ut) % P == 0
+        e = _fractional_floor(ys, ps)
+        assert 0 <= e < pr.K
+        assert (U - Ut) // P == U // P - e
+        assert B.crt(yc[:, c], pr.q[:level]) == ((U - Ut) // P) % Q, c
 
 
 def test_moddown_exact_on_multiples_of_P():
@@ -541,3 +567,105 @@ def test_new_mult_matches_mult_then_division_by_q_last():
     R = _crt_centered(O.decrypt_coef(pr, s, O.rescale(pr, plain, level), level - 1),
                       [int(q) for q in pr.q[: level - 1]])
     assert max(abs(e - r) for e, r in zip(E, R)) <= bound + pr.K * (hs + 1) + 2
+
+
+# ------------------------------------------------------------------ limb counts (paper's cost tables)
+
+
+def _paper_sizes():
+    return json.load(open(os.path.join(GOLDEN, "paper_sizes.json")))
+
+
+def test_decomp_limb_counts_reproduce_the_paper_cost_tables():
+    """Reading 3 (alpha = ceil(L/dnum), beta = ceil(l/alpha) over limb
+    counts, K = alpha) pinned by the paper's own numbers: Table "Hardware
+    Cost of Auxiliary Subroutines" and Table "Hardware Cost of FHE APIs"
+    (Sec. 2.5) at log N = 17, level index 35 (36 limbs), dnum = 3, 8-byte
+    words.  The C oracle's alpha and beta give E = 36 + alpha = 48 extended
+    limbs, so KSKInnerProd reads 2 dnum E limbs of key (0.3020 GB) and beta E
+    limbs of ModUp output (0.1510 GB), and a Rotate is beta ModUps.  The
+    literal '+1' reading over counts (alpha = ceil(37/3) = 13) would give
+    0.3083 GB of key, and beta = ceil(37/12) would give four ModUps."""
+    ps = _paper_sizes()
+    aux, api = ps["aux_cost"], ps["api_cost"]
+    n = 1 << ps["workload"]["log_n"]
+    limbs = ps["workload"]["level_index"] + 1
+    dnum = ps["workload"]["dnum"]
+    word = ps["workload"]["word_bytes"]
+    GB = 1e9
+    limb = n * word
+    # parameters with the paper's limb counts (the primes' size plays no part)
+    pr = O.Params(16, limbs, 1, dnum, O.gen_primes(50, 17, limbs), O.gen_primes(50, 17, 1))
+    alpha = O.c_alpha(pr)
+    assert alpha == pr.alpha
+    pr.K = alpha
+    beta = O.c_beta(pr, limbs)
+    assert beta == pr.beta(limbs)
+    E = limbs + alpha
+    assert (alpha, beta, E) == (12, 3, 48)
+
+    def close(model, table, rel=0.001):
+        return abs(model - table) <= rel * table + 5e-5
+
+    # KSKInnerProd: key reads, ModUp-output reads, products and additions
+    key_bytes = 2 * dnum * E * limb
+    assert close(key_bytes / GB, aux["KSKInnerProd"]["key_reads_GB"])
+    assert close(key_bytes / GB, ps["ksk_key_reads_GB"]["value"])
+    assert close(beta * E * limb / GB, aux["KSKInnerProd"]["limb_reads_GB"])
+    assert close(2 * beta * E * n / GB, aux["KSKInnerProd"]["mults_GOP"])
+    assert close((2 * beta * E + 2 * (beta - 1) * E) * n / GB, aux["KSKInnerProd"]["total_GOP"])
+    # the same key bytes in Rotate and Mult; r times in HRotate(r)
+    assert close(key_bytes / GB, api["Rotate"]["key_reads_GB"])
+    assert close(key_bytes / GB, api["Mult"]["key_reads_GB"])
+    assert close(api["HRotate"]["rotations"] * key_bytes / GB, api["HRotate"]["key_reads_GB"])
+    # ModUp of one digit: iNTT reads alpha limbs, NewLimb reads them again
+    # (slot-wise) and writes E - alpha, the NTT reads and writes those
+    assert close((2 * alpha + (E - alpha)) * limb / GB, aux["ModUp"]["limb_reads_GB"])
+    assert close((alpha + 2 * (E - alpha)) * limb / GB, aux["ModUp"]["limb_writes_GB"])
+    # a Rotate's operations: Decomp, beta ModUps, KSKInnerProd, ModDown of
+    # u and v, and one polynomial addition (b_rot)
+    ops = (aux["Decomp"]["total_GOP"] + beta * aux["ModUp"]["total_GOP"] + aux["KSKInnerProd"]["total_GOP"]
+           + 2 * aux["ModDown"]["total_GOP"] + api["PtAdd"]["total_GOP"])
+    assert close(ops, api["Rotate"]["total_GOP"])
+    mults = (aux["Decomp"]["mults_GOP"] + beta * aux["ModUp"]["mults_GOP"] + aux["KSKInnerProd"]["mults_GOP"]
+             + 2 * aux["ModDown"]["mults_GOP"])
+    assert close(mults, api["Rotate"]["mults_GOP"])
+    # the alternative readings miss the tables
+    lit_alpha = -(-(limbs + 1) // dnum)
+    assert not close(2 * dnum * (limbs + lit_alpha) * limb / GB, aux["KSKInnerProd"]["key_reads_GB"])
+    lit_beta = -(-(limbs + 1) // alpha)  # ceil(37/12) = 4 digits
+    assert lit_beta == 4
+    assert not close(aux["Decomp"]["total_GOP"] + lit_beta * aux["ModUp"]["total_GOP"]
+                     + aux["KSKInnerProd"]["total_GOP"] + 2 * aux["ModDown"]["total_GOP"]
+                     + api["PtAdd"]["total_GOP"], api["Rotate"]["total_GOP"])
+
+
+def test_ciphertext_and_automorph_sizes_match_the_paper():
+    """Sec. 2.3: a ciphertext is 2 N l words (73.4 MB at N = 2^17, 35 limbs);
+    Automorph reads and writes it once (Table of auxiliary costs), Decomp
+    reads and writes one polynomial."""
+    ps = _paper_sizes()
+    ex = ps["example"]
+    n = 1 << ex["log_n"]
+    ct = 2 * n * ex["limbs"] * ex["word_bytes"]
+    assert abs(ct / 1e6 - ex["ciphertext_MB"]) < 0.05
+    aux = ps["aux_cost"]
+    assert abs(ct / 1e9 - aux["Automorph"]["limb_reads_GB"]) < 5e-5
+    assert abs(2 * ct / 1e9 - ps["automorph_dram_GB"]["value"]) < 5e-5
+    assert abs(ct / 2 / 1e9 - ps["decomp_limb_reads_GB"]["value"]) < 5e-5
+    # the oracle's ciphertext layout holds exactly 2 l N words
+    pr = _pr(10, 4, 2, 2)
+    g = synth.rng(3)
+    c = O.encrypt(pr, synth.ternary(g, pr.n), synth.small_uniform(g, pr.n, 10), 3, g)
+    assert c.shape == (2, 3, pr.n) and c.dtype == np.uint64
+
+
+def test_switching_key_shape_is_2_dnum_extended_limbs():
+    """Eq. (kskShape): dnum digits, two rows each, over the L + K limbs of
+    the raised modulus; the oracle's keygen makes exactly that shape."""
+    pr = _pr(10, 6, 2, 3)
+    g = synth.rng(9)
+    s = synth.ternary(g, pr.n)
+    ksk = O.rotation_key(pr, s, pow(5, -1, 2 * pr.n), g)
+    assert ksk.shape == (pr.dnum, 2, pr.L + pr.K, pr.n)
+    assert O.c_alpha(pr) == 2 and O.c_beta(pr, 6) == 3 and O.c_beta(pr, 5) == 3 and O.c_beta(pr, 2) == 1
