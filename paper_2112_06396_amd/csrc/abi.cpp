@@ -24,6 +24,7 @@
 
 using namespace hks;
 
+
 namespace {
 
 int hip_status(hipError_t e) { return e == hipSuccess ? HKS_OK : HKS_EHIP; }
@@ -38,28 +39,41 @@ bool aligned(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 
 uint32_t ext_mod(const Ctx &c, uint32_t level, uint32_t t) { return t < level ? t : c.L + (t - level); }
 
+// The limbs of one call step, handed to the launchers MAXL at a time.  Fixed
+// capacity (no heap use on the call path): at most beta (L + K) <= 48 * 64
+// entries; an overflow makes run() fail.
 struct Lists {
-    std::vector<uint32_t> io, oo, md, ci, ns;
+    static constexpr size_t CAP = 4096;
+    uint16_t io[CAP], oo[CAP], ci[CAP];
+    uint8_t md[CAP], ns[CAP];
+    size_t size = 0;
+    bool overflow = false;
     void add(uint32_t in_off, uint32_t out_off, uint32_t mod, uint32_t cidx, uint32_t nsrc = 0) {
-        io.push_back(in_off);
-        oo.push_back(out_off);
-        md.push_back(mod);
-        ci.push_back(cidx);
-        ns.push_back(nsrc);
+        if (size == CAP) {
+            overflow = true;
+            return;
+        }
+        io[size] = (uint16_t)in_off;
+        oo[size] = (uint16_t)out_off;
+        md[size] = (uint8_t)mod;
+        ci[size] = (uint16_t)cidx;
+        ns[size] = (uint8_t)nsrc;
+        ++size;
     }
     template <typename F>
     hipError_t run(F fn) const {
+        if (overflow) return hipErrorInvalidValue;
         LimbMap m;
-        for (size_t s = 0; s < io.size(); s += MAXL) {
-            size_t cnt = std::min<size_t>(MAXL, io.size() - s);
+        for (size_t s = 0; s < size; s += MAXL) {
+            size_t cnt = std::min<size_t>(MAXL, size - s);
             std::memset(&m, 0, sizeof(m));
             m.count = (uint32_t)cnt;
             for (size_t i = 0; i < cnt; ++i) {
-                m.in_off[i] = (uint16_t)io[s + i];
-                m.out_off[i] = (uint16_t)oo[s + i];
-                m.mod[i] = (uint8_t)md[s + i];
-                m.cidx[i] = (uint16_t)ci[s + i];
-                m.nsrc[i] = (uint8_t)ns[s + i];
+                m.in_off[i] = io[s + i];
+                m.out_off[i] = oo[s + i];
+                m.mod[i] = md[s + i];
+                m.cidx[i] = ci[s + i];
+                m.nsrc[i] = ns[s + i];
             }
             hipError_t e = fn(m);
             if (e != hipSuccess) return e;
@@ -121,20 +135,20 @@ int check_inputs(Ctx &c, hipStream_t s, const std::vector<Chk> &items) {
 //   forward NTT of those limbs in place (own-digit slots untouched): both
 //   passes, or with cols_only just the column pass (the key-switch kernel
 //   runs the row pass on chip).
-int do_modup_new(Ctx &c, const uint64_t *const *a, const uint32_t *galois, uint32_t nb, uint32_t level,
-                 uint64_t *ext, size_t ext_bstride, hipStream_t s, bool cols_only) {
+int do_modup_new(Ctx &c, const Ws &w, const uint64_t *const *a, const uint32_t *galois, uint32_t nb,
+                 uint32_t level, uint64_t *ext, size_t ext_bstride, hipStream_t s, bool cols_only) {
     const uint32_t A = c.alpha, E = level + c.K, beta = beta_of(c, level);
     Lists inv, nl;
     for (uint32_t i = 0; i < level; ++i) inv.add(i, i, i, level * c.L + i);
     BatchIo io{};
     for (uint32_t b = 0; b < nb; ++b) {
         io.in[b] = a[b];
-        io.out[b] = c.ws_y + b * c.st_y();
+        io.out[b] = w.y + b * w.st_y;
         io.galois[b] = galois[b];
         io.add_galois[b] = 1;
     }
     HKS_TRY(inv.run([&](const LimbMap &m) { return launch_ntt_inv(c, m, io, c.li_modup, nb, s); }));
-    HKS_TRY(launch_conv_modup(c, c.ws_y, level, ext, nb, c.st_y(), ext_bstride, s));
+    HKS_TRY(launch_conv_modup(c, w.y, level, ext, nb, w.st_y, ext_bstride, s));
     for (uint32_t j = 0; j < beta; ++j) {
         const uint32_t lo = j * A, hi = std::min((j + 1) * A, level);
         for (uint32_t t = 0; t < E; ++t)
@@ -181,25 +195,26 @@ ModDownSpec spec_newmult(const Ctx &c, uint32_t level) {
 // by N^-1 [(S/s)^-1]_s; NewLimb into the `level` output q limbs (ws_z +
 // p*L*N); forward column pass; row pass + (u - z) S^-1 (+ add), with u, the
 // output, the addend and its automorph per polynomial in `epi`.
-int do_moddown_tail(Ctx &c, uint32_t level, uint32_t np, BatchIo epi, hipStream_t s, const ModDownSpec &sp) {
+int do_moddown_tail(Ctx &c, const Ws &w, uint32_t level, uint32_t np, BatchIo epi, hipStream_t s,
+                    const ModDownSpec &sp) {
     const uint32_t N = c.n, K = c.K, L = c.L;
-    const size_t pst = (size_t)sp.ns * N, zst = (size_t)L * N;
+    const size_t pst = (size_t)sp.ns * N, zst = w.st_z;
     Lists pl, ql;
     for (uint32_t k = 0; k < K; ++k) pl.add(k, k, L + k, k);
     if (sp.ns > K) pl.add(K, K, sp.extra_mod, K);
     for (uint32_t i = 0; i < level; ++i) ql.add(i, i, i, i);
-    const BatchIo pio = strided_io(c.ws_p, pst, c.ws_p, pst, np);
+    const BatchIo pio = strided_io(w.p, pst, w.p, pst, np);
     HKS_TRY(pl.run([&](const LimbMap &m) { return launch_ntt_inv_cols(c, m, pio, sp.li, np, s); }));
-    HKS_TRY(launch_conv_moddown(c, c.ws_p, level, c.ws_z, np, pst, zst, sp.conv, sp.ns, s));
-    const BatchIo zio = strided_io(c.ws_z, zst, c.ws_z, zst, np);
+    HKS_TRY(launch_conv_moddown(c, w.p, level, w.z, np, pst, zst, sp.conv, sp.ns, s));
+    const BatchIo zio = strided_io(w.z, zst, w.z, zst, np);
     HKS_TRY(ql.run([&](const LimbMap &m) { return launch_ntt_fwd_cols(c, m, zio, np, s); }));
-    for (uint32_t p = 0; p < np; ++p) epi.in[p] = c.ws_z + p * zst;
+    for (uint32_t p = 0; p < np; ++p) epi.in[p] = w.z + p * zst;
     HKS_TRY(ql.run([&](const LimbMap &m) { return launch_rows_mdepi(c, m, epi, np, sp.sinv, s); }));
     return HKS_OK;
 }
 
 int do_moddown_tail(Ctx &c, uint32_t level, uint32_t np, BatchIo epi, hipStream_t s) {
-    return do_moddown_tail(c, level, np, epi, s, spec_by_p(c));
+    return do_moddown_tail(c, ctx_ws(c), level, np, epi, s, spec_by_p(c));
 }
 
 // One key-switch of a batch: d (level limbs, gathered through galois) with
@@ -219,7 +234,7 @@ struct KsJob {
 // KeySwitch of nb <= min(batch_cap, MAXCT) jobs in shared launches (9 per
 // step); the digits' own limbs are read from d in the KSKInnerProd kernel
 // (never copied), which also runs the last forward pass of ModUp's NTT.
-int do_keyswitch_step(Ctx &c, const KsJob *jobs, uint32_t nb, uint32_t level, hipStream_t s) {
+int do_keyswitch_step(Ctx &c, const Ws &w, const KsJob *jobs, uint32_t nb, uint32_t level, hipStream_t s) {
     const size_t pl = (size_t)level * c.n;
     const uint64_t *d[MAXCT];
     uint32_t g[MAXCT];
@@ -240,18 +255,22 @@ int do_keyswitch_step(Ctx &c, const KsJob *jobs, uint32_t nb, uint32_t level, hi
         kb.newmult = nm ? 1u : 0u;
         for (uint32_t poly = 0; poly < 2; ++poly) {
             const uint32_t p = 2 * b + poly;
-            epi.uq[p] = c.ws_uv + b * c.st_uv() + poly * pl;
+            epi.uq[p] = w.uv + b * w.st_uv + poly * pl;
             epi.out[p] = jobs[b].out + poly * (size_t)out_level * c.n;
             epi.add[p] = poly ? jobs[b].add1 : jobs[b].add0;
             epi.add_galois[p] = jobs[b].galois;
         }
     }
-    int rc = do_modup_new(c, d, g, nb, level, c.ws_ext, c.st_ext(), s, true);
+    int rc = do_modup_new(c, w, d, g, nb, level, w.ext, w.st_ext, s, true);
     if (rc) return rc;
     const ModDownSpec sp = nm ? spec_newmult(c, level) : spec_by_p(c);
-    HKS_TRY(launch_ksk_rows(c, kb, nb, c.ws_ext, c.st_ext(), true, 0, 0, level, c.ws_uv, c.st_uv(), c.ws_p,
+    HKS_TRY(launch_ksk_rows(c, kb, nb, w.ext, w.st_ext, true, 0, 0, level, w.uv, w.st_uv, w.p,
                             (size_t)2 * sp.ns * c.n, s));
-    return do_moddown_tail(c, out_level, 2 * nb, epi, s, sp);
+    return do_moddown_tail(c, w, out_level, 2 * nb, epi, s, sp);
+}
+
+int do_keyswitch_step(Ctx &c, const KsJob *jobs, uint32_t nb, uint32_t level, hipStream_t s) {
+    return do_keyswitch_step(c, ctx_ws(c), jobs, nb, level, s);
 }
 
 int do_keyswitch_jobs(Ctx &c, const KsJob *jobs, uint32_t n, uint32_t level, hipStream_t s) {
@@ -490,7 +509,7 @@ int hks_modup(hks_ctx *h, const uint64_t *a, uint32_t level, uint64_t *ext, void
     hipStream_t s = (hipStream_t)stream;
     HKS_CHECKED(h->c, s, ct_chk(a, 1, level));
     const uint32_t one = 1;
-    int rc = do_modup_new(h->c, &a, &one, 1, level, ext, 0, s, false);
+    int rc = do_modup_new(h->c, ctx_ws(h->c), &a, &one, 1, level, ext, 0, s, false);
     return rc ? rc : do_modup_own(h->c, a, level, 1, ext, s);
     GUARD_END
 }
@@ -584,7 +603,7 @@ int hks_hrotate(hks_ctx *h, const uint64_t *ct, uint32_t level, uint32_t r, cons
     const uint32_t N = c.n, E = level + c.K;
     const size_t pl = (size_t)level * N;
     const uint32_t one = 1;
-    int rc = do_modup_new(c, &ct, &one, 1, level, c.ws_ext, 0, s, false);
+    int rc = do_modup_new(c, ctx_ws(c), &ct, &one, 1, level, c.ws_ext, 0, s, false);
     if (!rc) rc = do_modup_own(c, ct, level, 1, c.ws_ext, s);
     if (rc) return rc;
     // rotations in steps of up to batch_cap: one KSKInnerProd launch over the
@@ -672,7 +691,7 @@ int hks_ptmatvec(hks_ctx *h, const uint64_t *ct, uint32_t level, uint32_t r, con
     const size_t pl = (size_t)level * c.n;
     const uint32_t one = 1;
     if (keyed) {
-        int rc = do_modup_new(c, &ct, &one, 1, level, c.ws_ext, 0, s, false);
+        int rc = do_modup_new(c, ctx_ws(c), &ct, &one, 1, level, c.ws_ext, 0, s, false);
         if (!rc) rc = do_modup_own(c, ct, level, 1, c.ws_ext, s);
         if (rc) return rc;
     }

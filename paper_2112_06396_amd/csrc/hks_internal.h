@@ -155,6 +155,17 @@ struct Ctx {
     size_t ksk_words() const { return (size_t)dnum * 2 * M * n; }
 };
 
+// The workspace buffers one key-switch step uses, with the distance between
+// the slots of consecutive batch entries: the context's own workspace, or
+// the allocation-free scratch (hks_rotate_noalloc).
+struct Ws {
+    uint64_t *y, *ext, *uv, *p, *z;
+    size_t st_y, st_ext, st_uv, st_p, st_z;  // words per batch entry (z: per polynomial)
+};
+inline Ws ctx_ws(const Ctx &c) {
+    return Ws{c.ws_y, c.ws_ext, c.ws_uv, c.ws_p, c.ws_z, c.st_y(), c.st_ext(), c.st_uv(), c.st_p(), (size_t)c.L * c.n};
+}
+
 // Records a hipEvent pair around the launches in its scope when the class is
 // selected by the context's timing mask.
 struct ProfScope {

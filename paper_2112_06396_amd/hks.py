@@ -200,16 +200,81 @@ def _check(name, rc):
         raise HksError(name, rc)
 
 
-def _ptr(t: torch.Tensor):
+def _on_device(t: torch.Tensor) -> bool:
+    return t.is_cuda
+
+
+class HksSizeError(ValueError):
+    """A tensor holds fewer words than the call reads or writes through it."""
+
+
+def _need(t, words: int, what: str):
+    if words is not None and t.numel() < words:
+        raise HksSizeError(f"{what}: {t.numel()} words, the call touches {words}")
+
+
+def _ptr(t: torch.Tensor, words: int = None, what: str = "tensor"):
+    """Device pointer of t, after checking its dtype, that it holds at least
+    `words` words (the extent the C call reads or writes), and that it is a
+    contiguous GPU tensor."""
     if not isinstance(t, torch.Tensor):
         raise TypeError("expected a torch tensor")
     if t.dtype not in (torch.uint64, torch.int64):
         raise TypeError(f"expected 64-bit integer tensor, got {t.dtype}")
-    if not t.is_cuda:
+    _need(t, words, what)
+    if not _on_device(t):
         raise ValueError("tensor must live on the GPU")
     if not t.is_contiguous():
         raise ValueError("tensor must be contiguous")
     return ctypes.c_void_p(t.data_ptr())
+
+
+# Words a call touches through each argument (layouts of include/hks.h).  A
+# level outside [1, L] is left to the C call, which rejects it.
+def _lvl(ctx, level):
+    return int(level) if 1 <= int(level) <= ctx.L else None
+
+
+def _w_poly(ctx, level, polys=1):
+    lv = _lvl(ctx, level)
+    return None if lv is None else polys * lv * ctx.n
+
+
+def _w_ext(ctx, level):
+    """one polynomial over Q_level U P"""
+    lv = _lvl(ctx, level)
+    return None if lv is None else (lv + ctx.K) * ctx.n
+
+
+def _w_digits(ctx, level):
+    """the extended digits [beta][level + K][N]"""
+    lv = _lvl(ctx, level)
+    if lv is None:
+        return None
+    alpha = -(-ctx.L // ctx.dnum)
+    return -(-lv // alpha) * (lv + ctx.K) * ctx.n
+
+
+def _w_key(ctx):
+    """a switching key [dnum][2][L + K][N]"""
+    return ctx.dnum * 2 * (ctx.L + ctx.K) * ctx.n
+
+
+def _w_key_rows(ctx):
+    """one row per digit, [dnum][L + K][N] (a seeded key's b_j, or its a_j)"""
+    return ctx.dnum * (ctx.L + ctx.K) * ctx.n
+
+
+def _w_out(ctx, level, drop):
+    """a ciphertext [2][level - drop][N] (drop = 1 after a Rescale)"""
+    lv = _lvl(ctx, level)
+    return None if lv is None or lv - drop < 1 else 2 * (lv - drop) * ctx.n
+
+
+def _w_limbs(ctx, first_mod, n_limbs):
+    if first_mod + n_limbs > ctx.L + ctx.K:
+        return None
+    return n_limbs * ctx.n
 
 
 def _stream(stream):
@@ -303,36 +368,46 @@ def hks_query(ctx: Context, key: int, level: int = 0) -> int:
 # ---------------------------------------------------------------- calls
 
 def hks_ntt(ctx, x, first_mod: int, n_limbs: int, stream=None):
-    _check("hks_ntt", lib().hks_ntt(ctx.handle, _ptr(x), first_mod, n_limbs, _stream(stream)))
+    _check("hks_ntt", lib().hks_ntt(ctx.handle, _ptr(x, _w_limbs(ctx, first_mod, n_limbs), "x"), first_mod,
+                                    n_limbs, _stream(stream)))
 
 
 def hks_intt(ctx, x, first_mod: int, n_limbs: int, stream=None):
-    _check("hks_intt", lib().hks_intt(ctx.handle, _ptr(x), first_mod, n_limbs, _stream(stream)))
+    _check("hks_intt", lib().hks_intt(ctx.handle, _ptr(x, _w_limbs(ctx, first_mod, n_limbs), "x"), first_mod,
+                                      n_limbs, _stream(stream)))
 
 
 def hks_automorph(ctx, x, y, first_mod: int, n_limbs: int, galois: int, eval_domain: bool = True, stream=None):
-    _check("hks_automorph", lib().hks_automorph(ctx.handle, _ptr(x), _ptr(y), first_mod, n_limbs, galois,
+    w = _w_limbs(ctx, first_mod, n_limbs)
+    _check("hks_automorph", lib().hks_automorph(ctx.handle, _ptr(x, w, "x"), _ptr(y, w, "y"), first_mod, n_limbs, galois,
                                                 1 if eval_domain else 0, _stream(stream)))
 
 
 def hks_modup(ctx, a, level: int, ext, stream=None):
-    _check("hks_modup", lib().hks_modup(ctx.handle, _ptr(a), level, _ptr(ext), _stream(stream)))
+    _check("hks_modup", lib().hks_modup(ctx.handle, _ptr(a, _w_poly(ctx, level), "a"), level,
+                                        _ptr(ext, _w_digits(ctx, level), "ext"), _stream(stream)))
 
 
 def hks_ksk_inner(ctx, ext, level: int, ksk, uv, stream=None):
-    _check("hks_ksk_inner", lib().hks_ksk_inner(ctx.handle, _ptr(ext), level, _ptr(ksk), _ptr(uv), _stream(stream)))
+    _check("hks_ksk_inner", lib().hks_ksk_inner(ctx.handle, _ptr(ext, _w_digits(ctx, level), "ext"), level,
+                                                _ptr(ksk, _w_key(ctx), "ksk"), _ptr(uv, 2 * (_w_ext(ctx, level) or 0) or None, "uv"),
+                                                _stream(stream)))
 
 
 def hks_moddown(ctx, x, level: int, y, stream=None):
-    _check("hks_moddown", lib().hks_moddown(ctx.handle, _ptr(x), level, _ptr(y), _stream(stream)))
+    _check("hks_moddown", lib().hks_moddown(ctx.handle, _ptr(x, _w_ext(ctx, level), "x"), level,
+                                            _ptr(y, _w_poly(ctx, level), "y"), _stream(stream)))
 
 
 def hks_keyswitch(ctx, d, level: int, ksk, uv, stream=None):
-    _check("hks_keyswitch", lib().hks_keyswitch(ctx.handle, _ptr(d), level, _ptr(ksk), _ptr(uv), _stream(stream)))
+    _check("hks_keyswitch", lib().hks_keyswitch(ctx.handle, _ptr(d, _w_poly(ctx, level), "d"), level,
+                                                _ptr(ksk, _w_key(ctx), "ksk"), _ptr(uv, _w_poly(ctx, level, 2), "uv"),
+                                                _stream(stream)))
 
 
 def hks_rotate(ctx, ct, level: int, galois: int, ksk, ct_out, stream=None):
-    _check("hks_rotate", lib().hks_rotate(ctx.handle, _ptr(ct), level, galois, _ptr(ksk), _ptr(ct_out),
+    _check("hks_rotate", lib().hks_rotate(ctx.handle, _ptr(ct, _w_poly(ctx, level, 2), "ct"), level, galois,
+                                          _ptr(ksk, _w_key(ctx), "ksk"), _ptr(ct_out, _w_poly(ctx, level, 2), "ct_out"),
                                           _stream(stream)))
 
 
@@ -341,28 +416,32 @@ def hks_hrotate(ctx, ct, level: int, galois, ksks, outs, stream=None):
     if len(ksks) != r or len(outs) != r:
         raise ValueError("galois, ksks and outs must have the same length")
     ga = (_u32 * r)(*[int(g) for g in galois])
-    ka = (_vp * r)(*[_ptr(k) for k in ksks])
-    oa = (_vp * r)(*[_ptr(o) for o in outs])
-    _check("hks_hrotate", lib().hks_hrotate(ctx.handle, _ptr(ct), level, r, ga, ka, oa, _stream(stream)))
+    ka = (_vp * r)(*[_ptr(k, _w_key(ctx), "ksk") for k in ksks])
+    oa = (_vp * r)(*[_ptr(o, _w_poly(ctx, level, 2), "ct_out") for o in outs])
+    _check("hks_hrotate", lib().hks_hrotate(ctx.handle, _ptr(ct, _w_poly(ctx, level, 2), "ct"), level, r, ga, ka, oa,
+                                            _stream(stream)))
 
 
 def hks_batch_rotate(ctx, cts, level: int, galois, ksks, outs, stream=None):
     n = len(cts)
     if len(galois) != n or len(ksks) != n or len(outs) != n:
         raise ValueError("cts, galois, ksks and outs must have the same length")
-    ca = (_vp * n)(*[_ptr(c) for c in cts])
+    ca = (_vp * n)(*[_ptr(c, _w_poly(ctx, level, 2), "ct") for c in cts])
     ga = (_u32 * n)(*[int(g) for g in galois])
-    ka = (_vp * n)(*[_ptr(k) for k in ksks])
-    oa = (_vp * n)(*[_ptr(o) for o in outs])
+    ka = (_vp * n)(*[_ptr(k, _w_key(ctx), "ksk") for k in ksks])
+    oa = (_vp * n)(*[_ptr(o, _w_poly(ctx, level, 2), "ct_out") for o in outs])
     _check("hks_batch_rotate", lib().hks_batch_rotate(ctx.handle, n, ca, level, ga, ka, oa, _stream(stream)))
 
 
 def hks_rescale(ctx, ct, level: int, ct_out, stream=None):
-    _check("hks_rescale", lib().hks_rescale(ctx.handle, _ptr(ct), level, _ptr(ct_out), _stream(stream)))
+    _check("hks_rescale", lib().hks_rescale(ctx.handle, _ptr(ct, _w_poly(ctx, level, 2), "ct"), level,
+                                            _ptr(ct_out, _w_out(ctx, level, 1), "ct_out"), _stream(stream)))
 
 
 def hks_ptmult(ctx, ct, pt, level: int, rescale: bool, ct_out, stream=None):
-    _check("hks_ptmult", lib().hks_ptmult(ctx.handle, _ptr(ct), _ptr(pt), level, 1 if rescale else 0, _ptr(ct_out),
+    _check("hks_ptmult", lib().hks_ptmult(ctx.handle, _ptr(ct, _w_poly(ctx, level, 2), "ct"),
+                                          _ptr(pt, _w_poly(ctx, level), "pt"), level, 1 if rescale else 0,
+                                          _ptr(ct_out, _w_out(ctx, level, 1 if rescale else 0), "ct_out"),
                                           _stream(stream)))
 
 
@@ -370,10 +449,10 @@ def hks_batch_mult_relin(ctx, ct1s, ct2s, level: int, rlks, rescale: bool, outs,
     n = len(ct1s)
     if len(ct2s) != n or len(rlks) != n or len(outs) != n:
         raise ValueError("ct1s, ct2s, rlks and outs must have the same length")
-    a = (_vp * n)(*[_ptr(c) for c in ct1s])
-    b = (_vp * n)(*[_ptr(c) for c in ct2s])
-    k = (_vp * n)(*[_ptr(r) for r in rlks])
-    o = (_vp * n)(*[_ptr(x) for x in outs])
+    a = (_vp * n)(*[_ptr(c, _w_poly(ctx, level, 2), "ct1") for c in ct1s])
+    b = (_vp * n)(*[_ptr(c, _w_poly(ctx, level, 2), "ct2") for c in ct2s])
+    k = (_vp * n)(*[_ptr(r, _w_key(ctx), "rlk") for r in rlks])
+    o = (_vp * n)(*[_ptr(x, _w_out(ctx, level, 1 if rescale else 0), "ct_out") for x in outs])
     _check("hks_batch_mult_relin", lib().hks_batch_mult_relin(ctx.handle, n, a, b, level, k, 1 if rescale else 0, o,
                                                               _stream(stream)))
 
@@ -384,30 +463,33 @@ def hks_ptmatvec(ctx, ct, level: int, galois, ksks, pts, ct_out, stream=None):
     if len(ksks) != r or len(pts) != r:
         raise ValueError("galois, ksks and pts must have the same length")
     ga = (_u32 * r)(*[int(g) for g in galois])
-    ka = (_vp * r)(*[_vp() if k is None else _ptr(k) for k in ksks])
-    pa = (_vp * r)(*[_ptr(p) for p in pts])
-    _check("hks_ptmatvec", lib().hks_ptmatvec(ctx.handle, _ptr(ct), level, r, ga, ka, pa, _ptr(ct_out),
-                                              _stream(stream)))
+    ka = (_vp * r)(*[_vp() if k is None else _ptr(k, _w_key(ctx), "ksk") for k in ksks])
+    pa = (_vp * r)(*[_ptr(p, _w_ext(ctx, level), "pt") for p in pts])
+    _check("hks_ptmatvec", lib().hks_ptmatvec(ctx.handle, _ptr(ct, _w_poly(ctx, level, 2), "ct"), level, r, ga, ka,
+                                              pa, _ptr(ct_out, _w_poly(ctx, level, 2), "ct_out"), _stream(stream)))
 
 
 def hks_expand_key_a(ctx, seed: int, a, stream=None):
-    _check("hks_expand_key_a", lib().hks_expand_key_a(ctx.handle, int(seed), _ptr(a), _stream(stream)))
+    _check("hks_expand_key_a", lib().hks_expand_key_a(ctx.handle, int(seed), _ptr(a, _w_key_rows(ctx), "a"),
+                                                      _stream(stream)))
 
 
 def hks_rotate_seeded(ctx, ct, level: int, galois: int, seed: int, ksk_b, ct_out, stream=None):
-    _check("hks_rotate_seeded", lib().hks_rotate_seeded(ctx.handle, _ptr(ct), level, galois, int(seed), _ptr(ksk_b),
-                                                        _ptr(ct_out), _stream(stream)))
+    _check("hks_rotate_seeded", lib().hks_rotate_seeded(ctx.handle, _ptr(ct, _w_poly(ctx, level, 2), "ct"), level,
+                                                        galois, int(seed), _ptr(ksk_b, _w_key_rows(ctx), "ksk_b"),
+                                                        _ptr(ct_out, _w_poly(ctx, level, 2), "ct_out"),
+                                                        _stream(stream)))
 
 
 def hks_batch_rotate_seeded(ctx, cts, level: int, galois, seeds, ksk_bs, outs, stream=None):
     n = len(cts)
     if len(galois) != n or len(seeds) != n or len(ksk_bs) != n or len(outs) != n:
         raise ValueError("cts, galois, seeds, ksk_bs and outs must have the same length")
-    ca = (_vp * n)(*[_ptr(c) for c in cts])
+    ca = (_vp * n)(*[_ptr(c, _w_poly(ctx, level, 2), "ct") for c in cts])
     ga = (_u32 * n)(*[int(g) for g in galois])
     sa = (ctypes.c_uint64 * n)(*[int(x) for x in seeds])
-    ka = (_vp * n)(*[_ptr(k) for k in ksk_bs])
-    oa = (_vp * n)(*[_ptr(o) for o in outs])
+    ka = (_vp * n)(*[_ptr(k, _w_key_rows(ctx), "ksk_b") for k in ksk_bs])
+    oa = (_vp * n)(*[_ptr(o, _w_poly(ctx, level, 2), "ct_out") for o in outs])
     _check("hks_batch_rotate_seeded", lib().hks_batch_rotate_seeded(ctx.handle, n, ca, level, ga, sa, ka, oa,
                                                                     _stream(stream)))
 
@@ -416,17 +498,19 @@ def hks_batch_mult_relin_seeded(ctx, ct1s, ct2s, level: int, seeds, rlk_bs, resc
     n = len(ct1s)
     if len(ct2s) != n or len(seeds) != n or len(rlk_bs) != n or len(outs) != n:
         raise ValueError("ct1s, ct2s, seeds, rlk_bs and outs must have the same length")
-    a1 = (_vp * n)(*[_ptr(c) for c in ct1s])
-    a2 = (_vp * n)(*[_ptr(c) for c in ct2s])
+    a1 = (_vp * n)(*[_ptr(c, _w_poly(ctx, level, 2), "ct1") for c in ct1s])
+    a2 = (_vp * n)(*[_ptr(c, _w_poly(ctx, level, 2), "ct2") for c in ct2s])
     sa = (ctypes.c_uint64 * n)(*[int(x) for x in seeds])
-    ka = (_vp * n)(*[_ptr(k) for k in rlk_bs])
-    oa = (_vp * n)(*[_ptr(o) for o in outs])
+    ka = (_vp * n)(*[_ptr(k, _w_key_rows(ctx), "rlk_b") for k in rlk_bs])
+    oa = (_vp * n)(*[_ptr(o, _w_out(ctx, level, 1 if rescale else 0), "ct_out") for o in outs])
     _check("hks_batch_mult_relin_seeded", lib().hks_batch_mult_relin_seeded(ctx.handle, n, a1, a2, level, sa, ka,
                                                                             1 if rescale else 0, oa, _stream(stream)))
 
 
 def hks_new_mult(ctx, ct1, ct2, level: int, rlk, ct_out, stream=None):
-    _check("hks_new_mult", lib().hks_new_mult(ctx.handle, _ptr(ct1), _ptr(ct2), level, _ptr(rlk), _ptr(ct_out),
+    _check("hks_new_mult", lib().hks_new_mult(ctx.handle, _ptr(ct1, _w_poly(ctx, level, 2), "ct1"),
+                                              _ptr(ct2, _w_poly(ctx, level, 2), "ct2"), level,
+                                              _ptr(rlk, _w_key(ctx), "rlk"), _ptr(ct_out, _w_out(ctx, level, 1), "ct_out"),
                                               _stream(stream)))
 
 
@@ -438,8 +522,9 @@ def hks_encode(ctx, slots, scale: float, level: int, with_p: bool, pt_out, strea
         raise ValueError("slots must be a contiguous complex128/float64 device tensor")
     if slots.numel() != ctx.n:
         raise ValueError("expected N/2 complex slots")
+    w = _w_ext(ctx, level) if with_p else _w_poly(ctx, level)
     _check("hks_encode", lib().hks_encode(ctx.handle, ctypes.c_void_p(slots.data_ptr()), float(scale), level,
-                                          1 if with_p else 0, _ptr(pt_out), _stream(stream)))
+                                          1 if with_p else 0, _ptr(pt_out, w, "pt_out"), _stream(stream)))
 
 
 def hks_set_check(ctx, on: bool):
@@ -502,12 +587,17 @@ def hks_graph_end(stream) -> Graph:
 
 
 def hks_add(ctx, x, y, level: int, n_poly: int, out, stream=None):
-    _check("hks_add", lib().hks_add(ctx.handle, _ptr(x), _ptr(y), level, n_poly, _ptr(out), _stream(stream)))
+    w = _w_poly(ctx, level, int(n_poly)) if 1 <= int(n_poly) <= 3 else None
+    _check("hks_add", lib().hks_add(ctx.handle, _ptr(x, w, "x"), _ptr(y, w, "y"), level, n_poly, _ptr(out, w, "out"),
+                                    _stream(stream)))
 
 
 def hks_mult_relin(ctx, ct1, ct2, level: int, rlk, rescale: bool, ct_out, stream=None):
-    _check("hks_mult_relin", lib().hks_mult_relin(ctx.handle, _ptr(ct1), _ptr(ct2), level, _ptr(rlk),
-                                                  1 if rescale else 0, _ptr(ct_out), _stream(stream)))
+    _check("hks_mult_relin", lib().hks_mult_relin(ctx.handle, _ptr(ct1, _w_poly(ctx, level, 2), "ct1"),
+                                                  _ptr(ct2, _w_poly(ctx, level, 2), "ct2"), level,
+                                                  _ptr(rlk, _w_key(ctx), "rlk"), 1 if rescale else 0,
+                                                  _ptr(ct_out, _w_out(ctx, level, 1 if rescale else 0), "ct_out"),
+                                                  _stream(stream)))
 
 
 def hks_prof_enable(ctx, mask: int):
@@ -564,27 +654,31 @@ class Context32:
             pass
 
 
-def _ptr32(t: torch.Tensor):
+def _ptr32(t: torch.Tensor, words: int = None, what: str = "tensor"):
     if not isinstance(t, torch.Tensor):
         raise TypeError("expected a torch tensor")
     if t.dtype not in (torch.int32, torch.uint32):
         raise TypeError(f"expected 32-bit integer tensor, got {t.dtype}")
-    if not t.is_cuda or not t.is_contiguous():
+    _need(t, words, what)
+    if not _on_device(t) or not t.is_contiguous():
         raise ValueError("tensor must be a contiguous GPU tensor")
     return ctypes.c_void_p(t.data_ptr())
 
 
 def hks32_ntt(ctx, x, first_mod: int, n_limbs: int, stream=None):
-    _check("hks32_ntt", lib().hks32_ntt(ctx.handle, _ptr32(x), first_mod, n_limbs, _stream(stream)))
+    _check("hks32_ntt", lib().hks32_ntt(ctx.handle, _ptr32(x, _w_limbs(ctx, first_mod, n_limbs), "x"), first_mod,
+                                        n_limbs, _stream(stream)))
 
 
 def hks32_intt(ctx, x, first_mod: int, n_limbs: int, stream=None):
-    _check("hks32_intt", lib().hks32_intt(ctx.handle, _ptr32(x), first_mod, n_limbs, _stream(stream)))
+    _check("hks32_intt", lib().hks32_intt(ctx.handle, _ptr32(x, _w_limbs(ctx, first_mod, n_limbs), "x"), first_mod,
+                                          n_limbs, _stream(stream)))
 
 
 def hks32_rotate(ctx, ct, level: int, galois: int, ksk, ct_out, stream=None):
-    _check("hks32_rotate", lib().hks32_rotate(ctx.handle, _ptr32(ct), level, galois, _ptr32(ksk), _ptr32(ct_out),
-                                              _stream(stream)))
+    _check("hks32_rotate", lib().hks32_rotate(ctx.handle, _ptr32(ct, _w_poly(ctx, level, 2), "ct"), level, galois,
+                                              _ptr32(ksk, _w_key(ctx), "ksk"),
+                                              _ptr32(ct_out, _w_poly(ctx, level, 2), "ct_out"), _stream(stream)))
 
 
 def hks32_hrotate(ctx, ct, level: int, galois, ksks, outs, stream=None):
@@ -592,9 +686,10 @@ def hks32_hrotate(ctx, ct, level: int, galois, ksks, outs, stream=None):
     if len(ksks) != r or len(outs) != r:
         raise ValueError("galois, ksks and outs must have the same length")
     ga = (_u32 * r)(*[int(g) for g in galois])
-    ka = (_vp * r)(*[_ptr32(k) for k in ksks])
-    oa = (_vp * r)(*[_ptr32(o) for o in outs])
-    _check("hks32_hrotate", lib().hks32_hrotate(ctx.handle, _ptr32(ct), level, r, ga, ka, oa, _stream(stream)))
+    ka = (_vp * r)(*[_ptr32(k, _w_key(ctx), "ksk") for k in ksks])
+    oa = (_vp * r)(*[_ptr32(o, _w_poly(ctx, level, 2), "ct_out") for o in outs])
+    _check("hks32_hrotate", lib().hks32_hrotate(ctx.handle, _ptr32(ct, _w_poly(ctx, level, 2), "ct"), level, r, ga,
+                                                ka, oa, _stream(stream)))
 
 
 def to_device32(a, device="cuda") -> torch.Tensor:

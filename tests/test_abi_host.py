@@ -126,3 +126,97 @@ def test_create32_rejects_invalid_parameters(hks):
     assert lib.hks32_rotate(None, None, 1, 5, None, None, None) == EINVAL
     assert lib.hks32_ntt(None, None, 0, 1, None) == EINVAL
     lib.hks32_destroy(None)
+
+
+def test_binding_rejects_undersized_tensors(hks, monkeypatch):
+    """The binding checks every tensor against the words the C call touches
+    (computed from N, L, K, dnum and the level) before a pointer is formed,
+    so a short tensor never reaches a kernel.  Runs on the CPU with the
+    library replaced by a stub that records the calls (the tensors' device
+    check is lifted for the test, and no pointer reaches C code)."""
+    import types
+
+    import torch
+    calls = []
+
+    class StubLib:
+        def __getattr__(self, name):
+            def f(*args):
+                calls.append(name)
+                return hks.HKS_OK
+            return f
+
+    monkeypatch.setattr(hks, "lib", lambda: StubLib())
+    monkeypatch.setattr(hks, "_on_device", lambda t: True)
+    monkeypatch.setattr(hks, "_stream", lambda s: ctypes.c_void_p(0))
+    ctx = types.SimpleNamespace(n=1024, L=6, K=2, dnum=3, handle=None)
+    n, L, K, dnum = ctx.n, ctx.L, ctx.K, ctx.dnum
+    M = L + K
+
+    def t(words):
+        return torch.zeros(words, dtype=torch.int64)
+
+    def short(fn):
+        with pytest.raises(hks.HksSizeError):
+            fn()
+
+    def sized(fn):  # right size: the call goes through
+        n_calls = len(calls)
+        fn()
+        assert len(calls) == n_calls + 1
+
+    key, keyb = dnum * 2 * M * n, dnum * M * n
+    for level in (6, 5, 3, 1):
+        ct = 2 * level * n
+        beta = -(-level // 2)
+        for good, call in (
+            (True, lambda k, c, o: hks.hks_rotate(ctx, t(c), level, 5, t(k), t(o))),
+            (True, lambda k, c, o: hks.hks_rotate_seeded(ctx, t(c), level, 5, 1, t(k // 2), t(o))),
+            (True, lambda k, c, o: hks.hks_batch_rotate(ctx, [t(c)], level, [5], [t(k)], [t(o)])),
+            (True, lambda k, c, o: hks.hks_hrotate(ctx, t(c), level, [5, 25], [t(key), t(k)], [t(ct), t(o)])),
+            (True, lambda k, c, o: hks.hks_keyswitch(ctx, t(c // 2), level, t(k), t(o))),
+            (True, lambda k, c, o: hks.hks_mult_relin(ctx, t(c), t(ct), level, t(k), False, t(o))),
+        ):
+            sized(lambda: call(key, ct, ct))
+            short(lambda: call(key - 1, ct, ct))
+            short(lambda: call(key, ct - 1, ct))
+            short(lambda: call(key, ct, ct - 1))
+        # key built for another K or dnum
+        short(lambda: hks.hks_rotate(ctx, t(ct), level, 5, t(2 * 2 * M * n), t(ct)))
+        short(lambda: hks.hks_rotate(ctx, t(ct), level, 5, t(dnum * 2 * (L + 1) * n), t(ct)))
+        # the extended digits and the P limbs
+        sized(lambda: hks.hks_modup(ctx, t(level * n), level, t(beta * (level + K) * n)))
+        short(lambda: hks.hks_modup(ctx, t(level * n), level, t(beta * (level + K) * n - 1)))
+        sized(lambda: hks.hks_moddown(ctx, t((level + K) * n), level, t(level * n)))
+        short(lambda: hks.hks_moddown(ctx, t(level * n), level, t(level * n)))
+        sized(lambda: hks.hks_ksk_inner(ctx, t(beta * (level + K) * n), level, t(key), t(2 * (level + K) * n)))
+        short(lambda: hks.hks_ksk_inner(ctx, t(beta * (level + K) * n), level, t(key), t(2 * level * n)))
+        sized(lambda: hks.hks_ptmatvec(ctx, t(ct), level, [5], [t(key)], [t((level + K) * n)], t(ct)))
+        short(lambda: hks.hks_ptmatvec(ctx, t(ct), level, [5], [t(key)], [t(level * n)], t(ct)))
+        if level >= 2:
+            # outputs one limb shorter after a Rescale, and no shorter
+            sized(lambda: hks.hks_rescale(ctx, t(ct), level, t(2 * (level - 1) * n)))
+            short(lambda: hks.hks_rescale(ctx, t(ct), level, t(2 * (level - 1) * n - 1)))
+            sized(lambda: hks.hks_new_mult(ctx, t(ct), t(ct), level, t(key), t(2 * (level - 1) * n)))
+            short(lambda: hks.hks_new_mult(ctx, t(ct), t(ct), level, t(key), t(2 * (level - 1) * n - 1)))
+            short(lambda: hks.hks_ptmult(ctx, t(ct), t(level * n), level, False, t(2 * (level - 1) * n)))
+            sized(lambda: hks.hks_ptmult(ctx, t(ct), t(level * n), level, True, t(2 * (level - 1) * n)))
+            short(lambda: hks.hks_batch_mult_relin(ctx, [t(ct)], [t(ct)], level, [t(key)], True,
+                                                   [t(2 * (level - 1) * n - 1)]))
+            short(lambda: hks.hks_batch_mult_relin_seeded(ctx, [t(ct)], [t(ct)], level, [3], [t(keyb - 1)], True,
+                                                          [t(2 * (level - 1) * n)]))
+    short(lambda: hks.hks_ntt(ctx, t(3 * n - 1), 2, 3))
+    sized(lambda: hks.hks_ntt(ctx, t(3 * n), 2, 3))
+    short(lambda: hks.hks_intt(ctx, t(n), 0, 2))
+    short(lambda: hks.hks_automorph(ctx, t(2 * n), t(2 * n - 1), 0, 2, 5))
+    short(lambda: hks.hks_expand_key_a(ctx, 1, t(keyb - 1)))
+    sized(lambda: hks.hks_expand_key_a(ctx, 1, t(keyb)))
+    short(lambda: hks.hks_add(ctx, t(3 * 4 * n), t(3 * 4 * n), 4, 3, t(2 * 4 * n)))
+    # the 32-bit path
+    t32 = lambda words: torch.zeros(words, dtype=torch.int32)  # noqa: E731
+    with pytest.raises(hks.HksSizeError):
+        hks.hks32_rotate(ctx, t32(2 * 6 * n), 6, 5, t32(key - 1), t32(2 * 6 * n))
+    with pytest.raises(hks.HksSizeError):
+        hks.hks32_hrotate(ctx, t32(2 * 6 * n), 6, [5], [t32(key)], [t32(2 * 5 * n)])
+    with pytest.raises(hks.HksSizeError):
+        hks.hks32_ntt(ctx, t32(n - 1), 0, 1)
