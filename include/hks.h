@@ -57,6 +57,7 @@ extern "C" {
 #define HKS_EHIP (-3)         /* a HIP runtime call or kernel launch failed */
 #define HKS_EUNSUPPORTED (-4) /* valid request outside what this build supports */
 #define HKS_ERANGE (-5)       /* an input residue is not below its modulus (checks on) */
+#define HKS_ESCRATCH (-6)     /* the call needs more than the allocation-free scratch */
 
 /* hks_query keys */
 #define HKS_Q_N 1              /* ring degree N */
@@ -69,6 +70,13 @@ extern "C" {
 #define HKS_Q_K 8
 #define HKS_Q_DNUM 9
 #define HKS_Q_BATCH_CAP 10     /* ciphertexts (or rotations) per batched launch step */
+#define HKS_Q_NOALLOC_BYTES 11 /* scratch bytes hks_rotate_noalloc uses at `level` */
+#define HKS_Q_NOALLOC_MAX_BYTES 12 /* size of the allocation-free scratch */
+
+/* Size of the device array that serves as hks_rotate_noalloc's workspace
+ * (one per GPU, held from the library's first use on that GPU until the
+ * process ends). */
+#define HKS_NOALLOC_SCRATCH_BYTES (128ull << 20)
 
 typedef struct hks_ctx hks_ctx;
 
@@ -157,6 +165,24 @@ int hks_keyswitch(hks_ctx *ctx, const uint64_t *d, uint32_t level, const uint64_
  * KeySwitch(a_r, ksk); ct_out = (u, v + b_r).  ct, ct_out [2][level][N]. */
 int hks_rotate(hks_ctx *ctx, const uint64_t *ct, uint32_t level, uint32_t galois,
                const uint64_t *ksk, uint64_t *ct_out, void *stream);
+
+/* hks_rotate for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same arguments, results and bits as hks_rotate, but the call's workspace is
+ * the library's allocation-free scratch, a fixed device array of
+ * HKS_NOALLOC_SCRATCH_BYTES per GPU (128 MiB), instead of the context's
+ * workspace.  The call allocates nothing (no hipMalloc, hipFree or heap use;
+ * with the profiling hooks of hks_prof_enable off).
+ * A Rotate at `level` needs N (5 level + 2 K + beta (level + K)) words
+ * (hks_query HKS_Q_NOALLOC_BYTES): at N = 2^16, K = 8, dnum = 3 every level up
+ * to 24 fits; a larger request returns HKS_ESCRATCH with nothing enqueued.
+ * Every call on one GPU shares that GPU's scratch, whatever its context:
+ * calls that overlap in time on one GPU (other streams, other host threads,
+ * other contexts) race and give wrong results; calls on one stream are
+ * ordered and safe.  Nothing needs to start at zero: each call writes every
+ * scratch word it reads.  HKS_EUNSUPPORTED for a device index >= 64. */
+int hks_rotate_noalloc(hks_ctx *ctx, const uint64_t *ct, uint32_t level, uint32_t galois,
+                       const uint64_t *ksk, uint64_t *ct_out, void *stream);
 
 /* HRotate (Algorithm 4): ModUp of a once, then for each i < r: automorph the
  * extended digits by galois[i], KSKInnerProd with ksk[i], ModDown x2, add the

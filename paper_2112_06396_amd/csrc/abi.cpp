@@ -17,6 +17,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -102,14 +103,16 @@ void ext_chk(const Ctx &c, std::vector<Chk> &v, const uint64_t *p, uint32_t leve
 // With the context's checks on: HKS_ERANGE when a word of the items is not
 // below its modulus (nothing else is enqueued then).  The check reads the
 // result back and synchronizes the stream, so it refuses a capturing stream.
-int check_inputs(Ctx &c, hipStream_t s, const std::vector<Chk> &items) {
+int check_inputs(Ctx &c, hipStream_t s, const Chk *items, size_t n_items) {
     if (!c.check) return HKS_OK;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(s, &cs) != hipSuccess) return HKS_EHIP;
     if (cs != hipStreamCaptureStatusNone) return HKS_EUNSUPPORTED;
     if (launch_clear_flag(c.chk_flag, s) != hipSuccess) return HKS_EHIP;
-    for (const Chk &k : items)
+    for (size_t i = 0; i < n_items; ++i) {
+        const Chk &k = items[i];
         if (k.p && launch_check(c, k.p, k.reps, k.limbs, k.first_mod, c.chk_flag, s) != hipSuccess) return HKS_EHIP;
+    }
     uint32_t flag = 0;
     if (hipMemcpyAsync(&flag, c.chk_flag, sizeof(flag), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
@@ -117,13 +120,19 @@ int check_inputs(Ctx &c, hipStream_t s, const std::vector<Chk> &items) {
     return flag ? HKS_ERANGE : HKS_OK;
 }
 
-// (the item list is only built when checks are on)
-#define HKS_CHECKED(ctx, stream, ...)                                                          \
-    do {                                                                                       \
-        if ((ctx).check) {                                                                     \
-            const int _rc = check_inputs(ctx, (hipStream_t)(stream), std::vector<Chk>{__VA_ARGS__}); \
-            if (_rc) return _rc;                                                               \
-        }                                                                                      \
+int check_inputs(Ctx &c, hipStream_t s, const std::vector<Chk> &items) {
+    return check_inputs(c, s, items.data(), items.size());
+}
+
+// (the item list is built on the stack, only when checks are on)
+#define HKS_CHECKED(ctx, stream, ...)                                                             \
+    do {                                                                                          \
+        if ((ctx).check) {                                                                        \
+            const Chk _items[] = {__VA_ARGS__};                                                   \
+            const int _rc =                                                                       \
+                check_inputs(ctx, (hipStream_t)(stream), _items, sizeof(_items) / sizeof(_items[0])); \
+            if (_rc) return _rc;                                                                  \
+        }                                                                                         \
     } while (0)
 
 // ModUp of the converted limbs (Algorithm "ModUp") of nb polynomials at
@@ -307,8 +316,70 @@ const char *status_text(int s) {
         case HKS_EHIP: return "HIP runtime error";
         case HKS_EUNSUPPORTED: return "unsupported";
         case HKS_ERANGE: return "input residue not below its modulus";
+        case HKS_ESCRATCH: return "the call needs more workspace than the allocation-free scratch holds";
         default: return "unknown status";
     }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- allocation-free scratch
+// The workspace of hks_rotate_noalloc: a file-scope device array, one copy
+// on each GPU the library runs on, held until the process ends.  In host
+// code `scratch` names a host-side stand-in, not device memory: its device
+// address is looked up once per device (hipGetSymbolAddress with that device
+// current, at hks_create) and only that address is handed to kernels.
+static __device__ __align__(256) uint64_t scratch[HKS_NOALLOC_SCRATCH_BYTES / sizeof(uint64_t)];
+
+namespace {
+
+constexpr int SCRATCH_DEVICES = 64;
+std::mutex scratch_mu;
+uint64_t *scratch_dev[SCRATCH_DEVICES];  // device address of `scratch` per device
+
+// With `device` current: look up (once) the device address of its copy of
+// the scratch array.  Devices beyond the table get none (the entry point
+// then reports HKS_EUNSUPPORTED).
+int scratch_init(int device) {
+    if (device < 0 || device >= SCRATCH_DEVICES) return HKS_OK;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (scratch_dev[device]) return HKS_OK;
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return HKS_EHIP;
+    scratch_dev[device] = static_cast<uint64_t *>(ptr);
+    return HKS_OK;
+}
+
+uint64_t *scratch_of(int device) {
+    if (device < 0 || device >= SCRATCH_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    return scratch_dev[device];
+}
+
+// Words of scratch one Rotate at `level` uses: the coefficient-form input
+// (level limbs), the extended digits [beta][level + K], KSKInnerProd's q
+// limbs of u and v [2][level], the special limbs of u and v [2][K] and
+// ModDown's corrections [2][level].
+size_t noalloc_words(const Ctx &c, uint32_t level) {
+    const size_t N = c.n, beta = beta_of(c, level), E = level + c.K;
+    return N * ((size_t)level + beta * E + 2 * (size_t)level + 2 * (size_t)c.K + 2 * (size_t)level);
+}
+
+// The workspace view of one Rotate at `level` carved from the scratch array.
+Ws noalloc_ws(const Ctx &c, uint64_t *base, uint32_t level) {
+    const size_t N = c.n, beta = beta_of(c, level), E = level + c.K;
+    Ws w{};
+    w.st_y = (size_t)level * N;
+    w.st_ext = beta * E * N;
+    w.st_uv = 2 * (size_t)level * N;
+    w.st_p = 2 * (size_t)c.K * N;
+    w.st_z = (size_t)level * N;  // per polynomial; u's and v's corrections
+    w.y = base;
+    w.ext = w.y + w.st_y;
+    w.uv = w.ext + w.st_ext;
+    w.p = w.uv + w.st_uv;
+    w.z = w.p + w.st_p;
+    return w;
 }
 
 }  // namespace
@@ -373,6 +444,7 @@ int hks_create(const hks_params *p, int device, hks_ctx **out) {
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return HKS_EHIP;
     if (hipSetDevice(device) != hipSuccess) return HKS_EHIP;
+    if (scratch_init(device) != HKS_OK) return HKS_EHIP;
     hks_ctx *h = new hks_ctx();
     Ctx &c = h->c;
     c.device = device;
@@ -455,6 +527,11 @@ int hks_query(const hks_ctx *h, int key, uint32_t level, uint64_t *out) {
         case HKS_Q_K: *out = c.K; return HKS_OK;
         case HKS_Q_DNUM: *out = c.dnum; return HKS_OK;
         case HKS_Q_BATCH_CAP: *out = c.batch_cap; return HKS_OK;
+        case HKS_Q_NOALLOC_BYTES:
+            if (level < 1 || level > c.L) return HKS_EINVAL;
+            *out = noalloc_words(c, level) * sizeof(uint64_t);
+            return HKS_OK;
+        case HKS_Q_NOALLOC_MAX_BYTES: *out = HKS_NOALLOC_SCRATCH_BYTES; return HKS_OK;
         default: return HKS_EINVAL;
     }
 }
@@ -580,6 +657,23 @@ int hks_rotate(hks_ctx *h, const uint64_t *ct, uint32_t level, uint32_t galois, 
     // through the automorph to v
     const KsJob job{ct, galois, ksk, ct_out, nullptr, ct + (size_t)level * c.n};
     return do_keyswitch_jobs(c, &job, 1, level, (hipStream_t)stream);
+    GUARD_END
+}
+
+int hks_rotate_noalloc(hks_ctx *h, const uint64_t *ct, uint32_t level, uint32_t galois, const uint64_t *ksk,
+                       uint64_t *ct_out, void *stream) {
+    GUARD_BEGIN
+    if (!h || !ct || !ksk || !ct_out || !aligned(ct) || !aligned(ksk) || !aligned(ct_out) || level < 1 ||
+        level > h->c.L || ct == ct_out)
+        return HKS_EINVAL;
+    Ctx &c = h->c;
+    if (!valid_galois(c, galois)) return HKS_EINVAL;
+    if (noalloc_words(c, level) * sizeof(uint64_t) > HKS_NOALLOC_SCRATCH_BYTES) return HKS_ESCRATCH;
+    uint64_t *base = scratch_of(c.device);
+    if (!base) return HKS_EUNSUPPORTED;
+    HKS_CHECKED(c, stream, ct_chk(ct, 2, level), key_chk(c, ksk));
+    const KsJob job{ct, galois, ksk, ct_out, nullptr, ct + (size_t)level * c.n};
+    return do_keyswitch_step(c, noalloc_ws(c, base, level), &job, 1, level, (hipStream_t)stream);
     GUARD_END
 }
 

@@ -26,6 +26,7 @@ HKS_ENOMEM = -2
 HKS_EHIP = -3
 HKS_EUNSUPPORTED = -4
 HKS_ERANGE = -5
+HKS_ESCRATCH = -6
 
 HKS_Q_N = 1
 HKS_Q_ALPHA = 2
@@ -37,12 +38,16 @@ HKS_Q_L = 7
 HKS_Q_K = 8
 HKS_Q_DNUM = 9
 HKS_Q_BATCH_CAP = 10
+HKS_Q_NOALLOC_BYTES = 11
+HKS_Q_NOALLOC_MAX_BYTES = 12
+HKS_NOALLOC_SCRATCH_BYTES = 128 << 20  # the allocation-free scratch (include/hks.h)
 
 # every symbol declared in include/hks.h
 EXPORTS = (
     "hks_gen_primes", "hks_galois_for_rotation", "hks_galois_conjugate", "hks_strerror",
     "hks_create", "hks_destroy", "hks_query", "hks_ntt", "hks_intt", "hks_automorph",
-    "hks_modup", "hks_ksk_inner", "hks_moddown", "hks_keyswitch", "hks_rotate", "hks_hrotate",
+    "hks_modup", "hks_ksk_inner", "hks_moddown", "hks_keyswitch", "hks_rotate", "hks_rotate_noalloc",
+    "hks_hrotate",
     "hks_batch_rotate", "hks_rescale", "hks_ptmult", "hks_mult_relin", "hks_batch_mult_relin", "hks_new_mult",
     "hks_encode", "hks_add",
     "hks_expand_key_a", "hks_rotate_seeded", "hks_batch_rotate_seeded", "hks_batch_mult_relin_seeded",
@@ -145,6 +150,7 @@ def lib():
             "hks_moddown": (_i32, [_vp, _vp, _u32, _vp, _vp]),
             "hks_keyswitch": (_i32, [_vp, _vp, _u32, _vp, _vp, _vp]),
             "hks_rotate": (_i32, [_vp, _vp, _u32, _u32, _vp, _vp, _vp]),
+            "hks_rotate_noalloc": (_i32, [_vp, _vp, _u32, _u32, _vp, _vp, _vp]),
             "hks_hrotate": (_i32, [_vp, _vp, _u32, _u32, ctypes.POINTER(_u32), ctypes.POINTER(_vp),
                                    ctypes.POINTER(_vp), _vp]),
             "hks_batch_rotate": (_i32, [_vp, _u32, ctypes.POINTER(_vp), _u32, ctypes.POINTER(_u32),
@@ -409,6 +415,13 @@ def hks_rotate(ctx, ct, level: int, galois: int, ksk, ct_out, stream=None):
     _check("hks_rotate", lib().hks_rotate(ctx.handle, _ptr(ct, _w_poly(ctx, level, 2), "ct"), level, galois,
                                           _ptr(ksk, _w_key(ctx), "ksk"), _ptr(ct_out, _w_poly(ctx, level, 2), "ct_out"),
                                           _stream(stream)))
+
+
+def hks_rotate_noalloc(ctx, ct, level: int, galois: int, ksk, ct_out, stream=None):
+    _check("hks_rotate_noalloc",
+           lib().hks_rotate_noalloc(ctx.handle, _ptr(ct, _w_poly(ctx, level, 2), "ct"), level, galois,
+                                    _ptr(ksk, _w_key(ctx), "ksk"), _ptr(ct_out, _w_poly(ctx, level, 2), "ct_out"),
+                                    _stream(stream)))
 
 
 def hks_hrotate(ctx, ct, level: int, galois, ksks, outs, stream=None):
