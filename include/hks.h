@@ -173,9 +173,9 @@ int hks_rotate(hks_ctx *ctx, const uint64_t *ct, uint32_t level, uint32_t galois
  * HKS_NOALLOC_SCRATCH_BYTES per GPU (128 MiB), instead of the context's
  * workspace.  The call allocates nothing (no hipMalloc, hipFree or heap use;
  * with the profiling hooks of hks_prof_enable off).
- * A Rotate at `level` needs N (5 level + 2 K + beta (level + K)) words
- * (hks_query HKS_Q_NOALLOC_BYTES): at N = 2^16, K = 8, dnum = 3 every level up
- * to 24 fits; a larger request returns HKS_ESCRATCH with nothing enqueued.
+ * A Rotate at `level` needs N (5 level + 2 K + beta (L + K)) words
+ * (hks_query HKS_Q_NOALLOC_BYTES): at N = 2^16, L = 24, K = 8, dnum = 3 every
+ * level fits; a larger request returns HKS_ESCRATCH with nothing enqueued.
  * Every call on one GPU shares that GPU's scratch, whatever its context:
  * calls that overlap in time on one GPU (other streams, other host threads,
  * other contexts) race and give wrong results; calls on one stream are
@@ -220,7 +220,30 @@ int hks_batch_rotate(hks_ctx *ctx, uint32_t n_ct, const uint64_t *const *ct, uin
                      const uint32_t *galois, const uint64_t *const *ksk, uint64_t *const *ct_out,
                      void *stream);
 
-/* ---------------------------------------------------------------- seeded keys
+/* Rotate of n_ct ciphertexts at levels of uneven limb count, levels[i] for
+ * ciphertext i (1..L), in shared launches: one launch sequence serves up to
+ * max_batch ciphertexts whatever their levels (the batching of a
+ * bootstrapping trace's descending levels, Sec. 3, and of a serving mix).
+ * Same bits as hks_rotate on each ciphertext at its level.  ct[i] is
+ * [2][levels[i]][N], ct_out[i] likewise.  seeds NULL: ksk[i] are full keys;
+ * else ksk[i] holds the rows b_j of the seeded key seeds[i] (as in
+ * hks_rotate_seeded).  ct, levels, galois, seeds, ksk, ct_out are HOST
+ * arrays of n_ct entries.  HKS_EINVAL if an output equals any input or
+ * another output, or a level is outside [1, L]. */
+int hks_batch_rotate_mixed(hks_ctx *ctx, uint32_t n_ct, const uint64_t *const *ct, const uint32_t *levels,
+                           const uint32_t *galois, const uint64_t *seeds, const uint64_t *const *ksk,
+                           uint64_t *const *ct_out, void *stream);
+
+/* Mult + relinearization (Algorithm 2) of n pairs at levels of uneven limb
+ * count, pair i at levels[i], in shared launches; same bits as
+ * hks_mult_relin per pair.  ct1[i], ct2[i] are [2][levels[i]][N]; ct_out[i]
+ * is [2][levels[i] - 1][N] with rescale (levels[i] >= 2), else
+ * [2][levels[i]][N].  seeds as in hks_batch_rotate_mixed. */
+int hks_batch_mult_relin_mixed(hks_ctx *ctx, uint32_t n, const uint64_t *const *ct1, const uint64_t *const *ct2,
+                               const uint32_t *levels, const uint64_t *seeds, const uint64_t *const *rlk,
+                               int rescale, uint64_t *const *ct_out, void *stream);
+
+/* ---------------------------------------------------------------- seeded keys/* ---------------------------------------------------------------- seeded keys
  * Key compression (Sec. 5.3): a seeded switching key stores only its rows b_j,
  * ksk_b [dnum][L+K][N]; the uniform rows a_j are regenerated on the device
  * from a 64-bit seed.  Entry (j, kappa, i) of a_j, for key limb kappa and
@@ -285,6 +308,14 @@ int hks_batch_mult_relin(hks_ctx *ctx, uint32_t n, const uint64_t *const *ct1, c
  * HKS_EUNSUPPORTED when K + 1 > 16. */
 int hks_new_mult(hks_ctx *ctx, const uint64_t *ct1, const uint64_t *ct2, uint32_t level, const uint64_t *rlk,
                  uint64_t *ct_out, void *stream);
+
+/* NewMult of n pairs at one level in shared launches (up to max_batch pairs
+ * per step); same bits as hks_new_mult per pair.  ct1, ct2, rlk, ct_out are
+ * HOST arrays of n entries (device pointers); ct_out[i] is
+ * [2][level - 1][N].  HKS_EINVAL if an output equals any input or another
+ * output. */
+int hks_batch_new_mult(hks_ctx *ctx, uint32_t n, const uint64_t *const *ct1, const uint64_t *const *ct2,
+                       uint32_t level, const uint64_t *const *rlk, uint64_t *const *ct_out, void *stream);
 
 /* Encode (the CKKS canonical embedding, Sec. 2.1; the plaintexts of the
  * factored DFT's diagonals in bootstrapping, Sec. 3).  slots: DEVICE array of

@@ -46,10 +46,10 @@ uint32_t ext_mod(const Ctx &c, uint32_t level, uint32_t t) { return t < level ? 
 struct Lists {
     static constexpr size_t CAP = 4096;
     uint16_t io[CAP], oo[CAP], ci[CAP];
-    uint8_t md[CAP], ns[CAP];
+    uint8_t md[CAP], dg[CAP];
     size_t size = 0;
     bool overflow = false;
-    void add(uint32_t in_off, uint32_t out_off, uint32_t mod, uint32_t cidx, uint32_t nsrc = 0) {
+    void add(uint32_t in_off, uint32_t out_off, uint32_t mod, uint32_t cidx, uint32_t digit = NO_DIGIT) {
         if (size == CAP) {
             overflow = true;
             return;
@@ -58,7 +58,7 @@ struct Lists {
         oo[size] = (uint16_t)out_off;
         md[size] = (uint8_t)mod;
         ci[size] = (uint16_t)cidx;
-        ns[size] = (uint8_t)nsrc;
+        dg[size] = (uint8_t)digit;
         ++size;
     }
     template <typename F>
@@ -74,7 +74,7 @@ struct Lists {
                 m.out_off[i] = oo[s + i];
                 m.mod[i] = md[s + i];
                 m.cidx[i] = ci[s + i];
-                m.nsrc[i] = ns[s + i];
+                m.dig[i] = dg[s + i];
             }
             hipError_t e = fn(m);
             if (e != hipSuccess) return e;
@@ -136,38 +136,66 @@ int check_inputs(Ctx &c, hipStream_t s, const std::vector<Chk> &items) {
     } while (0)
 
 // ModUp of the converted limbs (Algorithm "ModUp") of nb polynomials at
-// once; entry b uses workspace slot b:
+// once, polynomial b at level levels[b]; entry b uses workspace slot b:
 //   iNTT of the level limbs of a[b] (gathered through the automorph
 //   galois[b]), scaled by N^-1 [(Qt_j/q_i)^-1]_{q_i} -> ws_y (coefficient form);
 //   NewLimb of every digit into every other limb of Q_level U P ->
-//   ext + b*ext_bstride, [j][t];
+//   ext + b*ext_bstride, packed [j][t] (all levels equal) or key-indexed
+//   [j][kappa] (keyidx; see launch_conv_modup);
 //   forward NTT of those limbs in place (own-digit slots untouched): both
 //   passes, or with cols_only just the column pass (the key-switch kernel
 //   runs the row pass on chip).
-int do_modup_new(Ctx &c, const Ws &w, const uint64_t *const *a, const uint32_t *galois, uint32_t nb,
-                 uint32_t level, uint64_t *ext, size_t ext_bstride, hipStream_t s, bool cols_only) {
-    const uint32_t A = c.alpha, E = level + c.K, beta = beta_of(c, level);
+int do_modup_new(Ctx &c, const Ws &w, const uint64_t *const *a, const uint32_t *galois, const uint32_t *levels,
+                 uint32_t nb, uint64_t *ext, size_t ext_bstride, bool keyidx, hipStream_t s, bool cols_only) {
+    const uint32_t A = c.alpha;
+    uint32_t top = 0;
+    bool uneven = false;
+    for (uint32_t b = 0; b < nb; ++b) {
+        top = std::max(top, levels[b]);
+        uneven = uneven || levels[b] != levels[0];
+    }
+    if (uneven && !keyidx) return HKS_EINVAL;  // the packed layout is per level
+    const uint32_t E = top + c.K, beta = beta_of(c, top);
     Lists inv, nl;
-    for (uint32_t i = 0; i < level; ++i) inv.add(i, i, i, level * c.L + i);
+    // the folded scales of ModUp's iNTT are per level, at level * L + i
+    // (entries at uneven levels add their own offset)
+    for (uint32_t i = 0; i < top; ++i) inv.add(i, i, i, uneven ? i : top * c.L + i);
     BatchIo io{};
     for (uint32_t b = 0; b < nb; ++b) {
         io.in[b] = a[b];
         io.out[b] = w.y + b * w.st_y;
         io.galois[b] = galois[b];
         io.add_galois[b] = 1;
+        if (uneven) {
+            io.lvl[b] = (uint8_t)levels[b];
+            io.cbase[b] = (uint16_t)(levels[b] * c.L);
+        }
     }
     HKS_TRY(inv.run([&](const LimbMap &m) { return launch_ntt_inv(c, m, io, c.li_modup, nb, s); }));
-    HKS_TRY(launch_conv_modup(c, w.y, level, ext, nb, w.st_y, ext_bstride, s));
+    HKS_TRY(launch_conv_modup(c, w.y, levels, ext, nb, w.st_y, ext_bstride, keyidx, s));
     for (uint32_t j = 0; j < beta; ++j) {
-        const uint32_t lo = j * A, hi = std::min((j + 1) * A, level);
-        for (uint32_t t = 0; t < E; ++t)
-            if (t < lo || t >= hi) nl.add(j * E + t, j * E + t, ext_mod(c, level, t), 0);
+        const uint32_t lo = j * A, hi = (j + 1) * A;
+        for (uint32_t t = 0; t < E; ++t) {
+            const uint32_t mod = ext_mod(c, top, t);
+            if (mod < c.L && mod >= lo && mod < hi) continue;  // the digit's own limbs
+            const uint32_t slot = keyidx ? j * (c.L + c.K) + mod : j * E + t;
+            nl.add(slot, slot, mod, 0, j);
+        }
     }
-    const BatchIo eio = strided_io(ext, ext_bstride, ext, ext_bstride, nb);
+    BatchIo eio = strided_io(ext, ext_bstride, ext, ext_bstride, nb);
+    for (uint32_t b = 0; b < nb && uneven; ++b) {
+        eio.lvl[b] = (uint8_t)levels[b];
+        eio.nbeta[b] = (uint8_t)beta_of(c, levels[b]);
+    }
     HKS_TRY(nl.run([&](const LimbMap &m) {
         return cols_only ? launch_ntt_fwd_cols(c, m, eio, nb, s) : launch_ntt_fwd(c, m, eio, nb, s);
     }));
     return HKS_OK;
+}
+
+int do_modup_new(Ctx &c, const Ws &w, const uint64_t *a, uint32_t level, uint64_t *ext, hipStream_t s) {
+    const uint32_t one = 1;
+    return do_modup_new(c, w, &a, &one, &level, 1, ext, 0, false, s, false);
 }
 
 // The digits' own limbs of ext, copied (automorph `galois` applied) from `a`.
@@ -201,29 +229,43 @@ ModDownSpec spec_newmult(const Ctx &c, uint32_t level) {
 
 // ModDown of np polynomials whose special limbs went through the inverse row
 // pass into ws_p (polynomial p at ws_p + p*ns*N): inverse column pass scaled
-// by N^-1 [(S/s)^-1]_s; NewLimb into the `level` output q limbs (ws_z +
-// p*L*N); forward column pass; row pass + (u - z) S^-1 (+ add), with u, the
+// by N^-1 [(S/s)^-1]_s; NewLimb into the levels[p] output q limbs (ws_z +
+// p*st_z); forward column pass; row pass + (u - z) S^-1 (+ add), with u, the
 // output, the addend and its automorph per polynomial in `epi`.
-int do_moddown_tail(Ctx &c, const Ws &w, uint32_t level, uint32_t np, BatchIo epi, hipStream_t s,
+int do_moddown_tail(Ctx &c, const Ws &w, const uint32_t *levels, uint32_t np, BatchIo epi, hipStream_t s,
                     const ModDownSpec &sp) {
     const uint32_t N = c.n, K = c.K, L = c.L;
     const size_t pst = (size_t)sp.ns * N, zst = w.st_z;
+    uint32_t top = 0;
+    bool uneven = false;
+    for (uint32_t p = 0; p < np; ++p) {
+        top = std::max(top, levels[p]);
+        uneven = uneven || levels[p] != levels[0];
+    }
     Lists pl, ql;
     for (uint32_t k = 0; k < K; ++k) pl.add(k, k, L + k, k);
     if (sp.ns > K) pl.add(K, K, sp.extra_mod, K);
-    for (uint32_t i = 0; i < level; ++i) ql.add(i, i, i, i);
+    for (uint32_t i = 0; i < top; ++i) ql.add(i, i, i, i);
     const BatchIo pio = strided_io(w.p, pst, w.p, pst, np);
     HKS_TRY(pl.run([&](const LimbMap &m) { return launch_ntt_inv_cols(c, m, pio, sp.li, np, s); }));
-    HKS_TRY(launch_conv_moddown(c, w.p, level, w.z, np, pst, zst, sp.conv, sp.ns, s));
-    const BatchIo zio = strided_io(w.z, zst, w.z, zst, np);
+    HKS_TRY(launch_conv_moddown(c, w.p, levels, w.z, np, pst, zst, sp.conv, sp.ns, s));
+    BatchIo zio = strided_io(w.z, zst, w.z, zst, np);
+    for (uint32_t p = 0; p < np; ++p) {
+        if (uneven) {
+            zio.lvl[p] = (uint8_t)levels[p];
+            epi.lvl[p] = (uint8_t)levels[p];
+        }
+        epi.in[p] = w.z + p * zst;
+    }
     HKS_TRY(ql.run([&](const LimbMap &m) { return launch_ntt_fwd_cols(c, m, zio, np, s); }));
-    for (uint32_t p = 0; p < np; ++p) epi.in[p] = w.z + p * zst;
     HKS_TRY(ql.run([&](const LimbMap &m) { return launch_rows_mdepi(c, m, epi, np, sp.sinv, s); }));
     return HKS_OK;
 }
 
 int do_moddown_tail(Ctx &c, uint32_t level, uint32_t np, BatchIo epi, hipStream_t s) {
-    return do_moddown_tail(c, ctx_ws(c), level, np, epi, s, spec_by_p(c));
+    uint32_t levels[MAXB];
+    for (uint32_t p = 0; p < np && p < (uint32_t)MAXB; ++p) levels[p] = level;
+    return do_moddown_tail(c, ctx_ws(c), levels, np, epi, s, spec_by_p(c));
 }
 
 // One key-switch of a batch: d (level limbs, gathered through galois) with
@@ -235,6 +277,7 @@ struct KsJob {
     const uint64_t *ksk;  // full key [dnum][2][L+K][N], or the rows b_j [dnum][L+K][N] of a seeded key
     uint64_t *out;
     const uint64_t *add0, *add1;
+    uint32_t level = 0;
     uint64_t seed = 0;
     bool seeded = false;
     const uint64_t *newmult_bc = nullptr;  // NewMult: b3, c3 ([2][level][N]); out at level - 1
@@ -243,49 +286,52 @@ struct KsJob {
 // KeySwitch of nb <= min(batch_cap, MAXCT) jobs in shared launches (9 per
 // step); the digits' own limbs are read from d in the KSKInnerProd kernel
 // (never copied), which also runs the last forward pass of ModUp's NTT.
-int do_keyswitch_step(Ctx &c, const Ws &w, const KsJob *jobs, uint32_t nb, uint32_t level, hipStream_t s) {
-    const size_t pl = (size_t)level * c.n;
+// Jobs may sit at different levels (NewMult jobs share one): every launch
+// covers the step's largest Q_level U P, and the extended digits are held
+// key-indexed so that their slots do not depend on the level.
+int do_keyswitch_step(Ctx &c, const Ws &w, const KsJob *jobs, uint32_t nb, hipStream_t s) {
     const uint64_t *d[MAXCT];
-    uint32_t g[MAXCT];
+    uint32_t g[MAXCT], lv[MAXCT], out_lv[2 * MAXCT];
     KskBatch kb{};
     BatchIo epi{};
     // one kind per step (the entry points never mix them)
     const bool nm = jobs[0].newmult_bc != nullptr;
-    const uint32_t out_level = nm ? level - 1 : level;
     for (uint32_t b = 0; b < nb; ++b) {
+        const uint32_t level = jobs[b].level;
+        if (level < 1 || level > c.L || (nm && level != jobs[0].level)) return HKS_EINVAL;
+        const uint32_t out_level = nm ? level - 1 : level;
         d[b] = jobs[b].d;
         g[b] = jobs[b].galois;
+        lv[b] = level;
         kb.direct[b] = jobs[b].d;
         kb.ksk[b] = jobs[b].ksk;
         kb.addp[b] = jobs[b].newmult_bc;
         kb.seed[b] = jobs[b].seed;
         kb.galois[b] = jobs[b].galois;
+        kb.level[b] = level;
         kb.seeded = jobs[b].seeded ? 1u : 0u;
         kb.newmult = nm ? 1u : 0u;
         for (uint32_t poly = 0; poly < 2; ++poly) {
             const uint32_t p = 2 * b + poly;
-            epi.uq[p] = w.uv + b * w.st_uv + poly * pl;
+            epi.uq[p] = w.uv + b * w.st_uv + poly * (size_t)level * c.n;
             epi.out[p] = jobs[b].out + poly * (size_t)out_level * c.n;
             epi.add[p] = poly ? jobs[b].add1 : jobs[b].add0;
             epi.add_galois[p] = jobs[b].galois;
+            out_lv[p] = out_level;
         }
     }
-    int rc = do_modup_new(c, w, d, g, nb, level, w.ext, w.st_ext, s, true);
+    int rc = do_modup_new(c, w, d, g, lv, nb, w.ext, w.st_ext, true, s, true);
     if (rc) return rc;
-    const ModDownSpec sp = nm ? spec_newmult(c, level) : spec_by_p(c);
-    HKS_TRY(launch_ksk_rows(c, kb, nb, w.ext, w.st_ext, true, 0, 0, level, w.uv, w.st_uv, w.p,
+    const ModDownSpec sp = nm ? spec_newmult(c, jobs[0].level) : spec_by_p(c);
+    HKS_TRY(launch_ksk_rows(c, kb, nb, w.ext, w.st_ext, true, true, 0, 0, w.uv, w.st_uv, w.p,
                             (size_t)2 * sp.ns * c.n, s));
-    return do_moddown_tail(c, w, out_level, 2 * nb, epi, s, sp);
+    return do_moddown_tail(c, w, out_lv, 2 * nb, epi, s, sp);
 }
 
-int do_keyswitch_step(Ctx &c, const KsJob *jobs, uint32_t nb, uint32_t level, hipStream_t s) {
-    return do_keyswitch_step(c, ctx_ws(c), jobs, nb, level, s);
-}
-
-int do_keyswitch_jobs(Ctx &c, const KsJob *jobs, uint32_t n, uint32_t level, hipStream_t s) {
+int do_keyswitch_jobs(Ctx &c, const KsJob *jobs, uint32_t n, hipStream_t s) {
     const uint32_t step = std::min<uint32_t>(c.batch_cap, MAXCT);
     for (uint32_t i = 0; i < n; i += step) {
-        int rc = do_keyswitch_step(c, jobs + i, std::min(step, n - i), level, s);
+        int rc = do_keyswitch_step(c, ctx_ws(c), jobs + i, std::min(step, n - i), s);
         if (rc) return rc;
     }
     return HKS_OK;
@@ -357,20 +403,20 @@ uint64_t *scratch_of(int device) {
 }
 
 // Words of scratch one Rotate at `level` uses: the coefficient-form input
-// (level limbs), the extended digits [beta][level + K], KSKInnerProd's q
-// limbs of u and v [2][level], the special limbs of u and v [2][K] and
-// ModDown's corrections [2][level].
+// (level limbs), the extended digits [beta][L + K] (key-indexed slots),
+// KSKInnerProd's q limbs of u and v [2][level], the special limbs of u and v
+// [2][K] and ModDown's corrections [2][level].
 size_t noalloc_words(const Ctx &c, uint32_t level) {
-    const size_t N = c.n, beta = beta_of(c, level), E = level + c.K;
-    return N * ((size_t)level + beta * E + 2 * (size_t)level + 2 * (size_t)c.K + 2 * (size_t)level);
+    const size_t N = c.n, beta = beta_of(c, level), M = c.M;
+    return N * ((size_t)level + beta * M + 2 * (size_t)level + 2 * (size_t)c.K + 2 * (size_t)level);
 }
 
 // The workspace view of one Rotate at `level` carved from the scratch array.
 Ws noalloc_ws(const Ctx &c, uint64_t *base, uint32_t level) {
-    const size_t N = c.n, beta = beta_of(c, level), E = level + c.K;
+    const size_t N = c.n, beta = beta_of(c, level), M = c.M;
     Ws w{};
     w.st_y = (size_t)level * N;
-    w.st_ext = beta * E * N;
+    w.st_ext = beta * M * N;
     w.st_uv = 2 * (size_t)level * N;
     w.st_p = 2 * (size_t)c.K * N;
     w.st_z = (size_t)level * N;  // per polynomial; u's and v's corrections
@@ -585,8 +631,7 @@ int hks_modup(hks_ctx *h, const uint64_t *a, uint32_t level, uint64_t *ext, void
     if (!h || !a || !ext || !aligned(a) || !aligned(ext) || level < 1 || level > h->c.L) return HKS_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     HKS_CHECKED(h->c, s, ct_chk(a, 1, level));
-    const uint32_t one = 1;
-    int rc = do_modup_new(h->c, ctx_ws(h->c), &a, &one, 1, level, ext, 0, s, false);
+    int rc = do_modup_new(h->c, ctx_ws(h->c), a, level, ext, s);
     return rc ? rc : do_modup_own(h->c, a, level, 1, ext, s);
     GUARD_END
 }
@@ -639,8 +684,8 @@ int hks_keyswitch(hks_ctx *h, const uint64_t *d, uint32_t level, const uint64_t 
         level > h->c.L)
         return HKS_EINVAL;
     HKS_CHECKED(h->c, stream, ct_chk(d, 1, level), key_chk(h->c, ksk));
-    const KsJob job{d, 1, ksk, uv, nullptr, nullptr};
-    return do_keyswitch_jobs(h->c, &job, 1, level, (hipStream_t)stream);
+    const KsJob job{d, 1, ksk, uv, nullptr, nullptr, level};
+    return do_keyswitch_jobs(h->c, &job, 1, (hipStream_t)stream);
     GUARD_END
 }
 
@@ -655,8 +700,8 @@ int hks_rotate(hks_ctx *h, const uint64_t *ct, uint32_t level, uint32_t galois, 
     HKS_CHECKED(c, stream, ct_chk(ct, 2, level), key_chk(c, ksk));
     // (u, v + b_rot): the ModDown epilogue adds b (poly 1 of ct) gathered
     // through the automorph to v
-    const KsJob job{ct, galois, ksk, ct_out, nullptr, ct + (size_t)level * c.n};
-    return do_keyswitch_jobs(c, &job, 1, level, (hipStream_t)stream);
+    const KsJob job{ct, galois, ksk, ct_out, nullptr, ct + (size_t)level * c.n, level};
+    return do_keyswitch_jobs(c, &job, 1, (hipStream_t)stream);
     GUARD_END
 }
 
@@ -672,8 +717,8 @@ int hks_rotate_noalloc(hks_ctx *h, const uint64_t *ct, uint32_t level, uint32_t 
     uint64_t *base = scratch_of(c.device);
     if (!base) return HKS_EUNSUPPORTED;
     HKS_CHECKED(c, stream, ct_chk(ct, 2, level), key_chk(c, ksk));
-    const KsJob job{ct, galois, ksk, ct_out, nullptr, ct + (size_t)level * c.n};
-    return do_keyswitch_step(c, noalloc_ws(c, base, level), &job, 1, level, (hipStream_t)stream);
+    const KsJob job{ct, galois, ksk, ct_out, nullptr, ct + (size_t)level * c.n, level};
+    return do_keyswitch_step(c, noalloc_ws(c, base, level), &job, 1, (hipStream_t)stream);
     GUARD_END
 }
 
@@ -696,8 +741,7 @@ int hks_hrotate(hks_ctx *h, const uint64_t *ct, uint32_t level, uint32_t r, cons
     }
     const uint32_t N = c.n, E = level + c.K;
     const size_t pl = (size_t)level * N;
-    const uint32_t one = 1;
-    int rc = do_modup_new(c, ctx_ws(c), &ct, &one, 1, level, c.ws_ext, 0, s, false);
+    int rc = do_modup_new(c, ctx_ws(c), ct, level, c.ws_ext, s);
     if (!rc) rc = do_modup_own(c, ct, level, 1, c.ws_ext, s);
     if (rc) return rc;
     // rotations in steps of up to batch_cap: one KSKInnerProd launch over the
@@ -712,6 +756,7 @@ int hks_hrotate(hks_ctx *h, const uint64_t *ct, uint32_t level, uint32_t r, cons
             kb.direct[b] = c.ws_ext;
             kb.ksk[b] = ksk[i0 + b];
             kb.galois[b] = galois[i0 + b];
+            kb.level[b] = level;
             for (uint32_t poly = 0; poly < 2; ++poly) {
                 const uint32_t p = 2 * b + poly;
                 epi.uq[p] = c.ws_uv + b * c.st_uv() + poly * pl;
@@ -720,7 +765,7 @@ int hks_hrotate(hks_ctx *h, const uint64_t *ct, uint32_t level, uint32_t r, cons
                 epi.add_galois[p] = galois[i0 + b];
             }
         }
-        HKS_TRY(launch_ksk_rows(c, kb, nb, c.ws_ext, 0, false, (size_t)E * N, 1, level, c.ws_uv, c.st_uv(), c.ws_p,
+        HKS_TRY(launch_ksk_rows(c, kb, nb, c.ws_ext, 0, false, false, (size_t)E * N, 1, c.ws_uv, c.st_uv(), c.ws_p,
                                 (size_t)2 * c.K * N, s));
         rc = do_moddown_tail(c, level, 2 * nb, epi, s);
         if (rc) return rc;
@@ -742,7 +787,7 @@ int hks_batch_rotate(hks_ctx *h, uint32_t n_ct, const uint64_t *const *ct, uint3
             return HKS_EINVAL;
         for (uint32_t j = 0; j < n_ct; ++j)
             if (ct_out[i] == ct[j] || (j != i && ct_out[i] == ct_out[j])) return HKS_EINVAL;
-        jobs[i] = KsJob{ct[i], galois[i], ksk[i], ct_out[i], nullptr, ct[i] + (size_t)level * c.n};
+        jobs[i] = KsJob{ct[i], galois[i], ksk[i], ct_out[i], nullptr, ct[i] + (size_t)level * c.n, level};
     }
     if (c.check) {
         std::vector<Chk> v;
@@ -753,7 +798,37 @@ int hks_batch_rotate(hks_ctx *h, uint32_t n_ct, const uint64_t *const *ct, uint3
         const int rc = check_inputs(c, (hipStream_t)stream, v);
         if (rc) return rc;
     }
-    return do_keyswitch_jobs(c, jobs.data(), n_ct, level, (hipStream_t)stream);
+    return do_keyswitch_jobs(c, jobs.data(), n_ct, (hipStream_t)stream);
+    GUARD_END
+}
+
+int hks_batch_rotate_mixed(hks_ctx *h, uint32_t n_ct, const uint64_t *const *ct, const uint32_t *levels,
+                           const uint32_t *galois, const uint64_t *seeds, const uint64_t *const *ksk,
+                           uint64_t *const *ct_out, void *stream) {
+    GUARD_BEGIN
+    if (!h || !ct || !levels || !galois || !ksk || !ct_out || n_ct == 0) return HKS_EINVAL;
+    Ctx &c = h->c;
+    std::vector<KsJob> jobs(n_ct);
+    for (uint32_t i = 0; i < n_ct; ++i) {
+        const uint32_t level = levels[i];
+        if (level < 1 || level > c.L || !ct[i] || !ksk[i] || !ct_out[i] || !aligned(ct[i]) || !aligned(ksk[i]) ||
+            !aligned(ct_out[i]) || !valid_galois(c, galois[i]))
+            return HKS_EINVAL;
+        for (uint32_t j = 0; j < n_ct; ++j)
+            if (ct_out[i] == ct[j] || (j != i && ct_out[i] == ct_out[j])) return HKS_EINVAL;
+        jobs[i] = KsJob{ct[i], galois[i], ksk[i], ct_out[i], nullptr, ct[i] + (size_t)level * c.n, level,
+                        seeds ? seeds[i] : 0, seeds != nullptr};
+    }
+    if (c.check) {
+        std::vector<Chk> v;
+        for (uint32_t i = 0; i < n_ct; ++i) {
+            v.push_back(ct_chk(ct[i], 2, levels[i]));
+            v.push_back(seeds ? keyb_chk(c, ksk[i]) : key_chk(c, ksk[i]));
+        }
+        const int rc = check_inputs(c, (hipStream_t)stream, v);
+        if (rc) return rc;
+    }
+    return do_keyswitch_jobs(c, jobs.data(), n_ct, (hipStream_t)stream);
     GUARD_END
 }
 
@@ -783,9 +858,8 @@ int hks_ptmatvec(hks_ctx *h, const uint64_t *ct, uint32_t level, uint32_t r, con
         if (rc) return rc;
     }
     const size_t pl = (size_t)level * c.n;
-    const uint32_t one = 1;
     if (keyed) {
-        int rc = do_modup_new(c, ctx_ws(c), &ct, &one, 1, level, c.ws_ext, 0, s, false);
+        int rc = do_modup_new(c, ctx_ws(c), ct, level, c.ws_ext, s);
         if (!rc) rc = do_modup_own(c, ct, level, 1, c.ws_ext, s);
         if (rc) return rc;
     }
@@ -846,7 +920,7 @@ int hks_batch_rotate_seeded(hks_ctx *h, uint32_t n_ct, const uint64_t *const *ct
             return HKS_EINVAL;
         for (uint32_t j = 0; j < n_ct; ++j)
             if (ct_out[i] == ct[j] || (j != i && ct_out[i] == ct_out[j])) return HKS_EINVAL;
-        jobs[i] = KsJob{ct[i], galois[i], ksk_b[i], ct_out[i], nullptr, ct[i] + (size_t)level * c.n, seeds[i], true};
+        jobs[i] = KsJob{ct[i], galois[i], ksk_b[i], ct_out[i], nullptr, ct[i] + (size_t)level * c.n, level, seeds[i], true};
     }
     if (c.check) {
         std::vector<Chk> v;
@@ -857,7 +931,7 @@ int hks_batch_rotate_seeded(hks_ctx *h, uint32_t n_ct, const uint64_t *const *ct
         const int rc = check_inputs(c, (hipStream_t)stream, v);
         if (rc) return rc;
     }
-    return do_keyswitch_jobs(c, jobs.data(), n_ct, level, (hipStream_t)stream);
+    return do_keyswitch_jobs(c, jobs.data(), n_ct, (hipStream_t)stream);
     GUARD_END
 }
 
@@ -870,8 +944,8 @@ int hks_rotate_seeded(hks_ctx *h, const uint64_t *ct, uint32_t level, uint32_t g
     Ctx &c = h->c;
     if (!valid_galois(c, galois)) return HKS_EINVAL;
     HKS_CHECKED(c, stream, ct_chk(ct, 2, level), keyb_chk(c, ksk_b));
-    const KsJob job{ct, galois, ksk_b, ct_out, nullptr, ct + (size_t)level * c.n, seed, true};
-    return do_keyswitch_jobs(c, &job, 1, level, (hipStream_t)stream);
+    const KsJob job{ct, galois, ksk_b, ct_out, nullptr, ct + (size_t)level * c.n, level, seed, true};
+    return do_keyswitch_jobs(c, &job, 1, (hipStream_t)stream);
     GUARD_END
 }
 
@@ -899,31 +973,34 @@ int hks_ptmult(hks_ctx *h, const uint64_t *ct, const uint64_t *pt, uint32_t leve
     GUARD_END
 }
 
-// Mult (Algorithm 2) of n pairs at one level in steps of batch_cap: per pair
-// the tensor product into its workspace slot, then one batched key-switch of
-// the a1 a2 terms with the (b3, c3) additions, then Rescale per pair.
+// Mult (Algorithm 2) of n pairs in steps of batch_cap, pair i at level
+// levels[i] (levels null: all at `level`): per pair the tensor product into
+// its workspace slot, then one batched key-switch of the a1 a2 terms with the
+// (b3, c3) additions, then Rescale per pair.
 // (seeds non-null: rlk[i] holds only the rows b_j of seeded key seeds[i])
 int do_mult_relin(Ctx &c, uint32_t n, const uint64_t *const *ct1, const uint64_t *const *ct2, uint32_t level,
                   const uint64_t *const *rlk, int rescale, uint64_t *const *out, hipStream_t s,
-                  const uint64_t *seeds = nullptr) {
-    const size_t pl = (size_t)level * c.n;
+                  const uint64_t *seeds = nullptr, const uint32_t *levels = nullptr) {
     const uint32_t step = std::min<uint32_t>(c.batch_cap, MAXCT);
     for (uint32_t i0 = 0; i0 < n; i0 += step) {
         const uint32_t nb = std::min(step, n - i0);
         KsJob jobs[MAXCT];
         for (uint32_t b = 0; b < nb; ++b) {
+            const uint32_t lv = levels ? levels[i0 + b] : level;
+            const size_t pl = (size_t)lv * c.n;
             uint64_t *t = c.ws_t + b * c.st_t();
-            HKS_TRY(launch_tensor(c, ct1[i0 + b], ct2[i0 + b], t, level, s));
-            jobs[b] = KsJob{t, 1, rlk[i0 + b], rescale ? c.ws_rot + b * c.st_rot() : out[i0 + b], t + pl, t + 2 * pl};
+            HKS_TRY(launch_tensor(c, ct1[i0 + b], ct2[i0 + b], t, lv, s));
+            jobs[b] = KsJob{t, 1, rlk[i0 + b], rescale ? c.ws_rot + b * c.st_rot() : out[i0 + b], t + pl, t + 2 * pl,
+                            lv};
             if (seeds) {
                 jobs[b].seed = seeds[i0 + b];
                 jobs[b].seeded = true;
             }
         }
-        int rc = do_keyswitch_step(c, jobs, nb, level, s);
+        int rc = do_keyswitch_step(c, ctx_ws(c), jobs, nb, s);
         if (rc) return rc;
         for (uint32_t b = 0; b < nb && rescale; ++b) {
-            rc = do_rescale(c, c.ws_rot + b * c.st_rot(), level, out[i0 + b], s);
+            rc = do_rescale(c, c.ws_rot + b * c.st_rot(), jobs[b].level, out[i0 + b], s);
             if (rc) return rc;
         }
     }
@@ -942,10 +1019,10 @@ int do_new_mult(Ctx &c, uint32_t n, const uint64_t *const *ct1, const uint64_t *
         for (uint32_t b = 0; b < nb; ++b) {
             uint64_t *t = c.ws_t + b * c.st_t();
             HKS_TRY(launch_tensor(c, ct1[i0 + b], ct2[i0 + b], t, level, s));
-            jobs[b] = KsJob{t, 1, rlk[i0 + b], out[i0 + b], nullptr, nullptr};
+            jobs[b] = KsJob{t, 1, rlk[i0 + b], out[i0 + b], nullptr, nullptr, level};
             jobs[b].newmult_bc = t + (size_t)level * c.n;
         }
-        int rc = do_keyswitch_step(c, jobs, nb, level, s);
+        int rc = do_keyswitch_step(c, ctx_ws(c), jobs, nb, s);
         if (rc) return rc;
     }
     return HKS_OK;
@@ -960,6 +1037,32 @@ int hks_new_mult(hks_ctx *h, const uint64_t *ct1, const uint64_t *ct2, uint32_t 
     if (h->c.K + 1 > 16) return HKS_EUNSUPPORTED;
     HKS_CHECKED(h->c, stream, ct_chk(ct1, 2, level), ct_chk(ct2, 2, level), key_chk(h->c, rlk));
     return do_new_mult(h->c, 1, &ct1, &ct2, level, &rlk, &ct_out, (hipStream_t)stream);
+    GUARD_END
+}
+
+int hks_batch_new_mult(hks_ctx *h, uint32_t n, const uint64_t *const *ct1, const uint64_t *const *ct2,
+                       uint32_t level, const uint64_t *const *rlk, uint64_t *const *ct_out, void *stream) {
+    GUARD_BEGIN
+    if (!h || !ct1 || !ct2 || !rlk || !ct_out || n == 0 || level < 2 || level > h->c.L) return HKS_EINVAL;
+    if (h->c.K + 1 > 16) return HKS_EUNSUPPORTED;
+    for (uint32_t i = 0; i < n; ++i) {
+        if (!ct1[i] || !ct2[i] || !rlk[i] || !ct_out[i] || !aligned(ct1[i]) || !aligned(ct2[i]) ||
+            !aligned(rlk[i]) || !aligned(ct_out[i]))
+            return HKS_EINVAL;
+        for (uint32_t j = 0; j < n; ++j)
+            if (ct_out[i] == ct1[j] || ct_out[i] == ct2[j] || (j != i && ct_out[i] == ct_out[j])) return HKS_EINVAL;
+    }
+    if (h->c.check) {
+        std::vector<Chk> v;
+        for (uint32_t i = 0; i < n; ++i) {
+            v.push_back(ct_chk(ct1[i], 2, level));
+            v.push_back(ct_chk(ct2[i], 2, level));
+            v.push_back(key_chk(h->c, rlk[i]));
+        }
+        const int rc = check_inputs(h->c, (hipStream_t)stream, v);
+        if (rc) return rc;
+    }
+    return do_new_mult(h->c, n, ct1, ct2, level, rlk, ct_out, (hipStream_t)stream);
     GUARD_END
 }
 
@@ -1026,6 +1129,33 @@ int hks_batch_mult_relin_seeded(hks_ctx *h, uint32_t n, const uint64_t *const *c
         if (rc) return rc;
     }
     return do_mult_relin(h->c, n, ct1, ct2, level, rlk_b, rescale, ct_out, (hipStream_t)stream, seeds);
+    GUARD_END
+}
+
+int hks_batch_mult_relin_mixed(hks_ctx *h, uint32_t n, const uint64_t *const *ct1, const uint64_t *const *ct2,
+                               const uint32_t *levels, const uint64_t *seeds, const uint64_t *const *rlk,
+                               int rescale, uint64_t *const *ct_out, void *stream) {
+    GUARD_BEGIN
+    if (!h || !ct1 || !ct2 || !levels || !rlk || !ct_out || n == 0) return HKS_EINVAL;
+    Ctx &c = h->c;
+    for (uint32_t i = 0; i < n; ++i) {
+        if (levels[i] < (rescale ? 2u : 1u) || levels[i] > c.L || !ct1[i] || !ct2[i] || !rlk[i] || !ct_out[i] ||
+            !aligned(ct1[i]) || !aligned(ct2[i]) || !aligned(rlk[i]) || !aligned(ct_out[i]))
+            return HKS_EINVAL;
+        for (uint32_t j = 0; j < n; ++j)
+            if (ct_out[i] == ct1[j] || ct_out[i] == ct2[j] || (j != i && ct_out[i] == ct_out[j])) return HKS_EINVAL;
+    }
+    if (c.check) {
+        std::vector<Chk> v;
+        for (uint32_t i = 0; i < n; ++i) {
+            v.push_back(ct_chk(ct1[i], 2, levels[i]));
+            v.push_back(ct_chk(ct2[i], 2, levels[i]));
+            v.push_back(seeds ? keyb_chk(c, rlk[i]) : key_chk(c, rlk[i]));
+        }
+        const int rc = check_inputs(c, (hipStream_t)stream, v);
+        if (rc) return rc;
+    }
+    return do_mult_relin(c, n, ct1, ct2, 0, rlk, rescale, ct_out, (hipStream_t)stream, seeds, levels);
     GUARD_END
 }
 

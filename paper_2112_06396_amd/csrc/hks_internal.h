@@ -12,21 +12,23 @@
 
 namespace hks {
 
-constexpr int MAXL = 160;  // limbs per launch descriptor
+constexpr int MAXL = 128;  // limbs per launch descriptor
 constexpr int MAXB = 32;   // batch entries (polynomials) per launch
 constexpr int MAXCT = 16;  // ciphertexts per batched key-switch step (two polynomials each)
 constexpr int MAXROT = 64; // rotations of one PtMatVecMult launch
 
 // A list of limbs for one launch.  Limb i is read at in_base + in_off[i]*N
 // (+ blockIdx.y * in_bstride for batches), written at out_base + out_off[i]*N,
-// reduced by modulus mod[i], and uses constant-table entry cidx[i].
+// reduced by modulus mod[i], and uses constant-table entry cidx[i]; dig[i] is
+// the digit a limb of extended digits belongs to (NO_DIGIT otherwise).
+constexpr uint8_t NO_DIGIT = 0xFF;
 struct LimbMap {
     uint32_t count;
     uint16_t in_off[MAXL];
     uint16_t out_off[MAXL];
     uint8_t mod[MAXL];
-    uint8_t nsrc[MAXL];  // conversion: number of source limbs
     uint16_t cidx[MAXL];
+    uint8_t dig[MAXL];
 };
 
 // Per batch entry b of a pass launch: where its limbs are read and written.
@@ -34,6 +36,9 @@ struct LimbMap {
 // out[b] + out_off[i]*N.  IO_GATHER reads through the automorph galois[b];
 // the ModDown epilogue reads u at uq[b] + cidx[i]*N and adds add[b] +
 // cidx[i]*N gathered through add_galois[b] (add[b] null: nothing added).
+// Entries of one launch may sit at different levels: entry b skips the limbs
+// of q primes at or above lvl[b] and the limbs of digits at or above nbeta[b]
+// (0: no limit), and reads the folded constants at cidx[i] + cbase[b].
 struct BatchIo {
     const uint64_t *in[MAXB];
     uint64_t *out[MAXB];
@@ -41,6 +46,9 @@ struct BatchIo {
     const uint64_t *add[MAXB];
     uint32_t galois[MAXB];
     uint32_t add_galois[MAXB];
+    uint8_t lvl[MAXB];
+    uint8_t nbeta[MAXB];
+    uint16_t cbase[MAXB];
 };
 
 // Entries at fixed strides from two bases (workspace buffers).
@@ -207,23 +215,28 @@ hipError_t launch_ntt_inv_cols(const Ctx &c, const LimbMap &m, const BatchIo &io
 hipError_t launch_rows_mdepi(const Ctx &c, const LimbMap &m, const BatchIo &io, uint32_t batch, const Shoup *pinv,
                              hipStream_t s);
 // NewLimb of every digit of the coefficient-form y [level][N] into the other
-// limbs of Q_level U P: ext[j][t] (coefficient form, canonical) for t outside
-// digit j; `batch` polynomials at strides y_bstride / ext_bstride.
-hipError_t launch_conv_modup(const Ctx &c, const uint64_t *y, uint32_t level, uint64_t *ext, uint32_t batch,
-                             size_t y_bstride, size_t ext_bstride, hipStream_t s);
+// limbs of Q_level U P (coefficient form, canonical) for t outside digit j,
+// for `batch` polynomials at strides y_bstride / ext_bstride, polynomial b at
+// level levels[b].  Layout of the extended digits: packed, [beta][level + K]
+// with limb t of digit j at j (level + K) + t; or key-indexed (keyidx),
+// [beta][L + K] with the limb of modulus kappa (q_i: i, p_k: L + k) at
+// j (L + K) + kappa, the same for every level.
+hipError_t launch_conv_modup(const Ctx &c, const uint64_t *y, const uint32_t *levels, uint64_t *ext,
+                             uint32_t batch, size_t y_bstride, size_t ext_bstride, bool keyidx, hipStream_t s);
 // NewLimb of ModDown: the ns coefficient-form special limbs p [ns][N] (scaled
-// by [(S/s)^-1]) into the nt q limbs z [nt][N] with constants table [nt][ns]
-// of [S/s]_{q_i}, for `batch` polynomials.
-hipError_t launch_conv_moddown(const Ctx &c, const uint64_t *p, uint32_t nt, uint64_t *z, uint32_t batch,
+// by [(S/s)^-1]) into the nt[b] q limbs z [nt[b]][N] with constants table
+// [nt][ns] of [S/s]_{q_i}, for `batch` polynomials.
+hipError_t launch_conv_moddown(const Ctx &c, const uint64_t *p, const uint32_t *nt, uint64_t *z, uint32_t batch,
                                size_t p_bstride, size_t z_bstride, const uint64_t *table, uint32_t ns,
                                hipStream_t s);
 // KSKInnerProd of `nb` ciphertexts per target limb and row tile (+ ModDown's
-// inverse row pass for the P limbs).  Entry b: converted limb t of digit j
-// at ext + b*ext_bstride + (j*E + t)*N, after the forward column pass only
-// (rowpass: the kernel runs the row pass) or in evaluation form; digit j's
-// own limb (all digits if all_direct) at direct[b] + j*dstride + t*N,
-// gathered through galois[b]; key ksk[b]; q limbs to uq + b*uq_bstride
-// ([2][level][N]), P limbs to pc + b*pc_bstride ([2][K][N]).
+// inverse row pass for the P limbs).  Entry b is at level level[b]: its
+// converted limb t of digit j at ext + b*ext_bstride + (j*E + t)*N (packed,
+// E = level[b] + K) or at (j*(L+K) + kappa(t))*N (keyidx), after the forward
+// column pass only (rowpass: the kernel runs the row pass) or in evaluation
+// form; digit j's own limb (all digits if all_direct) at direct[b] +
+// j*dstride + t*N, gathered through galois[b]; key ksk[b]; q limbs to uq +
+// b*uq_bstride ([2][level[b]][N]), P limbs to pc + b*pc_bstride ([2][K][N]).
 // With `seeded`, ksk[b] holds only the rows b_j ([dnum][L+K][N]) and the
 // rows a_j are regenerated from seed[b] (Philox4x32-10, see seeded_key_a).
 // With `newmult` (NewMult): P b3 and P c3 (b3 at addp[b], c3 at addp[b] +
@@ -235,11 +248,12 @@ struct KskBatch {
     const uint64_t *addp[MAXCT];
     uint64_t seed[MAXCT];
     uint32_t galois[MAXCT];
+    uint32_t level[MAXCT];
     uint32_t seeded;
     uint32_t newmult;
 };
 hipError_t launch_ksk_rows(const Ctx &c, const KskBatch &kb, uint32_t nb, const uint64_t *ext, size_t ext_bstride,
-                           bool rowpass, size_t dstride, uint32_t all_direct, uint32_t level, uint64_t *uq,
+                           bool rowpass, bool keyidx, size_t dstride, uint32_t all_direct, uint64_t *uq,
                            size_t uq_bstride, uint64_t *pc, size_t pc_bstride, hipStream_t s);
 // (the special limbs of one polynomial in pc: K, or K + 1 with newmult)
 // PtMatVecMult sums over Q_level U P (ModUp'd digits of a in ext, evaluation

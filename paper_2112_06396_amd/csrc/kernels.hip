@@ -57,21 +57,27 @@ struct ConvArgs {
     const uint64_t *conv;  // split constants
     const ModC *mc;
     size_t in_bstride, out_bstride;
-    uint32_t n, level, L, K, alpha, tgroups;
+    uint32_t n, L, K, alpha, tgroups, keyidx;
+    uint32_t level0, coff0;  // every entry's level and constants offset (uniform launches)
+    uint32_t coff[MAXB];     // mixed: entry b's constants at conv + coff[b] (its level's table)
+    uint8_t lvl[MAXB];       // mixed: entry b's level (MODUP) or number of q targets (ModDown)
 };
 
 // Fast basis conversion (NewLimb, Algorithm "ModUp"; also ModDown's step).
 // One thread = one coefficient of one digit: its n_src source residues are
 // loaded once (split into 25-bit halves) and every target limb of the digit
 // is produced from them (the alpha limbs stay on chip for all new limbs).
-//   MODUP:   digit j = blockIdx.y / tgroups, sources y[j*alpha .. +n_src),
-//            targets t of Q_level U P outside the digit, out[j*E + t],
-//            constants row j*E+t;
-//   ModDown: sources the K P limbs, targets the level q limbs, out[t],
+//   MODUP:   entry b at level lvl[b]; digit j = blockIdx.y / tgroups, sources
+//            y[j*alpha .. +n_src), targets t of Q_level U P outside the
+//            digit, written at j*E + t (packed, E = level + K) or at
+//            j*(L + K) + kappa(t) (keyidx), constants row j*E+t of the
+//            entry's level;
+//   ModDown: sources the K P limbs, targets the lvl[b] q limbs, out[t],
 //            constants row t.
 // blockIdx.y % tgroups picks a group of consecutive targets (more blocks for
-// a small launch; the groups re-read the sources from L2).
-template <bool MODUP, int MAXS>
+// a small launch; the groups re-read the sources from L2).  The grid covers
+// the launch's largest entry; blocks past an entry's digits leave.
+template <bool MODUP, int MAXS, bool MIXED>
 __global__ void __launch_bounds__(256) conv_kernel(const ConvArgs a) {
     constexpr int MAXT = 80;  // targets of one digit: level + K <= 64
     __shared__ uint64_t kc[MAXT * MAXS];
@@ -79,19 +85,22 @@ __global__ void __launch_bounds__(256) conv_kernel(const ConvArgs a) {
     const uint32_t N = 1u << a.n;
     const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t j = blockIdx.y / a.tgroups, grp = blockIdx.y % a.tgroups, b = blockIdx.z;
+    const uint32_t level = MIXED ? a.lvl[b] : a.level0;
     const uint32_t lo = MODUP ? j * a.alpha : 0;
-    const uint32_t ns = MODUP ? min(a.alpha, a.level - lo) : a.K;
-    const uint32_t E = a.level + a.K;
-    const uint32_t nt = MODUP ? E : a.level;
+    if (MODUP && lo >= level) return;  // the entry has fewer digits
+    const uint32_t ns = MODUP ? min(a.alpha, level - lo) : a.K;
+    const uint32_t E = level + a.K;
+    const uint32_t nt = MODUP ? E : level;
     const uint32_t cstride = MODUP ? a.alpha : a.K;
+    const uint32_t ds = a.keyidx ? a.L + a.K : E, pbase = a.keyidx ? a.L : level;
     // the digit's constant rows and target moduli, staged once per block
-    const uint64_t *rows = a.conv + (size_t)(MODUP ? j * E : 0) * cstride;
+    const uint64_t *rows = a.conv + (MODUP ? (MIXED ? a.coff[b] : a.coff0) : 0) + (size_t)(MODUP ? j * E : 0) * cstride;
     for (uint32_t i = threadIdx.x; i < nt * MAXS; i += blockDim.x) {
         const uint32_t t = i / MAXS, s = i % MAXS;
         kc[i] = (s < ns) ? rows[(size_t)t * cstride + s] : 0;
     }
     for (uint32_t t = threadIdx.x; t < nt; t += blockDim.x) {
-        const uint32_t mod = MODUP ? (t < a.level ? t : a.L + (t - a.level)) : t;
+        const uint32_t mod = MODUP ? (t < level ? t : a.L + (t - level)) : t;
         mt[t] = a.mc[mod];
     }
     const uint64_t *src = a.in + b * a.in_bstride + (size_t)lo * N + c;
@@ -113,7 +122,8 @@ __global__ void __launch_bounds__(256) conv_kernel(const ConvArgs a) {
         Mac25 acc;
 #pragma unroll
         for (int i = 0; i < MAXS; ++i) acc.mac(y0[i], y1[i], kr[i]);
-        dst[(size_t)(MODUP ? j * E + t : t) * N] = acc.reduce(m.q, m.mu, m.nq);
+        const uint32_t slot = MODUP ? j * ds + (t < level ? t : pbase + (t - level)) : t;
+        dst[(size_t)slot * N] = acc.reduce(m.q, m.mu, m.nq);
     }
 }
 
@@ -124,41 +134,59 @@ static uint32_t conv_groups(const Ctx &c, uint32_t nt, uint32_t batch) {
     return batch <= c.plan.conv_group_max_batch ? std::max<uint32_t>(1, nt / c.plan.conv_group_limbs) : 1;
 }
 
-template <bool MODUP>
-static hipError_t launch_conv_t(const ConvArgs &a, uint32_t ns_max, dim3 grid, hipStream_t s) {
-    if (ns_max <= 4) hipLaunchKernelGGL((conv_kernel<MODUP, 4>), grid, dim3(256), 0, s, a);
-    else if (ns_max <= 8) hipLaunchKernelGGL((conv_kernel<MODUP, 8>), grid, dim3(256), 0, s, a);
-    else if (ns_max <= 12) hipLaunchKernelGGL((conv_kernel<MODUP, 12>), grid, dim3(256), 0, s, a);
-    else if (ns_max <= 16) hipLaunchKernelGGL((conv_kernel<MODUP, 16>), grid, dim3(256), 0, s, a);
+template <bool MODUP, bool MIXED>
+static hipError_t launch_conv_m(const ConvArgs &a, uint32_t ns_max, dim3 grid, hipStream_t s) {
+    if (ns_max <= 4) hipLaunchKernelGGL((conv_kernel<MODUP, 4, MIXED>), grid, dim3(256), 0, s, a);
+    else if (ns_max <= 8) hipLaunchKernelGGL((conv_kernel<MODUP, 8, MIXED>), grid, dim3(256), 0, s, a);
+    else if (ns_max <= 12) hipLaunchKernelGGL((conv_kernel<MODUP, 12, MIXED>), grid, dim3(256), 0, s, a);
+    else if (ns_max <= 16) hipLaunchKernelGGL((conv_kernel<MODUP, 16, MIXED>), grid, dim3(256), 0, s, a);
     else return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
-hipError_t launch_conv_modup(const Ctx &c, const uint64_t *y, uint32_t level, uint64_t *ext, uint32_t batch,
-                             size_t y_bstride, size_t ext_bstride, hipStream_t s) {
+template <bool MODUP>
+static hipError_t launch_conv_t(const ConvArgs &a, bool mixed, uint32_t ns_max, dim3 grid, hipStream_t s) {
+    return mixed ? launch_conv_m<MODUP, true>(a, ns_max, grid, s) : launch_conv_m<MODUP, false>(a, ns_max, grid, s);
+}
+
+hipError_t launch_conv_modup(const Ctx &c, const uint64_t *y, const uint32_t *levels, uint64_t *ext,
+                             uint32_t batch, size_t y_bstride, size_t ext_bstride, bool keyidx, hipStream_t s) {
     if (batch == 0) return hipSuccess;
+    if (batch > (uint32_t)MAXB) return hipErrorInvalidValue;
     ConvArgs a{};
     a.in = y;
     a.out = ext;
     a.in_bstride = y_bstride;
     a.out_bstride = ext_bstride;
-    a.conv = c.conv_modup + c.conv_modup_off[level];
+    a.conv = c.conv_modup;
     a.mc = c.mc;
     a.n = c.log_n;
-    a.level = level;
     a.L = c.L;
     a.K = c.K;
     a.alpha = c.alpha;
-    const uint32_t beta = (level + c.alpha - 1) / c.alpha;
-    a.tgroups = conv_groups(c, level + c.K, batch);
+    a.keyidx = keyidx ? 1u : 0u;
+    uint32_t top = 0;
+    bool mixed = false;
+    for (uint32_t b = 0; b < batch; ++b) {
+        if (levels[b] < 1 || levels[b] > c.L) return hipErrorInvalidValue;
+        a.lvl[b] = (uint8_t)levels[b];
+        a.coff[b] = (uint32_t)c.conv_modup_off[levels[b]];
+        top = std::max(top, levels[b]);
+        mixed = mixed || levels[b] != levels[0];
+    }
+    a.level0 = levels[0];
+    a.coff0 = a.coff[0];
+    const uint32_t beta = (top + c.alpha - 1) / c.alpha;
+    a.tgroups = conv_groups(c, top + c.K, batch);
     ProfScope ps(c, HKS_K_CONV, s);
-    return launch_conv_t<true>(a, c.alpha, dim3((c.n + 255) / 256, beta * a.tgroups, batch), s);
+    return launch_conv_t<true>(a, mixed, c.alpha, dim3((c.n + 255) / 256, beta * a.tgroups, batch), s);
 }
 
-hipError_t launch_conv_moddown(const Ctx &c, const uint64_t *p, uint32_t nt, uint64_t *z, uint32_t batch,
+hipError_t launch_conv_moddown(const Ctx &c, const uint64_t *p, const uint32_t *nt, uint64_t *z, uint32_t batch,
                                size_t p_bstride, size_t z_bstride, const uint64_t *table, uint32_t ns,
                                hipStream_t s) {
     if (batch == 0) return hipSuccess;
+    if (batch > (uint32_t)MAXB) return hipErrorInvalidValue;
     ConvArgs a{};
     a.in = p;
     a.out = z;
@@ -167,13 +195,21 @@ hipError_t launch_conv_moddown(const Ctx &c, const uint64_t *p, uint32_t nt, uin
     a.in_bstride = p_bstride;
     a.out_bstride = z_bstride;
     a.n = c.log_n;
-    a.level = nt;  // targets q_0..q_{nt-1}
     a.L = c.L;
     a.K = ns;      // sources: the ns special limbs
     a.alpha = c.alpha;
-    a.tgroups = conv_groups(c, nt, batch);
+    uint32_t top = 0;
+    bool mixed = false;
+    for (uint32_t b = 0; b < batch; ++b) {
+        if (nt[b] < 1 || nt[b] > c.L) return hipErrorInvalidValue;
+        a.lvl[b] = (uint8_t)nt[b];  // targets q_0..q_{nt-1}
+        top = std::max(top, nt[b]);
+        mixed = mixed || nt[b] != nt[0];
+    }
+    a.level0 = nt[0];
+    a.tgroups = conv_groups(c, top, batch);
     ProfScope ps(c, HKS_K_CONV, s);
-    return launch_conv_t<false>(a, ns, dim3((c.n + 255) / 256, a.tgroups, batch), s);
+    return launch_conv_t<false>(a, mixed, ns, dim3((c.n + 255) / 256, a.tgroups, batch), s);
 }
 
 // ------------------------------------------------------------------ input checks

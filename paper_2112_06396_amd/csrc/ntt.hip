@@ -26,6 +26,8 @@
 //             (u - z) * P^-1 (+ the automorphed b of Rotate).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "device_util.h"
 #include "hks_internal.h"
 #include "modarith.h"
@@ -318,17 +320,28 @@ struct NttArgs {
     const ModC *mc;
     const LastInv *li;    // folded last inverse stage, indexed by cidx
     const Shoup *pinv;    // IO_MDEPI: P^-1 mod q_i
-    uint32_t n, n1, n2;
+    uint32_t n, n1, n2, L;
     uint32_t nb;          // batch entries in blockIdx.x (xcd_batch) or blockIdx.y
     uint32_t xcd_batch;   // the entries of one (limb, tile) on one XCD, one after another
     LimbMap m;
     BatchIo io;
 };
 
-enum { IO_PLAIN = 0, IO_GATHER = 1, IO_REDUCE = 2, IO_MDEPI = 4 };
+enum { IO_PLAIN = 0, IO_GATHER = 1, IO_REDUCE = 2, IO_MDEPI = 4, IO_MIXED = 8 };
+
+// Whether the entries of a launch sit at different levels (per-entry limb
+// limits or constant offsets set): only then do its blocks test whether their
+// entry has their limb.
+static bool io_mixed(const BatchIo &io, uint32_t batch) {
+    for (uint32_t b = 0; b < batch && b < (uint32_t)MAXB; ++b)
+        if (io.lvl[b] || io.nbeta[b] || io.cbase[b]) return true;
+    return false;
+}
 
 template <int LOGS, int LINES, bool COLS, bool FWD, int IO, int E>
 __global__ void __launch_bounds__((Tile<LOGS, LINES, COLS, E>::NT)) ntt_pass_kernel(const NttArgs a) {
+    constexpr int IOB = IO & 7;
+    constexpr bool MIXED = (IO & IO_MIXED) != 0;
     using TL = Tile<LOGS, LINES, COLS, E>;
     using IOL = IoLayout<LOGS, FWD, E>;
     __shared__ uint64_t lds[TL::WORDS];
@@ -350,6 +363,12 @@ __global__ void __launch_bounds__((Tile<LOGS, LINES, COLS, E>::NT)) ntt_pass_ker
     const uint32_t tile = bx % tiles;
     const uint32_t N = 1u << a.n;
     const uint32_t mod = a.m.mod[li];
+    if constexpr (MIXED) {
+        // an entry below the step's top level has no limb of the q primes at
+        // or above its level, nor of the digits at or above its digit count
+        const uint32_t lv = a.io.lvl[b], nbt = a.io.nbeta[b], dg = a.m.dig[li];
+        if ((lv && mod < a.L && mod >= lv) || (nbt && dg != NO_DIGIT && dg >= nbt)) return;
+    }
     const ModC mcv = a.mc[mod];
     const uint64_t q = mcv.q;
     const uint64_t *src = a.io.in[b] + (size_t)a.m.in_off[li] * N;
@@ -364,8 +383,8 @@ __global__ void __launch_bounds__((Tile<LOGS, LINES, COLS, E>::NT)) ntt_pass_ker
     // latency covers all three instead of a second one after the pass
     uint64_t uv[E], bv[E];
     const uint32_t ui = a.m.cidx[li];
-    const uint64_t *ad = (IO == IO_MDEPI && a.io.add[b]) ? a.io.add[b] + (size_t)ui * N : nullptr;
-    if (IO == IO_MDEPI) {
+    const uint64_t *ad = (IOB == IO_MDEPI && a.io.add[b]) ? a.io.add[b] + (size_t)ui * N : nullptr;
+    if (IOB == IO_MDEPI) {
         gload<LOGS, COLS, IOL::OUT_LO, IOL::OUT_HI, E>(uv, a.io.uq[b] + (size_t)ui * N, t, lg, a.n2);
         if (ad) {
             const uint32_t ag = a.io.add_galois[b];
@@ -378,7 +397,7 @@ __global__ void __launch_bounds__((Tile<LOGS, LINES, COLS, E>::NT)) ntt_pass_ker
     }
 
     uint64_t x[E];
-    if (IO == IO_GATHER) {
+    if (IOB == IO_GATHER) {
         const uint32_t g = a.io.galois[b];
 #pragma unroll
         for (int e = 0; e < E; ++e) {
@@ -389,14 +408,14 @@ __global__ void __launch_bounds__((Tile<LOGS, LINES, COLS, E>::NT)) ntt_pass_ker
         gload<LOGS, COLS, IOL::IN_LO, IOL::IN_HI, E>(x, src, t, lg, a.n2);
     }
 
-    const LastInv fold = (!FWD && COLS) ? a.li[a.m.cidx[li]] : LastInv{};
+    const LastInv fold = (!FWD && COLS) ? a.li[a.m.cidx[li] + (MIXED ? a.io.cbase[b] : 0u)] : LastInv{};
     if constexpr (COLS) {
         pass_regs<LOGS, LINES, COLS, FWD, TW_HOIST, E>(true, x, lds, line, t, q, mcv.nq, TwCols{tw}, fold);
     } else {
         pass_regs<LOGS, LINES, COLS, FWD, TW_HOIST, E>(true, x, lds, line, t, q, mcv.nq, TwRows{tw, lg, a.n1}, fold);
     }
 
-    if (IO == IO_MDEPI) {
+    if (IOB == IO_MDEPI) {
         const Shoup pi = a.pinv[ui];
 #pragma unroll
         for (int e = 0; e < E; ++e) {
@@ -405,7 +424,7 @@ __global__ void __launch_bounds__((Tile<LOGS, LINES, COLS, E>::NT)) ntt_pass_ker
             if (ad) r = add_mod(r, bv[e], q);
             x[e] = r;
         }
-    } else if (IO == IO_REDUCE) {
+    } else if (IOB == IO_REDUCE) {
 #pragma unroll
         for (int e = 0; e < E; ++e) x[e] = reduce64(x[e], q, mcv.mu, mcv.nq);
     }
@@ -452,14 +471,26 @@ static hipError_t dispatch_pass_e(const NttArgs &a, int logs, uint32_t count, ui
 }
 
 template <bool COLS, bool FWD, int IO>
-static hipError_t dispatch_pass(const NttArgs &a, int logs, uint32_t count, uint32_t batch, hipStream_t s) {
-    if (count == 0 || batch == 0) return hipSuccess;
-    if (batch > (uint32_t)MAXB) return hipErrorInvalidValue;
+static hipError_t dispatch_pass_m(const NttArgs &a, int logs, uint32_t count, uint32_t batch, hipStream_t s) {
     const uint64_t waves16 = (uint64_t)count * batch * ((1ull << a.n) / 16) / 64;
     const int cls = FWD ? (COLS ? HKS_K_NTT_FWD_COLS : HKS_K_NTT_FWD_ROWS)
                         : (COLS ? HKS_K_NTT_INV_COLS : HKS_K_NTT_INV_ROWS);
     return waves16 >= a.ctx->plan.e16_min_waves[cls] ? dispatch_pass_e<COLS, FWD, IO, 16>(a, logs, count, batch, s)
                                                      : dispatch_pass_e<COLS, FWD, IO, 8>(a, logs, count, batch, s);
+}
+
+template <bool COLS, bool FWD, int IO>
+static hipError_t dispatch_pass(const NttArgs &a, int logs, uint32_t count, uint32_t batch, hipStream_t s) {
+    if (count == 0 || batch == 0) return hipSuccess;
+    if (batch > (uint32_t)MAXB) return hipErrorInvalidValue;
+    // the forward row pass with a reduced output serves whole transforms
+    // (never a mixed-level step)
+    if constexpr (IO != IO_REDUCE) {
+        if (io_mixed(a.io, batch)) return dispatch_pass_m<COLS, FWD, IO | IO_MIXED>(a, logs, count, batch, s);
+    } else {
+        if (io_mixed(a.io, batch)) return hipErrorInvalidValue;
+    }
+    return dispatch_pass_m<COLS, FWD, IO>(a, logs, count, batch, s);
 }
 
 static NttArgs base_args(const Ctx &c, const LimbMap &m, const BatchIo &io, bool fwd) {
@@ -472,6 +503,7 @@ static NttArgs base_args(const Ctx &c, const LimbMap &m, const BatchIo &io, bool
     a.n = c.log_n;
     a.n1 = c.n1;
     a.n2 = c.n2;
+    a.L = c.L;
     a.m = m;
     a.io = io;
     return a;
@@ -548,7 +580,8 @@ struct KskRowArgs {
     const ModC *mc;
     const Shoup *pmod;  // NewMult: [P]_{q_i}
     size_t dstride, ext_bstride, uq_bstride, pc_bstride;
-    uint32_t n, n1, n2, level, L, K, E, alpha, beta, all_direct, nb, xcd_group, pck;
+    uint32_t n, n1, n2, L, K, alpha, all_direct, keyidx, nb, xcd_group, pck;
+    uint32_t level0, uniform;  // every entry at level0 (uniform), else kb.level[b]
 };
 
 // One block = one target limb t of Q_level U P and ROW_LINES rows, in the
@@ -588,9 +621,14 @@ ksk_rows_kernel(const KskRowArgs a) {
         x = blockIdx.x / a.nb;
     }
     const uint32_t tiles = (1u << a.n1) / ROW_LINES;
+    // the entry's level (entries of one step may differ): the grid covers
+    // the step's largest Q_level U P, smaller entries leave the rest
+    const uint32_t level = a.uniform ? a.level0 : a.kb.level[b], Eb = level + a.K;
+    if (x / tiles >= Eb) return;
+    const uint32_t beta = (level + a.alpha - 1) / a.alpha;
     // special-prime limbs first: their blocks also run ModDown's inverse row
     // passes, so they go out in the first wave of blocks rather than the tail
-    const uint32_t tgt = (x / tiles + a.level) % a.E;
+    const uint32_t tgt = (x / tiles + level) % Eb;
     const uint32_t tile = x % tiles;
     const uint32_t N = 1u << a.n;
     const uint64_t *ext = a.ext + b * a.ext_bstride;
@@ -600,14 +638,17 @@ ksk_rows_kernel(const KskRowArgs a) {
     const uint32_t galois = a.kb.galois[b];
     uint64_t *uq = a.uq + b * a.uq_bstride;
     uint64_t *pc = a.pc + b * a.pc_bstride;
-    const uint32_t mod = tgt < a.level ? tgt : a.L + (tgt - a.level);
+    const uint32_t mod = tgt < level ? tgt : a.L + (tgt - level);
     const ModC mcv = a.mc[mod];
     const uint64_t q = mcv.q;
     const size_t KL = (size_t)a.L + a.K;
-    const uint32_t own = (tgt < a.level) ? tgt / a.alpha : 0xffffffffu;
+    const uint32_t own = (tgt < level) ? tgt / a.alpha : 0xffffffffu;
     // special limbs: the P limbs, and with NM also q_(level-1) (stored after them)
-    const bool is_p = tgt >= a.level || (NM && tgt == a.level - 1);
-    const uint32_t kp = tgt >= a.level ? tgt - a.level : a.K;
+    const bool is_p = tgt >= level || (NM && tgt == level - 1);
+    const uint32_t kp = tgt >= level ? tgt - level : a.K;
+    // the converted limbs of this target: packed digits of E limbs, or
+    // key-indexed digits of L + K limbs (the same slots at every level)
+    const size_t ext_ds = a.keyidx ? KL : Eb, ext_slot = a.keyidx ? mod : tgt;
     int line, t;
     thread_coords<LOGS, ROW_LINES, false, E>(threadIdx.x, line, t);
     const uint32_t lg = tile * ROW_LINES + line;
@@ -622,7 +663,7 @@ ksk_rows_kernel(const KskRowArgs a) {
 #pragma unroll
     for (int e = 0; e < E; ++e) u[e] = v[e] = 0;
     bool lds_used = false;
-    for (uint32_t jd = 0; jd < a.beta; ++jd) {
+    for (uint32_t jd = 0; jd < beta; ++jd) {
         if (LAZY && jd && (jd & 15) == 0) {
 #pragma unroll
             for (int e = 0; e < E; ++e) {
@@ -640,7 +681,7 @@ ksk_rows_kernel(const KskRowArgs a) {
                 xv[e] = src[galois != 1 ? aut_eval_src(j, galois, a.n) : j];
             }
         } else {
-            const uint64_t *src = ext + ((size_t)jd * a.E + tgt) * N;
+            const uint64_t *src = ext + (jd * ext_ds + ext_slot) * N;
             if (ROWPASS) {
                 gload<LOGS, false, IOF::IN_LO, IOF::IN_HI, E>(xv, src, t, lg, a.n2);
                 if (lds_used) __syncthreads();
@@ -693,10 +734,10 @@ ksk_rows_kernel(const KskRowArgs a) {
     }
     if constexpr (NM) {
         // NewMult: u += P b3, v += P c3 on the q limbs (PModUp)
-        if (tgt < a.level) {
+        if (tgt < level) {
             const Shoup pm = a.pmod[tgt];
             const uint64_t *b3 = a.kb.addp[b] + (size_t)tgt * N + (lg << a.n2) + E * t;
-            const uint64_t *c3 = b3 + (size_t)a.level * N;
+            const uint64_t *c3 = b3 + (size_t)level * N;
 #pragma unroll
             for (int e = 0; e < E; ++e) {
                 u[e] = add_mod(u[e], mul_shoup(b3[e], pm.w, pm.wp, q), q);
@@ -706,7 +747,7 @@ ksk_rows_kernel(const KskRowArgs a) {
     }
     if (!is_p) {
         gstore<LOGS, false, IOF::OUT_LO, IOF::OUT_HI, E>(u, uq + (size_t)tgt * N, t, lg, a.n2);
-        gstore<LOGS, false, IOF::OUT_LO, IOF::OUT_HI, E>(v, uq + ((size_t)a.level + tgt) * N, t, lg, a.n2);
+        gstore<LOGS, false, IOF::OUT_LO, IOF::OUT_HI, E>(v, uq + ((size_t)level + tgt) * N, t, lg, a.n2);
         return;
     }
     // special limb: inverse row pass (first pass of ModDown's iNTT) of u and v
@@ -742,11 +783,20 @@ static hipError_t launch_ksk_rows_t(const KskRowArgs &a, uint32_t n2, dim3 grid,
 }
 
 hipError_t launch_ksk_rows(const Ctx &c, const KskBatch &kb, uint32_t nb, const uint64_t *ext, size_t ext_bstride,
-                           bool rowpass, size_t dstride, uint32_t all_direct, uint32_t level, uint64_t *uq,
+                           bool rowpass, bool keyidx, size_t dstride, uint32_t all_direct, uint64_t *uq,
                            size_t uq_bstride, uint64_t *pc, size_t pc_bstride, hipStream_t s) {
     if (nb == 0) return hipSuccess;
     if (nb > (uint32_t)MAXCT) return hipErrorInvalidValue;
+    uint32_t top = 0;
+    bool uniform = true;
+    for (uint32_t b = 0; b < nb; ++b) {
+        if (kb.level[b] < 1 || kb.level[b] > c.L) return hipErrorInvalidValue;
+        top = std::max(top, kb.level[b]);
+        uniform = uniform && kb.level[b] == kb.level[0];
+    }
     KskRowArgs a{};
+    a.level0 = kb.level[0];
+    a.uniform = uniform ? 1u : 0u;
     a.kb = kb;
     a.ext = ext;
     a.ext_bstride = ext_bstride;
@@ -762,16 +812,15 @@ hipError_t launch_ksk_rows(const Ctx &c, const KskBatch &kb, uint32_t nb, const 
     a.n = c.log_n;
     a.n1 = c.n1;
     a.n2 = c.n2;
-    a.level = level;
     a.L = c.L;
     a.K = c.K;
-    a.E = level + c.K;
     a.alpha = c.alpha;
-    a.beta = (level + c.alpha - 1) / c.alpha;
+    a.keyidx = keyidx ? 1u : 0u;
     a.nb = nb;
     a.pmod = c.pmod;
     a.pck = kb.newmult ? c.K + 1 : c.K;
-    const uint32_t xs = ((1u << c.n1) / ROW_LINES) * a.E;
+    // (target limb, row tile) items of the step's largest entry
+    const uint32_t xs = ((1u << c.n1) / ROW_LINES) * (top + c.K);
     a.xcd_group = (nb > 1 && xs % 8 == 0 && c.plan.ksk_xcd_order) ? 1u : 0u;
     ProfScope ps(c, HKS_K_KSK, s);
     const dim3 grid(xs * nb);

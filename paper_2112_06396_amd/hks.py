@@ -48,7 +48,8 @@ EXPORTS = (
     "hks_create", "hks_destroy", "hks_query", "hks_ntt", "hks_intt", "hks_automorph",
     "hks_modup", "hks_ksk_inner", "hks_moddown", "hks_keyswitch", "hks_rotate", "hks_rotate_noalloc",
     "hks_hrotate",
-    "hks_batch_rotate", "hks_rescale", "hks_ptmult", "hks_mult_relin", "hks_batch_mult_relin", "hks_new_mult",
+    "hks_batch_rotate", "hks_batch_rotate_mixed", "hks_batch_mult_relin_mixed", "hks_rescale", "hks_ptmult", "hks_mult_relin", "hks_batch_mult_relin", "hks_new_mult",
+    "hks_batch_new_mult",
     "hks_encode", "hks_add",
     "hks_expand_key_a", "hks_rotate_seeded", "hks_batch_rotate_seeded", "hks_batch_mult_relin_seeded",
     "hks_ptmatvec", "hks_set_check",
@@ -155,12 +156,20 @@ def lib():
                                    ctypes.POINTER(_vp), _vp]),
             "hks_batch_rotate": (_i32, [_vp, _u32, ctypes.POINTER(_vp), _u32, ctypes.POINTER(_u32),
                                         ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp]),
+            "hks_batch_rotate_mixed": (_i32, [_vp, _u32, ctypes.POINTER(_vp), ctypes.POINTER(_u32),
+                                              ctypes.POINTER(_u32), u64p, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
+                                              _vp]),
+            "hks_batch_mult_relin_mixed": (_i32, [_vp, _u32, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
+                                                  ctypes.POINTER(_u32), u64p, ctypes.POINTER(_vp), _i32,
+                                                  ctypes.POINTER(_vp), _vp]),
             "hks_rescale": (_i32, [_vp, _vp, _u32, _vp, _vp]),
             "hks_ptmult": (_i32, [_vp, _vp, _vp, _u32, _i32, _vp, _vp]),
             "hks_mult_relin": (_i32, [_vp, _vp, _vp, _u32, _vp, _i32, _vp, _vp]),
             "hks_batch_mult_relin": (_i32, [_vp, _u32, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _u32,
                                             ctypes.POINTER(_vp), _i32, ctypes.POINTER(_vp), _vp]),
             "hks_new_mult": (_i32, [_vp, _vp, _vp, _u32, _vp, _vp, _vp]),
+            "hks_batch_new_mult": (_i32, [_vp, _u32, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _u32,
+                                          ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp]),
             "hks_encode": (_i32, [_vp, _vp, ctypes.c_double, _u32, _i32, _vp, _vp]),
             "hks_add": (_i32, [_vp, _vp, _vp, _u32, _u32, _vp, _vp]),
             "hks_expand_key_a": (_i32, [_vp, ctypes.c_uint64, _vp, _vp]),
@@ -468,6 +477,52 @@ def hks_batch_mult_relin(ctx, ct1s, ct2s, level: int, rlks, rescale: bool, outs,
     o = (_vp * n)(*[_ptr(x, _w_out(ctx, level, 1 if rescale else 0), "ct_out") for x in outs])
     _check("hks_batch_mult_relin", lib().hks_batch_mult_relin(ctx.handle, n, a, b, level, k, 1 if rescale else 0, o,
                                                               _stream(stream)))
+
+
+def hks_batch_new_mult(ctx, ct1s, ct2s, level: int, rlks, outs, stream=None):
+    n = len(ct1s)
+    if len(ct2s) != n or len(rlks) != n or len(outs) != n:
+        raise ValueError("ct1s, ct2s, rlks and outs must have the same length")
+    a = (_vp * n)(*[_ptr(c, _w_poly(ctx, level, 2), "ct1") for c in ct1s])
+    b = (_vp * n)(*[_ptr(c, _w_poly(ctx, level, 2), "ct2") for c in ct2s])
+    k = (_vp * n)(*[_ptr(r, _w_key(ctx), "rlk") for r in rlks])
+    o = (_vp * n)(*[_ptr(x, _w_out(ctx, level, 1), "ct_out") for x in outs])
+    _check("hks_batch_new_mult", lib().hks_batch_new_mult(ctx.handle, n, a, b, level, k, o, _stream(stream)))
+
+
+def hks_batch_rotate_mixed(ctx, cts, levels, galois, ksks, outs, seeds=None, stream=None):
+    """Rotate of ciphertexts at uneven levels in shared launches; seeds given:
+    ksks[i] holds the rows b_j of seeded key seeds[i]."""
+    n = len(cts)
+    if len(levels) != n or len(galois) != n or len(ksks) != n or len(outs) != n or (seeds is not None
+                                                                                     and len(seeds) != n):
+        raise ValueError("cts, levels, galois, ksks, outs (and seeds) must have the same length")
+    ca = (_vp * n)(*[_ptr(c, _w_poly(ctx, lv, 2), "ct") for c, lv in zip(cts, levels)])
+    la = (_u32 * n)(*[int(lv) for lv in levels])
+    ga = (_u32 * n)(*[int(g) for g in galois])
+    sa = None if seeds is None else (ctypes.c_uint64 * n)(*[int(x) for x in seeds])
+    kw = _w_key(ctx) if seeds is None else _w_key_rows(ctx)
+    ka = (_vp * n)(*[_ptr(k, kw, "ksk") for k in ksks])
+    oa = (_vp * n)(*[_ptr(o, _w_poly(ctx, lv, 2), "ct_out") for o, lv in zip(outs, levels)])
+    _check("hks_batch_rotate_mixed", lib().hks_batch_rotate_mixed(ctx.handle, n, ca, la, ga, sa, ka, oa,
+                                                                  _stream(stream)))
+
+
+def hks_batch_mult_relin_mixed(ctx, ct1s, ct2s, levels, rlks, rescale: bool, outs, seeds=None, stream=None):
+    """Mult + relinearization of pairs at uneven levels in shared launches."""
+    n = len(ct1s)
+    if len(ct2s) != n or len(levels) != n or len(rlks) != n or len(outs) != n or (seeds is not None
+                                                                                  and len(seeds) != n):
+        raise ValueError("ct1s, ct2s, levels, rlks, outs (and seeds) must have the same length")
+    a = (_vp * n)(*[_ptr(c, _w_poly(ctx, lv, 2), "ct1") for c, lv in zip(ct1s, levels)])
+    b = (_vp * n)(*[_ptr(c, _w_poly(ctx, lv, 2), "ct2") for c, lv in zip(ct2s, levels)])
+    la = (_u32 * n)(*[int(lv) for lv in levels])
+    sa = None if seeds is None else (ctypes.c_uint64 * n)(*[int(x) for x in seeds])
+    kw = _w_key(ctx) if seeds is None else _w_key_rows(ctx)
+    k = (_vp * n)(*[_ptr(r, kw, "rlk") for r in rlks])
+    o = (_vp * n)(*[_ptr(x, _w_out(ctx, lv, 1 if rescale else 0), "ct_out") for x, lv in zip(outs, levels)])
+    _check("hks_batch_mult_relin_mixed", lib().hks_batch_mult_relin_mixed(ctx.handle, n, a, b, la, sa, k,
+                                                                          1 if rescale else 0, o, _stream(stream)))
 
 
 def hks_ptmatvec(ctx, ct, level: int, galois, ksks, pts, ct_out, stream=None):

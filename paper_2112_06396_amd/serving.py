@@ -9,9 +9,10 @@ clients each holding its own rotation and relinearization keys.  The loop
     least recently used key that no in-flight step reads, and uploading
     misses from pinned host copies on the step's stream (full keys, or
     seeded keys whose rows b_j alone are stored and moved);
-  - forms a step from the queue: the oldest request's (N, level, op) group,
-    up to max_batch requests of it in arrival order, issued as one batched
-    call (hks_batch_rotate / hks_batch_mult_relin, or their seeded forms);
+  - forms a step from the queue: the oldest request's (N, op) group, up to
+    max_batch requests of it in arrival order whatever their levels, issued
+    as one batched call over uneven limb counts (hks_batch_rotate_mixed /
+    hks_batch_mult_relin_mixed, with full or seeded keys);
   - keeps up to `lanes` steps in flight, each lane with its own stream and
     contexts (workspaces), so steps of different groups overlap on the GPU;
   - records arrival, start and completion times; completion is when the
@@ -44,7 +45,9 @@ class Request:
 
     @property
     def group(self):
-        return (self.log_n, self.level, self.op)
+        # requests of one N and op share a step at any levels (one launch
+        # sequence serves uneven limb counts)
+        return (self.log_n, self.op)
 
 
 def poisson_requests(n_req: int, rate: float, n_clients: int, log_ns=(15, 16), levels=(3, 35),
@@ -197,17 +200,13 @@ class HksExecutor:
         with torch.cuda.stream(s):
             outs = [self.out_view(r) for r in batch]
             a, b = [self.in_ct(r) for r in batch], [self.in_ct(r, 1) for r in batch]
+            levels = [r.level for r in batch]
+            seeds = None if self.seeds is None else [self.seeds[k] for k in kids]
             if r0.op == "rotate":
                 gals = [hks.hks_galois_for_rotation(r.k, r.log_n) for r in batch]
-                if self.seeds is None:
-                    hks.hks_batch_rotate(ctx, a, r0.level, gals, keys, outs, s)
-                else:
-                    hks.hks_batch_rotate_seeded(ctx, a, r0.level, gals, [self.seeds[k] for k in kids], keys, outs, s)
-            elif self.seeds is None:
-                hks.hks_batch_mult_relin(ctx, a, b, r0.level, keys, True, outs, s)
+                hks.hks_batch_rotate_mixed(ctx, a, levels, gals, keys, outs, seeds=seeds, stream=s)
             else:
-                hks.hks_batch_mult_relin_seeded(ctx, a, b, r0.level, [self.seeds[k] for k in kids], keys, True,
-                                                outs, s)
+                hks.hks_batch_mult_relin_mixed(ctx, a, b, levels, keys, True, outs, seeds=seeds, stream=s)
             ev = torch.cuda.Event()
             ev.record(s)
         self.keys.hold(kids, ev)

@@ -8,7 +8,9 @@ polynomial evaluation (Sec. 3: CoeffToSlot, EvalMod, SlotToCoeff):
     every rotation by a plaintext diagonal (Algorithm 1 without Rescale),
     summing, then one Rescale; one level per stage;
   - EvalMod-like: per level, two Mult + relinearization + Rescale
-    (Algorithm 2), or two NewMult (Sec. 5.1), x' = x y and y' = x x;
+    (Algorithm 2), or two NewMult (Sec. 5.1), x' = x y and y' = x x,
+    issued as one batched call (the level's two key-switches share every
+    launch);
   - SlotToCoeff: the CoeffToSlot stages again with negated indices.
 Levels fall by one per stage or EvalMod level, so the limb count is uneven
 along the trace.  The plan is plain data; `run_plan` issues it through the
@@ -69,6 +71,8 @@ def bootstrap_plan(top: int, counts=(12, 12, 16), strides=(1, 32, 1024), evalmod
       ("rescale", src, level, dst)        -> level - 1
       ("mult", a, b, level, dst)          -> level - 1 (relinearized, rescaled)
       ("newmult", a, b, level, dst)       -> level - 1 (Sec. 5.1, one ModDown by P q_(level-1))
+      ("mults", [(a, b, dst), ...], level)    the products of one level in one batched call
+      ("newmults", [(a, b, dst), ...], level)
     With `hoisted`, each linear stage is one ptmatvec (Sec. 5.2) instead of
     an HRotate followed by PtMult and Add per rotation; with `new_mult`, the
     EvalMod products are NewMult instead of Mult + Rescale.  With
@@ -119,9 +123,7 @@ def bootstrap_plan(top: int, counts=(12, 12, 16), strides=(1, 32, 1024), evalmod
     y = x
     for _ in range(evalmod_levels):
         a, b = next(nxt), next(nxt)
-        mult = "newmult" if new_mult else "mult"
-        p.ops.append((mult, x, y, level, a))
-        p.ops.append((mult, x, x, level, b))
+        p.ops.append(("newmults" if new_mult else "mults", [(x, y, a), (x, x, b)], level))
         p.key_switches += 2
         p.buffers.update([a, b])
         x, y, level = a, b, level - 1
@@ -195,6 +197,15 @@ def run_plan(ctx, plan: Plan, bufs: TraceBuffers, diag, keys, rlk, stream=None, 
             _, a, b, level, dst = op
             hks.hks_new_mult(ctx, bufs.view(a, level), bufs.view(b, level), level, rlk, bufs.view(dst, level - 1),
                              stream)
+        elif kind in ("mults", "newmults"):
+            _, prods, level = op
+            c1 = [bufs.view(a, level) for a, _, _ in prods]
+            c2 = [bufs.view(b, level) for _, b, _ in prods]
+            outs = [bufs.view(d, level - 1) for _, _, d in prods]
+            if kind == "mults":
+                hks.hks_batch_mult_relin(ctx, c1, c2, level, [rlk] * len(prods), True, outs, stream)
+            else:
+                hks.hks_batch_new_mult(ctx, c1, c2, level, [rlk] * len(prods), outs, stream)
         else:
             raise ValueError(f"unknown op {kind}")
     return bufs.view(plan.out, plan.out_level)

@@ -438,6 +438,12 @@ def _oracle_plan(pr, plan, x0, diag, keys, rlk):
         elif kind == "newmult":
             _, a, b, level, dst = op
             bufs[dst] = O.new_mult(pr, bufs[a], bufs[b], level, rlk)
+        elif kind in ("mults", "newmults"):
+            _, prods, level = op
+            res = [O.mult_relin(pr, bufs[a], bufs[b], level, rlk, True) if kind == "mults"
+                   else O.new_mult(pr, bufs[a], bufs[b], level, rlk) for a, b, _ in prods]
+            for (_, _, d), r in zip(prods, res):
+                bufs[d] = r
     return bufs[plan.out]
 
 

@@ -1,6 +1,6 @@
 """The serving loop's scheduling on the CPU, with a simulated executor and
 clock (no GPU): every request completes once; a step only holds requests of
-one (N, level, op) group, in arrival order within the group; admission never
+one (N, op) group (at any levels), in arrival order within the group; admission never
 exceeds the output slots of an N; steps run on at most `lanes` lanes at once;
 and under load, continuous batching serves the same arrivals with lower
 latency than one request at a time."""

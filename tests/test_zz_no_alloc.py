@@ -53,6 +53,7 @@ def test_noalloc_rotate_equals_rotate_twice_in_a_row():
     with hks.Context(16, big.q, big.p, 3) as cb:
         assert hks.hks_query(cb, hks.HKS_Q_NOALLOC_MAX_BYTES) == 128 << 20
         assert hks.hks_query(cb, hks.HKS_Q_NOALLOC_BYTES, 24) == (5 * 24 + 2 * 8 + 3 * 32) * (1 << 16) * 8
+        assert hks.hks_query(cb, hks.HKS_Q_NOALLOC_BYTES, 11) == (5 * 11 + 2 * 8 + 2 * 32) * (1 << 16) * 8
         # the bench shape, then a smaller level on the same scratch
         _both(hks, cb, big, 24, 1, 31, oracle=False)
         _both(hks, cb, big, 11, -3, 32, oracle=True)
