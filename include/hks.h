@@ -380,13 +380,25 @@ typedef struct {
      * 0 orders blocks entry by entry.  Defaults 1 and 1. */
     uint32_t row_xcd_order;  /* batched NTT row passes */
     uint32_t ksk_xcd_order;  /* batched KSKInnerProd */
+    /* Tile shapes of the two-pass NTT (Sec. 2.3): N = 2^n1 x 2^n2 with the
+     * column pass over stages 0..n1-1 and the row pass over the rest.  n1:
+     * 0 = log2(N)/2 (the default), else any value with 5 <= n1 <= 9 and
+     * 5 <= log2(N) - n1 <= 9.  col_lines: columns per column-pass block (8,
+     * 16 or 32; default 16); row_lines: rows per row-pass block (4, 8 or 16;
+     * default 8); both apply to passes of 7 or more stages whose block stays
+     * within 1024 threads, the defaults elsewhere.  The key-switch kernel
+     * keeps 8 rows per block. */
+    uint32_t n1;
+    uint32_t col_lines;
+    uint32_t row_lines;
 } hks_plan;
 
 /* Copies the context's plan into *out. */
 int hks_get_plan(hks_ctx *ctx, hks_plan *out);
 /* Replaces the plan for the calls that follow (enqueued work keeps the plan
  * it was launched with).  HKS_EINVAL, plan unchanged, if conv_group_limbs is
- * 0 or above 64 or an order flag is above 1. */
+ * 0 or above 64, an order flag is above 1, n1 is outside its range, or a
+ * width is not one of its three values. */
 int hks_set_plan(hks_ctx *ctx, const hks_plan *plan);
 
 /* ---------------------------------------------------------------- graphs */

@@ -12,10 +12,12 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhks.so")
-SOURCES = ["ntt.hip", "kernels.hip", "tables.cpp", "abi.cpp", "ks32.hip", "ctx32.cpp"]
+SOURCES = ["ntt.hip", "ntt_cols.hip", "ntt_rows_fwd.hip", "ntt_rows_inv.hip", "ksk.hip", "kernels.hip", "tables.cpp",
+           "abi.cpp", "ks32.hip", "ctx32.cpp"]
 # the files that define the 64-bit kernels and their launch shapes (host
 # orchestration excluded): counter summaries are valid for one hash of them
-KERNEL_SOURCES = ["ntt.hip", "kernels.hip", "modarith.h", "device_util.h", "hks_internal.h"]
+KERNEL_SOURCES = ["ntt_device.h", "pass_shapes.h", "ntt.hip", "ntt_cols.hip", "ntt_rows_fwd.hip", "ntt_rows_inv.hip",
+                  "ksk.hip", "kernels.hip", "modarith.h", "device_util.h", "hks_internal.h"]
 
 
 def source_hash() -> str:

@@ -502,7 +502,7 @@ int hks_create(const hks_params *p, int device, hks_ctx **out) {
     c.alpha = alpha;
     c.M = p->L + p->K;
     c.batch_cap = p->max_batch ? p->max_batch : 1;
-    c.n1 = p->log_n / 2;
+    c.n1 = plan_n1(c.plan, p->log_n);
     c.n2 = p->log_n - c.n1;
     c.mods = mods;
     int rc = build_tables(c);
@@ -1233,9 +1233,14 @@ int hks_get_plan(hks_ctx *h, hks_plan *out) {
 int hks_set_plan(hks_ctx *h, const hks_plan *p) {
     GUARD_BEGIN
     if (!h || !p || p->conv_group_limbs == 0 || p->conv_group_limbs > 64 || p->row_xcd_order > 1 ||
-        p->ksk_xcd_order > 1)
+        p->ksk_xcd_order > 1 || (p->col_lines != 8 && p->col_lines != 16 && p->col_lines != 32) ||
+        (p->row_lines != 4 && p->row_lines != 8 && p->row_lines != 16))
         return HKS_EINVAL;
+    const uint32_t n1 = plan_n1(*p, h->c.log_n);
+    if (!n1) return HKS_EINVAL;
     h->c.plan = *p;
+    h->c.n1 = n1;
+    h->c.n2 = h->c.log_n - n1;
     return HKS_OK;
     GUARD_END
 }

@@ -97,7 +97,16 @@ inline hks_plan default_plan() {
     p.conv_group_max_batch = 2;
     p.row_xcd_order = 1;
     p.ksk_xcd_order = 1;
+    p.n1 = 0;
+    p.col_lines = 16;
+    p.row_lines = 8;
     return p;
+}
+
+// The NTT split a plan asks for at ring degree 2^log_n (0 if out of range).
+inline uint32_t plan_n1(const hks_plan &p, uint32_t log_n) {
+    const uint32_t n1 = p.n1 ? p.n1 : log_n / 2;
+    return (n1 >= 5 && n1 <= 9 && log_n >= n1 + 5 && log_n <= n1 + 9) ? n1 : 0;
 }
 
 struct Ctx {

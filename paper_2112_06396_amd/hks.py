@@ -103,12 +103,15 @@ class _Plan(ctypes.Structure):
         ("conv_group_max_batch", ctypes.c_uint32),
         ("row_xcd_order", ctypes.c_uint32),
         ("ksk_xcd_order", ctypes.c_uint32),
+        ("n1", ctypes.c_uint32),
+        ("col_lines", ctypes.c_uint32),
+        ("row_lines", ctypes.c_uint32),
     ]
 
 
 # hks_plan fields as a flat dict: e16_min_waves is split per NTT pass class
 PLAN_FIELDS = ("e16_fwd_cols", "e16_fwd_rows", "e16_inv_rows", "e16_inv_cols", "conv_group_limbs",
-               "conv_group_max_batch", "row_xcd_order", "ksk_xcd_order")
+               "conv_group_max_batch", "row_xcd_order", "ksk_xcd_order", "n1", "col_lines", "row_lines")
 
 
 class _Params32(ctypes.Structure):
@@ -603,7 +606,8 @@ def hks_get_plan(ctx) -> dict:
     """The context's launch plan as a flat dict (keys PLAN_FIELDS)."""
     p = _Plan()
     _check("hks_get_plan", lib().hks_get_plan(ctx.handle, ctypes.byref(p)))
-    vals = list(p.e16_min_waves) + [p.conv_group_limbs, p.conv_group_max_batch, p.row_xcd_order, p.ksk_xcd_order]
+    vals = list(p.e16_min_waves) + [p.conv_group_limbs, p.conv_group_max_batch, p.row_xcd_order, p.ksk_xcd_order,
+                                    p.n1, p.col_lines, p.row_lines]
     return dict(zip(PLAN_FIELDS, (int(v) for v in vals)))
 
 
@@ -620,6 +624,7 @@ def hks_set_plan(ctx, plan: dict):
         p.e16_min_waves[i] = cur[k]
     p.conv_group_limbs, p.conv_group_max_batch = cur["conv_group_limbs"], cur["conv_group_max_batch"]
     p.row_xcd_order, p.ksk_xcd_order = cur["row_xcd_order"], cur["ksk_xcd_order"]
+    p.n1, p.col_lines, p.row_lines = cur["n1"], cur["col_lines"], cur["row_lines"]
     _check("hks_set_plan", lib().hks_set_plan(ctx.handle, ctypes.byref(p)))
 
 

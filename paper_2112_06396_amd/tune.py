@@ -3,7 +3,9 @@
 Times a workload (a callable that enqueues library calls on one stream)
 under candidate launch plans (include/hks.h, ``hks_plan``) and keeps the
 fastest.  No plan field changes a result, so the tuner only trades launch
-shapes: elements per thread of each NTT pass class, the grouping of NewLimb's
+shapes: the NTT's tile shapes (the split N = 2^n1 x 2^n2 between the column
+and row passes, columns per column-pass block, rows per row-pass block),
+elements per thread of each NTT pass class, the grouping of NewLimb's
 target limbs, and the XCD-aware block order of batched launches.  Before a
 plan is kept, the workload's outputs under it are compared word for word
 with those under the starting plan.
@@ -44,13 +46,26 @@ CANDIDATES = {
     "conv_group_max_batch": (0, 1, 2, 4, 16),
     "row_xcd_order": (0, 1),
     "ksk_xcd_order": (0, 1),
+    "n1": (0,),  # the default split; candidates_for() adds the neighbouring ones
+    "col_lines": (8, 16, 32),
+    "row_lines": (4, 8, 16),
 }
+
+
+def candidates_for(log_n: int) -> dict:
+    """CANDIDATES with the NTT splits valid at ring degree 2^log_n: the
+    default (0 = log_n // 2) and one stage more or fewer in the column pass,
+    within 5..9 stages per pass."""
+    c = dict(CANDIDATES)
+    h = log_n // 2
+    c["n1"] = (0,) + tuple(v for v in (h - 1, h + 1) if 5 <= v <= 9 and 5 <= log_n - v <= 9)
+    return c
 
 DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "plans.json")
 
 
 def coordinate_descent(measure, start: dict, candidates=None, rounds: int = 2, min_gain: float = 0.01,
-                       log=None):
+                       log=None, verbose: bool = False):
     """Minimise measure(plan) (seconds) over the candidate values, one field
     at a time, from `start`.  Returns (best plan, its time, the time of
     `start`, the list of (plan, time) measured)."""
@@ -68,6 +83,8 @@ def coordinate_descent(measure, start: dict, candidates=None, rounds: int = 2, m
                 trial[field] = v
                 t = measure(trial)
                 trace.append((trial, t))
+                if log and verbose:
+                    log(f"[tune]   {field} = {v}: {t * 1e6:.1f} us (incumbent {t_best * 1e6:.1f})")
                 if t < t_best * (1.0 - min_gain):
                     if log:
                         log(f"[tune] {field} {best.get(field)} -> {v}: {t_best * 1e6:.1f} -> {t * 1e6:.1f} us")
@@ -140,7 +157,8 @@ def event_measure(ctx, run, stream, reps: int, trials: int = 3):
     return measure
 
 
-def tune(ctx, run, outputs, stream, reps: int, rounds: int = 2, min_gain: float = 0.01, log=None):
+def tune(ctx, run, outputs, stream, reps: int, rounds: int = 2, min_gain: float = 0.01, log=None,
+         verbose: bool = False):
     """Tunes the context's plan for `run`.  `outputs()` returns the tensors
     run(0) writes; the plan the search keeps must reproduce them exactly
     (else the starting plan stays).  Returns the entry for the cache."""
@@ -151,7 +169,8 @@ def tune(ctx, run, outputs, stream, reps: int, rounds: int = 2, min_gain: float 
     torch.cuda.synchronize()
     ref = [t.view(torch.int64).clone() for t in outputs()]
     best, t_best, t_start, trace = coordinate_descent(event_measure(ctx, run, stream, reps), start,
-                                                      rounds=rounds, min_gain=min_gain, log=log)
+                                                      candidates=candidates_for(ctx.log_n), rounds=rounds,
+                                                      min_gain=min_gain, log=log, verbose=verbose)
     hks.hks_set_plan(ctx, best)
     for o in outputs():
         o.view(torch.int64).zero_()
@@ -234,6 +253,7 @@ def main(argv=None):
     ap.add_argument("--level", type=int, default=24)
     ap.add_argument("--rounds", type=int, default=2)
     ap.add_argument("--cache", default=DEFAULT_CACHE)
+    ap.add_argument("--verbose", action="store_true", help="log the time of every plan timed")
     args = ap.parse_args(argv)
     import torch
     from . import hks, synth
@@ -250,7 +270,7 @@ def main(argv=None):
     arch = torch.cuda.get_device_properties(0).gcnArchName
     key = cache_key(arch, args.log_n, args.L, args.K, args.dnum, wl)
     log(f"[tune] {key}: {reps} calls per timing")
-    entry = tune(ctx, run, outputs, stream, reps, rounds=args.rounds, log=log)
+    entry = tune(ctx, run, outputs, stream, reps, rounds=args.rounds, log=log, verbose=args.verbose)
     log(f"[tune] {key}: {entry['default_us']:.1f} us (start) -> {entry['us']:.1f} us, "
         f"{entry['plans_timed']} plans timed, outputs equal: {entry['outputs_equal']}")
     save_entry(key, entry, args.cache)

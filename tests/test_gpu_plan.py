@@ -1,8 +1,10 @@
 """Launch plans (include/hks.h, hks_plan) change only how launches are laid
 over the chip: under extreme plans (16 or 8 elements per thread in every
 pass, one NewLimb target per block row or all in one, block orders on or
-off) Rotate, HRotate, batched Rotate, Mult+relin and PtMatVecMult equal the
-oracle bit for bit at small sizes and equal the default plan at full size."""
+off, the NTT split one stage either way of the default, 8 or 32 columns per
+column-pass block, 4 or 16 rows per row-pass block) Rotate, HRotate,
+batched Rotate, Mult+relin and PtMatVecMult equal the oracle bit for bit at
+small sizes and equal the default plan at full size."""
 import numpy as np
 import pytest
 import torch
@@ -13,14 +15,28 @@ from paper_2112_06396_amd import synth, tune
 pytestmark = pytest.mark.gpu
 
 A8 = tune.ALWAYS8
+# n1 "lo" / "hi": one stage fewer / more in the column pass than the default
+# split, where the ring degree allows it (_resolve)
 PLANS = {
     "e16_all_split": {"e16_fwd_cols": 0, "e16_fwd_rows": 0, "e16_inv_rows": 0, "e16_inv_cols": 0,
-                      "conv_group_limbs": 1, "conv_group_max_batch": 64, "row_xcd_order": 0, "ksk_xcd_order": 0},
+                      "conv_group_limbs": 1, "conv_group_max_batch": 64, "row_xcd_order": 0, "ksk_xcd_order": 0,
+                      "n1": "lo", "col_lines": 32, "row_lines": 16},
     "e8_all_whole": {"e16_fwd_cols": A8, "e16_fwd_rows": A8, "e16_inv_rows": A8, "e16_inv_cols": A8,
-                     "conv_group_limbs": 64, "conv_group_max_batch": 0, "row_xcd_order": 1, "ksk_xcd_order": 1},
+                     "conv_group_limbs": 64, "conv_group_max_batch": 0, "row_xcd_order": 1, "ksk_xcd_order": 1,
+                     "n1": "hi", "col_lines": 8, "row_lines": 4},
     "mixed": {"e16_fwd_cols": 0, "e16_fwd_rows": A8, "e16_inv_rows": 0, "e16_inv_cols": A8,
-              "conv_group_limbs": 4, "conv_group_max_batch": 1, "row_xcd_order": 1, "ksk_xcd_order": 0},
+              "conv_group_limbs": 4, "conv_group_max_batch": 1, "row_xcd_order": 1, "ksk_xcd_order": 0,
+              "n1": 0, "col_lines": 16, "row_lines": 8},
 }
+
+
+def _resolve(plan, log_n):
+    p = dict(plan)
+    if p["n1"] in ("lo", "hi"):
+        h = log_n // 2
+        want = h - 1 if p["n1"] == "lo" else h + 1
+        p["n1"] = want if want in tune.candidates_for(log_n)["n1"] else 0
+    return p
 CFGS = {"n10": (10, 6, 2, 3), "n13": (13, 7, 3, 3), "n15": (15, 6, 2, 3)}
 _CTX = {}
 
@@ -69,10 +85,13 @@ def test_plan_get_set_and_rejection():
     pr, ctx = _get("n10")
     d = hks.hks_get_plan(ctx)
     assert d == {"e16_fwd_cols": 6144, "e16_fwd_rows": A8, "e16_inv_rows": 6144, "e16_inv_cols": 6144,
-                 "conv_group_limbs": 8, "conv_group_max_batch": 2, "row_xcd_order": 1, "ksk_xcd_order": 1}
+                 "conv_group_limbs": 8, "conv_group_max_batch": 2, "row_xcd_order": 1, "ksk_xcd_order": 1,
+                 "n1": 0, "col_lines": 16, "row_lines": 8}
     hks.hks_set_plan(ctx, PLANS["mixed"])
     assert hks.hks_get_plan(ctx) == PLANS["mixed"]
-    for bad in ({"conv_group_limbs": 0}, {"conv_group_limbs": 65}, {"row_xcd_order": 2}, {"ksk_xcd_order": 7}):
+    # N = 2^10 allows only the 5 x 5 split
+    for bad in ({"conv_group_limbs": 0}, {"conv_group_limbs": 65}, {"row_xcd_order": 2}, {"ksk_xcd_order": 7},
+                {"col_lines": 12}, {"row_lines": 32}, {"n1": 4}, {"n1": 6}):
         with pytest.raises(hks.HksError) as e:
             hks.hks_set_plan(ctx, bad)
         assert e.value.status == hks.HKS_EINVAL
@@ -86,7 +105,7 @@ def test_calls_equal_oracle_under_plan(cfg, plan):
     hks = H()
     pr, ctx = _get(cfg)
     default = hks.hks_get_plan(ctx)
-    hks.hks_set_plan(ctx, PLANS[plan])
+    hks.hks_set_plan(ctx, _resolve(PLANS[plan], pr.log_n))
     try:
         level = pr.L
         ct = _ct(pr, level, 900)
@@ -151,7 +170,7 @@ def test_full_size_plans_equal_default():
 
         ref = [t.view(torch.int64).clone() for t in run_all()]
         for name, plan in PLANS.items():
-            hks.hks_set_plan(ctx, plan)
+            hks.hks_set_plan(ctx, _resolve(plan, 16))
             got = run_all()
             assert all(torch.equal(a, b.view(torch.int64)) for a, b in zip(ref, got)), name
     finally:

@@ -21,12 +21,14 @@ def _cost(best):
 
 def _default():
     return {"e16_fwd_cols": 6144, "e16_fwd_rows": tune.ALWAYS8, "e16_inv_rows": 6144, "e16_inv_cols": 6144,
-            "conv_group_limbs": 8, "conv_group_max_batch": 2, "row_xcd_order": 1, "ksk_xcd_order": 1}
+            "conv_group_limbs": 8, "conv_group_max_batch": 2, "row_xcd_order": 1, "ksk_xcd_order": 1,
+            "n1": 0, "col_lines": 16, "row_lines": 8}
 
 
 def test_descent_finds_the_minimum_of_a_separable_cost():
     best = {"e16_fwd_cols": 0, "e16_fwd_rows": tune.ALWAYS8, "e16_inv_rows": 4096, "e16_inv_cols": 6144,
-            "conv_group_limbs": 16, "conv_group_max_batch": 4, "row_xcd_order": 0, "ksk_xcd_order": 1}
+            "conv_group_limbs": 16, "conv_group_max_batch": 4, "row_xcd_order": 0, "ksk_xcd_order": 1,
+            "n1": 0, "col_lines": 32, "row_lines": 4}
     plan, t, t0, trace = tune.coordinate_descent(_cost(best), _default())
     assert plan == best
     assert abs(t - 100e-6) < 1e-12 and t0 > t
@@ -73,6 +75,14 @@ def test_candidate_fields_are_the_plan_fields():
     assert all(v in tune.CANDIDATES[k] for k, v in _default().items())
 
 
+def test_split_candidates_follow_the_ring_degree():
+    """The NTT split candidates keep both passes within 5..9 stages."""
+    assert tune.candidates_for(16)["n1"] == (0, 7, 9)
+    assert tune.candidates_for(15)["n1"] == (0, 6, 8)
+    assert tune.candidates_for(10)["n1"] == (0,)
+    assert tune.candidates_for(12)["n1"] == (0, 5, 7)
+
+
 def test_committed_plans_are_valid():
     """Every plan in the package's cache names only plan fields with values
     the library accepts."""
@@ -82,4 +92,5 @@ def test_committed_plans_are_valid():
         assert set(plan) == set(hks.PLAN_FIELDS), key
         assert 1 <= plan["conv_group_limbs"] <= 64
         assert plan["row_xcd_order"] in (0, 1) and plan["ksk_xcd_order"] in (0, 1)
+        assert plan["col_lines"] in (8, 16, 32) and plan["row_lines"] in (4, 8, 16)
         assert entry["outputs_equal"] and entry["us"] <= entry["default_us"]
