@@ -85,6 +85,11 @@ __device__ __forceinline__ int k_of(int t, int e) {
 #define HKS_TW_HOIST 1
 #endif
 constexpr bool TW_HOIST = HKS_TW_HOIST != 0;  // pass kernels load a phase's twiddles up front
+// Row passes load all their twiddles before the first butterfly (measured:
+// Rotate -1.4%); column passes, whose few twiddles are cache hits, per phase
+// (loading all up front measured no better).
+constexpr bool TW_PRE_ROWS = true;
+constexpr bool TW_PRE_COLS = false;
 
 // Twiddle sources.  The butterfly group m = k >> (bit+1) of local stage ls
 // (0-based within the pass) uses
@@ -123,6 +128,61 @@ __device__ __forceinline__ void stage_row_twiddles(Shoup *lds_tw, const Shoup *_
         for (uint32_t i = threadIdx.x; i < (LINES << ls); i += blockDim.x) dst[i] = src[i];
     }
 }
+// The twiddles of one phase (layout [LO, HI)) for the thread: E >> (vb+1)
+// distinct ones per stage (none for the folded last inverse stage).
+template <int LOGS, bool FWD, bool FOLD, int LO, int HI, int E, typename TW>
+__device__ __forceinline__ void phase_tw(Shoup (&w)[HI - LO][E / 2], int t, const TW &tws) {
+    constexpr int B = HI - LO, H = E / 2;
+#pragma unroll
+    for (int st = 0; st < B; ++st) {
+        const int bit = FWD ? (HI - 1 - st) : (LO + st);
+        const int vb = bit - LO;
+        const int ls = LOGS - 1 - bit;
+#pragma unroll
+        for (int key = 0; key < H; ++key) {
+            if (key < (E >> (vb + 1)) && !(FOLD && ls == 0)) {
+                const uint32_t k = (uint32_t)k_of<LO, HI, E>(t, key << (vb + 1));
+                w[st][key] = tws(ls, k >> (bit + 1));
+            }
+        }
+    }
+}
+
+// The butterflies of one phase with its twiddles already in registers.
+template <int LOGS, bool FWD, bool FOLD, int LO, int HI, int E>
+__device__ __forceinline__ void phase_bfly(uint64_t (&x)[E], uint64_t q, uint64_t nq,
+                                           const Shoup (&w)[HI - LO][E / 2], const LastInv &fold) {
+    constexpr int B = HI - LO, H = E / 2;
+    const uint64_t q2 = 2 * q;
+#pragma unroll
+    for (int st = 0; st < B; ++st) {
+        const int bit = FWD ? (HI - 1 - st) : (LO + st);
+        const int vb = bit - LO;
+        const bool fold_stage = FOLD && (LOGS - 1 - bit) == 0;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            if ((e >> vb) & 1) continue;
+            const int e2 = e + (1 << vb);
+            const Shoup wc = w[st][(e >> (vb + 1)) & (H - 1)];
+            if (FWD) {
+                const uint64_t u = x[e];
+                const uint64_t tv = mul_shoup_lazy_nq(x[e2], wc.w, wc.wp, nq);
+                x[e] = u + tv;
+                x[e2] = u + q2 - tv;
+            } else {
+                const uint64_t u = x[e], v = x[e2];
+                if (fold_stage) {
+                    x[e] = mul_shoup(u + v, fold.c.w, fold.c.wp, q);
+                    x[e2] = mul_shoup(u + q2 - v, fold.cw.w, fold.cw.wp, q);
+                } else {
+                    x[e] = csub(u + v, q2);
+                    x[e2] = mul_shoup_lazy_nq(u + q2 - v, wc.w, wc.wp, nq);
+                }
+            }
+        }
+    }
+}
+
 // The butterflies of one phase on the thread's E registers (layout [LO, HI)).
 // Each stage loads E >> (vb+1) distinct twiddles.  With FOLD (the inverse
 // column pass) the global last inverse stage multiplies by the folded
@@ -208,11 +268,61 @@ __device__ __forceinline__ void lds_get(const uint64_t *lds, uint64_t (&x)[E], i
 // P2, inverse: P0).  The LDS tile carries the exchanges between phases; the
 // caller synchronizes before this tile is written again.  Work is done only
 // where `active` holds, but every thread reaches every barrier.
-template <int LOGS, int LINES, bool COLS, bool FWD, bool HOIST, int E = 16, typename TW>
+// With PRE every twiddle of the pass is loaded before the first butterfly:
+// one memory latency for the pass (overlapping the data loads the caller
+// issued before) instead of one per phase, for their registers.
+template <int LOGS, int LINES, bool COLS, bool FWD, bool HOIST, int E = 16, bool PRE = false, typename TW>
 __device__ __forceinline__ void pass_regs(bool active, uint64_t (&x)[E], uint64_t *lds, int line, int t, uint64_t q,
                                           uint64_t nq, const TW &tws, const LastInv &fold) {
     using P = Phases<LOGS, Log2<E>::value>;
     constexpr bool FOLD = !FWD && COLS;
+    if constexpr (PRE) {
+        constexpr int H = E / 2;
+        Shoup w0[P::P0H - P::P0L][H], w1[P::P1H - P::P1L][H], w2[P::THREE ? P::P2H - P::P2L : 1][H];
+        phase_tw<LOGS, FWD, FOLD, P::P0L, P::P0H, E>(w0, t, tws);
+        phase_tw<LOGS, FWD, FOLD, P::P1L, P::P1H, E>(w1, t, tws);
+        if constexpr (P::THREE) phase_tw<LOGS, FWD, FOLD, P::P2L, P::P2H, E>(w2, t, tws);
+        if (FWD) {
+            if (active) {
+                phase_bfly<LOGS, true, FOLD, P::P0L, P::P0H, E>(x, q, nq, w0, fold);
+                lds_put<LOGS, LINES, COLS, P::P0L, P::P0H, E>(lds, x, line, t);
+            }
+            __syncthreads();
+            if (active) {
+                lds_get<LOGS, LINES, COLS, P::P1L, P::P1H, E>(lds, x, line, t);
+                phase_bfly<LOGS, true, FOLD, P::P1L, P::P1H, E>(x, q, nq, w1, fold);
+            }
+            if constexpr (P::THREE) {
+                __syncthreads();
+                if (active) lds_put<LOGS, LINES, COLS, P::P1L, P::P1H, E>(lds, x, line, t);
+                __syncthreads();
+                if (active) {
+                    lds_get<LOGS, LINES, COLS, P::P2L, P::P2H, E>(lds, x, line, t);
+                    phase_bfly<LOGS, true, FOLD, P::P2L, P::P2H, E>(x, q, nq, w2, fold);
+                }
+            }
+        } else {
+            if constexpr (P::THREE) {
+                if (active) {
+                    phase_bfly<LOGS, false, FOLD, P::P2L, P::P2H, E>(x, q, nq, w2, fold);
+                    lds_put<LOGS, LINES, COLS, P::P2L, P::P2H, E>(lds, x, line, t);
+                }
+                __syncthreads();
+                if (active) lds_get<LOGS, LINES, COLS, P::P1L, P::P1H, E>(lds, x, line, t);
+                __syncthreads();
+            }
+            if (active) {
+                phase_bfly<LOGS, false, FOLD, P::P1L, P::P1H, E>(x, q, nq, w1, fold);
+                lds_put<LOGS, LINES, COLS, P::P1L, P::P1H, E>(lds, x, line, t);
+            }
+            __syncthreads();
+            if (active) {
+                lds_get<LOGS, LINES, COLS, P::P0L, P::P0H, E>(lds, x, line, t);
+                phase_bfly<LOGS, false, FOLD, P::P0L, P::P0H, E>(x, q, nq, w0, fold);
+            }
+        }
+        return;
+    }
     if (FWD) {
         if (active) {
             phase_regs<LOGS, true, FOLD, P::P0L, P::P0H, HOIST, E>(x, t, q, nq, tws, fold);
@@ -403,9 +513,11 @@ __global__ void __launch_bounds__((Tile<LOGS, LINES, COLS, E>::NT)) ntt_pass_ker
 
     const LastInv fold = (!FWD && COLS) ? a.li[a.m.cidx[li] + (MIXED ? a.io.cbase[b] : 0u)] : LastInv{};
     if constexpr (COLS) {
-        pass_regs<LOGS, LINES, COLS, FWD, TW_HOIST, E>(true, x, lds, line, t, q, mcv.nq, TwCols{tw}, fold);
+        pass_regs<LOGS, LINES, COLS, FWD, TW_HOIST, E, TW_PRE_COLS>(true, x, lds, line, t, q, mcv.nq, TwCols{tw},
+                                                                    fold);
     } else {
-        pass_regs<LOGS, LINES, COLS, FWD, TW_HOIST, E>(true, x, lds, line, t, q, mcv.nq, TwRows{tw, lg, a.n1}, fold);
+        pass_regs<LOGS, LINES, COLS, FWD, TW_HOIST, E, TW_PRE_ROWS>(true, x, lds, line, t, q, mcv.nq,
+                                                                    TwRows{tw, lg, a.n1}, fold);
     }
 
     if (IOB == IO_MDEPI) {
