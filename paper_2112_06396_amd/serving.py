@@ -275,6 +275,14 @@ class KeyStore:
         src = self.host[kid]
         return self.slots[s][: src.numel()].view(src.shape)
 
+    def preload(self, stream):
+        """Uploads every key (in key order) until the budget is full: with a
+        budget above the key set, every key is resident afterwards."""
+        for kid in list(self.host)[: self.n_slots]:
+            self.acquire(kid, stream)
+            self.refs[kid] -= 1
+        stream.synchronize()
+
     def hold(self, kids, handle):
         self.held[id(handle)] = kids
 
