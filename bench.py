@@ -79,8 +79,9 @@ def kernel_work(cls: int, n: int, level: int, k: int, alpha: int, beta: int):
     `cls` (butterflies for NTT passes, product terms for the conversion and
     KSKInnerProd) and the algorithmic HBM bytes it moves (8-byte words: each
     limb a launch touches read once and written once)."""
-    n1 = LOG_N // 2
-    n2 = LOG_N - n1
+    log_n = n.bit_length() - 1
+    n1 = log_n // 2
+    n2 = log_n - n1
     E = level + k
     new_limbs = beta * E - level  # ModUp's converted limbs (the digits' own limbs are not copied)
     half = n // 2
