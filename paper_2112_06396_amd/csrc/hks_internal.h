@@ -69,6 +69,7 @@ struct ModC {
     uint64_t q;
     uint64_t mu;  // floor(2^112 / q), Barrett for 128-bit values
     uint64_t nq;  // 2^64 - q (held in the table so that products add instead of subtract)
+    uint64_t qi;  // -q^-1 mod 2^64 (Montgomery reduction)
 };
 
 // Constant pair for Shoup multiplication: (w, floor(w * 2^64 / q)).
@@ -119,6 +120,8 @@ struct Ctx {
     // device tables
     Shoup *tw_fwd = nullptr;  // [M][N]: psi^brv(i)
     Shoup *tw_inv = nullptr;  // [M][N]: psi^-brv(i)
+    uint64_t *twm_fwd = nullptr;  // [M][N]: tw_fwd's w 2^64 mod q (Montgomery form)
+    uint64_t *twm_inv = nullptr;  // [M][N]: tw_inv's w 2^64 mod q
     ModC *mc = nullptr;       // [M]
     LastInv *li_plain = nullptr;  // [M]: scale 1
     LastInv *li_modup = nullptr;  // [L+1][L]: level l, limb i: scale (Qt_j/q_i)^-1 mod q_i

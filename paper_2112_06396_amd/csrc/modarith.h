@@ -89,6 +89,18 @@ __device__ __forceinline__ uint64_t mul_mod(uint64_t x, uint64_t y, uint64_t q, 
     return reduce128((uint64_t)(p >> 64), (uint64_t)p, q, mu, nq);
 }
 
+// Montgomery product x w 2^-64 mod q, in [0, 2q) when x w < q 2^64 (the
+// butterflies' lazy x < 4q and w < q with 50-bit q give x w < 2^102): with
+// T = x w and m = (T mod 2^64) q' mod 2^64, q' = -q^-1 mod 2^64, T + m q is
+// a multiple of 2^64 and (T + m q) / 2^64 = hi(T) + hi(m q) + [lo(T) != 0]
+// (the low words sum to 0 or to 2^64), below T / 2^64 + q.
+__device__ __forceinline__ uint64_t mont_lazy(uint64_t x, uint64_t w, uint64_t q, uint64_t qinv) {
+    const u128 t = (u128)x * w;
+    const uint64_t lo = (uint64_t)t, hi = (uint64_t)(t >> 64);
+    const uint64_t m = lo * qinv;
+    return hi + __umul64hi(m, q) + (lo != 0 ? 1u : 0u);
+}
+
 __device__ __forceinline__ uint64_t add_mod(uint64_t x, uint64_t y, uint64_t q) { return csub(x + y, q); }
 __device__ __forceinline__ uint64_t sub_mod(uint64_t x, uint64_t y, uint64_t q) { return csub(x + q - y, q); }
 

@@ -59,6 +59,7 @@ static NttArgs base_args(const Ctx &c, const LimbMap &m, const BatchIo &io, bool
     NttArgs a{};
     a.ctx = &c;
     a.tw = fwd ? c.tw_fwd : c.tw_inv;
+    a.twm = fwd ? c.twm_fwd : c.twm_inv;
     a.mc = c.mc;
     a.li = c.li_plain;
     a.pinv = c.pinv;

@@ -107,6 +107,26 @@ struct TwRows {
         return tw[(((1u << n1) + row) << ls) + m];
     }
 };
+// Row twiddles in Montgomery form (w 2^64 mod q): the butterfly multiplies
+// with a Montgomery product, from 8 bytes per twiddle where a Shoup pair
+// takes 16.
+struct TwRowsM {
+    const uint64_t *tw;  // the modulus's [N] table
+    uint32_t row, n1;
+    __device__ __forceinline__ uint64_t operator()(int ls, uint32_t m) const {
+        return tw[(((1u << n1) + row) << ls) + m];
+    }
+};
+
+// The butterfly's product with a twiddle: Shoup with a (w, w') pair, or
+// Montgomery with a Montgomery-form twiddle.
+__device__ __forceinline__ uint64_t tw_mul(uint64_t x, const Shoup &w, uint64_t, uint64_t nq, uint64_t) {
+    return mul_shoup_lazy_nq(x, w.w, w.wp, nq);
+}
+__device__ __forceinline__ uint64_t tw_mul(uint64_t x, uint64_t wm, uint64_t q, uint64_t, uint64_t qinv) {
+    return mont_lazy(x, wm, q, qinv);
+}
+
 // The row twiddles of `lines` consecutive rows from row0, staged in LDS: for
 // local stage ls the rows' entries ((2^n1 + r) << ls) + m form one
 // contiguous run of lines << ls entries, stored at lines (2^ls - 1).
@@ -130,8 +150,8 @@ __device__ __forceinline__ void stage_row_twiddles(Shoup *lds_tw, const Shoup *_
 }
 // The twiddles of one phase (layout [LO, HI)) for the thread: E >> (vb+1)
 // distinct ones per stage (none for the folded last inverse stage).
-template <int LOGS, bool FWD, bool FOLD, int LO, int HI, int E, typename TW>
-__device__ __forceinline__ void phase_tw(Shoup (&w)[HI - LO][E / 2], int t, const TW &tws) {
+template <int LOGS, bool FWD, bool FOLD, int LO, int HI, int E, typename TW, typename TV>
+__device__ __forceinline__ void phase_tw(TV (&w)[HI - LO][E / 2], int t, const TW &tws) {
     constexpr int B = HI - LO, H = E / 2;
 #pragma unroll
     for (int st = 0; st < B; ++st) {
@@ -149,9 +169,9 @@ __device__ __forceinline__ void phase_tw(Shoup (&w)[HI - LO][E / 2], int t, cons
 }
 
 // The butterflies of one phase with its twiddles already in registers.
-template <int LOGS, bool FWD, bool FOLD, int LO, int HI, int E>
-__device__ __forceinline__ void phase_bfly(uint64_t (&x)[E], uint64_t q, uint64_t nq,
-                                           const Shoup (&w)[HI - LO][E / 2], const LastInv &fold) {
+template <int LOGS, bool FWD, bool FOLD, int LO, int HI, int E, typename TV>
+__device__ __forceinline__ void phase_bfly(uint64_t (&x)[E], uint64_t q, uint64_t nq, uint64_t qinv,
+                                           const TV (&w)[HI - LO][E / 2], const LastInv &fold) {
     constexpr int B = HI - LO, H = E / 2;
     const uint64_t q2 = 2 * q;
 #pragma unroll
@@ -163,10 +183,10 @@ __device__ __forceinline__ void phase_bfly(uint64_t (&x)[E], uint64_t q, uint64_
         for (int e = 0; e < E; ++e) {
             if ((e >> vb) & 1) continue;
             const int e2 = e + (1 << vb);
-            const Shoup wc = w[st][(e >> (vb + 1)) & (H - 1)];
+            const TV wc = w[st][(e >> (vb + 1)) & (H - 1)];
             if (FWD) {
                 const uint64_t u = x[e];
-                const uint64_t tv = mul_shoup_lazy_nq(x[e2], wc.w, wc.wp, nq);
+                const uint64_t tv = tw_mul(x[e2], wc, q, nq, qinv);
                 x[e] = u + tv;
                 x[e2] = u + q2 - tv;
             } else {
@@ -176,7 +196,7 @@ __device__ __forceinline__ void phase_bfly(uint64_t (&x)[E], uint64_t q, uint64_
                     x[e2] = mul_shoup(u + q2 - v, fold.cw.w, fold.cw.wp, q);
                 } else {
                     x[e] = csub(u + v, q2);
-                    x[e2] = mul_shoup_lazy_nq(u + q2 - v, wc.w, wc.wp, nq);
+                    x[e2] = tw_mul(u + q2 - v, wc, q, nq, qinv);
                 }
             }
         }
@@ -189,13 +209,14 @@ __device__ __forceinline__ void phase_bfly(uint64_t (&x)[E], uint64_t q, uint64_
 // constants instead.
 template <int LOGS, bool FWD, bool FOLD, int LO, int HI, bool HOIST, int E, typename TW>
 __device__ __forceinline__ void phase_regs(uint64_t (&x)[E], int t, uint64_t q, uint64_t nq, const TW &tws,
-                                           const LastInv &fold) {
+                                           const LastInv &fold, uint64_t qinv) {
     constexpr int B = HI - LO, H = E / 2;
+    using TV = decltype(tws(0, 0u));
     const uint64_t q2 = 2 * q;
     // HOIST: every twiddle of the phase loaded up front (E >> (vb+1) per
     // stage), one memory latency per phase instead of one per stage, for
     // more registers
-    Shoup wall[HOIST ? B : 1][H];
+    TV wall[HOIST ? B : 1][H];
 #pragma unroll
     for (int st = 0; st < (HOIST ? B : 0); ++st) {
         const int bit = FWD ? (HI - 1 - st) : (LO + st);
@@ -215,7 +236,7 @@ __device__ __forceinline__ void phase_regs(uint64_t (&x)[E], int t, uint64_t q, 
         const int vb = bit - LO;
         const int ls = LOGS - 1 - bit;  // stage within this pass
         const bool fold_stage = FOLD && ls == 0;
-        Shoup wc[H];
+        TV wc[H];
 #pragma unroll
         for (int key = 0; key < H; ++key) {
             if (HOIST) {
@@ -229,10 +250,10 @@ __device__ __forceinline__ void phase_regs(uint64_t (&x)[E], int t, uint64_t q, 
         for (int e = 0; e < E; ++e) {
             if ((e >> vb) & 1) continue;
             const int e2 = e + (1 << vb);
-            const Shoup w = wc[(e >> (vb + 1)) & (H - 1)];
+            const TV w = wc[(e >> (vb + 1)) & (H - 1)];
             if (FWD) {
                 const uint64_t u = x[e];
-                const uint64_t tv = mul_shoup_lazy_nq(x[e2], w.w, w.wp, nq);
+                const uint64_t tv = tw_mul(x[e2], w, q, nq, qinv);
                 x[e] = u + tv;
                 x[e2] = u + q2 - tv;
             } else {
@@ -242,7 +263,7 @@ __device__ __forceinline__ void phase_regs(uint64_t (&x)[E], int t, uint64_t q, 
                     x[e2] = mul_shoup(u + q2 - v, fold.cw.w, fold.cw.wp, q);
                 } else {
                     x[e] = csub(u + v, q2);
-                    x[e2] = mul_shoup_lazy_nq(u + q2 - v, w.w, w.wp, nq);
+                    x[e2] = tw_mul(u + q2 - v, w, q, nq, qinv);
                 }
             }
         }
@@ -273,24 +294,25 @@ __device__ __forceinline__ void lds_get(const uint64_t *lds, uint64_t (&x)[E], i
 // issued before) instead of one per phase, for their registers.
 template <int LOGS, int LINES, bool COLS, bool FWD, bool HOIST, int E = 16, bool PRE = false, typename TW>
 __device__ __forceinline__ void pass_regs(bool active, uint64_t (&x)[E], uint64_t *lds, int line, int t, uint64_t q,
-                                          uint64_t nq, const TW &tws, const LastInv &fold) {
+                                          uint64_t nq, const TW &tws, const LastInv &fold, uint64_t qinv = 0) {
     using P = Phases<LOGS, Log2<E>::value>;
+    using TV = decltype(tws(0, 0u));
     constexpr bool FOLD = !FWD && COLS;
     if constexpr (PRE) {
         constexpr int H = E / 2;
-        Shoup w0[P::P0H - P::P0L][H], w1[P::P1H - P::P1L][H], w2[P::THREE ? P::P2H - P::P2L : 1][H];
+        TV w0[P::P0H - P::P0L][H], w1[P::P1H - P::P1L][H], w2[P::THREE ? P::P2H - P::P2L : 1][H];
         phase_tw<LOGS, FWD, FOLD, P::P0L, P::P0H, E>(w0, t, tws);
         phase_tw<LOGS, FWD, FOLD, P::P1L, P::P1H, E>(w1, t, tws);
         if constexpr (P::THREE) phase_tw<LOGS, FWD, FOLD, P::P2L, P::P2H, E>(w2, t, tws);
         if (FWD) {
             if (active) {
-                phase_bfly<LOGS, true, FOLD, P::P0L, P::P0H, E>(x, q, nq, w0, fold);
+                phase_bfly<LOGS, true, FOLD, P::P0L, P::P0H, E>(x, q, nq, qinv, w0, fold);
                 lds_put<LOGS, LINES, COLS, P::P0L, P::P0H, E>(lds, x, line, t);
             }
             __syncthreads();
             if (active) {
                 lds_get<LOGS, LINES, COLS, P::P1L, P::P1H, E>(lds, x, line, t);
-                phase_bfly<LOGS, true, FOLD, P::P1L, P::P1H, E>(x, q, nq, w1, fold);
+                phase_bfly<LOGS, true, FOLD, P::P1L, P::P1H, E>(x, q, nq, qinv, w1, fold);
             }
             if constexpr (P::THREE) {
                 __syncthreads();
@@ -298,13 +320,13 @@ __device__ __forceinline__ void pass_regs(bool active, uint64_t (&x)[E], uint64_
                 __syncthreads();
                 if (active) {
                     lds_get<LOGS, LINES, COLS, P::P2L, P::P2H, E>(lds, x, line, t);
-                    phase_bfly<LOGS, true, FOLD, P::P2L, P::P2H, E>(x, q, nq, w2, fold);
+                    phase_bfly<LOGS, true, FOLD, P::P2L, P::P2H, E>(x, q, nq, qinv, w2, fold);
                 }
             }
         } else {
             if constexpr (P::THREE) {
                 if (active) {
-                    phase_bfly<LOGS, false, FOLD, P::P2L, P::P2H, E>(x, q, nq, w2, fold);
+                    phase_bfly<LOGS, false, FOLD, P::P2L, P::P2H, E>(x, q, nq, qinv, w2, fold);
                     lds_put<LOGS, LINES, COLS, P::P2L, P::P2H, E>(lds, x, line, t);
                 }
                 __syncthreads();
@@ -312,26 +334,26 @@ __device__ __forceinline__ void pass_regs(bool active, uint64_t (&x)[E], uint64_
                 __syncthreads();
             }
             if (active) {
-                phase_bfly<LOGS, false, FOLD, P::P1L, P::P1H, E>(x, q, nq, w1, fold);
+                phase_bfly<LOGS, false, FOLD, P::P1L, P::P1H, E>(x, q, nq, qinv, w1, fold);
                 lds_put<LOGS, LINES, COLS, P::P1L, P::P1H, E>(lds, x, line, t);
             }
             __syncthreads();
             if (active) {
                 lds_get<LOGS, LINES, COLS, P::P0L, P::P0H, E>(lds, x, line, t);
-                phase_bfly<LOGS, false, FOLD, P::P0L, P::P0H, E>(x, q, nq, w0, fold);
+                phase_bfly<LOGS, false, FOLD, P::P0L, P::P0H, E>(x, q, nq, qinv, w0, fold);
             }
         }
         return;
     }
     if (FWD) {
         if (active) {
-            phase_regs<LOGS, true, FOLD, P::P0L, P::P0H, HOIST, E>(x, t, q, nq, tws, fold);
+            phase_regs<LOGS, true, FOLD, P::P0L, P::P0H, HOIST, E>(x, t, q, nq, tws, fold, qinv);
             lds_put<LOGS, LINES, COLS, P::P0L, P::P0H, E>(lds, x, line, t);
         }
         __syncthreads();
         if (active) {
             lds_get<LOGS, LINES, COLS, P::P1L, P::P1H, E>(lds, x, line, t);
-            phase_regs<LOGS, true, FOLD, P::P1L, P::P1H, HOIST, E>(x, t, q, nq, tws, fold);
+            phase_regs<LOGS, true, FOLD, P::P1L, P::P1H, HOIST, E>(x, t, q, nq, tws, fold, qinv);
         }
         if constexpr (P::THREE) {
             __syncthreads();
@@ -339,13 +361,13 @@ __device__ __forceinline__ void pass_regs(bool active, uint64_t (&x)[E], uint64_
             __syncthreads();
             if (active) {
                 lds_get<LOGS, LINES, COLS, P::P2L, P::P2H, E>(lds, x, line, t);
-                phase_regs<LOGS, true, FOLD, P::P2L, P::P2H, HOIST, E>(x, t, q, nq, tws, fold);
+                phase_regs<LOGS, true, FOLD, P::P2L, P::P2H, HOIST, E>(x, t, q, nq, tws, fold, qinv);
             }
         }
     } else {
         if constexpr (P::THREE) {
             if (active) {
-                phase_regs<LOGS, false, FOLD, P::P2L, P::P2H, HOIST, E>(x, t, q, nq, tws, fold);
+                phase_regs<LOGS, false, FOLD, P::P2L, P::P2H, HOIST, E>(x, t, q, nq, tws, fold, qinv);
                 lds_put<LOGS, LINES, COLS, P::P2L, P::P2H, E>(lds, x, line, t);
             }
             __syncthreads();
@@ -353,13 +375,13 @@ __device__ __forceinline__ void pass_regs(bool active, uint64_t (&x)[E], uint64_
             __syncthreads();
         }
         if (active) {
-            phase_regs<LOGS, false, FOLD, P::P1L, P::P1H, HOIST, E>(x, t, q, nq, tws, fold);
+            phase_regs<LOGS, false, FOLD, P::P1L, P::P1H, HOIST, E>(x, t, q, nq, tws, fold, qinv);
             lds_put<LOGS, LINES, COLS, P::P1L, P::P1H, E>(lds, x, line, t);
         }
         __syncthreads();
         if (active) {
             lds_get<LOGS, LINES, COLS, P::P0L, P::P0H, E>(lds, x, line, t);
-            phase_regs<LOGS, false, FOLD, P::P0L, P::P0H, HOIST, E>(x, t, q, nq, tws, fold);
+            phase_regs<LOGS, false, FOLD, P::P0L, P::P0H, HOIST, E>(x, t, q, nq, tws, fold, qinv);
         }
     }
 }
@@ -429,6 +451,7 @@ __device__ __forceinline__ void thread_coords(int tid, int &line, int &t) {
 struct NttArgs {
     const Ctx *ctx;  // host-side only (timing); not read by kernels
     const Shoup *tw;      // [M][N] forward or inverse table
+    const uint64_t *twm;  // [M][N] the same table in Montgomery form (row passes)
     const ModC *mc;
     const LastInv *li;    // folded last inverse stage, indexed by cidx
     const Shoup *pinv;    // IO_MDEPI: P^-1 mod q_i
@@ -516,8 +539,8 @@ __global__ void __launch_bounds__((Tile<LOGS, LINES, COLS, E>::NT)) ntt_pass_ker
         pass_regs<LOGS, LINES, COLS, FWD, TW_HOIST, E, TW_PRE_COLS>(true, x, lds, line, t, q, mcv.nq, TwCols{tw},
                                                                     fold);
     } else {
-        pass_regs<LOGS, LINES, COLS, FWD, TW_HOIST, E, TW_PRE_ROWS>(true, x, lds, line, t, q, mcv.nq,
-                                                                    TwRows{tw, lg, a.n1}, fold);
+        pass_regs<LOGS, LINES, COLS, FWD, TW_HOIST, E, TW_PRE_ROWS>(
+            true, x, lds, line, t, q, mcv.nq, TwRowsM{a.twm + (size_t)mod * N, lg, a.n1}, fold, mcv.qi);
     }
 
     if (IOB == IO_MDEPI) {

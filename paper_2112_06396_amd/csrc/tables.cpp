@@ -122,9 +122,26 @@ int build_tables(Ctx &c) {
         mc[m].q = q;
         mc[m].mu = (uint64_t)(((u128)1 << 112) / q);
         mc[m].nq = 0 - q;
+        {
+            // -q^-1 mod 2^64 by Newton's iteration (q odd: x = q is q^-1 mod 2^3)
+            uint64_t x = q;
+            for (int it = 0; it < 5; ++it) x *= 2 - q * x;
+            mc[m].qi = 0 - x;
+        }
         ninv[m] = h_invmod(N, q);
         w0inv[m] = twi[(size_t)m * N + 1].w;
         lip[m] = make_last(q, ninv[m], 1, w0inv[m]);
+    }
+
+    // the twiddles in Montgomery form for the row passes
+    std::vector<uint64_t> tmf((size_t)M * N), tmi((size_t)M * N);
+    for (uint32_t m = 0; m < M; ++m) {
+        const uint64_t q = c.mods[m];
+        const uint64_t r64 = (uint64_t)(((u128)1 << 64) % q);  // 2^64 mod q
+        for (uint32_t i = 0; i < N; ++i) {
+            tmf[(size_t)m * N + i] = h_mulmod(twf[(size_t)m * N + i].w, r64, q);
+            tmi[(size_t)m * N + i] = h_mulmod(twi[(size_t)m * N + i].w, r64, q);
+        }
     }
 
     // ModUp, per level l: digit j covers [jA, min((j+1)A, l)); Qt_j over present limbs.
@@ -243,6 +260,8 @@ int build_tables(Ctx &c) {
     if ((rc = upload(&c.enc_roots, roots))) return rc;
     if ((rc = upload(&c.tw_fwd, twf))) return rc;
     if ((rc = upload(&c.tw_inv, twi))) return rc;
+    if ((rc = upload(&c.twm_fwd, tmf))) return rc;
+    if ((rc = upload(&c.twm_inv, tmi))) return rc;
     if ((rc = upload(&c.mc, mc))) return rc;
     if ((rc = upload(&c.li_plain, lip))) return rc;
     if ((rc = upload(&c.li_modup, limu))) return rc;
@@ -260,12 +279,13 @@ int build_tables(Ctx &c) {
 }
 
 void free_tables(Ctx &c) {
-    void *ptrs[] = {c.tw_fwd, c.tw_inv, c.mc, c.li_plain, c.li_modup, c.li_moddown, c.conv_modup,
+    void *ptrs[] = {c.tw_fwd, c.tw_inv, c.twm_fwd, c.twm_inv, c.mc, c.li_plain, c.li_modup, c.li_moddown, c.conv_modup,
                     c.conv_moddown, c.pinv, c.pmod, c.rs_qinv, c.rs_h, c.ws,
                     c.li_nm, c.conv_nm, c.sinv_nm, c.enc_rotg, c.enc_roots, c.chk_flag};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     c.tw_fwd = c.tw_inv = nullptr;
+    c.twm_fwd = c.twm_inv = nullptr;
     c.mc = nullptr;
     c.li_plain = c.li_modup = c.li_moddown = nullptr;
     c.conv_modup = c.conv_moddown = nullptr;
