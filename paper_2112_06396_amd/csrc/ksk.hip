@@ -44,6 +44,51 @@ struct KskRowArgs {
 // (a reduction per digit, half the accumulator registers) both fit three
 // waves, which batched launches of many rounds turn into throughput
 // (measured: batched KSKInnerProd -5%, a single Rotate +2% against lazy).
+#ifndef HKS_KSK_TWL
+#define HKS_KSK_TWL 1
+#endif
+
+// The forward row twiddles (Montgomery form) of the block's rows, staged in
+// LDS by each wave for the wave's own lines (line = threadIdx.x / T; a
+// wave's LDS operations take effect in order, so its threads read them
+// without a barrier): line l's S entries hold at [0, 2) the aligned pair
+// around its stage-0 entry (2^n1 + row) and at [2^ls, 2^(ls+1)) the 2^ls
+// entries ((2^n1 + row) << ls) + m of stage ls >= 1; each lane copies E/2 of
+// the wave's 16-byte chunks.
+template <int LOGS, int E, int NT>
+__device__ __forceinline__ void row_twiddle_stage(uint64_t *twbuf, const uint64_t *tw, uint32_t row0, uint32_t n1) {
+    constexpr int S = 1 << LOGS, T = S / E, W = NT < 64 ? NT : 64, CPL = S / 2;
+    const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const uint32_t line0 = wave * 64 / T;  // the wave's first line
+    ulonglong2 v[E / 2];
+#pragma unroll
+    for (int i = 0; i < E / 2; ++i) {
+        const uint32_t g = i * W + lane;  // chunk within the wave's lines
+        const uint32_t l = line0 + g / CPL, cc = g % CPL;
+        const uint32_t hi = (1u << n1) + row0 + l;
+        size_t src;
+        if (cc == 0) {
+            src = hi & ~1u;
+        } else {
+            const uint32_t e = 2 * cc, ls = 31 - __builtin_clz(e);
+            src = ((size_t)hi << ls) + (e - (1u << ls));
+        }
+        v[i] = *reinterpret_cast<const ulonglong2 *>(tw + src);
+    }
+    ulonglong2 *dst = reinterpret_cast<ulonglong2 *>(twbuf) + (size_t)line0 * CPL;
+#pragma unroll
+    for (int i = 0; i < E / 2; ++i) dst[i * W + lane] = v[i];
+    __builtin_amdgcn_wave_barrier();
+}
+// Twiddles from row_twiddle_stage's buffer for one line.
+struct TwRowsLdsM {
+    const uint64_t *tw;  // the line's S entries in LDS
+    uint32_t odd;        // row & 1: the stage-0 entry's place in its pair
+    __device__ __forceinline__ uint64_t operator()(int ls, uint32_t m) const {
+        return ls == 0 ? tw[odd] : tw[(1u << ls) + m];
+    }
+};
+
 template <int LOGS, bool ROWPASS, int E, bool SEEDED, bool NM, bool LZ = true>
 __global__ void __launch_bounds__((Tile<LOGS, ROW_LINES, false, E>::NT))
 __attribute__((amdgpu_waves_per_eu(E == 8 ? ((LZ && ROWPASS) ? 2 : 3) : 2)))
@@ -62,6 +107,9 @@ ksk_rows_kernel(const KskRowArgs a) {
     // Montgomery product per butterfly) in the row-pass form with lazy sums
     // (measured: Rotate -1.8%; batched launches without lazy sums +3%)
     constexpr bool MT = ROWPASS && LZ;
+    // TWL: the forward row twiddles, the same for every digit, staged in LDS once
+    constexpr bool TWL = MT && HKS_KSK_TWL;
+    __shared__ __attribute__((aligned(16))) uint64_t twbuf[TWL ? ROW_LINES * (1 << LOGS) : 2];
     // block -> (x = target limb and row tile, b = ciphertext).  With
     // xcd_group the nb blocks of one x get ids that are equal modulo 8, so
     // that they run on one XCD (ids are dealt round-robin over the 8 XCDs)
@@ -118,6 +166,7 @@ ksk_rows_kernel(const KskRowArgs a) {
 #pragma unroll
     for (int e = 0; e < E; ++e) u[e] = v[e] = 0;
     bool lds_used = false;
+    if constexpr (TWL) row_twiddle_stage<LOGS, E, TL::NT>(twbuf, a.twmf + (size_t)mod * N, tile * ROW_LINES, a.n1);
     for (uint32_t jd = 0; jd < beta; ++jd) {
         if (LAZY && jd && (jd & 15) == 0) {
 #pragma unroll
@@ -140,7 +189,11 @@ ksk_rows_kernel(const KskRowArgs a) {
             if (ROWPASS) {
                 gload<LOGS, false, IOF::IN_LO, IOF::IN_HI, E>(xv, src, t, lg, a.n2);
                 if (lds_used) __syncthreads();
-                if constexpr (MT) {
+                if constexpr (TWL) {
+                    pass_regs<LOGS, ROW_LINES, false, true, false, E>(
+                        true, xv, lds, line, t, q, mcv.nq, TwRowsLdsM{twbuf + (size_t)line * (1 << LOGS), lg & 1u},
+                        LastInv{}, mcv.qi);
+                } else if constexpr (MT) {
                     pass_regs<LOGS, ROW_LINES, false, true, false, E>(true, xv, lds, line, t, q, mcv.nq,
                                                                       TwRowsM{a.twmf + (size_t)mod * N, lg, a.n1},
                                                                       LastInv{}, mcv.qi);

@@ -448,6 +448,46 @@ __device__ __forceinline__ void thread_coords(int tid, int &line, int &t) {
     }
 }
 
+#ifndef HKS_GATHER_LDS
+#define HKS_GATHER_LDS 1
+#endif
+constexpr bool GATHER_LDS = HKS_GATHER_LDS != 0;
+
+// A row pass's input under X -> X^g (bit-reversed evaluation order): the
+// aligned block of 2^n2 slots of row lg is the image of one whole source row
+// (the automorphism maps aligned blocks onto aligned blocks), so the line's
+// threads load that row with contiguous loads (E words each) into the line's
+// part of the LDS tile and take their elements from there in the pass's
+// input layout.  A line's threads are one wave's (T divides 64), and a
+// wave's LDS operations take effect in order: no block barrier.  The caller
+// has synchronized since the tile was last read.
+template <int LOGS, int LINES, bool FWD, int E>
+__device__ __forceinline__ void gather_row(uint64_t (&x)[E], const uint64_t *src, uint64_t *lds, int line, int t,
+                                           uint32_t lg, uint32_t g, uint32_t n, uint32_t n2) {
+    using TL = Tile<LOGS, LINES, false, E>;
+    using IOL = IoLayout<LOGS, FWD, E>;
+    static_assert(TL::T <= 64 && 64 % TL::T == 0, "a line's threads are in one wave");
+    const uint32_t row0 = lg << n2;
+    const uint32_t srow = aut_eval_src(row0, g, n) >> n2;
+    const ulonglong2 *s2 = reinterpret_cast<const ulonglong2 *>(src + ((size_t)srow << n2) + E * t);
+    ulonglong2 v[E / 2];
+#pragma unroll
+    for (int c = 0; c < E / 2; ++c) v[c] = s2[c];
+#pragma unroll
+    for (int c = 0; c < E / 2; ++c) {
+        lds[TL::idx(line, E * t + 2 * c)] = v[c].x;
+        lds[TL::idx(line, E * t + 2 * c + 1)] = v[c].y;
+    }
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const uint32_t k = k_of<IOL::IN_LO, IOL::IN_HI, E>(t, e);
+        const uint32_t col = aut_eval_src(row0 + k, g, n) & ((1u << LOGS) - 1u);
+        x[e] = lds[TL::idx(line, col)];
+    }
+    __builtin_amdgcn_wave_barrier();
+}
+
 struct NttArgs {
     const Ctx *ctx;  // host-side only (timing); not read by kernels
     const Shoup *tw;      // [M][N] forward or inverse table
@@ -523,7 +563,9 @@ __global__ void __launch_bounds__((Tile<LOGS, LINES, COLS, E>::NT)) ntt_pass_ker
     }
 
     uint64_t x[E];
-    if (IOB == IO_GATHER) {
+    if (IOB == IO_GATHER && !COLS && GATHER_LDS) {
+        gather_row<LOGS, LINES, FWD, E>(x, src, lds, line, t, lg, a.io.galois[b], a.n, a.n2);
+    } else if (IOB == IO_GATHER) {
         const uint32_t g = a.io.galois[b];
 #pragma unroll
         for (int e = 0; e < E; ++e) {
