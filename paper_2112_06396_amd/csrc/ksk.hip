@@ -44,10 +44,6 @@ struct KskRowArgs {
 // (a reduction per digit, half the accumulator registers) both fit three
 // waves, which batched launches of many rounds turn into throughput
 // (measured: batched KSKInnerProd -5%, a single Rotate +2% against lazy).
-#ifndef HKS_KSK_TWL
-#define HKS_KSK_TWL 1
-#endif
-
 // The forward row twiddles (Montgomery form) of the block's rows, staged in
 // LDS by each wave for the wave's own lines (line = threadIdx.x / T; a
 // wave's LDS operations take effect in order, so its threads read them
@@ -78,7 +74,7 @@ __device__ __forceinline__ void row_twiddle_stage(uint64_t *twbuf, const uint64_
     ulonglong2 *dst = reinterpret_cast<ulonglong2 *>(twbuf) + (size_t)line0 * CPL;
 #pragma unroll
     for (int i = 0; i < E / 2; ++i) dst[i * W + lane] = v[i];
-    __builtin_amdgcn_wave_barrier();
+    wave_sync();
 }
 // Twiddles from row_twiddle_stage's buffer for one line.
 struct TwRowsLdsM {
@@ -103,13 +99,12 @@ ksk_rows_kernel(const KskRowArgs a) {
     // u's and v's passes (measured: HRotate +2%; with the forward row passes
     // of ROWPASS the staging latency costs more than it saves)
     __shared__ Shoup lds_tw[(ROWPASS || LOGS > 8) ? 1 : ROW_LINES * ((1 << LOGS) - 1)];
-    // row passes with Montgomery-form twiddles (half the table bytes, a
-    // Montgomery product per butterfly) in the row-pass form with lazy sums
-    // (measured: Rotate -1.8%; batched launches without lazy sums +3%)
-    constexpr bool MT = ROWPASS && LZ;
-    // TWL: the forward row twiddles, the same for every digit, staged in LDS once
-    constexpr bool TWL = MT && HKS_KSK_TWL;
-    __shared__ __attribute__((aligned(16))) uint64_t twbuf[TWL ? ROW_LINES * (1 << LOGS) : 2];
+    // the row-pass form: Montgomery-form twiddles (half the bytes of a
+    // Shoup pair), the forward ones staged in LDS once (the same for every
+    // digit).  Measured against Shoup pairs from the global table: Rotate
+    // -2%, ksk -5%; batched launches -7% per launch.
+    constexpr bool MT = ROWPASS;
+    __shared__ __attribute__((aligned(16))) uint64_t twbuf[MT ? ROW_LINES * (1 << LOGS) : 2];
     // block -> (x = target limb and row tile, b = ciphertext).  With
     // xcd_group the nb blocks of one x get ids that are equal modulo 8, so
     // that they run on one XCD (ids are dealt round-robin over the 8 XCDs)
@@ -166,7 +161,7 @@ ksk_rows_kernel(const KskRowArgs a) {
 #pragma unroll
     for (int e = 0; e < E; ++e) u[e] = v[e] = 0;
     bool lds_used = false;
-    if constexpr (TWL) row_twiddle_stage<LOGS, E, TL::NT>(twbuf, a.twmf + (size_t)mod * N, tile * ROW_LINES, a.n1);
+    if constexpr (MT) row_twiddle_stage<LOGS, E, TL::NT>(twbuf, a.twmf + (size_t)mod * N, tile * ROW_LINES, a.n1);
     for (uint32_t jd = 0; jd < beta; ++jd) {
         if (LAZY && jd && (jd & 15) == 0) {
 #pragma unroll
@@ -188,15 +183,11 @@ ksk_rows_kernel(const KskRowArgs a) {
             const uint64_t *src = ext + (jd * ext_ds + ext_slot) * N;
             if (ROWPASS) {
                 gload<LOGS, false, IOF::IN_LO, IOF::IN_HI, E>(xv, src, t, lg, a.n2);
-                if (lds_used) __syncthreads();
-                if constexpr (TWL) {
+                if (lds_used) pass_sync<false>();
+                if constexpr (MT) {
                     pass_regs<LOGS, ROW_LINES, false, true, false, E>(
                         true, xv, lds, line, t, q, mcv.nq, TwRowsLdsM{twbuf + (size_t)line * (1 << LOGS), lg & 1u},
                         LastInv{}, mcv.qi);
-                } else if constexpr (MT) {
-                    pass_regs<LOGS, ROW_LINES, false, true, false, E>(true, xv, lds, line, t, q, mcv.nq,
-                                                                      TwRowsM{a.twmf + (size_t)mod * N, lg, a.n1},
-                                                                      LastInv{}, mcv.qi);
                 } else {
                     pass_regs<LOGS, ROW_LINES, false, true, false, E>(true, xv, lds, line, t, q, mcv.nq,
                                                                       TwRows{a.twf + (size_t)mod * N, lg, a.n1},
@@ -266,20 +257,20 @@ ksk_rows_kernel(const KskRowArgs a) {
         return;
     }
     // special limb: inverse row pass (first pass of ModDown's iNTT) of u and v
-    if (lds_used) __syncthreads();
+    if (lds_used) pass_sync<false>();
     if constexpr (MT) {
         const TwRowsM twi{a.twmi + (size_t)mod * N, lg, a.n1};
         pass_regs<LOGS, ROW_LINES, false, false, false, E>(true, u, lds, line, t, q, mcv.nq, twi, LastInv{},
                                                            mcv.qi);
         gstore<LOGS, false, IOI::OUT_LO, IOI::OUT_HI, E>(u, pc + (size_t)kp * N, t, lg, a.n2);
-        __syncthreads();
+        pass_sync<false>();
         pass_regs<LOGS, ROW_LINES, false, false, false, E>(true, v, lds, line, t, q, mcv.nq, twi, LastInv{},
                                                            mcv.qi);
     } else if constexpr (ROWPASS || LOGS > 8) {
         const TwRows twi{a.twi + (size_t)mod * N, lg, a.n1};
         pass_regs<LOGS, ROW_LINES, false, false, false, E>(true, u, lds, line, t, q, mcv.nq, twi, LastInv{});
         gstore<LOGS, false, IOI::OUT_LO, IOI::OUT_HI, E>(u, pc + (size_t)kp * N, t, lg, a.n2);
-        __syncthreads();
+        pass_sync<false>();
         pass_regs<LOGS, ROW_LINES, false, false, false, E>(true, v, lds, line, t, q, mcv.nq, twi, LastInv{});
     } else {
         const TwRowsLds<ROW_LINES> twl{lds_tw, (uint32_t)line};
@@ -287,7 +278,7 @@ ksk_rows_kernel(const KskRowArgs a) {
         __syncthreads();
         pass_regs<LOGS, ROW_LINES, false, false, false, E>(true, u, lds, line, t, q, mcv.nq, twl, LastInv{});
         gstore<LOGS, false, IOI::OUT_LO, IOI::OUT_HI, E>(u, pc + (size_t)kp * N, t, lg, a.n2);
-        __syncthreads();
+        pass_sync<false>();
         pass_regs<LOGS, ROW_LINES, false, false, false, E>(true, v, lds, line, t, q, mcv.nq, twl, LastInv{});
     }
     gstore<LOGS, false, IOI::OUT_LO, IOI::OUT_HI, E>(v, pc + ((size_t)a.pck + kp) * N, t, lg, a.n2);
@@ -489,7 +480,7 @@ __global__ void __launch_bounds__((Tile<LOGS, ROW_LINES, false, E>::NT)) ksk_mat
     const TwRows twi{a.twi + (size_t)mod * N, lg, a.n1};
     pass_regs<LOGS, ROW_LINES, false, false, false, E>(true, ya, lds, line, t, q, mcv.nq, twi, LastInv{});
     gstore<LOGS, false, IOI::OUT_LO, IOI::OUT_HI, E>(ya, a.pc + (size_t)kp * N, t, lg, a.n2);
-    __syncthreads();
+    pass_sync<false>();
     pass_regs<LOGS, ROW_LINES, false, false, false, E>(true, yb, lds, line, t, q, mcv.nq, twi, LastInv{});
     gstore<LOGS, false, IOI::OUT_LO, IOI::OUT_HI, E>(yb, a.pc + ((size_t)a.K + kp) * N, t, lg, a.n2);
 }

@@ -148,6 +148,26 @@ __device__ __forceinline__ void stage_row_twiddles(Shoup *lds_tw, const Shoup *_
         for (uint32_t i = threadIdx.x; i < (LINES << ls); i += blockDim.x) dst[i] = src[i];
     }
 }
+// Order of LDS accesses within a wave: a wave's LDS operations take effect
+// in issue order, so only the compiler must not move them across
+// (wavefront-scope fences around a wave barrier; no instruction is needed).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+// The synchronization of a pass's LDS exchanges.  A column's threads span
+// the block (line = tid % LINES): block barrier.  A row's T threads are
+// consecutive and T divides 64 (line = tid / T), so each row lives in one
+// wave and its exchanges only need wave_sync; the block's waves then run
+// their passes independently (measured against block barriers: Rotate
+// -2.5%, the key-switch kernel -7%).
+template <bool COLS>
+__device__ __forceinline__ void pass_sync() {
+    if constexpr (COLS) __syncthreads();
+    else wave_sync();
+}
+
 // The twiddles of one phase (layout [LO, HI)) for the thread: E >> (vb+1)
 // distinct ones per stage (none for the folded last inverse stage).
 template <int LOGS, bool FWD, bool FOLD, int LO, int HI, int E, typename TW, typename TV>
@@ -298,6 +318,7 @@ __device__ __forceinline__ void pass_regs(bool active, uint64_t (&x)[E], uint64_
     using P = Phases<LOGS, Log2<E>::value>;
     using TV = decltype(tws(0, 0u));
     constexpr bool FOLD = !FWD && COLS;
+    static_assert(COLS || 64 % Tile<LOGS, LINES, COLS, E>::T == 0, "a row's threads are in one wave");
     if constexpr (PRE) {
         constexpr int H = E / 2;
         TV w0[P::P0H - P::P0L][H], w1[P::P1H - P::P1L][H], w2[P::THREE ? P::P2H - P::P2L : 1][H];
@@ -309,15 +330,15 @@ __device__ __forceinline__ void pass_regs(bool active, uint64_t (&x)[E], uint64_
                 phase_bfly<LOGS, true, FOLD, P::P0L, P::P0H, E>(x, q, nq, qinv, w0, fold);
                 lds_put<LOGS, LINES, COLS, P::P0L, P::P0H, E>(lds, x, line, t);
             }
-            __syncthreads();
+            pass_sync<COLS>();
             if (active) {
                 lds_get<LOGS, LINES, COLS, P::P1L, P::P1H, E>(lds, x, line, t);
                 phase_bfly<LOGS, true, FOLD, P::P1L, P::P1H, E>(x, q, nq, qinv, w1, fold);
             }
             if constexpr (P::THREE) {
-                __syncthreads();
+                pass_sync<COLS>();
                 if (active) lds_put<LOGS, LINES, COLS, P::P1L, P::P1H, E>(lds, x, line, t);
-                __syncthreads();
+                pass_sync<COLS>();
                 if (active) {
                     lds_get<LOGS, LINES, COLS, P::P2L, P::P2H, E>(lds, x, line, t);
                     phase_bfly<LOGS, true, FOLD, P::P2L, P::P2H, E>(x, q, nq, qinv, w2, fold);
@@ -329,15 +350,15 @@ __device__ __forceinline__ void pass_regs(bool active, uint64_t (&x)[E], uint64_
                     phase_bfly<LOGS, false, FOLD, P::P2L, P::P2H, E>(x, q, nq, qinv, w2, fold);
                     lds_put<LOGS, LINES, COLS, P::P2L, P::P2H, E>(lds, x, line, t);
                 }
-                __syncthreads();
+                pass_sync<COLS>();
                 if (active) lds_get<LOGS, LINES, COLS, P::P1L, P::P1H, E>(lds, x, line, t);
-                __syncthreads();
+                pass_sync<COLS>();
             }
             if (active) {
                 phase_bfly<LOGS, false, FOLD, P::P1L, P::P1H, E>(x, q, nq, qinv, w1, fold);
                 lds_put<LOGS, LINES, COLS, P::P1L, P::P1H, E>(lds, x, line, t);
             }
-            __syncthreads();
+            pass_sync<COLS>();
             if (active) {
                 lds_get<LOGS, LINES, COLS, P::P0L, P::P0H, E>(lds, x, line, t);
                 phase_bfly<LOGS, false, FOLD, P::P0L, P::P0H, E>(x, q, nq, qinv, w0, fold);
@@ -350,15 +371,15 @@ __device__ __forceinline__ void pass_regs(bool active, uint64_t (&x)[E], uint64_
             phase_regs<LOGS, true, FOLD, P::P0L, P::P0H, HOIST, E>(x, t, q, nq, tws, fold, qinv);
             lds_put<LOGS, LINES, COLS, P::P0L, P::P0H, E>(lds, x, line, t);
         }
-        __syncthreads();
+        pass_sync<COLS>();
         if (active) {
             lds_get<LOGS, LINES, COLS, P::P1L, P::P1H, E>(lds, x, line, t);
             phase_regs<LOGS, true, FOLD, P::P1L, P::P1H, HOIST, E>(x, t, q, nq, tws, fold, qinv);
         }
         if constexpr (P::THREE) {
-            __syncthreads();
+            pass_sync<COLS>();
             if (active) lds_put<LOGS, LINES, COLS, P::P1L, P::P1H, E>(lds, x, line, t);
-            __syncthreads();
+            pass_sync<COLS>();
             if (active) {
                 lds_get<LOGS, LINES, COLS, P::P2L, P::P2H, E>(lds, x, line, t);
                 phase_regs<LOGS, true, FOLD, P::P2L, P::P2H, HOIST, E>(x, t, q, nq, tws, fold, qinv);
@@ -370,15 +391,15 @@ __device__ __forceinline__ void pass_regs(bool active, uint64_t (&x)[E], uint64_
                 phase_regs<LOGS, false, FOLD, P::P2L, P::P2H, HOIST, E>(x, t, q, nq, tws, fold, qinv);
                 lds_put<LOGS, LINES, COLS, P::P2L, P::P2H, E>(lds, x, line, t);
             }
-            __syncthreads();
+            pass_sync<COLS>();
             if (active) lds_get<LOGS, LINES, COLS, P::P1L, P::P1H, E>(lds, x, line, t);
-            __syncthreads();
+            pass_sync<COLS>();
         }
         if (active) {
             phase_regs<LOGS, false, FOLD, P::P1L, P::P1H, HOIST, E>(x, t, q, nq, tws, fold, qinv);
             lds_put<LOGS, LINES, COLS, P::P1L, P::P1H, E>(lds, x, line, t);
         }
-        __syncthreads();
+        pass_sync<COLS>();
         if (active) {
             lds_get<LOGS, LINES, COLS, P::P0L, P::P0H, E>(lds, x, line, t);
             phase_regs<LOGS, false, FOLD, P::P0L, P::P0H, HOIST, E>(x, t, q, nq, tws, fold, qinv);
@@ -448,19 +469,15 @@ __device__ __forceinline__ void thread_coords(int tid, int &line, int &t) {
     }
 }
 
-#ifndef HKS_GATHER_LDS
-#define HKS_GATHER_LDS 1
-#endif
-constexpr bool GATHER_LDS = HKS_GATHER_LDS != 0;
-
 // A row pass's input under X -> X^g (bit-reversed evaluation order): the
 // aligned block of 2^n2 slots of row lg is the image of one whole source row
 // (the automorphism maps aligned blocks onto aligned blocks), so the line's
 // threads load that row with contiguous loads (E words each) into the line's
 // part of the LDS tile and take their elements from there in the pass's
-// input layout.  A line's threads are one wave's (T divides 64), and a
-// wave's LDS operations take effect in order: no block barrier.  The caller
-// has synchronized since the tile was last read.
+// input layout (coalesced loads instead of one scattered word per element;
+// measured: Rotate -1 us).  A line's threads are one wave's (T
+// divides 64), and a wave's LDS operations take effect in order: no block
+// barrier.  The caller has synchronized since the tile was last read.
 template <int LOGS, int LINES, bool FWD, int E>
 __device__ __forceinline__ void gather_row(uint64_t (&x)[E], const uint64_t *src, uint64_t *lds, int line, int t,
                                            uint32_t lg, uint32_t g, uint32_t n, uint32_t n2) {
@@ -478,14 +495,14 @@ __device__ __forceinline__ void gather_row(uint64_t (&x)[E], const uint64_t *src
         lds[TL::idx(line, E * t + 2 * c)] = v[c].x;
         lds[TL::idx(line, E * t + 2 * c + 1)] = v[c].y;
     }
-    __builtin_amdgcn_wave_barrier();
+    wave_sync();
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const uint32_t k = k_of<IOL::IN_LO, IOL::IN_HI, E>(t, e);
         const uint32_t col = aut_eval_src(row0 + k, g, n) & ((1u << LOGS) - 1u);
         x[e] = lds[TL::idx(line, col)];
     }
-    __builtin_amdgcn_wave_barrier();
+    wave_sync();
 }
 
 struct NttArgs {
@@ -563,7 +580,7 @@ __global__ void __launch_bounds__((Tile<LOGS, LINES, COLS, E>::NT)) ntt_pass_ker
     }
 
     uint64_t x[E];
-    if (IOB == IO_GATHER && !COLS && GATHER_LDS) {
+    if (IOB == IO_GATHER && !COLS) {
         gather_row<LOGS, LINES, FWD, E>(x, src, lds, line, t, lg, a.io.galois[b], a.n, a.n2);
     } else if (IOB == IO_GATHER) {
         const uint32_t g = a.io.galois[b];
