@@ -38,12 +38,6 @@ struct KskRowArgs {
 // canonical sums).  q limbs store (u_t, v_t); special-prime limbs run
 // ModDown's inverse row pass on both in registers before storing (the
 // forward pass ends in the layout the inverse pass starts from).
-// Register budget: with LZ (lazy 128-bit sums, 8 elements per thread) the
-// row-pass form keeps two waves per SIMD (a launch of one ciphertext is two
-// rounds of waves either way) and the direct form fits three; without LZ
-// (a reduction per digit, half the accumulator registers) both fit three
-// waves, which batched launches of many rounds turn into throughput
-// (measured: batched KSKInnerProd -5%, a single Rotate +2% against lazy).
 // The forward row twiddles (Montgomery form) of the block's rows, staged in
 // LDS by each wave for the wave's own lines (line = threadIdx.x / T; a
 // wave's LDS operations take effect in order, so its threads read them
@@ -85,6 +79,12 @@ struct TwRowsLdsM {
     }
 };
 
+// Register budget: with LZ (lazy 128-bit sums, 8 elements per thread) the
+// row-pass form needs two waves per SIMD and the direct form fits three;
+// without LZ (a reduction per digit, half the accumulator registers) both
+// fit three.  Row-pass launches go without LZ (measured against lazy sums:
+// batched KSKInnerProd -5%, a single Rotate -1%, with the twiddles from LDS
+// and per-wave row synchronization); the direct form and NewMult keep LZ.
 template <int LOGS, bool ROWPASS, int E, bool SEEDED, bool NM, bool LZ = true>
 __global__ void __launch_bounds__((Tile<LOGS, ROW_LINES, false, E>::NT))
 __attribute__((amdgpu_waves_per_eu(E == 8 ? ((LZ && ROWPASS) ? 2 : 3) : 2)))
@@ -348,17 +348,14 @@ hipError_t launch_ksk_rows(const Ctx &c, const KskBatch &kb, uint32_t nb, const 
         if (!rowpass || kb.seeded) return hipErrorInvalidValue;
         return launch_ksk_rows_t<true, 8, false, true>(a, c.n2, grid, s);
     }
-    // a seeded key's rows a_j are generated in the kernel; a launch of
-    // several ciphertexts with the row pass reduces per digit (three waves
-    // per SIMD)
+    // a seeded key's rows a_j are generated in the kernel; launches with the
+    // row pass reduce per digit (three waves per SIMD)
     if (kb.seeded) {
         if (!rowpass) return launch_ksk_rows_t<false, 8, true>(a, c.n2, grid, s);
-        return nb > 1 ? launch_ksk_rows_t<true, 8, true, false, false>(a, c.n2, grid, s)
-                      : launch_ksk_rows_t<true, 8, true>(a, c.n2, grid, s);
+        return launch_ksk_rows_t<true, 8, true, false, false>(a, c.n2, grid, s);
     }
     if (!rowpass) return launch_ksk_rows_t<false, 8, false>(a, c.n2, grid, s);
-    return nb > 1 ? launch_ksk_rows_t<true, 8, false, false, false>(a, c.n2, grid, s)
-                  : launch_ksk_rows_t<true, 8, false>(a, c.n2, grid, s);
+    return launch_ksk_rows_t<true, 8, false, false, false>(a, c.n2, grid, s);
 }
 
 // ------------------------------------------------------------------ PtMatVecMult with one ModDown
