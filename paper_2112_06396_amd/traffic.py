@@ -12,6 +12,13 @@ kernel sources the counters were taken on, HBM bytes per launch), which
 bench.py checks before it reports `traffic`:
 
     python -m paper_2112_06396_amd.traffic gpurun_out/pmcF gpurun_out/pmcW
+
+With --sq, the arguments are instead directories of `rocprofv3 --pmc` runs
+of SQ counters over the same command, and the medians per launch position
+of every counter they hold are printed, with the wait and activity
+counters as fractions of SQ_WAVE_CYCLES:
+
+    python -m paper_2112_06396_amd.traffic --sq gpurun_out/sq1 gpurun_out/sq2
 """
 import argparse
 import collections
@@ -54,15 +61,65 @@ def per_launch(fetch, write, launches: int, steps: int):
     return (cf, cw, sf, sw), rows
 
 
+def load_all(directory: str):
+    """{dispatch id: (kernel name, grid size, {counter: value summed over
+    its instances})} of a counter run."""
+    path = os.path.join(directory, "p_counter_collection.csv")
+    out = collections.OrderedDict()
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            d = int(r["Dispatch_Id"])
+            if d not in out:
+                out[d] = (r["Kernel_Name"], int(r["Grid_Size"]), collections.Counter())
+            out[d][2][r["Counter_Name"]] += float(r["Counter_Value"])
+    return out
+
+
+def sq_summary(dirs, launches: int, steps: int):
+    """Per launch position of a step: (kernel, grid, {counter: median over
+    the last `steps` steps}), every counter of every run merged."""
+    rows = [dict() for _ in range(launches)]
+    names = [None] * launches
+    for d in dirs:
+        lib = [v for _, v in sorted(load_all(d).items()) if v[0].startswith(LIBRARY_KERNELS)]
+        lib = lib[-launches * steps:]
+        if len(lib) != launches * steps:
+            raise ValueError(f"{d}: fewer library dispatches than launches * steps")
+        for i in range(launches):
+            sel = lib[i::launches]
+            names[i] = (sel[0][0], sel[0][1])
+            for c in sel[0][2]:
+                rows[i][c] = statistics.median(x[2][c] for x in sel)
+    return [(names[i][0], names[i][1], rows[i]) for i in range(launches)]
+
+
+SQ_FRACTIONS = ("SQ_WAIT_ANY", "SQ_WAIT_INST_ANY", "SQ_WAIT_INST_LDS", "SQ_ACTIVE_INST_VALU", "SQ_ACTIVE_INST_LDS",
+                "SQ_ACTIVE_INST_VMEM", "SQ_ACTIVE_INST_ANY")
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("fetch_dir")
-    ap.add_argument("write_dir")
+    ap.add_argument("write_dir", nargs="?")
+    ap.add_argument("more", nargs="*", help="--sq: further counter directories")
+    ap.add_argument("--sq", action="store_true", help="summarize SQ counter runs instead")
     ap.add_argument("--launches", type=int, default=9, help="library kernels per Rotate")
     ap.add_argument("--steps", type=int, default=10, help="Rotates to take the median over")
     ap.add_argument("--kernel", default="ksk_rows", help="the kernel whose bytes per launch are printed")
     args = ap.parse_args(argv)
     from .build import source_hash
+    if args.sq:
+        dirs = [args.fetch_dir] + ([args.write_dir] if args.write_dir else []) + list(args.more)
+        print(f"source_hash: {source_hash()}")
+        for i, (k, g, c) in enumerate(sq_summary(dirs, args.launches, args.steps)):
+            print(f"{i} {k[:60]} grid {g}")
+            print("    " + ", ".join(f"{n} {v:.0f}" for n, v in sorted(c.items())))
+            wc = c.get("SQ_WAVE_CYCLES")
+            if wc:
+                print("    per SQ_WAVE_CYCLES: " + ", ".join(f"{n[3:]} {c[n] / wc:.3f}" for n in SQ_FRACTIONS if n in c))
+        return
+    if not args.write_dir:
+        ap.error("the WRITE_SIZE run's directory is missing")
     (cf, cw, sf, sw), rows = per_launch(load(args.fetch_dir, "FETCH_SIZE"), load(args.write_dir, "WRITE_SIZE"),
                                         args.launches, args.steps)
     print(f"calibration: the largest copy ({cw / 1024:.0f} MiB) reads FETCH_SIZE {cf:.0f} KiB (x{sf:.3f}) and "

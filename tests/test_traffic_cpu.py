@@ -43,3 +43,25 @@ def test_calibration_and_medians(tmp_path):
         # steps 2..11 are the last ten; median of (1024 (i+1) + step) * 2 / 1024 MiB
         assert abs(rd - 2 * (1024.0 * (i + 1) + 6.5) / 1024) < 1e-9
         assert wr == 2.0 * (i + 1)
+
+
+def test_sq_summary_merges_runs_per_launch(tmp_path):
+    """Two SQ counter runs over the same steps: per launch position, the
+    median of each counter over the last `steps` steps, both runs merged."""
+    names = ["ntt_pass_kernel<a>", "ksk_rows_kernel<c>"]
+    runs = {"S1": ("SQ_WAVE_CYCLES", lambda i, st: 1000.0 * (i + 1) + st),
+            "S2": ("SQ_WAIT_ANY", lambda i, st: 100.0 * (i + 1) + 2 * st)}
+    for d, (counter, val) in runs.items():
+        rows = [(0, "__amd_rocclr_copyBuffer", 1, 5.0)]
+        did = 1
+        for st in range(12):
+            for i, nm in enumerate(names):
+                rows.append((did, nm, 64 + i, val(i, st)))
+                did += 1
+        _write(str(tmp_path / d), counter, rows)
+    out = traffic.sq_summary([str(tmp_path / "S1"), str(tmp_path / "S2")], 2, 10)
+    for i, (name, grid, c) in enumerate(out):
+        assert name == names[i] and grid == 64 + i
+        # the last ten steps are 2..11: median step 6.5
+        assert c["SQ_WAVE_CYCLES"] == 1000.0 * (i + 1) + 6.5
+        assert c["SQ_WAIT_ANY"] == 100.0 * (i + 1) + 13.0
