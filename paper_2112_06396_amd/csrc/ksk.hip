@@ -96,14 +96,14 @@ ksk_rows_kernel(const KskRowArgs a) {
     __shared__ uint64_t lds[TL::WORDS];
     // direct digits (hoisted rotations): the special limbs' inverse row-pass
     // twiddles for the block's ROW_LINES rows (every stage), staged once for
-    // u's and v's passes (measured: HRotate +2%; with the forward row passes
-    // of ROWPASS the staging latency costs more than it saves)
+    // u's and v's passes (measured: HRotate +2%)
     __shared__ Shoup lds_tw[(ROWPASS || LOGS > 8) ? 1 : ROW_LINES * ((1 << LOGS) - 1)];
-    // the row-pass form: Montgomery-form twiddles (half the bytes of a
-    // Shoup pair), the forward ones staged in LDS once (the same for every
-    // digit).  Measured against Shoup pairs from the global table: Rotate
-    // -2%, ksk -5%; batched launches -7% per launch.
-    constexpr bool MT = ROWPASS;
+    // the row-pass form with passes of 8 or more stages: Montgomery-form
+    // twiddles (half the bytes of a Shoup pair), the forward ones staged in
+    // LDS once (the same for every digit).  Measured against Shoup pairs
+    // from the global table: Rotate -2%, ksk -5%; batched launches -7% per
+    // launch.  Shorter passes read Shoup pairs from the table.
+    constexpr bool MT = ROWPASS && MONT_ROWS<LOGS>;
     __shared__ __attribute__((aligned(16))) uint64_t twbuf[MT ? ROW_LINES * (1 << LOGS) : 2];
     // block -> (x = target limb and row tile, b = ciphertext).  With
     // xcd_group the nb blocks of one x get ids that are equal modulo 8, so

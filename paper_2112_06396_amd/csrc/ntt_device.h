@@ -118,6 +118,15 @@ struct TwRowsM {
     }
 };
 
+// Row passes of 8 or more stages (N >= 2^15 at the default split) read
+// their twiddles in Montgomery form: half the table bytes for one more
+// multiply-high on the butterfly's path.  Shorter passes belong to small
+// rings, whose launches are a few blocks each and bound by the latency of
+// that path (measured at N = 2^12: Rotate 41.6 us with Shoup pairs, 46.9 us
+// with Montgomery twiddles), so they keep Shoup pairs.
+template <int LOGS>
+constexpr bool MONT_ROWS = LOGS >= 8;
+
 // The butterfly's product with a twiddle: Shoup with a (w, w') pair, or
 // Montgomery with a Montgomery-form twiddle.
 __device__ __forceinline__ uint64_t tw_mul(uint64_t x, const Shoup &w, uint64_t, uint64_t nq, uint64_t) {
@@ -597,9 +606,12 @@ __global__ void __launch_bounds__((Tile<LOGS, LINES, COLS, E>::NT)) ntt_pass_ker
     if constexpr (COLS) {
         pass_regs<LOGS, LINES, COLS, FWD, TW_HOIST, E, TW_PRE_COLS>(true, x, lds, line, t, q, mcv.nq, TwCols{tw},
                                                                     fold);
-    } else {
+    } else if constexpr (MONT_ROWS<LOGS>) {
         pass_regs<LOGS, LINES, COLS, FWD, TW_HOIST, E, TW_PRE_ROWS>(
             true, x, lds, line, t, q, mcv.nq, TwRowsM{a.twm + (size_t)mod * N, lg, a.n1}, fold, mcv.qi);
+    } else {
+        pass_regs<LOGS, LINES, COLS, FWD, TW_HOIST, E, TW_PRE_ROWS>(true, x, lds, line, t, q, mcv.nq,
+                                                                    TwRows{tw, lg, a.n1}, fold);
     }
 
     if (IOB == IO_MDEPI) {
