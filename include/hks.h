@@ -436,8 +436,9 @@ void hks_graph_destroy(hks_graph *graph);
  * class k records a hipEvent pair on the launch stream; hks_prof_read()
  * waits for the recorded events and returns the summed milliseconds and the
  * launch count of class k since the last hks_prof_enable() call.  mask = 0
- * turns recording off.  Events are created on the host side only; no device
- * memory is allocated. */
+ * turns recording off.  The events are timing-only (hipEventDisableSystemFence:
+ * no system-scope cache writeback at the record), created on the host side
+ * only; no device memory is allocated. */
 int hks_prof_enable(hks_ctx *ctx, uint32_t mask);
 int hks_prof_read(hks_ctx *ctx, int kernel_class, double *ms, uint64_t *launches);
 

@@ -21,8 +21,11 @@ static hipEvent_t prof_event(const Ctx &c) {
         c.prof_pool.pop_back();
         return e;
     }
+    // timing only (read after the work has finished): no system-scope fence
+    // at the record, whose cache writeback and invalidation would land in
+    // the measured interval and slow the launch that follows
     hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
     return e;
 }
 
