@@ -5,6 +5,7 @@ Every HIP translation unit is compiled with packed-FP32 instructions disabled
 fp64; the flag keeps the compiler from forming packed FP32 ops anywhere).
 """
 import hashlib
+import re
 import os
 import subprocess
 import sys
@@ -20,11 +21,21 @@ KERNEL_SOURCES = ["ntt_device.h", "pass_shapes.h", "ntt.hip", "ntt_cols.hip", "n
                   "ksk.hip", "kernels.hip", "modarith.h", "device_util.h", "hks_internal.h"]
 
 
+def _code_only(text: str) -> str:
+    """C++ source without its comments and with whitespace runs collapsed
+    (no kernel source holds a string literal containing comment markers)."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def source_hash() -> str:
+    """Hash of the code (comments and layout excluded) of KERNEL_SOURCES."""
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(CSRC, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(CSRC, f), encoding="utf-8") as fh:
+            h.update(_code_only(fh.read()).encode())
+            h.update(b"\0")
     return h.hexdigest()[:16]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

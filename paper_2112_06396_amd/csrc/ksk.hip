@@ -29,15 +29,6 @@ struct KskRowArgs {
     uint32_t level0, uniform;  // every entry at level0 (uniform), else kb.level[b]
 };
 
-// One block = one target limb t of Q_level U P and ROW_LINES rows, in the
-// row-pass layout (each thread 16 elements of one row).  For each digit j:
-// the converted limb x_{j,t} gets the forward row pass on chip (ROWPASS: the
-// last pass of ModUp's NTT; lazy values < 2^56), or the digit's own limb is
-// read from the input through the automorph; then u_t += x ksk[j][0][t],
-// v_t += x ksk[j][1][t] (Barrett products of the lazy value and the key,
-// canonical sums).  q limbs store (u_t, v_t); special-prime limbs run
-// ModDown's inverse row pass on both in registers before storing (the
-// forward pass ends in the layout the inverse pass starts from).
 // The forward row twiddles (Montgomery form) of the block's rows, staged in
 // LDS by each wave for the wave's own lines (line = threadIdx.x / T; a
 // wave's LDS operations take effect in order, so its threads read them
@@ -79,6 +70,16 @@ struct TwRowsLdsM {
     }
 };
 
+// One block = one target limb t of Q_level U P and ROW_LINES rows, in the
+// row-pass layout (each thread E elements of one row; every launch takes
+// E = 8).  For each digit j:
+// the converted limb x_{j,t} gets the forward row pass on chip (ROWPASS: the
+// last pass of ModUp's NTT; lazy values < 2^56), or the digit's own limb is
+// read from the input through the automorph; then u_t += x ksk[j][0][t],
+// v_t += x ksk[j][1][t] (Barrett products of the lazy value and the key,
+// canonical sums).  q limbs store (u_t, v_t); special-prime limbs run
+// ModDown's inverse row pass on both in registers before storing (the
+// forward pass ends in the layout the inverse pass starts from).
 // Register budget: with LZ (lazy 128-bit sums, 8 elements per thread) the
 // row-pass form needs two waves per SIMD and the direct form fits three;
 // without LZ (a reduction per digit, half the accumulator registers) both
