@@ -36,8 +36,8 @@ HBM_PEAK_GBS = 8000.0
 # instructions.  Plain 32-bit VALU instructions issue at the fp32 vector
 # rate, 157.3 TFLOP/s / 2 / (256 CUs x 4 SIMDs x 2.4 GHz) = 32 lanes per SIMD
 # per clock: 2 clocks per 64-wide wave instruction.  v_mad_u64_u32 issues at
-# a quarter of that rate (8 clocks; AMD publishes no figure, this build's
-# probe measures 20 T/s against 35 T/s for v_fma_f64).  So one wave-wide
+# a quarter of that rate (8 clocks; AMD publishes no figure, a probe of
+# independent chains measures 20 T/s against 35 T/s for v_fma_f64).  So one wave-wide
 # product takes 5 x 8 + 12 x 2 = 64 SIMD clocks: one product per SIMD per
 # clock.
 SIMDS, CLOCK_HZ = 256 * 4, 2.4e9
@@ -622,8 +622,8 @@ def main():
     USE_TUNED_PLANS = not args.default_plans
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: the key-switching path here runs on a single MI355X "
-              "(multi-GPU sharding is a design note, not part of this build). Run with --gpus 1.",
+        print("bench.py measures one GPU only: the key-switching path runs on a single MI355X "
+              "(how it would shard over several GPUs is described, not implemented). Run with --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
 

@@ -55,7 +55,7 @@ extern "C" {
 #define HKS_EINVAL (-1)       /* bad argument: level, galois, pointer, size, parameters */
 #define HKS_ENOMEM (-2)       /* device or host allocation failed */
 #define HKS_EHIP (-3)         /* a HIP runtime call or kernel launch failed */
-#define HKS_EUNSUPPORTED (-4) /* valid request outside what this build supports */
+#define HKS_EUNSUPPORTED (-4) /* valid request outside what the library supports */
 #define HKS_ERANGE (-5)       /* an input residue is not below its modulus (checks on) */
 #define HKS_ESCRATCH (-6)     /* the call needs more than the allocation-free scratch */
 
