@@ -139,8 +139,14 @@ def _cpu_model() -> str:
 _CPU_CASE = None
 
 
+# the small configuration (N = 2^12, L = 4, K = 2, dnum = 2) and the hoisted
+# sample's rotations per call
+SMALL = (12, 4, 2, 2)
+HROT_SAMPLE = 4
+
+
 def _cpu_worker_init():
-    global _CPU_CASE
+    global _CPU_CASE, _CPU_SMALL
     import numpy as np
     from oracle import oracle as O
     from paper_2112_06396_amd import synth
@@ -151,6 +157,11 @@ def _cpu_worker_init():
                     for _ in range(DNUM)])
     _CPU_CASE = (pr, ct, ksk, pow(5, -1, 2 * pr.n))
     O.rotate(pr, ct, LEVEL, _CPU_CASE[3], ksk)  # warm (library loaded, pages touched)
+    ps = O.make_params(*SMALL)
+    cs = np.stack([synth.uniform_residues(g, ps.q[:SMALL[1]], ps.n) for _ in range(2)])
+    ks = np.stack([np.stack([synth.uniform_residues(g, ps.key_mods(), ps.n) for _ in range(2)])
+                   for _ in range(SMALL[3])])
+    _CPU_SMALL = (ps, cs, ks, pow(5, -1, 2 * ps.n))
 
 
 def _cpu_worker_rotates(count: int) -> int:
@@ -159,6 +170,25 @@ def _cpu_worker_rotates(count: int) -> int:
     for _ in range(count):
         O.rotate(pr, ct, LEVEL, gal, ksk)
     return count
+
+
+def _cpu_worker_job(job) -> int:
+    """(kind, count): count calls of the small Rotate ("c1") or of an
+    HRotate over HROT_SAMPLE rotations at the benchmark's shape ("c3a", one
+    key for every rotation: the oracle's cost does not depend on key values);
+    returns the key-switches done."""
+    from oracle import oracle as O
+    kind, count = job
+    if kind == "c1":
+        ps, cs, ks, gal = _CPU_SMALL
+        for _ in range(count):
+            O.rotate(ps, cs, SMALL[1], gal, ks)
+        return count
+    pr, ct, ksk, _ = _CPU_CASE
+    gals = [pow(5, k + 1, 2 * pr.n) for k in range(HROT_SAMPLE)]
+    for _ in range(count):
+        O.hrotate(pr, ct, LEVEL, gals, [ksk] * HROT_SAMPLE)
+    return count * HROT_SAMPLE
 
 
 def cpu_baseline(per_worker: int, workers: int):
@@ -181,12 +211,39 @@ def cpu_baseline(per_worker: int, workers: int):
             t0 = time.perf_counter()
             done = sum(pool.map(_cpu_worker_rotates, [per_worker] * workers, chunksize=1))
             many.append(done / (time.perf_counter() - t0))
+        def timed(kind, count):
+            """Median over 3 runs of the key-switches/s on one core and on all
+            `workers` cores."""
+            o, m = [], []
+            for _ in range(3):
+                t0 = time.perf_counter()
+                done = pool.apply(_cpu_worker_job, ((kind, count),))
+                o.append(done / (time.perf_counter() - t0))
+            for _ in range(3):
+                t0 = time.perf_counter()
+                done = sum(pool.map(_cpu_worker_job, [(kind, count)] * workers, chunksize=1))
+                m.append(done / (time.perf_counter() - t0))
+            return {"value": statistics.median(m), "runs": m, "single_core": statistics.median(o),
+                    "single_core_runs": o}
+        small = timed("c1", 40)
+        hoisted = timed("c3a", 1)
     res = {"value": statistics.median(many), "unit": "key-switch/s", "cores": workers, "kind": "oracle",
            "sample": f"3 timed runs of {workers} x {per_worker} Rotate calls at N=2^16, L=24, K=8, dnum=3, one "
                      f"single-threaded C-oracle process per core; median of the runs' throughputs",
            "runs": many, "cpu_model": _cpu_model(), "nproc": os.cpu_count(),
            "single_core": {"value": statistics.median(one), "runs": one,
-                           "sample": f"3 timed runs of {per_worker} Rotate calls on one core"}}
+                           "sample": f"3 timed runs of {per_worker} Rotate calls on one core"},
+           "other_configs": {
+               "C1_small_rotate": dict(small, unit="key-switch/s",
+                                       sample="3 timed runs of 40 Rotate calls at N=2^12, L=4, K=2, dnum=2 per "
+                                              "core (all cores, and one core)"),
+               "C3a_hoisted": dict(hoisted, unit="rotations/s",
+                                   sample=f"3 timed runs of one HRotate over {HROT_SAMPLE} rotations at N=2^16, "
+                                          f"L=24, K=8, dnum=3 per core (ModUp once per call; the 64-rotation "
+                                          f"form amortizes it further)"),
+               "C3b_batch": {"note": "32 independent Rotates: the oracle's rate is the plain Rotate's above"},
+               "C4_trace": {"note": "not timed: the 120 key-switches at L = 35 -> 9 take minutes on the oracle; "
+                                    "each costs about a plain Rotate at its level"}}}
     return res
 
 
