@@ -792,7 +792,7 @@ def main():
     ms_per_step = gpu_ms / args.steps
     value = args.steps / (gpu_ms / 1e3)
     log(f"[bench] timed {args.steps} steps: {ms_per_step * 1e3:.1f} us/step, {value:.0f} ks/s "
-        f"(host wall {wall * 1e3 / args.steps:.1f} us/step)")
+        f"(host wall {wall * 1e6 / args.steps:.1f} us/step)")
 
     # roofline of the dominant kernel
     mm, byt = kernel_work(dom_cls, n, LEVEL, K, alpha, beta)
